@@ -1,0 +1,214 @@
+"""Discontinuity sensor, modal filters and positivity-preserving limiter (Sec. 4).
+
+Modal form (Sec. 4, Eq. modal solution): inside an element the solution is
+sum_j sum_k u~_{j,k} Psi_j Phi_k with Psi orthonormal under dr/2 and Phi the
+gPC basis; the spatial modal coefficients follow from the nodal ones with the
+inverse Vandermonde matrix (tensor product in 2D).  With both bases
+orthonormal, the inner product over element x random space is the sum of
+squared coefficients.
+
+Sensor (Sec. 4.2, Eq. detector): S_e = <u^N - u^{N-1}, same> / <u^N, u^N> on
+the first state, where u^N - u^{N-1} is the outermost shell of the expansion:
+spatial degree p in some direction, or total chaos degree N_c.  An element is
+flagged when theta < 0.99, i.e. S_e > S* = 10^(s0 - (2 kappa/pi) asin 0.98);
+a zero denominator is not flagged.
+
+Filters (Sec. 4.1): u~* = Lambda o u~ and back to nodal with V.
+* exponential (Sec. 4.1.1): lambda = exp(-alpha dt sum_i eta_i^s) with
+  eta = j/p per spatial direction and |k|/N_c in random space, cutoff N* = 0
+  (App. A);
+* L2 (Sec. 4.1.2, Eq. filter function, Eq. l2 strength):
+  lambda = 1 / (1 + alpha1 sum_d j_d^2 (j_d+1)^2 + alpha2 |k|^2 (|k|+1)^2),
+  alpha1 = 1/(eps1 N_p^2 (N_p-1)^2), alpha2 = 1/(eps2 N_c^2 (N_c+1)^2).
+
+Limiter (Sec. 4.3): per element, mean state u_bar over element x random space,
+eps = min(1e-8, rho_bar, p_bar); if the minimum of density or pressure over
+(solution and flux points) x (random nodes) is below eps, density slopes are
+scaled by beta1 = min((rho_bar - eps)/(rho_bar - rho_min), 1), then every
+point whose pressure is still below eps gets the root beta_l of
+p(beta (u* - u_bar) + u_bar) = eps, and all states are scaled by
+beta2 = min_l beta_l.  Because the map u -> beta (u - u_bar) + u_bar is
+affine, it is applied to the gPC coefficients directly (only the k = 0 mode
+carries the mean).
+"""
+
+import numpy as np
+
+from .fr import euler_pressure, nodal_at_face_points, nodal_at_solution_points
+from .tables import sensor_threshold
+
+
+class NotRealizable(ArithmeticError):
+    pass
+
+
+# ----------------------------------------------------------------------------
+# spatial modal transforms
+# ----------------------------------------------------------------------------
+
+def to_spatial_modal(prob, T, u):
+    if prob.dim == 1:
+        return np.einsum("jl,skel->skej", T.Vinv, u)
+    S, M, E, _ = u.shape
+    n = T.n
+    u5 = u.reshape(S, M, E, n, n)  # [.., b, a]
+    m = np.einsum("ac,bd,skedc->skeba", T.Vinv, T.Vinv, u5)
+    return m.reshape(S, M, E, n * n)
+
+
+def to_nodal(prob, T, ut):
+    if prob.dim == 1:
+        return np.einsum("jl,skel->skej", T.V, ut)
+    S, M, E, _ = ut.shape
+    n = T.n
+    u5 = ut.reshape(S, M, E, n, n)
+    m = np.einsum("ac,bd,skedc->skeba", T.V, T.V, u5)
+    return m.reshape(S, M, E, n * n)
+
+
+def spatial_degrees(prob, T):
+    """Per solution-point mode index: tuple of per-direction degrees."""
+    n = T.n
+    if prob.dim == 1:
+        return [(j,) for j in range(n)]
+    return [(j % n, j // n) for j in range(n * n)]
+
+
+# ----------------------------------------------------------------------------
+# sensor and filter
+# ----------------------------------------------------------------------------
+
+def sensor_flags(prob, T, R, u):
+    """Boolean flag per element (Eq. detector)."""
+    E = u.shape[2]
+    if prob.sensor == "always":
+        return np.ones(E, dtype=bool)
+    ut = to_spatial_modal(prob, T, u)[0]  # first state: [k, e, j]
+    degs = spatial_degrees(prob, T)
+    shell = np.zeros((R.M, len(degs)), dtype=bool)
+    for k in range(R.M):
+        for j, d in enumerate(degs):
+            shell[k, j] = (max(d) == prob.p) or (R.kdeg[k] == prob.gpc_order)
+    e2 = ut * ut
+    num = np.einsum("kej,kj->e", e2, shell.astype(np.float64))
+    den = np.einsum("kej->e", e2)
+    thr = sensor_threshold(prob.s0, prob.kappa)
+    flags = np.zeros(E, dtype=bool)
+    nz = den > 0.0
+    flags[nz] = (num[nz] / den[nz]) > thr
+    return flags
+
+
+def filter_strength(prob, T, R, dt):
+    """Lambda[k, j]: filter factor per (gPC mode, spatial mode)."""
+    degs = spatial_degrees(prob, T)
+    lam = np.ones((R.M, len(degs)))
+    Nc = prob.gpc_order
+    if prob.filter == "exp":
+        for k in range(R.M):
+            ez = (R.kdeg[k] / Nc) ** prob.s if Nc > 0 else 0.0
+            for j, d in enumerate(degs):
+                ex = sum((dj / prob.p) ** prob.s for dj in d)
+                lam[k, j] = np.exp(-prob.alpha * dt * (ex + ez))
+    elif prob.filter == "l2":
+        Np = T.n
+        a1 = 1.0 / (prob.eps1 * Np * Np * (Np - 1) * (Np - 1))
+        a2 = 1.0 / (prob.eps2 * Nc * Nc * (Nc + 1) * (Nc + 1)) if Nc > 0 else 0.0
+        for k in range(R.M):
+            kk = R.kdeg[k]
+            for j, d in enumerate(degs):
+                pen = a1 * sum(dj * dj * (dj + 1) * (dj + 1) for dj in d) + a2 * kk * kk * (kk + 1) * (kk + 1)
+                lam[k, j] = 1.0 / (1.0 + pen)
+    return lam
+
+
+def sensor_filter(prob, T, R, u, dt):
+    """Sensor-gated filter; returns (u_filtered, flags)."""
+    if prob.filter == "none":
+        return u.copy(), np.zeros(u.shape[2], dtype=bool)
+    flags = sensor_flags(prob, T, R, u)
+    lam = filter_strength(prob, T, R, dt)
+    ut = to_spatial_modal(prob, T, u)
+    uf = to_nodal(prob, T, ut * lam[None, :, None, :])
+    out = u.copy()
+    out[:, :, flags, :] = uf[:, :, flags, :]
+    return out, flags
+
+
+# ----------------------------------------------------------------------------
+# positivity-preserving limiter
+# ----------------------------------------------------------------------------
+
+def element_mean(prob, T, u):
+    """Mean over element x random space: sum_j (w_j/2) u[s, 0, e, j] (tensor in 2D)."""
+    if prob.dim == 1:
+        wts = T.w / 2.0
+    else:
+        wts = np.outer(T.w / 2.0, T.w / 2.0).ravel()  # index b*n + a
+    return np.einsum("sej,j->se", u[:, 0], wts)
+
+
+def pressure_root(prob, ubar, ustar, eps):
+    """Root in (0, 1) of p(beta (u* - u_bar) + u_bar) = eps.
+
+    With d = u* - u_bar and e' = eps/(gamma-1), rho (E - e') - |m|^2/2 = 0 is
+    the quadratic a beta^2 + b beta + c with
+      a = dE drho - |dm|^2/2,  b = dE rho_bar + (E_bar - e') drho - m_bar.dm,
+      c = (E_bar - e') rho_bar - |m_bar|^2/2 > 0;
+    its root in (0, 1) is taken in the cancellation-free form.
+    """
+    g = prob.gamma
+    ep = eps / (g - 1.0)
+    d = ustar - ubar
+    rb, Eb = ubar[0], ubar[-1]
+    mb = ubar[1:-1]
+    dr, dE = d[0], d[-1]
+    dm = d[1:-1]
+    a = dE * dr - 0.5 * np.sum(dm * dm, axis=0)
+    b = dE * rb + (Eb - ep) * dr - np.sum(mb * dm, axis=0)
+    c = (Eb - ep) * rb - 0.5 * np.sum(mb * mb, axis=0)
+    disc = np.maximum(b * b - 4.0 * a * c, 0.0)
+    sq = np.sqrt(disc)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        beta = np.where(b < 0.0, 2.0 * c / (-b + sq), (-b - sq) / (2.0 * a))
+    return beta
+
+
+def limit(prob, T, R, u):
+    """Positivity-preserving limiter; returns (u_limited, flags)."""
+    E = u.shape[2]
+    flags = np.zeros(E, dtype=bool)
+    if not prob.limiter:
+        return u.copy(), flags
+    dim = prob.dim
+    out = u.copy()
+    ubar = element_mean(prob, T, u)  # [s, e]
+    pbar = euler_pressure(ubar, prob.gamma, dim)
+    if np.any(ubar[0] <= 0.0) or np.any(pbar <= 0.0) or not np.all(np.isfinite(ubar)):
+        raise NotRealizable("element mean density or pressure not positive")
+    Usp = nodal_at_solution_points(R, u)                  # [s, q, e, j]
+    Ufp = nodal_at_face_points(prob, T, Usp)              # [s, q, e, f]
+    for e in range(E):
+        pts = np.concatenate([Usp[:, :, e, :].reshape(prob.S, -1), Ufp[:, :, e, :].reshape(prob.S, -1)], axis=1)
+        rb = ubar[0, e]
+        eps = min(1e-8, rb, pbar[e])
+        rho_min = pts[0].min()
+        p_min = euler_pressure(pts, prob.gamma, dim).min()
+        if not (min(rho_min, p_min) < eps):
+            continue
+        flags[e] = True
+        beta1 = 1.0 if rho_min >= eps else (rb - eps) / (rb - rho_min)
+        star = pts.copy()
+        star[0] = beta1 * (pts[0] - rb) + rb
+        out[0, :, e, :] = beta1 * (out[0, :, e, :] - rb * (np.arange(R.M) == 0)[:, None]) \
+            + rb * (np.arange(R.M) == 0)[:, None]
+        pstar = euler_pressure(star, prob.gamma, dim)
+        low = pstar < eps
+        beta2 = 1.0
+        if np.any(low):
+            roots = pressure_root(prob, ubar[:, e][:, None], star[:, low], eps)
+            beta2 = float(np.min(roots))
+        mode0 = (np.arange(R.M) == 0)[:, None]
+        for s in range(prob.S):
+            out[s, :, e, :] = beta2 * (out[s, :, e, :] - ubar[s, e] * mode0) + ubar[s, e] * mode0
+    return out, flags

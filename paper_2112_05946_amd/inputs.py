@@ -1,0 +1,207 @@
+"""Workload definitions and seeded synthetic inputs.
+
+This module is shared by the HIP path and by the CPU oracle.  It holds only
+problem statements (sizes, parameters, analytic initial data) and seeded
+random states; it contains no part of the FR-SG method (no quadrature, no
+basis, no projection, no flux).  Each side evaluates initial data at its own
+solution points and random nodes and projects with its own tables.
+
+Workloads are shaped like the paper's experiments (Sec. 5):
+
+* ``advection_sine``      stochastic linear advection u_t + u_x = 0 (Sec. 5.1)
+                          with u0 = sin(2 pi (x + 0.1 z)) on periodic [0, 1];
+* ``burgers_sine``        inviscid Burgers f = u^2/2 (Sec. 5.2) with
+                          u0 = 1 + 0.5 sin(pi x) + 0.2 z sin(pi x) on periodic [0, 2];
+* ``sod_interface``       1D Euler Sod tube with uncertain interface
+                          x0 = 0.5 + 0.05 z (Sec. 5.3, second case);
+* ``shock_vortex``        2D Euler stationary Mach 1.1 normal shock at x = 0.5
+                          and an isentropic vortex of strength 0.3 + 0.05 z1
+                          centred at (0.25 + 0.02 z2, 0.5) (Sec. 5.4 setup with
+                          two random dimensions).
+"""
+
+import math
+
+import numpy as np
+
+GAMMA = 1.4
+
+
+def _cons1d(rho, u, p, gamma=GAMMA):
+    return np.stack([rho, rho * u, p / (gamma - 1.0) + 0.5 * rho * u * u])
+
+
+def _cons2d(rho, u, v, p, gamma=GAMMA):
+    return np.stack([rho, rho * u, rho * v, p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)])
+
+
+# ----------------------------------------------------------------------------
+# shock-vortex problem data (Sec. 5.4, Rankine-Hugoniot + isentropic vortex)
+# ----------------------------------------------------------------------------
+
+SV_MACH = 1.1
+SV_XSHOCK = 0.5
+SV_MU = 0.204
+SV_RC = 0.05
+
+
+def shock_states(mach=SV_MACH, gamma=GAMMA):
+    """Upstream (x < shock) and downstream primitive states (rho, u, v, p)."""
+    rho1, p1 = 1.0, 1.0
+    u1 = mach * math.sqrt(gamma * p1 / rho1)
+    m2 = mach * mach
+    rho2 = rho1 * (gamma + 1.0) * m2 / ((gamma - 1.0) * m2 + 2.0)
+    p2 = p1 * (1.0 + 2.0 * gamma / (gamma + 1.0) * (m2 - 1.0))
+    u2 = u1 * rho1 / rho2
+    return (rho1, u1, 0.0, p1), (rho2, u2, 0.0, p2)
+
+
+def shock_vortex_ic(x, y, z1, z2, gamma=GAMMA):
+    up, down = shock_states(gamma=gamma)
+    zeta = 0.3 + 0.05 * z1
+    xc = 0.25 + 0.02 * z2
+    yc = 0.5
+    upstream = x < SV_XSHOCK
+    rho0 = np.where(upstream, up[0], down[0])
+    u0 = np.where(upstream, up[1], down[1])
+    p0 = np.where(upstream, up[3], down[3])
+    dx, dy = x - xc, y - yc
+    r = np.sqrt(dx * dx + dy * dy)
+    eta = r / SV_RC
+    # (du, dv) = zeta eta exp(mu (1 - eta^2)) (sin theta, -cos theta)
+    amp = zeta * eta * np.exp(SV_MU * (1.0 - eta * eta))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        st = np.where(r > 0, dy / np.where(r > 0, r, 1.0), 0.0)
+        ct = np.where(r > 0, dx / np.where(r > 0, r, 1.0), 0.0)
+    du, dv = amp * st, -amp * ct
+    dT = -(gamma - 1.0) * zeta * zeta / (4.0 * SV_MU * gamma) * np.exp(2.0 * SV_MU * (1.0 - eta * eta))
+    T0 = p0 / rho0
+    T = T0 + dT
+    # isentropic: p / rho^gamma unchanged  =>  rho = rho0 (T/T0)^(1/(gamma-1))
+    rho = rho0 * (T / T0) ** (1.0 / (gamma - 1.0))
+    p = rho * T
+    return _cons2d(rho, u0 + du, dv, p, gamma)
+
+
+def initial_condition(name, x, y, z, gamma=GAMMA):
+    """Conservative initial data at points x, y (same shape) and random z[..., rdim]."""
+    z1 = z[..., 0]
+    if name == "advection_sine":
+        return np.sin(2.0 * np.pi * (x + 0.1 * z1))[None]
+    if name == "burgers_sine":
+        return (1.0 + 0.5 * np.sin(np.pi * x) + 0.2 * z1 * np.sin(np.pi * x))[None]
+    if name == "sod_interface":
+        left = x < 0.5 + 0.05 * z1
+        rho = np.where(left, 1.0, 0.125)
+        p = np.where(left, 1.0, 0.1)
+        return _cons1d(rho, np.zeros_like(rho), p, gamma)
+    if name == "shock_vortex":
+        return shock_vortex_ic(x, y, z1, z[..., 1], gamma)
+    raise ValueError(name)
+
+
+# ----------------------------------------------------------------------------
+# configurations
+# ----------------------------------------------------------------------------
+
+def _sod_bc():
+    L = list(_cons1d(np.array(1.0), np.array(0.0), np.array(1.0))) + [0.0]
+    R = list(_cons1d(np.array(0.125), np.array(0.0), np.array(0.1))) + [0.0]
+    return [[float(v) for v in L], [float(v) for v in R], [0.0] * 4, [0.0] * 4]
+
+
+def _sv_bc():
+    up, _ = shock_states()
+    st = [float(v) for v in _cons2d(*[np.array(c) for c in up])]
+    return [st, [0.0] * 4, [0.0] * 4, [0.0] * 4]
+
+
+ADVECTION = dict(
+    name="advection_sine", equation="advection", ic="advection_sine",
+    nx=64, xlo=0.0, xhi=1.0, p=2, gpc_order=4, nq1d=8, rdim=1,
+    bc=["periodic"] * 4, adv_speed=1.0, filter="none", limiter=False,
+    cfl=0.3, t_end=0.5)
+
+BURGERS = dict(
+    name="burgers_sine", equation="burgers", ic="burgers_sine",
+    nx=1024, xlo=0.0, xhi=2.0, p=3, gpc_order=8, nq1d=16, rdim=1,
+    bc=["periodic"] * 4, filter="exp", alpha=36.0, s=8.0,
+    sensor="detector", s0=-2.0 * math.log10(3.0), kappa=4.0,
+    limiter=False, cfl=0.3, t_end=1.0)
+
+SOD = dict(
+    name="sod_interface", equation="euler1d", ic="sod_interface",
+    nx=2048, xlo=0.0, xhi=1.0, p=3, gpc_order=10, nq1d=24, rdim=1,
+    bc=["dirichlet", "dirichlet", "periodic", "periodic"], bc_state=_sod_bc(),
+    gamma=GAMMA, filter="l2", eps1=0.6, eps2=0.6,
+    sensor="detector", s0=-3.0 * math.log10(3.0), kappa=4.0,
+    limiter=True, cfl=0.3, t_end=0.2)
+
+SHOCK_VORTEX = dict(
+    name="shock_vortex", equation="euler2d", ic="shock_vortex",
+    nx=256, ny=128, xlo=0.0, xhi=2.0, ylo=0.0, yhi=1.0,
+    p=3, gpc_order=4, nq1d=5, rdim=2,
+    bc=["dirichlet", "outflow", "reflect", "reflect"], bc_state=_sv_bc(),
+    gamma=GAMMA, filter="l2", eps1=0.6, eps2=1.0,
+    sensor="detector", s0=-3.0 * math.log10(3.0), kappa=4.0,
+    limiter=True, cfl=0.3, t_end=0.3)
+
+BURGERS_ADJOINT = dict(BURGERS, name="burgers_adjoint", nx=4096, n_steps=500, checkpoint_every=25)
+
+CONFIGS = {c["name"]: c for c in (ADVECTION, BURGERS, SOD, SHOCK_VORTEX, BURGERS_ADJOINT)}
+
+
+def small(cfg, nx, ny=None, **kw):
+    """Same problem on a smaller mesh (parity-test sizes)."""
+    out = dict(cfg, nx=nx, **kw)
+    if ny is not None:
+        out["ny"] = ny
+    return out
+
+
+# ----------------------------------------------------------------------------
+# seeded random modal states (fuzz inputs)
+# ----------------------------------------------------------------------------
+
+def fuzz_scalar(M, E, nsp, seed, scale=0.5, decay=0.6, offset=0.0):
+    rng = np.random.default_rng(seed)
+    u = rng.standard_normal((1, M, E, nsp)) * scale
+    u *= (decay ** np.arange(M))[None, :, None, None]
+    u[:, 0] += offset
+    return u
+
+
+def fuzz_euler(dim, M, E, nsp, seed, pert=0.02, vacuum_frac=0.0, gamma=GAMMA):
+    """Realizable Euler states with small gPC perturbations.
+
+    A fraction `vacuum_frac` of the elements gets a low mean density and
+    pressure with strong spatial and random variation so that density or
+    pressure dips below zero at some nodes (elements the limiter must act on).
+    """
+    rng = np.random.default_rng(seed)
+    S = dim + 2
+    rho = rng.uniform(0.5, 2.0, (E, 1)) * (1.0 + 0.1 * rng.uniform(-1, 1, (E, nsp)))
+    vel = rng.uniform(-0.5, 0.5, (dim, E, 1)) + 0.05 * rng.uniform(-1, 1, (dim, E, nsp))
+    p = rng.uniform(0.5, 2.0, (E, 1)) * (1.0 + 0.1 * rng.uniform(-1, 1, (E, nsp)))
+    if dim == 1:
+        base = _cons1d(rho, vel[0], p, gamma)
+    else:
+        base = _cons2d(rho, vel[0], vel[1], p, gamma)
+    u = np.zeros((S, M, E, nsp))
+    u[:, 0] = base
+    k = np.arange(1, M)
+    u[:, 1:] = rng.standard_normal((S, M - 1, E, nsp)) * pert * (0.5 ** k)[None, :, None, None]
+    u[:, 1:] *= np.abs(u[:, :1])  # relative to the local mean
+    nvac = int(round(vacuum_frac * E))
+    if nvac > 0:
+        idx = rng.choice(E, nvac, replace=False)
+        pattern = np.where(np.arange(nsp) % 2 == 0, 1.0, -1.0)
+        for e in idx:
+            r0 = 10.0 ** rng.uniform(-3, -1)
+            u[:, :, e, :] = 0.0
+            u[0, 0, e, :] = r0 * (1.0 + 0.9 * pattern)
+            u[0, 1, e, :] = 0.8 * r0
+            u[1, 0, e, :] = r0 * 0.3 * pattern
+            u[-1, 0, e, :] = r0 * (1.0 + 0.5 * pattern) / (gamma - 1.0)
+            u[-1, 1, e, :] = -0.7 * r0 / (gamma - 1.0)
+    return u

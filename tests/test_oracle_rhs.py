@@ -1,0 +1,128 @@
+"""Pins for the oracle's FR-SG right-hand side (Sec. 2.1, Sec. 3.2-3.5)."""
+
+import numpy as np
+import pytest
+
+from indep import dg_weak_rhs_1d
+from oracle.fr import rhs
+from oracle.problem import Problem
+from oracle.tables import build_tables
+from paper_2112_05946_amd import inputs
+
+
+def _prob(**kw):
+    base = dict(equation="advection", nx=12, p=2, gpc_order=3, nq1d=6, xlo=0.0, xhi=1.0)
+    base.update(kw)
+    return Problem.from_config(base)
+
+
+@pytest.mark.parametrize("eq,p,order,nq,a", [
+    ("advection", 2, 4, 8, 1.0), ("advection", 3, 3, 5, -0.7), ("burgers", 3, 8, 16, 0.0),
+    ("burgers", 1, 2, 3, 0.0), ("burgers", 4, 5, 9, 0.0)])
+def test_fr_radau_equals_dg_weak_form_scalar(eq, p, order, nq, a):
+    """FR with Radau correction == nodal DG weak form (Huynh, Sec. 3.3), SG in z."""
+    prob = _prob(equation=eq, p=p, gpc_order=order, nq1d=nq, adv_speed=a, nx=11, xhi=2.0)
+    T, R = build_tables(prob)
+    u = inputs.fuzz_scalar(R.M, prob.E, p + 1, seed=3, offset=0.3)
+    got = rhs(prob, T, R, u)
+    ref = dg_weak_rhs_1d(eq, u, p, order, nq, prob.dx, a=a)
+    assert np.max(np.abs(got - ref)) < 1e-11 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+@pytest.mark.parametrize("p,order,nq", [(3, 4, 8), (2, 2, 5)])
+def test_fr_radau_equals_dg_weak_form_euler1d(bc, p, order, nq):
+    st = [[1.0, 0.2, 2.6, 0.0], [0.125, 0.0, 0.25, 0.0], [0] * 4, [0] * 4]
+    prob = _prob(equation="euler1d", p=p, gpc_order=order, nq1d=nq, nx=9,
+                 bc=[bc, bc, "periodic", "periodic"], bc_state=st)
+    T, R = build_tables(prob)
+    u = inputs.fuzz_euler(1, R.M, prob.E, p + 1, seed=5)
+    got = rhs(prob, T, R, u)
+    ref = dg_weak_rhs_1d("euler1d", u, p, order, nq, prob.dx, bc=bc, bc_states=st)
+    assert np.max(np.abs(got - ref)) < 1e-10 * np.max(np.abs(ref))
+
+
+def test_free_stream_preserved():
+    for eq, S in (("euler1d", 3), ("euler2d", 4)):
+        kw = dict(equation=eq, p=3, gpc_order=3, nq1d=5, nx=6)
+        if eq == "euler2d":
+            kw.update(ny=5, rdim=2, gpc_order=2, nq1d=3, yhi=0.7)
+        prob = _prob(**kw)
+        T, R = build_tables(prob)
+        u = np.zeros((S, R.M, prob.E, prob.nsp))
+        const = [1.3, 0.4, 2.9] if S == 3 else [1.3, 0.4, -0.3, 2.9]
+        u[:, 0] = np.asarray(const)[:, None, None]
+        assert np.max(np.abs(rhs(prob, T, R, u))) < 1e-12
+
+
+def test_periodic_rhs_conserves_every_mode():
+    """Periodic: sum_e J sum_j w_j du_k/dt = 0 for every mode and state (Sec. 3.3 conservation)."""
+    for eq in ("burgers", "euler1d"):
+        prob = _prob(equation=eq, p=3, gpc_order=5, nq1d=7, nx=10)
+        T, R = build_tables(prob)
+        if eq == "burgers":
+            u = inputs.fuzz_scalar(R.M, prob.E, 4, seed=1, offset=0.5)
+        else:
+            u = inputs.fuzz_euler(1, R.M, prob.E, 4, seed=1)
+        d = rhs(prob, T, R, u)
+        tot = np.einsum("skej,j->sk", d, T.w)
+        assert np.max(np.abs(tot)) < 1e-11 * np.max(np.abs(d))
+
+
+def _to2d_yconst(u1, ny, n):
+    """Embed a 1D Euler state as a y-independent 2D state (my = 0)."""
+    S, M, E, _ = u1.shape
+    u2 = np.zeros((4, M, ny, E, n, n))
+    for s_src, s_dst in ((0, 0), (1, 1), (2, 3)):
+        u2[s_dst] = u1[s_src][:, None, :, None, :]
+    return u2.reshape(4, M, ny * E, n * n)
+
+
+@pytest.mark.parametrize("bcy", ["periodic", "reflect"])
+def test_2d_y_independent_equals_1d(bcy):
+    """A y-independent 2D Euler problem reduces to the 1D one (Sec. 3.5 tensor extension)."""
+    p, order, nq = 3, 3, 4
+    p1 = _prob(equation="euler1d", p=p, gpc_order=order, nq1d=nq, nx=7, xhi=1.4)
+    p2 = _prob(equation="euler2d", p=p, gpc_order=order, nq1d=nq, nx=7, ny=3, xhi=1.4, yhi=0.9,
+               rdim=1, bc=["periodic", "periodic", bcy, bcy])
+    T1, R1 = build_tables(p1)
+    T2, R2 = build_tables(p2)
+    u1 = inputs.fuzz_euler(1, R1.M, p1.E, p + 1, seed=7)
+    d1 = rhs(p1, T1, R1, u1)
+    d2 = rhs(p2, T2, R2, _to2d_yconst(u1, 3, p + 1))
+    ref = _to2d_yconst(d1, 3, p + 1)
+    assert np.max(np.abs(d2 - ref)) < 1e-11 * np.max(np.abs(ref))
+
+
+def test_2d_transpose_symmetry():
+    """Swapping x<->y (and the momenta) maps the RHS onto its transpose."""
+    n, nx, ny = 4, 5, 3
+    kw = dict(equation="euler2d", p=n - 1, gpc_order=2, nq1d=3, rdim=2)
+    pa = _prob(nx=nx, ny=ny, xhi=1.0, yhi=0.6, bc=["periodic", "periodic", "reflect", "reflect"], **kw)
+    pb = _prob(nx=ny, ny=nx, xhi=0.6, yhi=1.0, bc=["reflect", "reflect", "periodic", "periodic"], **kw)
+    T, R = build_tables(pa)
+    ua = inputs.fuzz_euler(2, R.M, pa.E, n * n, seed=11)
+
+    def tr(u, ny_, nx_):
+        v = u.reshape(4, R.M, ny_, nx_, n, n).transpose(0, 1, 3, 2, 5, 4)
+        v = v[[0, 2, 1, 3]]
+        return v.reshape(4, R.M, ny_ * nx_, n * n)
+
+    da = rhs(pa, T, R, ua)
+    db = rhs(pb, T, R, tr(ua, ny, nx))
+    assert np.max(np.abs(db - tr(da, ny, nx))) < 1e-11 * np.max(np.abs(da))
+
+
+def test_linear_advection_modes_decouple():
+    """Linear flux: mode k of the RHS depends on mode k only (Sec. 2.1 SG system)."""
+    prob = _prob(equation="advection", p=2, gpc_order=4, nq1d=8, nx=8, adv_speed=1.0)
+    T, R = build_tables(prob)
+    u = inputs.fuzz_scalar(R.M, prob.E, 3, seed=2)
+    full = rhs(prob, T, R, u)
+    for k in range(R.M):
+        uk = np.zeros_like(u)
+        uk[:, k] = u[:, k]
+        dk = rhs(prob, T, R, uk)
+        assert np.max(np.abs(dk[:, k] - full[:, k])) < 1e-12
+        others = np.delete(dk, k, axis=1)
+        assert np.max(np.abs(others)) < 1e-12
