@@ -1,0 +1,152 @@
+"""Benchmark: FR-SG SSP-RK3 steps on one MI355X.
+
+Workload: the 2D Euler shock-vortex problem, 256 x 128 quadrilateral elements,
+FR degree 3 (4 x 4 Legendre-Gauss points), total-degree-4 Legendre chaos in two
+random dimensions (15 modes), 5 x 5 Gauss nodes, L2 filter switched by the
+modal-decay detector, positivity limiter, CFL 0.3; FP64.  Inputs are synthetic
+(analytic initial data projected by the library) and resident in HBM before the
+timed region.  One step = the whole hot path: three right-hand sides, the
+stage combinations, the CFL reduction, the limiter after each stage and the
+detector-switched filter plus limiter at the end of the step.
+
+Prints one JSON line.  `value` = DOF-updates/s, DOF = S * M * E * N_sp stored
+coefficients advanced by one full step.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FR-SG DOF-updates/s, FP64 vs FP32-mixed at stated L2 err; adjoint/forward cost"
+HBM_PEAK_GBS = 8000.0
+
+
+def traffic_for(kernel, alg_bytes):
+    """HBM bytes per launch measured with rocprofv3 counters, if they match this build's kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(kernel)
+        src = os.path.join(ROOT, rec["source"])
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if digest != rec["source_sha256"]:
+            return None
+        return float(rec["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def cpu_baseline(cfg_full):
+    """Oracle timed on the host: one SSP-RK3 step of the same problem on a quarter-size mesh."""
+    import numpy as np  # noqa: F401
+    from oracle.initial import project_initial
+    from oracle.problem import Problem
+    from oracle.stepper import step
+    from oracle.tables import build_tables
+    from paper_2112_05946_amd import inputs
+
+    cfg = inputs.small(cfg_full, cfg_full["nx"] // 2, cfg_full.get("ny", 1) // 2 if cfg_full.get("ny") else None)
+    prob = Problem.from_config(cfg)
+    T, R = build_tables(prob)
+    u = project_initial(prob, cfg["ic"], (T, R))
+    threads = 1
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([1] + [int(i.get("num_threads", 1)) for i in threadpool_info()])
+    except Exception:
+        pass
+    t0 = time.perf_counter()
+    step(prob, u, None, (T, R))
+    el = time.perf_counter() - t0
+    dof = prob.S * R.M * prob.E * prob.nsp
+    return {"value": dof / el, "unit": "DOF-updates/s", "cores": threads, "kind": "oracle",
+            "sample": "1 SSP-RK3 step of the same problem on a %dx%d mesh (%d DOF), %.1f s" %
+                      (prob.nx, prob.ny, dof, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="shock_vortex")
+    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the multi-GPU halo exchange is not built); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2112_05946_amd import inputs
+    from paper_2112_05946_amd.binding import Solver
+
+    torch.cuda.set_device(0)
+    cfg = inputs.CONFIGS[args.config]
+    sol = Solver(cfg, precision=args.precision)
+    u = sol.initial_state()
+    dt_used = torch.empty(1, dtype=torch.float64, device=u.device)
+    flags = torch.empty(4 * sol.E, dtype=torch.uint8, device=u.device)
+    for _ in range(args.warmup):
+        sol.step(u, None, dt_used, flags)
+    sol.sync()
+
+    # timed region: K whole steps, inputs resident in HBM
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        sol.step(u, None, dt_used, flags)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / args.steps
+    sol.sync()
+    n_dof = int(sol.info["n_dof"])
+    value = n_dof / (ms / 1e3)
+
+    # per-pass device times over a second run of K steps (events around each launch)
+    sol.timing(True)
+    for _ in range(args.steps):
+        sol.step(u, None, dt_used, flags)
+    passes = sol.timing_read()
+    sol.timing(False)
+    sol.sync()
+    dom = max(passes, key=lambda k: passes[k][1])
+    launches, tot_ms, alg = passes[dom]
+    avg_s = tot_ms / launches / 1e3
+    achieved = alg / avg_s / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(dom, alg), "kernel": dom,
+                "alg_bytes_per_launch": alg, "avg_launch_ms": avg_s * 1e3}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "DOF-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "%s %dx%d elements, p=%d, %d gPC modes (rdim %d), %d random nodes, %d states, "
+                               "%d DOF" % (args.config, cfg["nx"], cfg.get("ny", 1), cfg["p"], sol.shape[1],
+                                           cfg.get("rdim", 1), sol.info["n_nodes"], sol.shape[0], n_dof),
+                   "precision": args.precision, "wall_s_timed": wall},
+        "roofline": roofline,
+        "passes_ms_per_step": {k: v[1] / args.steps for k, v in passes.items()},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

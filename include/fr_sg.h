@@ -1,0 +1,200 @@
+/*
+ * fr_sg.h -- C ABI of the MI355X flux reconstruction stochastic Galerkin
+ * (FR-SG) hot path.
+ *
+ * Method: Xiao, Kusch, Koellermeier, Frank, "A flux reconstruction stochastic
+ * Galerkin scheme for hyperbolic conservation laws" (arXiv 2112.05946).
+ *
+ * All device pointers are HIP device memory (e.g. torch CUDA tensors on
+ * ROCm); host pointers are ordinary memory.  Every call that launches work is
+ * asynchronous on the stream given to fr_sg_init (or fr_sg_set_stream); none
+ * synchronises except fr_sg_init, fr_sg_query, fr_sg_points and fr_sg_sync.
+ * No exception crosses this boundary: every entry point returns a status.
+ *
+ * State layout (every state-shaped argument): double u[S][M][E][N_sp],
+ * C-contiguous, where
+ *   S    conserved variables (1 scalar, 3 Euler 1D, 4 Euler 2D),
+ *   M    gPC modes (N_c + 1 in 1D random space; (N_c+1)(N_c+2)/2 for the
+ *        total-degree set in 2D random space, graded order
+ *        (0,0),(1,0),(0,1),(2,0),(1,1),(0,2),...),
+ *   E    elements, row-major e = iy * nx + ix,
+ *   N_sp solution points per element, (p+1)^dim, j = a + (p+1) * b with a
+ *        the x index; points are Legendre-Gauss in each direction.
+ * i.e. the gPC coefficients (Sec. 2.1, Eq. polynomial chaos) held at the FR
+ * solution points (Sec. 3.2) of each element.
+ *
+ * Ownership: the caller owns every state, right-hand-side, adjoint, flag and
+ * time-step buffer.  The library owns the context, its operator tables and a
+ * workspace allocated once by fr_sg_init (two stage states plus nodal
+ * scratch; fr_sg_query reports its size) and freed by fr_sg_destroy.  No
+ * other call allocates device memory.
+ *
+ * Errors: invalid or unsupported problems are rejected by fr_sg_init before
+ * any launch.  Non-finite or non-realizable states met on the device are
+ * latched in a device status word and returned by the next fr_sg_sync.
+ */
+#ifndef FR_SG_H
+#define FR_SG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FRSG_ABI_VERSION 1
+
+typedef int32_t fr_sg_status;
+#define FRSG_OK 0
+#define FRSG_EINVAL (-1)          /* bad argument or inconsistent problem            */
+#define FRSG_EUNSUPPORTED (-2)    /* valid but not implemented combination           */
+#define FRSG_EDEVICE (-3)         /* HIP runtime error (allocation, launch, copy)    */
+#define FRSG_ENONFINITE (-4)      /* a non-finite value met on the device            */
+#define FRSG_ENOTREALIZABLE (-5)  /* element mean density or pressure not positive   */
+#define FRSG_EABI (-6)            /* problem.abi_version != FRSG_ABI_VERSION        */
+
+/* conservation law (Sec. 5: advection, Burgers, Euler 1D, Euler 2D) */
+#define FRSG_ADVECTION 0
+#define FRSG_BURGERS 1
+#define FRSG_EULER1D 2
+#define FRSG_EULER2D 3
+
+/* boundary kinds, per side [x-lo, x-hi, y-lo, y-hi] (Sec. 2.1 boundary operator) */
+#define FRSG_BC_PERIODIC 0
+#define FRSG_BC_DIRICHLET 1   /* ghost = bc_state[side] (conservative variables) */
+#define FRSG_BC_OUTFLOW 2     /* ghost = interior trace                           */
+#define FRSG_BC_REFLECT 3     /* ghost = interior trace, normal momentum negated  */
+
+/* modal filter (Sec. 4.1.1 exponential, Sec. 4.1.2 L2) */
+#define FRSG_FILTER_NONE 0
+#define FRSG_FILTER_EXP 1
+#define FRSG_FILTER_L2 2
+
+/* filter switch: every element, or the modal-decay detector of Sec. 4.2 */
+#define FRSG_SENSOR_ALWAYS 0
+#define FRSG_SENSOR_DETECTOR 1
+
+#define FRSG_FP64 0
+#define FRSG_FP32_MIXED 1
+
+typedef struct fr_sg_problem {
+  int32_t abi_version;     /* FRSG_ABI_VERSION                                        */
+  int32_t equation;        /* FRSG_ADVECTION .. FRSG_EULER2D                          */
+  int32_t nx, ny;          /* elements per direction (ny ignored in 1D)               */
+  double xlo, xhi, ylo, yhi;
+  int32_t bc[4];           /* FRSG_BC_* for x-lo, x-hi, y-lo, y-hi                    */
+  double bc_state[4][4];   /* Dirichlet ghost states, conservative                    */
+  int32_t fr_degree;       /* p, 1..7; p+1 Legendre-Gauss points, Radau correction    */
+  int32_t rdim;            /* random dimensions, 1 or 2, i.i.d. U(-1, 1)              */
+  int32_t gpc_order;       /* N_c, total degree of the Legendre chaos                 */
+  int32_t nq1d;            /* Gauss-Legendre nodes per random dimension, >= N_c + 1   */
+  double adv_speed;        /* a in u_t + a u_x = 0                                    */
+  double gamma;            /* ratio of specific heats                                 */
+  int32_t filter;          /* FRSG_FILTER_*                                           */
+  double alpha, s;         /* exponential filter strength and order                   */
+  double eps1, eps2;       /* L2 filter damping of the last spatial / chaos mode      */
+  int32_t sensor;          /* FRSG_SENSOR_*                                           */
+  double s0, kappa;        /* detector parameters, Eq. (detector), s_e = log10(S_e)   */
+  int32_t limiter;         /* 1: positivity-preserving limiter (Euler only)           */
+  double cfl;              /* dt = cfl dx / ((p+1) lambda_max) (1D); 2D analogue      */
+  int32_t precision;       /* FRSG_FP64 or FRSG_FP32_MIXED                            */
+} fr_sg_problem;
+
+typedef struct fr_sg_info {
+  int64_t n_elem;          /* E                                                       */
+  int32_t nsp;             /* N_sp                                                    */
+  int32_t n_modes;         /* M                                                       */
+  int32_t n_nodes;         /* N_q (nq1d^rdim)                                         */
+  int32_t n_states;        /* S                                                       */
+  int64_t n_dof;           /* S * M * E * N_sp                                        */
+  int64_t state_bytes;     /* 8 * n_dof                                               */
+  int64_t flags_len;       /* 4 * E: see fr_sg_step                                   */
+  int64_t workspace_bytes; /* device memory held by the context                       */
+} fr_sg_info;
+
+typedef struct fr_sg_ctx fr_sg_ctx;
+
+/* Validate the problem (Sec. 1 problem statement; Sec. 2.1 gPC degree and
+ * quadrature; Sec. 3.1 mesh; Sec. 3.2 FR degree), build the operator tables
+ * in FP64 on the host (Legendre-Gauss points, Lagrange derivative matrix,
+ * Radau correction derivatives, Vandermonde matrix, chaos basis at the Gauss
+ * nodes), upload them and allocate the workspace.  hip_stream: a hipStream_t
+ * (NULL = default stream).  On failure *out is NULL and nothing is kept. */
+fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ctx** out);
+
+/* Sizes of the problem (host struct out). */
+fr_sg_status fr_sg_query(const fr_sg_ctx* ctx, fr_sg_info* out);
+
+/* Replace the stream used by later launches. */
+fr_sg_status fr_sg_set_stream(fr_sg_ctx* ctx, void* hip_stream);
+
+/* Coordinates of the library's solution points and random nodes, host arrays:
+ * x[E*N_sp], y[E*N_sp] (zeros in 1D) in the state's (e, j) order, and
+ * z[N_q*rdim] with node q = a + nq1d * b (first coordinate fastest).  Any
+ * pointer may be NULL. */
+fr_sg_status fr_sg_points(const fr_sg_ctx* ctx, double* x, double* y, double* z);
+
+/* Galerkin projection of nodal initial data (Sec. 2.1, Eq. sg conservation
+ * laws, initial condition u_k = <u0 Phi_k> by the quadrature of Eq. discrete
+ * expectation value).  u0_nodal: device, double[S][N_q][E][N_sp], values at
+ * the points of fr_sg_points; u: device state, fully overwritten. */
+fr_sg_status fr_sg_project(fr_sg_ctx* ctx, const double* u0_nodal, double* u);
+
+/* Positivity-preserving limiter of Sec. 4.3 applied in place to a state
+ * (Euler problems with limiter = 1; otherwise a no-op that clears flags).
+ * flags: device uint8[E] or NULL; 1 where the limiter acted. */
+fr_sg_status fr_sg_limit(fr_sg_ctx* ctx, double* u, uint8_t* flags);
+
+/* Semi-discrete right-hand side du/dt = -div f (Sec. 3.2-3.5, Eq. fr
+ * update): gPC expansion at the random nodes, flux, Lax-Friedrichs interface
+ * flux per node, Radau correction, Galerkin projection.  u, dudt: device
+ * states, distinct; dudt fully overwritten.  No limiter or filter. */
+fr_sg_status fr_sg_rhs(fr_sg_ctx* ctx, const double* u, double* dudt);
+
+/* One three-stage SSP Runge-Kutta step in place (limit after each stage,
+ * sensor-gated filter then limiter at the end of the step; the paper's
+ * limit/update/filter order of Eq. schemefullDiscr applied stage-wise).
+ * dt > 0: fixed step.  dt <= 0: dt from the CFL condition on u at the start
+ * of the step (maximum over solution points x random nodes).
+ * dt_used: device double[1] or NULL, receives the step used.
+ * flags: device uint8[4*E] or NULL: [0*E+e] limiter after stage 1,
+ * [1*E+e] limiter after stage 2, [2*E+e] sensor/filter at the end of the
+ * step, [3*E+e] limiter at the end of the step (1 = acted). */
+fr_sg_status fr_sg_step(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, uint8_t* flags);
+
+/* Synchronise the stream and return (then clear) the latched device status:
+ * FRSG_OK, FRSG_ENONFINITE or FRSG_ENOTREALIZABLE. */
+fr_sg_status fr_sg_sync(fr_sg_ctx* ctx);
+
+/* Per-pass device timing.  While enabled, every pass launched by fr_sg_rhs,
+ * fr_sg_step and fr_sg_limit is bracketed by a pair of HIP events recorded on
+ * the context's stream; fr_sg_timing_read synchronises the stream, sums the
+ * elapsed times per pass name and clears the record.  Enabling (or disabling)
+ * clears the record too.  Each entry also states the algorithmic HBM bytes of
+ * one launch of that pass (the state-sized arrays the method has to read and
+ * write in it, 8 bytes per coefficient; 0 for passes that only move
+ * intermediate data). */
+typedef struct fr_sg_pass_time {
+  char name[32];           /* pass name, NUL-terminated                              */
+  int64_t launches;        /* launches recorded                                      */
+  double total_ms;         /* summed event-to-event device time                      */
+  double alg_bytes;        /* algorithmic HBM bytes of one launch                    */
+} fr_sg_pass_time;
+
+fr_sg_status fr_sg_timing_enable(fr_sg_ctx* ctx, int enable);
+
+/* out: host array of `capacity` entries; *count receives the number written. */
+fr_sg_status fr_sg_timing_read(fr_sg_ctx* ctx, fr_sg_pass_time* out, int32_t capacity, int32_t* count);
+
+/* Free the context and its device memory.  NULL is accepted. */
+fr_sg_status fr_sg_destroy(fr_sg_ctx* ctx);
+
+/* Text of the last error on this context (or of the last failed fr_sg_init
+ * when ctx is NULL).  Valid until the next call on the same context. */
+const char* fr_sg_last_error(const fr_sg_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FR_SG_H */

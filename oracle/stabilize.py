@@ -174,6 +174,40 @@ def pressure_root(prob, ubar, ustar, eps):
     return beta
 
 
+def limiter_margin(prob, T, R, u):
+    """Per element: min(rho_min, p_min) - eps and the magnitude of the state.
+
+    Diagnostic for comparing switch decisions made in different arithmetic
+    orders: a decision whose margin is at the rounding level of the state
+    (about 1e-16 times its magnitude) is a tie.
+    """
+    E = u.shape[2]
+    dim = prob.dim
+    ubar = element_mean(prob, T, u)
+    pbar = euler_pressure(ubar, prob.gamma, dim)
+    Usp = nodal_at_solution_points(R, u)
+    Ufp = nodal_at_face_points(prob, T, Usp)
+    pts = np.concatenate([Usp.transpose(0, 2, 1, 3).reshape(prob.S, E, -1),
+                          Ufp.transpose(0, 2, 1, 3).reshape(prob.S, E, -1)], axis=2)
+    eps = np.minimum(1e-8, np.minimum(ubar[0], pbar))
+    m = np.minimum(pts[0].min(axis=1), euler_pressure(pts, prob.gamma, dim).min(axis=1)) - eps
+    scale = np.abs(pts).max(axis=(0, 2))
+    return m, scale
+
+
+def sensor_margin(prob, T, R, u):
+    """Per element: (S_e, S*) of the detector (diagnostic, see limiter_margin)."""
+    ut = to_spatial_modal(prob, T, u)[0]
+    degs = spatial_degrees(prob, T)
+    shell = np.array([[(max(d) == prob.p) or (R.kdeg[k] == prob.gpc_order) for d in degs] for k in range(R.M)])
+    e2 = ut * ut
+    num = np.einsum("kej,kj->e", e2, shell.astype(np.float64))
+    den = np.einsum("kej->e", e2)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        se = np.where(den > 0, num / np.where(den > 0, den, 1.0), 0.0)
+    return se, sensor_threshold(prob.s0, prob.kappa)
+
+
 def limit(prob, T, R, u):
     """Positivity-preserving limiter; returns (u_limited, flags)."""
     E = u.shape[2]
@@ -188,27 +222,28 @@ def limit(prob, T, R, u):
         raise NotRealizable("element mean density or pressure not positive")
     Usp = nodal_at_solution_points(R, u)                  # [s, q, e, j]
     Ufp = nodal_at_face_points(prob, T, Usp)              # [s, q, e, f]
-    for e in range(E):
-        pts = np.concatenate([Usp[:, :, e, :].reshape(prob.S, -1), Ufp[:, :, e, :].reshape(prob.S, -1)], axis=1)
-        rb = ubar[0, e]
-        eps = min(1e-8, rb, pbar[e])
-        rho_min = pts[0].min()
-        p_min = euler_pressure(pts, prob.gamma, dim).min()
-        if not (min(rho_min, p_min) < eps):
-            continue
+    # density and pressure at (solution + flux points) x nodes, per element
+    pts_all = np.concatenate([Usp.transpose(0, 2, 1, 3).reshape(prob.S, E, -1),
+                              Ufp.transpose(0, 2, 1, 3).reshape(prob.S, E, -1)], axis=2)
+    rho_min = pts_all[0].min(axis=1)
+    p_min = euler_pressure(pts_all, prob.gamma, dim).min(axis=1)
+    eps_all = np.minimum(1e-8, np.minimum(ubar[0], pbar))
+    mode0 = (np.arange(R.M) == 0)[:, None]
+    for e in np.nonzero(np.minimum(rho_min, p_min) < eps_all)[0]:
         flags[e] = True
-        beta1 = 1.0 if rho_min >= eps else (rb - eps) / (rb - rho_min)
+        pts = pts_all[:, e, :]
+        rb = ubar[0, e]
+        eps = eps_all[e]
+        beta1 = 1.0 if rho_min[e] >= eps else (rb - eps) / (rb - rho_min[e])
         star = pts.copy()
         star[0] = beta1 * (pts[0] - rb) + rb
-        out[0, :, e, :] = beta1 * (out[0, :, e, :] - rb * (np.arange(R.M) == 0)[:, None]) \
-            + rb * (np.arange(R.M) == 0)[:, None]
+        out[0, :, e, :] = beta1 * (out[0, :, e, :] - rb * mode0) + rb * mode0
         pstar = euler_pressure(star, prob.gamma, dim)
         low = pstar < eps
         beta2 = 1.0
         if np.any(low):
             roots = pressure_root(prob, ubar[:, e][:, None], star[:, low], eps)
             beta2 = float(np.min(roots))
-        mode0 = (np.arange(R.M) == 0)[:, None]
         for s in range(prob.S):
             out[s, :, e, :] = beta2 * (out[s, :, e, :] - ubar[s, e] * mode0) + ubar[s, e] * mode0
     return out, flags

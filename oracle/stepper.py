@@ -25,16 +25,21 @@ from .stabilize import limit, sensor_filter
 from .tables import build_tables
 
 
-def ssprk3(u, dt, R, L=lambda w: (w, None), F=lambda w: (w, None)):
+def ssprk3(u, dt, R, L=lambda w: (w, None), F=lambda w: (w, None), record=None):
     """Generic SSP-RK3 step with stage post-processing L and end-of-step F.
 
-    R(u) is the right-hand side; L and F return (state, flags).
+    R(u) is the right-hand side; L and F return (state, flags).  If `record`
+    is a list, the inputs of the four switch passes are appended to it.
     """
-    w1, f1 = L(u + dt * R(u))
-    w2, f2 = L(0.75 * u + 0.25 * (w1 + dt * R(w1)))
+    a = u + dt * R(u)
+    w1, f1 = L(a)
+    b = 0.75 * u + 0.25 * (w1 + dt * R(w1))
+    w2, f2 = L(b)
     v = (1.0 / 3.0) * u + (2.0 / 3.0) * (w2 + dt * R(w2))
     vf, ff = F(v)
     un, f3 = L(vf)
+    if record is not None:
+        record.extend([a, b, v, vf])
     return un, (f1, f2, ff, f3)
 
 
@@ -48,11 +53,12 @@ def cfl_dt(prob, T, R, u):
     return prob.cfl / (n * rate.max())
 
 
-def step(prob, u, dt=None, tables=None):
+def step(prob, u, dt=None, tables=None, record=None):
     """One SSP-RK3 step.  Returns (u_new, dt_used, flags[4, E] uint8).
 
     flags rows: limiter after stage 1, limiter after stage 2, sensor/filter at
-    the end of the step, limiter at the end of the step.
+    the end of the step, limiter at the end of the step.  `record`: optional
+    list that receives the inputs of those four passes.
     """
     T, R = tables if tables is not None else build_tables(prob)
     if dt is None or dt <= 0.0:
@@ -68,7 +74,7 @@ def step(prob, u, dt=None, tables=None):
     def Filt(w):
         return sensor_filter(prob, T, R, w, dt)
 
-    un, (f1, f2, ff, f3) = ssprk3(u, dt, lambda w: rhs(prob, T, R, w), Lim, Filt)
+    un, (f1, f2, ff, f3) = ssprk3(u, dt, lambda w: rhs(prob, T, R, w), Lim, Filt, record)
     flags = np.stack([f1, f2, ff, f3]).astype(np.uint8)
     return un, dt, flags
 

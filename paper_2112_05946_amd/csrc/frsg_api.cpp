@@ -1,0 +1,542 @@
+// C ABI of the FR-SG hot path: problem validation, tables, workspace and the
+// orchestration of the HIP passes for the right-hand side and the SSP-RK3 step.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "internal.hpp"
+
+using namespace frsg;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+#define FRSG_TRY_HIP(expr, ctx)                                        \
+  do {                                                                 \
+    hipError_t e_ = (expr);                                            \
+    if (e_ != hipSuccess) {                                            \
+      (ctx)->err = std::string("HIP error: ") + hipGetErrorString(e_); \
+      return FRSG_EDEVICE;                                             \
+    }                                                                  \
+  } while (0)
+
+int nstates(int eq) { return eq <= FRSG_BURGERS ? 1 : (eq == FRSG_EULER1D ? 3 : 4); }
+
+fr_sg_status validate(const fr_sg_problem& P, std::string& err) {
+  if (P.abi_version != FRSG_ABI_VERSION) {
+    err = "abi_version mismatch";
+    return FRSG_EABI;
+  }
+  if (P.equation < FRSG_ADVECTION || P.equation > FRSG_EULER2D) {
+    err = "unknown equation";
+    return FRSG_EINVAL;
+  }
+  const int dim = P.equation == FRSG_EULER2D ? 2 : 1;
+  if (P.fr_degree < 1 || P.fr_degree > kMaxNp1 - 1) {
+    err = "fr_degree must be in 1..7";
+    return P.fr_degree < 1 ? FRSG_EINVAL : FRSG_EUNSUPPORTED;
+  }
+  if (P.nx < 1 || (dim == 2 && P.ny < 1)) {
+    err = "element counts must be positive";
+    return FRSG_EINVAL;
+  }
+  if (!(P.xhi > P.xlo) || (dim == 2 && !(P.yhi > P.ylo))) {
+    err = "empty domain";
+    return FRSG_EINVAL;
+  }
+  if (P.rdim != 1 && P.rdim != 2) {
+    err = "rdim must be 1 or 2";
+    return FRSG_EINVAL;
+  }
+  if (P.gpc_order < 0 || P.nq1d < P.gpc_order + 1) {
+    err = "need gpc_order >= 0 and nq1d >= gpc_order + 1";
+    return FRSG_EINVAL;
+  }
+  const long M = P.rdim == 1 ? P.gpc_order + 1 : (long)(P.gpc_order + 1) * (P.gpc_order + 2) / 2;
+  const long Nq = P.rdim == 1 ? P.nq1d : (long)P.nq1d * P.nq1d;
+  if (M > kMaxModes || Nq > kMaxNodes) {
+    err = "too many gPC modes or random nodes";
+    return FRSG_EUNSUPPORTED;
+  }
+  const long E = (long)P.nx * (dim == 2 ? P.ny : 1);
+  const long nsp = dim == 2 ? (long)(P.fr_degree + 1) * (P.fr_degree + 1) : P.fr_degree + 1;
+  if (E * nsp * Nq > (1l << 31) / 4) {
+    err = "problem too large for 32-bit node indexing";
+    return FRSG_EUNSUPPORTED;
+  }
+  for (int side = 0; side < 2 * dim; ++side) {
+    const int k = P.bc[side];
+    if (k < FRSG_BC_PERIODIC || k > FRSG_BC_REFLECT) {
+      err = "unknown boundary kind";
+      return FRSG_EINVAL;
+    }
+    if (k == FRSG_BC_REFLECT && P.equation < FRSG_EULER1D) {
+      err = "reflecting boundaries need the Euler equations";
+      return FRSG_EUNSUPPORTED;
+    }
+  }
+  for (int d = 0; d < dim; ++d)
+    if ((P.bc[2 * d] == FRSG_BC_PERIODIC) != (P.bc[2 * d + 1] == FRSG_BC_PERIODIC)) {
+      err = "periodic boundaries must be paired";
+      return FRSG_EINVAL;
+    }
+  if (P.filter < FRSG_FILTER_NONE || P.filter > FRSG_FILTER_L2) {
+    err = "unknown filter";
+    return FRSG_EINVAL;
+  }
+  if (P.filter == FRSG_FILTER_EXP && !(P.alpha >= 0.0 && P.s > 0.0)) {
+    err = "exponential filter needs alpha >= 0 and s > 0";
+    return FRSG_EINVAL;
+  }
+  if (P.filter == FRSG_FILTER_L2 && !(P.eps1 > 0.0 && P.eps2 > 0.0)) {
+    err = "L2 filter needs eps1, eps2 > 0";
+    return FRSG_EINVAL;
+  }
+  if (P.sensor != FRSG_SENSOR_ALWAYS && P.sensor != FRSG_SENSOR_DETECTOR) {
+    err = "unknown sensor";
+    return FRSG_EINVAL;
+  }
+  if (P.sensor == FRSG_SENSOR_DETECTOR && !(P.kappa > 0.0)) {
+    err = "detector needs kappa > 0";
+    return FRSG_EINVAL;
+  }
+  if (P.limiter != 0 && P.limiter != 1) {
+    err = "limiter must be 0 or 1";
+    return FRSG_EINVAL;
+  }
+  if (P.limiter && P.equation < FRSG_EULER1D) {
+    err = "the positivity limiter applies to the Euler equations only";
+    return FRSG_EUNSUPPORTED;
+  }
+  if (P.equation >= FRSG_EULER1D && !(P.gamma > 1.0)) {
+    err = "gamma must exceed 1";
+    return FRSG_EINVAL;
+  }
+  if (!(P.cfl > 0.0)) {
+    err = "cfl must be positive";
+    return FRSG_EINVAL;
+  }
+  if (P.precision != FRSG_FP64) {
+    err = "only FRSG_FP64 is implemented";
+    return FRSG_EUNSUPPORTED;
+  }
+  return FRSG_OK;
+}
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+int take_event(fr_sg_ctx* c) {
+  if (c->events_used == (int)c->events.size()) {
+    hipEvent_t ev;
+    if (hipEventCreate(&ev) != hipSuccess) return -1;
+    c->events.push_back(ev);
+  }
+  return c->events_used++;
+}
+
+// Launch one pass; when timing is on, bracket it with events on the stream.
+fr_sg_status timed(fr_sg_ctx* c, const char* name, double alg_bytes, const std::function<hipError_t()>& launch) {
+  int e0 = -1, e1 = -1;
+  if (c->timing) {
+    e0 = take_event(c);
+    e1 = take_event(c);
+    if (e0 < 0 || e1 < 0 || hipEventRecord(c->events[e0], c->stream) != hipSuccess) {
+      c->err = "event creation/record failed";
+      return FRSG_EDEVICE;
+    }
+  }
+  hipError_t e = launch();
+  if (e != hipSuccess) {
+    c->err = std::string(name) + ": " + hipGetErrorString(e);
+    return FRSG_EDEVICE;
+  }
+  if (c->timing) {
+    if (hipEventRecord(c->events[e1], c->stream) != hipSuccess) {
+      c->err = "event record failed";
+      return FRSG_EDEVICE;
+    }
+    c->pending.push_back({name, alg_bytes, e0, e1});
+  }
+  return FRSG_OK;
+}
+
+double state_bytes(const fr_sg_ctx* c) { return 8.0 * c->S * c->T.M * (double)c->E * c->nsp; }
+
+}  // namespace
+
+extern "C" {
+
+fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ctx** out) {
+  if (!out) {
+    g_init_error = "out is NULL";
+    return FRSG_EINVAL;
+  }
+  *out = nullptr;
+  if (!problem) {
+    g_init_error = "problem is NULL";
+    return FRSG_EINVAL;
+  }
+  std::string err;
+  fr_sg_status st = validate(*problem, err);
+  if (st != FRSG_OK) {
+    g_init_error = err;
+    return st;
+  }
+  fr_sg_ctx* c = new (std::nothrow) fr_sg_ctx();
+  if (!c) {
+    g_init_error = "out of host memory";
+    return FRSG_EDEVICE;
+  }
+  c->prob = *problem;
+  c->stream = (hipStream_t)hip_stream;
+  if (!build_host_tables(c->prob, c->T, err)) {
+    g_init_error = err;
+    delete c;
+    return FRSG_EINVAL;
+  }
+  const fr_sg_problem& P = c->prob;
+  c->dim = P.equation == FRSG_EULER2D ? 2 : 1;
+  c->S = nstates(P.equation);
+  c->E = P.nx * (c->dim == 2 ? P.ny : 1);
+  const int n = P.fr_degree + 1;
+  c->nsp = c->dim == 2 ? n * n : n;
+  const HostTables& T = c->T;
+
+  // one device buffer for all tables
+  std::vector<double> blob;
+  std::vector<size_t> off;
+  auto add = [&](const std::vector<double>& v) {
+    off.push_back(blob.size());
+    blob.insert(blob.end(), v.begin(), v.end());
+  };
+  add(T.r);
+  add(T.w);
+  add(T.D);
+  add(T.lL);
+  add(T.lR);
+  add(T.dhL);
+  add(T.dhR);
+  add(T.V);
+  add(T.Vinv);
+  add(T.Phi);
+  add(T.PW);
+  add(T.filt);
+  add(T.shell);
+  add(T.swts);
+  hipError_t he = hipMalloc(&c->dtab, blob.size() * sizeof(double));
+  if (he == hipSuccess)
+    he = hipMemcpy(c->dtab, blob.data(), blob.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (he != hipSuccess) {
+    g_init_error = std::string("HIP error: ") + hipGetErrorString(he);
+    if (c->dtab) (void)hipFree(c->dtab);
+    delete c;
+    return FRSG_EDEVICE;
+  }
+  DevTab tab;
+  const double* b = c->dtab;
+  tab.r = b + off[0];
+  tab.w = b + off[1];
+  tab.D = b + off[2];
+  tab.lL = b + off[3];
+  tab.lR = b + off[4];
+  tab.dhL = b + off[5];
+  tab.dhR = b + off[6];
+  tab.V = b + off[7];
+  tab.Vinv = b + off[8];
+  tab.Phi = b + off[9];
+  tab.PW = b + off[10];
+  tab.filt = b + off[11];
+  tab.shell = b + off[12];
+  tab.swts = b + off[13];
+
+  // workspace
+  const size_t state = (size_t)c->S * T.M * c->E * c->nsp;
+  const size_t nodal = (size_t)c->S * T.Nq * c->E * c->nsp;
+  const size_t corr = (size_t)c->S * T.Nq * c->E * (c->dim == 2 ? 4 * n : 2);
+  size_t o_w1 = 0;
+  size_t o_w2 = align_up(o_w1 + state * 8);
+  size_t o_un = align_up(o_w2 + state * 8);
+  size_t o_fn = align_up(o_un + nodal * 8);
+  size_t o_gn = align_up(o_fn + nodal * 8);
+  size_t o_co = align_up(o_gn + (c->dim == 2 ? nodal * 8 : 0));
+  size_t o_sc = align_up(o_co + corr * 8);
+  size_t total = align_up(o_sc + 256);
+  char* ws = nullptr;
+  he = hipMalloc(&ws, total);
+  if (he != hipSuccess) {
+    g_init_error = std::string("workspace allocation failed: ") + hipGetErrorString(he);
+    (void)hipFree(c->dtab);
+    delete c;
+    return FRSG_EDEVICE;
+  }
+  he = hipMemset(ws + o_sc, 0, 256);
+  if (he != hipSuccess) {
+    g_init_error = std::string("HIP error: ") + hipGetErrorString(he);
+    (void)hipFree(ws);
+    (void)hipFree(c->dtab);
+    delete c;
+    return FRSG_EDEVICE;
+  }
+  c->ws.w1 = (double*)(ws + o_w1);
+  c->ws.w2 = (double*)(ws + o_w2);
+  c->ws.Un = (double*)(ws + o_un);
+  c->ws.Fn = (double*)(ws + o_fn);
+  c->ws.Gn = c->dim == 2 ? (double*)(ws + o_gn) : nullptr;
+  c->ws.Corr = (double*)(ws + o_co);
+  c->ws.scal = (double*)(ws + o_sc);
+  c->ws.bytes = total + blob.size() * sizeof(double);
+
+  KParams& K = c->kp;
+  std::memset(&K, 0, sizeof(K));
+  K.eq = P.equation;
+  K.dim = c->dim;
+  K.E = c->E;
+  K.nx = P.nx;
+  K.ny = c->dim == 2 ? P.ny : 1;
+  K.nsp = c->nsp;
+  K.M = T.M;
+  K.Nq = T.Nq;
+  K.S = c->S;
+  K.np1 = n;
+  K.dx = (P.xhi - P.xlo) / P.nx;
+  K.dy = c->dim == 2 ? (P.yhi - P.ylo) / P.ny : 1.0;
+  K.Jx = K.dx / 2.0;
+  K.Jy = K.dy / 2.0;
+  K.adv = P.adv_speed;
+  K.gamma = P.gamma;
+  for (int i = 0; i < 4; ++i) {
+    K.bc[i] = P.bc[i];
+    for (int s = 0; s < 4; ++s) K.bc_state[i][s] = P.bc_state[i][s];
+  }
+  if (c->dim == 1) K.bc[2] = K.bc[3] = FRSG_BC_PERIODIC;
+  K.cfl = P.cfl;
+  K.filter = P.filter;
+  K.sensor = P.sensor;
+  K.limiter = P.limiter;
+  K.alpha = P.alpha;
+  K.sensor_thr = std::pow(10.0, P.s0 - (2.0 * P.kappa / M_PI) * std::asin(0.98));
+  K.tab = tab;
+  K.dt = c->ws.scal;
+  K.lam_bits = (unsigned long long*)(c->ws.scal + 1);
+  K.status = (unsigned*)(c->ws.scal + 2);
+  *out = c;
+  return FRSG_OK;
+}
+
+fr_sg_status fr_sg_query(const fr_sg_ctx* ctx, fr_sg_info* out) {
+  if (!ctx || !out) return FRSG_EINVAL;
+  out->n_elem = ctx->E;
+  out->nsp = ctx->nsp;
+  out->n_modes = ctx->T.M;
+  out->n_nodes = ctx->T.Nq;
+  out->n_states = ctx->S;
+  out->n_dof = (int64_t)ctx->S * ctx->T.M * ctx->E * ctx->nsp;
+  out->state_bytes = out->n_dof * 8;
+  out->flags_len = 4 * (int64_t)ctx->E;
+  out->workspace_bytes = (int64_t)ctx->ws.bytes;
+  return FRSG_OK;
+}
+
+fr_sg_status fr_sg_set_stream(fr_sg_ctx* ctx, void* hip_stream) {
+  if (!ctx) return FRSG_EINVAL;
+  ctx->stream = (hipStream_t)hip_stream;
+  return FRSG_OK;
+}
+
+fr_sg_status fr_sg_points(const fr_sg_ctx* ctx, double* x, double* y, double* z) {
+  if (!ctx) return FRSG_EINVAL;
+  const KParams& K = ctx->kp;
+  const int n = K.np1;
+  const fr_sg_problem& P = ctx->prob;
+  for (int e = 0; e < K.E; ++e) {
+    const int ix = e % K.nx, iy = e / K.nx;
+    const double xc = P.xlo + (ix + 0.5) * K.dx;
+    const double yc = P.ylo + (iy + 0.5) * K.dy;
+    for (int j = 0; j < K.nsp; ++j) {
+      const int a = j % n, b = j / n;
+      if (x) x[(long)e * K.nsp + j] = xc + 0.5 * K.dx * ctx->T.r[a];
+      if (y) y[(long)e * K.nsp + j] = ctx->dim == 2 ? yc + 0.5 * K.dy * ctx->T.r[b] : 0.0;
+    }
+  }
+  if (z)
+    for (size_t i = 0; i < ctx->T.z.size(); ++i) z[i] = ctx->T.z[i];
+  return FRSG_OK;
+}
+
+fr_sg_status fr_sg_project(fr_sg_ctx* ctx, const double* u0_nodal, double* u) {
+  if (!ctx) return FRSG_EINVAL;
+  if (!u0_nodal || !u) {
+    ctx->err = "null pointer";
+    return FRSG_EINVAL;
+  }
+  FRSG_TRY_HIP(launch_project_ic(ctx->kp, u0_nodal, u, ctx->stream), ctx);
+  return FRSG_OK;
+}
+
+fr_sg_status fr_sg_limit(fr_sg_ctx* ctx, double* u, uint8_t* flags) {
+  if (!ctx) return FRSG_EINVAL;
+  if (!u) {
+    ctx->err = "null pointer";
+    return FRSG_EINVAL;
+  }
+  if (ctx->prob.limiter)
+    return timed(ctx, "limiter", 2 * state_bytes(ctx), [&] { return launch_limiter(ctx->kp, u, flags, ctx->stream); });
+  if (flags) FRSG_TRY_HIP(launch_fill_flags(flags, ctx->E, ctx->stream), ctx);
+  return FRSG_OK;
+}
+
+static fr_sg_status rhs_passes(fr_sg_ctx* ctx, const double* in, int do_cfl) {
+  const KParams& K = ctx->kp;
+  Workspace& W = ctx->ws;
+  hipStream_t s = ctx->stream;
+  fr_sg_status st;
+  if ((st = timed(ctx, "nodal", state_bytes(ctx), [&] { return launch_nodal(K, in, W.Un, W.Fn, W.Gn, do_cfl, s); })))
+    return st;
+  if ((st = timed(ctx, "faces", 0.0, [&] { return launch_faces(K, W.Un, W.Fn, W.Gn, W.Corr, s); }))) return st;
+  return timed(ctx, "resid", 0.0, [&] { return launch_resid(K, W.Fn, W.Gn, W.Corr, W.Un, s); });
+}
+
+fr_sg_status fr_sg_rhs(fr_sg_ctx* ctx, const double* u, double* dudt) {
+  if (!ctx) return FRSG_EINVAL;
+  if (!u || !dudt || u == dudt) {
+    ctx->err = "u and dudt must be distinct device pointers";
+    return FRSG_EINVAL;
+  }
+  fr_sg_status st = rhs_passes(ctx, u, 0);
+  if (st != FRSG_OK) return st;
+  return timed(ctx, "project_rhs", state_bytes(ctx),
+               [&] { return launch_project_stage(ctx->kp, ctx->ws.Un, u, u, dudt, 0.0, 1.0, 1, ctx->stream); });
+}
+
+fr_sg_status fr_sg_step(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, uint8_t* flags) {
+  if (!ctx) return FRSG_EINVAL;
+  if (!u) {
+    ctx->err = "null state";
+    return FRSG_EINVAL;
+  }
+  if (!std::isfinite(dt)) {
+    ctx->err = "dt must be finite";
+    return FRSG_EINVAL;
+  }
+  const KParams& K = ctx->kp;
+  Workspace& W = ctx->ws;
+  hipStream_t s = ctx->stream;
+  const int E = ctx->E;
+  const bool cfl = !(dt > 0.0);
+  uint8_t* f0 = flags ? flags : nullptr;
+  uint8_t* f1 = flags ? flags + E : nullptr;
+  uint8_t* f2 = flags ? flags + 2 * E : nullptr;
+  uint8_t* f3 = flags ? flags + 3 * E : nullptr;
+  fr_sg_status st;
+
+  FRSG_TRY_HIP(launch_set_scalars(K, cfl ? 0.0 : dt, s), ctx);
+  // stage 1: w1 = Lim(u + dt R(u)); the CFL maximum is taken in the same pass over u
+  if ((st = rhs_passes(ctx, u, cfl ? 1 : 0)) != FRSG_OK) return st;
+  if (cfl) FRSG_TRY_HIP(launch_dt(K, ctx->dim, nullptr, s), ctx);
+  const double sb = state_bytes(ctx);
+  if ((st = timed(ctx, "project_stage1", 2 * sb,
+                  [&] { return launch_project_stage(K, W.Un, u, u, W.w1, 0.0, 1.0, 0, s); })))
+    return st;
+  if ((st = fr_sg_limit(ctx, W.w1, f0)) != FRSG_OK) return st;
+  // stage 2: w2 = Lim(3/4 u + 1/4 (w1 + dt R(w1)))
+  if ((st = rhs_passes(ctx, W.w1, 0)) != FRSG_OK) return st;
+  if ((st = timed(ctx, "project_stage2", 3 * sb,
+                  [&] { return launch_project_stage(K, W.Un, u, W.w1, W.w2, 0.75, 0.25, 0, s); })))
+    return st;
+  if ((st = fr_sg_limit(ctx, W.w2, f1)) != FRSG_OK) return st;
+  // stage 3: v = 1/3 u + 2/3 (w2 + dt R(w2)), written over u
+  if ((st = rhs_passes(ctx, W.w2, 0)) != FRSG_OK) return st;
+  if ((st = timed(ctx, "project_stage3", 3 * sb,
+                  [&] { return launch_project_stage(K, W.Un, u, W.w2, u, 1.0 / 3.0, 2.0 / 3.0, 0, s); })))
+    return st;
+  // end of step: sensor-gated filter, then limiter
+  if (ctx->prob.filter != FRSG_FILTER_NONE) {
+    if ((st = timed(ctx, "sensor_filter", 2 * sb, [&] { return launch_sensor_filter(K, u, f2, s); }))) return st;
+  } else if (f2)
+    FRSG_TRY_HIP(launch_fill_flags(f2, E, s), ctx);
+  if ((st = fr_sg_limit(ctx, u, f3)) != FRSG_OK) return st;
+  if (dt_used) FRSG_TRY_HIP(launch_copy_dt(K, dt_used, s), ctx);
+  return FRSG_OK;
+}
+
+fr_sg_status fr_sg_sync(fr_sg_ctx* ctx) {
+  if (!ctx) return FRSG_EINVAL;
+  FRSG_TRY_HIP(hipStreamSynchronize(ctx->stream), ctx);
+  unsigned status = 0;
+  FRSG_TRY_HIP(hipMemcpy(&status, ctx->kp.status, sizeof(unsigned), hipMemcpyDeviceToHost), ctx);
+  if (status) {
+    unsigned zero = 0;
+    FRSG_TRY_HIP(hipMemcpy(ctx->kp.status, &zero, sizeof(unsigned), hipMemcpyHostToDevice), ctx);
+  }
+  if (status & kStatusNotRealizable) {
+    ctx->err = "element mean density or pressure not positive";
+    return FRSG_ENOTREALIZABLE;
+  }
+  if (status & kStatusNonFinite) {
+    ctx->err = "non-finite value (time step or wave speed)";
+    return FRSG_ENONFINITE;
+  }
+  return FRSG_OK;
+}
+
+fr_sg_status fr_sg_timing_enable(fr_sg_ctx* ctx, int enable) {
+  if (!ctx) return FRSG_EINVAL;
+  ctx->timing = enable != 0;
+  ctx->pending.clear();
+  ctx->events_used = 0;
+  return FRSG_OK;
+}
+
+fr_sg_status fr_sg_timing_read(fr_sg_ctx* ctx, fr_sg_pass_time* out, int32_t capacity, int32_t* count) {
+  if (!ctx || !count || (capacity > 0 && !out)) return FRSG_EINVAL;
+  FRSG_TRY_HIP(hipStreamSynchronize(ctx->stream), ctx);
+  std::vector<PassTotal> tot;
+  for (const PassRecord& r : ctx->pending) {
+    float ms = 0.0f;
+    FRSG_TRY_HIP(hipEventElapsedTime(&ms, ctx->events[r.ev0], ctx->events[r.ev1]), ctx);
+    PassTotal* t = nullptr;
+    for (auto& x : tot)
+      if (x.name == r.name) t = &x;
+    if (!t) {
+      tot.push_back(PassTotal());
+      t = &tot.back();
+      t->name = r.name;
+      t->alg_bytes = r.alg_bytes;
+    }
+    t->launches += 1;
+    t->ms += ms;
+  }
+  ctx->pending.clear();
+  ctx->events_used = 0;
+  int n = 0;
+  for (const auto& t : tot) {
+    if (n >= capacity) break;
+    std::memset(&out[n], 0, sizeof(fr_sg_pass_time));
+    std::strncpy(out[n].name, t.name.c_str(), sizeof(out[n].name) - 1);
+    out[n].launches = t.launches;
+    out[n].total_ms = t.ms;
+    out[n].alg_bytes = t.alg_bytes;
+    ++n;
+  }
+  *count = n;
+  return FRSG_OK;
+}
+
+fr_sg_status fr_sg_destroy(fr_sg_ctx* ctx) {
+  if (!ctx) return FRSG_OK;
+  (void)hipStreamSynchronize(ctx->stream);
+  for (hipEvent_t ev : ctx->events) (void)hipEventDestroy(ev);
+  if (ctx->ws.w1) (void)hipFree(ctx->ws.w1);
+  if (ctx->dtab) (void)hipFree(ctx->dtab);
+  delete ctx;
+  return FRSG_OK;
+}
+
+const char* fr_sg_last_error(const fr_sg_ctx* ctx) {
+  if (!ctx) return g_init_error.c_str();
+  return ctx->err.c_str();
+}
+
+}  // extern "C"

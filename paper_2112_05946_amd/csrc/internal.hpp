@@ -1,0 +1,144 @@
+// Internal declarations shared by the host API and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "fr_sg.h"
+
+namespace frsg {
+
+constexpr int kMaxNp1 = 8;      // p <= 7
+constexpr int kMaxModes = 128;  // gPC modes
+constexpr int kMaxNodes = 256;  // random quadrature nodes
+
+// device status bits (latched, cleared by fr_sg_sync)
+constexpr unsigned kStatusNonFinite = 1u;
+constexpr unsigned kStatusNotRealizable = 2u;
+
+// ---------------------------------------------------------------------------
+// host tables (FP64), built once per context
+// ---------------------------------------------------------------------------
+struct HostTables {
+  int np1 = 0;                     // p + 1 solution points per direction
+  std::vector<double> r, w;        // Legendre-Gauss points / weights (sum 2)
+  std::vector<double> D;           // D[i*np1 + j] = l_j'(r_i)
+  std::vector<double> lL, lR;      // l_j(-1), l_j(+1)
+  std::vector<double> dhL, dhR;    // Radau correction derivatives at r_j
+  std::vector<double> V, Vinv;     // V[j*np1 + k] = sqrt(2k+1) P_k(r_j)
+  int M = 0, Nq = 0, rdim = 1;
+  std::vector<std::array<int, 2>> kidx;  // gPC multi-indices
+  std::vector<int> kdeg;                 // |k|
+  std::vector<double> z;                 // [Nq * rdim]
+  std::vector<double> wq;                // [Nq], sum 1
+  std::vector<double> Phi, PW;           // [M * Nq]
+  std::vector<double> filt;              // [M * nsp]: exp filter exponent sum or L2 factor
+  std::vector<double> shell;             // [M * nsp]: 1 on the outer modal shell
+  std::vector<double> swts;              // [nsp]: element-mean weights
+};
+
+bool build_host_tables(const fr_sg_problem& P, HostTables& T, std::string& err);
+
+// ---------------------------------------------------------------------------
+// device-side view of the tables (one allocation, sub-arrays by offset)
+// ---------------------------------------------------------------------------
+struct DevTab {
+  const double* r;
+  const double* w;
+  const double* D;
+  const double* lL;
+  const double* lR;
+  const double* dhL;
+  const double* dhR;
+  const double* V;
+  const double* Vinv;
+  const double* Phi;
+  const double* PW;
+  const double* filt;
+  const double* shell;
+  const double* swts;
+};
+
+// Everything a kernel needs about the problem, passed by value.
+struct KParams {
+  int eq, dim;
+  int E, nx, ny, nsp, M, Nq, S, np1;
+  double dx, dy, Jx, Jy;
+  double adv, gamma;
+  int bc[4];
+  double bc_state[4][4];
+  double cfl;
+  int filter, sensor, limiter;
+  double alpha, sensor_thr;
+  DevTab tab;
+  unsigned* status;
+  unsigned long long* lam_bits;  // CFL accumulator (bit pattern of a positive double)
+  double* dt;                    // device time step of the current step
+};
+
+struct Workspace {
+  double* w1 = nullptr;
+  double* w2 = nullptr;
+  double* Un = nullptr;    // [S][Nq][E][nsp] nodal solution, then nodal residual
+  double* Fn = nullptr;    // [S][Nq][E][nsp] nodal x-flux
+  double* Gn = nullptr;    // [S][Nq][E][nsp] nodal y-flux (2D)
+  double* Corr = nullptr;  // [S][Nq][E][nface] interface-flux minus interpolated flux
+  double* scal = nullptr;  // scalars: dt, lam bits, status
+  size_t bytes = 0;
+};
+
+}  // namespace frsg
+
+struct PassRecord {
+  std::string name;
+  double alg_bytes;
+  int ev0, ev1;  // indices into the event pool
+};
+
+struct PassTotal {
+  std::string name;
+  long launches = 0;
+  double ms = 0.0;
+  double alg_bytes = 0.0;
+};
+
+struct fr_sg_ctx {
+  fr_sg_problem prob;
+  bool timing = false;
+  std::vector<hipEvent_t> events;
+  int events_used = 0;
+  std::vector<PassRecord> pending;
+  frsg::HostTables T;
+  hipStream_t stream = nullptr;
+  int dim = 1;
+  int S = 1;
+  int E = 0;
+  int nsp = 0;
+  double* dtab = nullptr;
+  frsg::KParams kp;
+  frsg::Workspace ws;
+  std::string err;
+};
+
+namespace frsg {
+// launchers (kernels_generic.hip)
+hipError_t launch_set_scalars(const KParams& P, double dt_fixed, hipStream_t s);
+hipError_t launch_nodal(const KParams& P, const double* u, double* Un, double* Fn, double* Gn, int do_cfl,
+                        hipStream_t s);
+hipError_t launch_dt(const KParams& P, int dim, double* dt_used, hipStream_t s);
+hipError_t launch_faces(const KParams& P, const double* Un, const double* Fn, const double* Gn, double* Corr,
+                        hipStream_t s);
+hipError_t launch_resid(const KParams& P, const double* Fn, const double* Gn, const double* Corr, double* Rn,
+                        hipStream_t s);
+hipError_t launch_project_stage(const KParams& P, const double* Rn, const double* u, const double* w,
+                                double* out, double cu, double cw, int rhs_only, hipStream_t s);
+hipError_t launch_project_ic(const KParams& P, const double* U0, double* u, hipStream_t s);
+hipError_t launch_limiter(const KParams& P, double* u, unsigned char* flags, hipStream_t s);
+hipError_t launch_sensor_filter(const KParams& P, double* u, unsigned char* flags, hipStream_t s);
+hipError_t launch_fill_flags(unsigned char* flags, long n, hipStream_t s);
+hipError_t launch_copy_dt(const KParams& P, double* dt_used, hipStream_t s);
+}  // namespace frsg

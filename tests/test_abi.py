@@ -1,0 +1,78 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared
+symbol, and rejects invalid problems with the documented status before any
+device call."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fr_sg.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2112_05946_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_2112_05946_amd import build
+        build.build()
+    return binding.load_library()
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(fr_sg_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for need in ("fr_sg_init", "fr_sg_rhs", "fr_sg_step", "fr_sg_destroy", "fr_sg_last_error"):
+        assert need in syms
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2112_05946_amd import binding
+    bound = {name for name, _, _ in binding.SYMBOLS}
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+        assert name in bound, "binding lacks " + name
+
+
+def _init(lib, P):
+    ctx = ctypes.c_void_p()
+    st = lib.fr_sg_init(ctypes.byref(P), None, ctypes.byref(ctx))
+    return st, ctx, lib.fr_sg_last_error(None).decode()
+
+
+@pytest.mark.parametrize("mutate,status", [
+    (lambda P: setattr(P, "abi_version", 99), -6),
+    (lambda P: setattr(P, "equation", 7), -1),
+    (lambda P: setattr(P, "fr_degree", 0), -1),
+    (lambda P: setattr(P, "fr_degree", 8), -2),
+    (lambda P: setattr(P, "nx", 0), -1),
+    (lambda P: setattr(P, "nq1d", 3), -1),
+    (lambda P: setattr(P, "rdim", 3), -1),
+    (lambda P: setattr(P, "cfl", 0.0), -1),
+    (lambda P: setattr(P, "limiter", 1), -2),          # scalar equation
+    (lambda P: P.bc.__setitem__(0, 1), -1),            # unpaired periodic side
+    (lambda P: P.bc.__setitem__(0, 9), -1),
+    (lambda P: setattr(P, "filter", 5), -1),
+    (lambda P: setattr(P, "precision", 1), -2),
+])
+def test_invalid_problems_rejected_before_launch(lib, mutate, status):
+    from paper_2112_05946_amd import binding, inputs
+    P = binding.problem_from_config(inputs.BURGERS)
+    mutate(P)
+    st, ctx, msg = _init(lib, P)
+    assert st == status, msg
+    assert not ctx.value and msg
+
+
+def test_null_arguments(lib):
+    assert lib.fr_sg_init(None, None, None) == -1
+    assert lib.fr_sg_query(None, None) == -1
+    assert lib.fr_sg_rhs(None, None, None) == -1
+    assert lib.fr_sg_step(None, None, 0.0, None, None) == -1
+    assert lib.fr_sg_destroy(None) == 0
