@@ -162,6 +162,14 @@ fr_sg_status fr_sg_rhs(fr_sg_ctx* ctx, const double* u, double* dudt);
  * step, [3*E+e] limiter at the end of the step (1 = acted). */
 fr_sg_status fr_sg_step(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, uint8_t* flags);
 
+/* nsteps CFL steps in a row (dt from the CFL condition at the start of each
+ * step), in place.  The wave-speed maximum of the first step is computed from
+ * u; that of every later step is taken in the previous step's end-of-step
+ * pass, so a time loop makes no extra pass over the state for it.
+ * dt_used: device double[nsteps] or NULL; flags: device uint8[nsteps * 4 * E]
+ * or NULL, laid out per step as in fr_sg_step. */
+fr_sg_status fr_sg_steps(fr_sg_ctx* ctx, double* u, int32_t nsteps, double* dt_used, uint8_t* flags);
+
 /* Synchronise the stream and return (then clear) the latched device status:
  * FRSG_OK, FRSG_ENONFINITE or FRSG_ENOTREALIZABLE. */
 fr_sg_status fr_sg_sync(fr_sg_ctx* ctx);

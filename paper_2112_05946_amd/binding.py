@@ -71,6 +71,7 @@ SYMBOLS = [
     ("fr_sg_limit", ctypes.c_int32, [_VP, _VP, _VP]),
     ("fr_sg_rhs", ctypes.c_int32, [_VP, _VP, _VP]),
     ("fr_sg_step", ctypes.c_int32, [_VP, _VP, ctypes.c_double, _VP, _VP]),
+    ("fr_sg_steps", ctypes.c_int32, [_VP, _VP, ctypes.c_int32, _VP, _VP]),
     ("fr_sg_sync", ctypes.c_int32, [_VP]),
     ("fr_sg_timing_enable", ctypes.c_int32, [_VP, ctypes.c_int32]),
     ("fr_sg_timing_read", ctypes.c_int32, [_VP, ctypes.POINTER(PassTime), ctypes.c_int32,
@@ -235,6 +236,11 @@ class Solver:
             flags = torch.empty(4 * self.E, dtype=torch.uint8, device=self.device)
         self._check(self.lib.fr_sg_step(self._ctx, _ptr(u), float(dt) if dt else 0.0, _ptr(dt_used), _ptr(flags)))
         return dt_used, flags
+
+    def steps(self, u, nsteps, dt_used=None, flags=None):
+        """nsteps in-place CFL steps; the CFL maximum of each later step comes from the step before."""
+        self._state(u, "u")
+        self._check(self.lib.fr_sg_steps(self._ctx, _ptr(u), int(nsteps), _ptr(dt_used), _ptr(flags)))
 
     def timing(self, enable=True):
         self._check(self.lib.fr_sg_timing_enable(self._ctx, 1 if enable else 0))

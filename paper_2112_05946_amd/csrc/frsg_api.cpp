@@ -225,6 +225,8 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
   add(T.filt);
   add(T.shell);
   add(T.swts);
+  add(T.Dt);
+  add(T.cmax);
   hipError_t he = hipMalloc(&c->dtab, blob.size() * sizeof(double));
   if (he == hipSuccess)
     he = hipMemcpy(c->dtab, blob.data(), blob.size() * sizeof(double), hipMemcpyHostToDevice);
@@ -250,11 +252,24 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
   tab.filt = b + off[11];
   tab.shell = b + off[12];
   tab.swts = b + off[13];
+  c->dDt = b + off[14];
+  c->dcmax = b + off[15];
 
-  // workspace
+  // workspace (the nodal scratch is only needed by the generic passes)
+  {
+    KParams probe;
+    std::memset(&probe, 0, sizeof(probe));
+    probe.eq = P.equation;
+    probe.np1 = n;
+    probe.nx = P.nx;
+    probe.ny = c->dim == 2 ? P.ny : 1;
+    probe.M = T.M;
+    probe.Nq = T.Nq;
+    c->fused = fused2d_supported(probe);
+  }
   const size_t state = (size_t)c->S * T.M * c->E * c->nsp;
-  const size_t nodal = (size_t)c->S * T.Nq * c->E * c->nsp;
-  const size_t corr = (size_t)c->S * T.Nq * c->E * (c->dim == 2 ? 4 * n : 2);
+  const size_t nodal = c->fused ? 0 : (size_t)c->S * T.Nq * c->E * c->nsp;
+  const size_t corr = c->fused ? 0 : (size_t)c->S * T.Nq * c->E * (c->dim == 2 ? 4 * n : 2);
   size_t o_w1 = 0;
   size_t o_w2 = align_up(o_w1 + state * 8);
   size_t o_un = align_up(o_w2 + state * 8);
@@ -320,7 +335,7 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
   K.tab = tab;
   K.dt = c->ws.scal;
   K.lam_bits = (unsigned long long*)(c->ws.scal + 1);
-  K.status = (unsigned*)(c->ws.scal + 2);
+  K.status = (unsigned*)(c->ws.scal + 2);  // scal[3] is the second CFL accumulator
   *out = c;
   return FRSG_OK;
 }
@@ -404,22 +419,17 @@ fr_sg_status fr_sg_rhs(fr_sg_ctx* ctx, const double* u, double* dudt) {
     ctx->err = "u and dudt must be distinct device pointers";
     return FRSG_EINVAL;
   }
+  if (ctx->fused) {
+    FusedStage S{u, u, dudt, 0.0, 1.0, 0, nullptr, nullptr, nullptr, ctx->dDt, ctx->dcmax};
+    return timed(ctx, "stage_rhs", 2 * state_bytes(ctx), [&] { return launch_fused_stage(ctx->kp, S, ctx->stream); });
+  }
   fr_sg_status st = rhs_passes(ctx, u, 0);
   if (st != FRSG_OK) return st;
   return timed(ctx, "project_rhs", state_bytes(ctx),
                [&] { return launch_project_stage(ctx->kp, ctx->ws.Un, u, u, dudt, 0.0, 1.0, 1, ctx->stream); });
 }
 
-fr_sg_status fr_sg_step(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, uint8_t* flags) {
-  if (!ctx) return FRSG_EINVAL;
-  if (!u) {
-    ctx->err = "null state";
-    return FRSG_EINVAL;
-  }
-  if (!std::isfinite(dt)) {
-    ctx->err = "dt must be finite";
-    return FRSG_EINVAL;
-  }
+static fr_sg_status step_generic(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, uint8_t* flags) {
   const KParams& K = ctx->kp;
   Workspace& W = ctx->ws;
   hipStream_t s = ctx->stream;
@@ -458,6 +468,81 @@ fr_sg_status fr_sg_step(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, u
     FRSG_TRY_HIP(launch_fill_flags(f2, E, s), ctx);
   if ((st = fr_sg_limit(ctx, u, f3)) != FRSG_OK) return st;
   if (dt_used) FRSG_TRY_HIP(launch_copy_dt(K, dt_used, s), ctx);
+  return FRSG_OK;
+}
+
+// fused 2D Euler step: one kernel per stage.  reuse_cfl: take the CFL maximum of
+// u from the accumulator filled by the previous step's end-of-step pass.
+static fr_sg_status step_fused(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, uint8_t* flags,
+                               bool reuse_cfl) {
+  const KParams& K = ctx->kp;
+  Workspace& W = ctx->ws;
+  hipStream_t s = ctx->stream;
+  const int E = ctx->E;
+  const double sb = state_bytes(ctx);
+  unsigned long long* lam[2] = {(unsigned long long*)(W.scal + 1), (unsigned long long*)(W.scal + 3)};
+  const int cur = ctx->lam_cur;
+  fr_sg_status st;
+  if (dt > 0.0) {
+    FRSG_TRY_HIP(launch_set_dt(K, dt, nullptr, lam[cur ^ 1], s), ctx);
+  } else {
+    if (!reuse_cfl)
+      if ((st = timed(ctx, "cfl", sb, [&] { return launch_fused_cfl(K, u, lam[cur], s); }))) return st;
+    FRSG_TRY_HIP(launch_dt_from(K, lam[cur], lam[cur ^ 1], nullptr, s), ctx);
+  }
+  uint8_t* f0 = flags ? flags : nullptr;
+  uint8_t* f1 = flags ? flags + E : nullptr;
+  uint8_t* f2 = flags ? flags + 2 * E : nullptr;
+  uint8_t* f3 = flags ? flags + 3 * E : nullptr;
+  FusedStage s1{u, u, W.w1, 0.0, 1.0, 1, f0, nullptr, nullptr, ctx->dDt, ctx->dcmax};
+  if ((st = timed(ctx, "stage1", 2 * sb, [&] { return launch_fused_stage(K, s1, s); }))) return st;
+  FusedStage s2{W.w1, u, W.w2, 0.75, 0.25, 2, f1, nullptr, nullptr, ctx->dDt, ctx->dcmax};
+  if ((st = timed(ctx, "stage2", 3 * sb, [&] { return launch_fused_stage(K, s2, s); }))) return st;
+  FusedStage s3{W.w2, u, u, 1.0 / 3.0, 2.0 / 3.0, 3, f3, f2, lam[cur ^ 1], ctx->dDt, ctx->dcmax};
+  if ((st = timed(ctx, "stage3", 3 * sb, [&] { return launch_fused_stage(K, s3, s); }))) return st;
+  ctx->lam_cur = cur ^ 1;
+  ctx->lam_for = u;
+  if (dt_used) FRSG_TRY_HIP(launch_copy_dt(K, dt_used, s), ctx);
+  return FRSG_OK;
+}
+
+static fr_sg_status check_step_args(fr_sg_ctx* ctx, double* u, double dt) {
+  if (!ctx) return FRSG_EINVAL;
+  if (!u) {
+    ctx->err = "null state";
+    return FRSG_EINVAL;
+  }
+  if (!std::isfinite(dt)) {
+    ctx->err = "dt must be finite";
+    return FRSG_EINVAL;
+  }
+  return FRSG_OK;
+}
+
+fr_sg_status fr_sg_step(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, uint8_t* flags) {
+  fr_sg_status st = check_step_args(ctx, u, dt);
+  if (st != FRSG_OK) return st;
+  if (ctx->fused) return step_fused(ctx, u, dt, dt_used, flags, false);
+  return step_generic(ctx, u, dt, dt_used, flags);
+}
+
+fr_sg_status fr_sg_steps(fr_sg_ctx* ctx, double* u, int32_t nsteps, double* dt_used, uint8_t* flags) {
+  fr_sg_status st = check_step_args(ctx, u, 0.0);
+  if (st != FRSG_OK) return st;
+  if (nsteps < 0) {
+    ctx->err = "nsteps must be >= 0";
+    return FRSG_EINVAL;
+  }
+  const long fl = 4l * ctx->E;
+  for (int i = 0; i < nsteps; ++i) {
+    double* dtu = dt_used ? dt_used + i : nullptr;
+    uint8_t* f = flags ? flags + i * fl : nullptr;
+    if (ctx->fused)
+      st = step_fused(ctx, u, 0.0, dtu, f, i > 0);
+    else
+      st = step_generic(ctx, u, 0.0, dtu, f);
+    if (st != FRSG_OK) return st;
+  }
   return FRSG_OK;
 }
 

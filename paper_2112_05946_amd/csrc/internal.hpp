@@ -39,6 +39,8 @@ struct HostTables {
   std::vector<double> filt;              // [M * nsp]: exp filter exponent sum or L2 factor
   std::vector<double> shell;             // [M * nsp]: 1 on the outer modal shell
   std::vector<double> swts;              // [nsp]: element-mean weights
+  std::vector<double> Dt;                // D - h_L' l(-1)^T - h_R' l(+1)^T (np1 x np1)
+  std::vector<double> cmax;              // [M]: max_q |Phi_k(z_q)|
 };
 
 bool build_host_tables(const fr_sg_problem& P, HostTables& T, std::string& err);
@@ -119,12 +121,37 @@ struct fr_sg_ctx {
   int E = 0;
   int nsp = 0;
   double* dtab = nullptr;
+  const double* dDt = nullptr;
+  const double* dcmax = nullptr;
+  bool fused = false;
+  int lam_cur = 0;              // which CFL accumulator holds the maximum of the current state
+  const double* lam_for = nullptr;  // state whose maximum the previous step recorded (fr_sg_steps)
   frsg::KParams kp;
   frsg::Workspace ws;
   std::string err;
 };
 
 namespace frsg {
+// one fused stage of the 2D Euler path (kernels_euler2d.hip)
+struct FusedStage {
+  const double* in;
+  const double* u;
+  double* out;
+  double cu, cw;
+  int stage;  // 0: rhs; 1, 2: limited stage output; 3: end of step
+  unsigned char* flag_lim;
+  unsigned char* flag_filt;
+  unsigned long long* lam_next;
+  const double* Dt;
+  const double* cmax;
+};
+bool fused2d_supported(const KParams& P);
+hipError_t launch_fused_stage(const KParams& P, const FusedStage& S, hipStream_t s);
+hipError_t launch_fused_cfl(const KParams& P, const double* u, unsigned long long* lam, hipStream_t s);
+hipError_t launch_dt_from(const KParams& P, const unsigned long long* lam, unsigned long long* lam_reset,
+                          double* dt_used, hipStream_t s);
+hipError_t launch_set_dt(const KParams& P, double dt, double* dt_used, unsigned long long* lam_reset, hipStream_t s);
+
 // launchers (kernels_generic.hip)
 hipError_t launch_set_scalars(const KParams& P, double dt_fixed, hipStream_t s);
 hipError_t launch_nodal(const KParams& P, const double* u, double* Un, double* Fn, double* Gn, int do_cfl,

@@ -226,6 +226,13 @@ bool build_host_tables(const fr_sg_problem& P, HostTables& T, std::string& err) 
       }
     }
   }
+  // derivative matrix that also removes the interpolated flux at both faces
+  T.Dt.assign(n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int c = 0; c < n; ++c) T.Dt[i * n + c] = T.D[i * n + c] - T.dhL[i] * T.lL[c] - T.dhR[i] * T.lR[c];
+  T.cmax.assign(T.M, 0.0);
+  for (int k = 0; k < T.M; ++k)
+    for (int q = 0; q < T.Nq; ++q) T.cmax[k] = std::max(T.cmax[k], std::fabs(T.Phi[k * T.Nq + q]));
   T.swts.assign(nsp, 0.0);
   for (int j = 0; j < nsp; ++j)
     T.swts[j] = (dim == 1) ? T.w[j] / 2.0 : (T.w[j % n] / 2.0) * (T.w[j / n] / 2.0);

@@ -184,3 +184,65 @@ def test_advection_full_horizon():
         sol.step(ud)
     sol.sync()
     assert rel_l2(to_np(ud), ref) < RTOL_FP64
+
+
+# ---------------------------------------------------------------------------
+# fused 2D Euler path (p = 3, meshes in multiples of the 4 x 4 element tile)
+# ---------------------------------------------------------------------------
+SV_TILED = inputs.small(inputs.SHOCK_VORTEX, 12, 8)
+SV_PERIODIC = dict(inputs.small(inputs.SHOCK_VORTEX, 8, 8), gpc_order=3, nq1d=4,
+                   bc=["periodic"] * 4, sensor="always", filter="l2")
+
+
+@pytest.mark.parametrize("label,cfg", [("tiled", SV_TILED), ("periodic", SV_PERIODIC)])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_fused_rhs_fuzz(label, cfg, seed):
+    announce("fused_rhs_fuzz", label, seed)
+    prob, (T, R) = oracle_for(cfg)
+    u = inputs.fuzz_euler(2, R.M, prob.E, 16, seed)
+    ref = ofr.rhs(prob, T, R, u)
+    sol = solver_for(cfg)
+    got = to_np(sol.rhs(to_dev(u)))
+    sol.sync()
+    assert rel_l2(got, ref) < RTOL_FP64
+
+
+@pytest.mark.parametrize("label,cfg", [("tiled", SV_TILED), ("periodic", SV_PERIODIC)])
+def test_fused_steps_from_initial_state(label, cfg):
+    announce("fused_steps", label)
+    prob, (T, R) = oracle_for(cfg)
+    u0 = project_initial(prob, cfg["ic"], (T, R))
+    _run_steps(cfg, u0, 6)
+
+
+def test_fused_limiter_exact_path():
+    """Near-vacuum elements: the bound test fails and the node-by-node limiter acts in every stage."""
+    cfg = dict(SV_TILED, bc=["periodic"] * 4)
+    announce("fused_vacuum")
+    prob, (T, R) = oracle_for(cfg)
+    u = inputs.fuzz_euler(2, R.M, prob.E, 16, 6, vacuum_frac=0.15)
+    u, fl = ost.limit(prob, T, R, u)
+    assert fl.sum() > 0
+    _run_steps(cfg, u, 3, dt=1e-5)
+
+
+def test_fused_multi_step_cfl_reuse():
+    """fr_sg_steps: the CFL maximum of each later step comes from the previous step's epilogue."""
+    import torch
+    cfg = SV_TILED
+    announce("fused_steps_reuse")
+    prob, (T, R) = oracle_for(cfg)
+    u0 = project_initial(prob, cfg["ic"], (T, R))
+    n = 5
+    ref = u0.copy()
+    rdts = []
+    for _ in range(n):
+        ref, rdt, _ = ostep.step(prob, ref, None, (T, R))
+        rdts.append(rdt)
+    sol = solver_for(cfg)
+    ud = to_dev(u0)
+    dts = torch.empty(n, dtype=torch.float64, device=ud.device)
+    sol.steps(ud, n, dts)
+    sol.sync()
+    assert np.allclose(to_np(dts), rdts, rtol=1e-13, atol=0)
+    assert rel_l2(to_np(ud), ref) < RTOL_FP64
