@@ -227,6 +227,8 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
   add(T.swts);
   add(T.Dt);
   add(T.cmax);
+  add(T.PhiT);
+  add(T.PWT);
   hipError_t he = hipMalloc(&c->dtab, blob.size() * sizeof(double));
   if (he == hipSuccess)
     he = hipMemcpy(c->dtab, blob.data(), blob.size() * sizeof(double), hipMemcpyHostToDevice);
@@ -254,6 +256,8 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
   tab.swts = b + off[13];
   c->dDt = b + off[14];
   c->dcmax = b + off[15];
+  c->dPhiT = b + off[16];
+  c->dPWT = b + off[17];
 
   // workspace (the nodal scratch is only needed by the generic passes)
   {
@@ -420,7 +424,7 @@ fr_sg_status fr_sg_rhs(fr_sg_ctx* ctx, const double* u, double* dudt) {
     return FRSG_EINVAL;
   }
   if (ctx->fused) {
-    FusedStage S{u, u, dudt, 0.0, 1.0, 0, nullptr, nullptr, nullptr, ctx->dDt, ctx->dcmax};
+    FusedStage S{u, u, dudt, 0.0, 1.0, 0, nullptr, nullptr, nullptr, ctx->dDt, ctx->dcmax, ctx->dPhiT, ctx->dPWT};
     return timed(ctx, "stage_rhs", 2 * state_bytes(ctx), [&] { return launch_fused_stage(ctx->kp, S, ctx->stream); });
   }
   fr_sg_status st = rhs_passes(ctx, u, 0);
@@ -494,11 +498,12 @@ static fr_sg_status step_fused(fr_sg_ctx* ctx, double* u, double dt, double* dt_
   uint8_t* f1 = flags ? flags + E : nullptr;
   uint8_t* f2 = flags ? flags + 2 * E : nullptr;
   uint8_t* f3 = flags ? flags + 3 * E : nullptr;
-  FusedStage s1{u, u, W.w1, 0.0, 1.0, 1, f0, nullptr, nullptr, ctx->dDt, ctx->dcmax};
+  FusedStage s1{u, u, W.w1, 0.0, 1.0, 1, f0, nullptr, nullptr, ctx->dDt, ctx->dcmax, ctx->dPhiT, ctx->dPWT};
   if ((st = timed(ctx, "stage1", 2 * sb, [&] { return launch_fused_stage(K, s1, s); }))) return st;
-  FusedStage s2{W.w1, u, W.w2, 0.75, 0.25, 2, f1, nullptr, nullptr, ctx->dDt, ctx->dcmax};
+  FusedStage s2{W.w1, u, W.w2, 0.75, 0.25, 2, f1, nullptr, nullptr, ctx->dDt, ctx->dcmax, ctx->dPhiT, ctx->dPWT};
   if ((st = timed(ctx, "stage2", 3 * sb, [&] { return launch_fused_stage(K, s2, s); }))) return st;
-  FusedStage s3{W.w2, u, u, 1.0 / 3.0, 2.0 / 3.0, 3, f3, f2, lam[cur ^ 1], ctx->dDt, ctx->dcmax};
+  FusedStage s3{W.w2, u, u, 1.0 / 3.0, 2.0 / 3.0, 3, f3, f2, lam[cur ^ 1], ctx->dDt, ctx->dcmax, ctx->dPhiT,
+                ctx->dPWT};
   if ((st = timed(ctx, "stage3", 3 * sb, [&] { return launch_fused_stage(K, s3, s); }))) return st;
   ctx->lam_cur = cur ^ 1;
   ctx->lam_for = u;

@@ -41,6 +41,7 @@ struct HostTables {
   std::vector<double> swts;              // [nsp]: element-mean weights
   std::vector<double> Dt;                // D - h_L' l(-1)^T - h_R' l(+1)^T (np1 x np1)
   std::vector<double> cmax;              // [M]: max_q |Phi_k(z_q)|
+  std::vector<double> PhiT, PWT;         // [Nq * M] node-major copies of Phi, PW
 };
 
 bool build_host_tables(const fr_sg_problem& P, HostTables& T, std::string& err);
@@ -123,6 +124,8 @@ struct fr_sg_ctx {
   double* dtab = nullptr;
   const double* dDt = nullptr;
   const double* dcmax = nullptr;
+  const double* dPhiT = nullptr;
+  const double* dPWT = nullptr;
   bool fused = false;
   int lam_cur = 0;              // which CFL accumulator holds the maximum of the current state
   const double* lam_for = nullptr;  // state whose maximum the previous step recorded (fr_sg_steps)
@@ -144,6 +147,8 @@ struct FusedStage {
   unsigned long long* lam_next;
   const double* Dt;
   const double* cmax;
+  const double* PhiT;  // [Nq][M] chaos basis at the nodes, node-major
+  const double* PWT;   // [Nq][M] quadrature-weighted basis, node-major
 };
 bool fused2d_supported(const KParams& P);
 hipError_t launch_fused_stage(const KParams& P, const FusedStage& S, hipStream_t s);

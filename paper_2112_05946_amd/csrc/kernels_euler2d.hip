@@ -53,7 +53,21 @@ constexpr int BLK = 256;    // threads per workgroup
 // ---------------------------------------------------------------------------
 template <int CTRL>
 __device__ __forceinline__ double dpp(double v) {
-  return __builtin_amdgcn_update_dpp(0.0, v, CTRL, 0xf, 0xf, false);
+  // all lanes active and every source lane inside the row: bound_ctrl lets the
+  // move skip the old-value operand
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)x, CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), CTRL, 0xf, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// 1/x to double accuracy: hardware estimate refined by two Newton steps
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
 }
 // value at point ((a + k) & 3, b)
 template <int K>
@@ -133,9 +147,6 @@ __device__ __forceinline__ void euler_fg(const double* U, double* F, double* G, 
 // arguments
 // ---------------------------------------------------------------------------
 struct StageArgs {
-  const double* in;          // right-hand-side input state (already limited)
-  const double* u;           // u^n for the stage combination
-  double* out;               // output state (may equal u in stage 3)
   double cu, cw;             // out = cu u + cw (in + dt R)
   int stage;                 // 0: right-hand side only; 1, 2: limited stage output; 3: end of step
   unsigned char* flag_lim;   // per element: limiter acted on the output (stages 1-3)
@@ -145,112 +156,142 @@ struct StageArgs {
   const double* cmax;        // [M] max_q |Phi_k(z_q)|
 };
 
+// Lane layout of a workgroup (one 4 x 4 tile of elements, 512 threads):
+//   tid = 32 le + 16 h + j,  j = a + 4 b;
+// lane (le, h, j) owns conserved variables 2h and 2h+1 at solution point j of
+// local element le.  The 16 lanes with equal (le, h) form one DPP row.
+constexpr int BLK2 = 512;
+
+// value held by the partner lane (same point, other pair of variables)
+__device__ __forceinline__ double other_half(double v) { return __shfl_xor(v, 16); }
+
+// all four conserved variables from this lane's pair and the partner's pair
+__device__ __forceinline__ void full4(int h, double v0, double v1, double* U) {
+  const double o0 = other_half(v0), o1 = other_half(v1);
+  U[0] = h ? o0 : v0;
+  U[1] = h ? o1 : v1;
+  U[2] = h ? v0 : o0;
+  U[3] = h ? v1 : o1;
+}
+
+// Lax-Friedrichs flux of the 2D Euler equations along direction dir (0: x, 1: y)
+__device__ __forceinline__ void rusanov_e2(const double* L, const double* R, double* Fs, double g, int dir) {
+  double fL[4], fR[4], sL, sR;
+  auto side = [&](const double* U, double* f, double& sp) {
+    const double ir = recip(U[0]);
+    const double p = (g - 1.0) * (U[3] - 0.5 * (U[1] * U[1] + U[2] * U[2]) * ir);
+    const double vn = (dir == 0 ? U[1] : U[2]) * ir;
+    f[0] = dir == 0 ? U[1] : U[2];
+    f[1] = U[1] * vn + (dir == 0 ? p : 0.0);
+    f[2] = U[2] * vn + (dir == 0 ? 0.0 : p);
+    f[3] = (U[3] + p) * vn;
+    sp = fabs(vn) + sqrt(g * p * ir);
+  };
+  side(L, fL, sL);
+  side(R, fR, sR);
+  const double lam = fmax(sL, sR);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) Fs[s] = 0.5 * (fL[s] + fR[s]) - 0.5 * lam * (R[s] - L[s]);
+}
+
+struct LaneOps {
+  double rlx[4], rly[4], rrx[4], rry[4];  // rotated l(-1), l(+1) for x (row a) and y (row b)
+};
+
 // ---------------------------------------------------------------------------
-// positivity limiter on the 16 lanes of one element (Sec. 4.3)
-// o[s][k]: this lane's coefficients (solution point j = a + 4 b)
-// returns 1 on lanes of elements that were limited
+// positivity limiter on one element (Sec. 4.3); o[i][k]: this lane's pair
 // ---------------------------------------------------------------------------
 template <int M, int NQ>
-__device__ int limit_element(const KParams& P, double (&o)[4][M], int a, int b, const Rot4& rw, const Rot4& rl,
-                             const Rot4& rr, const double* cmax, bool active) {
+__device__ int limit_pair(const KParams& P, const double* __restrict__ Phi, double (&o)[2][M], int h, int a, int b,
+                          const LaneOps& L, const double* cmax) {
   const double g = P.gamma;
-  // element x random mean: sum_j (w_a/2)(w_b/2) o[s][0](j)
-  double ub[4];
+  double rwx[4], rwy[4];
 #pragma unroll
-  for (int s = 0; s < 4; ++s) ub[s] = row_bcast0(ydot(rw.y, xdot(rw.x, o[s][0])));
+  for (int k = 0; k < 4; ++k) {
+    rwx[k] = 0.5 * P.tab.w[(a + k) & 3];
+    rwy[k] = 0.5 * P.tab.w[(b - k) & 3];
+  }
+  // element x random mean: sum_j (w_a/2)(w_b/2) o(j, mode 0)
+  double ub[4];
+  full4(h, row_bcast0(ydot(rwy, xdot(rwx, o[0][0]))), row_bcast0(ydot(rwy, xdot(rwx, o[1][0]))), ub);
   const double pb = euler_p(ub, g);
   const bool realizable = ub[0] > 0.0 && pb > 0.0 && isfinite(ub[0]) && isfinite(ub[1]) && isfinite(ub[2]) &&
                           isfinite(ub[3]);
-  if (active && !realizable && a == 0 && b == 0) atomicOr(P.status, kStatusNotRealizable);
+  if (!realizable && a == 0 && b == 0 && h == 0) atomicOr(P.status, kStatusNotRealizable);
   const double eps = fmin(1e-8, fmin(ub[0], pb));
 
   // rigorous bounds: value(z) = mean + sum_{k>=1} c_k Phi_k(z), |Phi_k(z_q)| <= cmax_k
-  double mean[4], var[4];
+  double mean[2], var[2];
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    mean[s] = o[s][0];
+  for (int i = 0; i < 2; ++i) {
+    mean[i] = o[i][0];
     double v = 0.0;
 #pragma unroll
-    for (int k = 1; k < M; ++k) v += fabs(o[s][k]) * cmax[k];
-    var[s] = v;
+    for (int k = 1; k < M; ++k) v += fabs(o[i][k]) * cmax[k];
+    var[i] = v;
   }
-  auto safe = [&](const double* mn, const double* vr) {
+  auto safe = [&](double m0, double m1, double v0, double v1) {
+    double mn[4], vr[4];
+    full4(h, m0, m1, mn);
+    full4(h, v0, v1, vr);
     const double rlo = mn[0] - vr[0];
     const double elo = mn[3] - vr[3];
     const double mx = fabs(mn[1]) + vr[1];
     const double my = fabs(mn[2]) + vr[2];
-    const double tol_r = 1e-10 * (fabs(mn[0]) + vr[0]) + 1e-300;
+    const double tol_r = 1e-10 * (fabs(mn[0]) + vr[0]);
     if (!(rlo > eps + tol_r)) return false;
     const double kin = 0.5 * (mx * mx + my * my) / rlo;
     const double plo = (g - 1.0) * (elo - kin);
     const double tol_p = 1e-10 * (g - 1.0) * (fabs(mn[3]) + vr[3] + kin);
     return plo > eps + tol_p;
   };
-  bool ok = safe(mean, var);
-  // flux points on this lane's row (x faces) and column (y faces)
-  {
-    double mn[4], vr[4];
-    Rot4 al, ar;
+  double ax[4], ay[4], bx[4], by[4];  // |l(-1)|, |l(+1)| rotated
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      al.x[k] = fabs(rl.x[k]);
-      al.y[k] = fabs(rl.y[k]);
-      ar.x[k] = fabs(rr.x[k]);
-      ar.y[k] = fabs(rr.y[k]);
-    }
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      mn[s] = xdot(rl.x, mean[s]);
-      vr[s] = xdot(al.x, var[s]);
-    }
-    ok = ok && safe(mn, vr);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      mn[s] = xdot(rr.x, mean[s]);
-      vr[s] = xdot(ar.x, var[s]);
-    }
-    ok = ok && safe(mn, vr);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      mn[s] = ydot(rl.y, mean[s]);
-      vr[s] = ydot(al.y, var[s]);
-    }
-    ok = ok && safe(mn, vr);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      mn[s] = ydot(rr.y, mean[s]);
-      vr[s] = ydot(ar.y, var[s]);
-    }
-    ok = ok && safe(mn, vr);
+  for (int k = 0; k < 4; ++k) {
+    ax[k] = fabs(L.rlx[k]);
+    ay[k] = fabs(L.rly[k]);
+    bx[k] = fabs(L.rrx[k]);
+    by[k] = fabs(L.rry[k]);
   }
-  // element-wide: every lane of the row must be safe
+  bool ok = safe(mean[0], mean[1], var[0], var[1]);
+  ok = safe(xdot(L.rlx, mean[0]), xdot(L.rlx, mean[1]), xdot(ax, var[0]), xdot(ax, var[1])) && ok;
+  ok = safe(xdot(L.rrx, mean[0]), xdot(L.rrx, mean[1]), xdot(bx, var[0]), xdot(bx, var[1])) && ok;
+  ok = safe(ydot(L.rly, mean[0]), ydot(L.rly, mean[1]), ydot(ay, var[0]), ydot(ay, var[1])) && ok;
+  ok = safe(ydot(L.rry, mean[0]), ydot(L.rry, mean[1]), ydot(by, var[0]), ydot(by, var[1])) && ok;
+  // element-wide decision
   double okd = ok ? 1.0 : 0.0;
   okd = ymin4(xmin4(okd));
-  bool need = active && realizable && okd < 0.5;
+  okd = fmin(okd, other_half(okd));
+  const bool need = realizable && okd < 0.5;
   if (__ballot(need) == 0) return 0;
 
-  // node-by-node test on the elements that need it (all lanes of the wave take part)
-  const double* Phi = P.tab.Phi;
+  // node-by-node test (all lanes of the wave take part)
   double rmin = INFINITY, pmin = INFINITY;
   for (int q = 0; q < NQ; ++q) {
-    double U[4], TxL[4], TxR[4], TyL[4], TyR[4];
+    double u2[2];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      double acc = 0.0;
+    for (int i = 0; i < 2; ++i) {
+      double t = 0.0;
 #pragma unroll
-      for (int k = 0; k < M; ++k) acc += o[s][k] * Phi[k * NQ + q];
-      U[s] = acc;
+      for (int k = 0; k < M; ++k) t += o[i][k] * Phi[k * NQ + q];
+      u2[i] = t;
     }
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      TxL[s] = xdot(rl.x, U[s]);
-      TxR[s] = xdot(rr.x, U[s]);
-      TyL[s] = ydot(rl.y, U[s]);
-      TyR[s] = ydot(rr.y, U[s]);
-    }
-    rmin = fmin(rmin, fmin(fmin(U[0], TxL[0]), fmin(TxR[0], fmin(TyL[0], TyR[0]))));
-    pmin = fmin(pmin, fmin(fmin(euler_p(U, g), euler_p(TxL, g)),
-                           fmin(euler_p(TxR, g), fmin(euler_p(TyL, g), euler_p(TyR, g)))));
+    double U[4], T[4];
+    full4(h, u2[0], u2[1], U);
+    rmin = fmin(rmin, U[0]);
+    pmin = fmin(pmin, euler_p(U, g));
+    full4(h, xdot(L.rlx, u2[0]), xdot(L.rlx, u2[1]), T);
+    rmin = fmin(rmin, T[0]);
+    pmin = fmin(pmin, euler_p(T, g));
+    full4(h, xdot(L.rrx, u2[0]), xdot(L.rrx, u2[1]), T);
+    rmin = fmin(rmin, T[0]);
+    pmin = fmin(pmin, euler_p(T, g));
+    full4(h, ydot(L.rly, u2[0]), ydot(L.rly, u2[1]), T);
+    rmin = fmin(rmin, T[0]);
+    pmin = fmin(pmin, euler_p(T, g));
+    full4(h, ydot(L.rry, u2[0]), ydot(L.rry, u2[1]), T);
+    rmin = fmin(rmin, T[0]);
+    pmin = fmin(pmin, euler_p(T, g));
   }
   rmin = ymin4(xmin4(rmin));
   pmin = ymin4(xmin4(pmin));
@@ -259,37 +300,39 @@ __device__ int limit_element(const KParams& P, double (&o)[4][M], int a, int b, 
   const double beta1 = (rmin >= eps) ? 1.0 : (ub[0] - eps) / (ub[0] - rmin);
   double bmin = 1.0;
   for (int q = 0; q < NQ; ++q) {
-    double U[4], T[4][4];
+    double u2[2];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      double acc = 0.0;
+    for (int i = 0; i < 2; ++i) {
+      double t = 0.0;
 #pragma unroll
-      for (int k = 0; k < M; ++k) acc += o[s][k] * Phi[k * NQ + q];
-      U[s] = acc;
+      for (int k = 0; k < M; ++k) t += o[i][k] * Phi[k * NQ + q];
+      u2[i] = t;
     }
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      T[0][s] = xdot(rl.x, U[s]);
-      T[1][s] = xdot(rr.x, U[s]);
-      T[2][s] = ydot(rl.y, U[s]);
-      T[3][s] = ydot(rr.y, U[s]);
-    }
-    U[0] = beta1 * (U[0] - ub[0]) + ub[0];
-    if (euler_p(U, g) < eps) bmin = fmin(bmin, pressure_root<kEuler2>(ub, U, eps, g));
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      T[f][0] = beta1 * (T[f][0] - ub[0]) + ub[0];
-      if (euler_p(T[f], g) < eps) bmin = fmin(bmin, pressure_root<kEuler2>(ub, T[f], eps, g));
-    }
+    double T[4];
+    auto check = [&](double v0, double v1) {
+      full4(h, v0, v1, T);
+      T[0] = beta1 * (T[0] - ub[0]) + ub[0];
+      if (euler_p(T, g) < eps) bmin = fmin(bmin, pressure_root<kEuler2>(ub, T, eps, g));
+    };
+    check(u2[0], u2[1]);
+    check(xdot(L.rlx, u2[0]), xdot(L.rlx, u2[1]));
+    check(xdot(L.rrx, u2[0]), xdot(L.rrx, u2[1]));
+    check(ydot(L.rly, u2[0]), ydot(L.rly, u2[1]));
+    check(ydot(L.rry, u2[0]), ydot(L.rry, u2[1]));
   }
-  const double beta2 = ymin4(xmin4(bmin));
+  double beta2 = ymin4(xmin4(bmin));
+  beta2 = fmin(beta2, other_half(beta2));
   if (on) {
 #pragma unroll
     for (int k = 0; k < M; ++k) {
       const double m0 = (k == 0) ? 1.0 : 0.0;
-      o[0][k] = beta1 * (o[0][k] - ub[0] * m0) + ub[0] * m0;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) o[s][k] = beta2 * (o[s][k] - ub[s] * m0) + ub[s] * m0;
+      for (int i = 0; i < 2; ++i) {
+        const int s = 2 * h + i;
+        double v = o[i][k];
+        if (s == 0) v = beta1 * (v - ub[0] * m0) + ub[0] * m0;
+        o[i][k] = beta2 * (v - ub[s] * m0) + ub[s] * m0;
+      }
     }
   }
   return on ? 1 : 0;
@@ -299,30 +342,41 @@ __device__ int limit_element(const KParams& P, double (&o)[4][M], int a, int b, 
 // detector + modal filter on one element (Sec. 4.1, 4.2)
 // ---------------------------------------------------------------------------
 template <int M>
-__device__ int sensor_filter_element(const KParams& P, double (&o)[4][M], int j, const Rot4& rvi, const Rot4& rv,
-                                     const double* lam, bool active) {
-  // spatial modal coefficients of the first state: (V^-1 x V^-1) per chaos mode
+__device__ int sensor_filter_pair(const KParams& P, double (&o)[2][M], int h, int a, int b, int j,
+                                  const double* lam) {
+  double vix[4], viy[4], vx[4], vy[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    vix[k] = P.tab.Vinv[a * NP + ((a + k) & 3)];
+    viy[k] = P.tab.Vinv[b * NP + ((b - k) & 3)];
+    vx[k] = P.tab.V[a * NP + ((a + k) & 3)];
+    vy[k] = P.tab.V[b * NP + ((b - k) & 3)];
+  }
+  // energies of the first variable's spatial-chaos modes (meaningful on the h = 0 row)
   double num = 0.0, den = 0.0;
 #pragma unroll
   for (int k = 0; k < M; ++k) {
-    const double t = ydot(rvi.y, xdot(rvi.x, o[0][k]));
+    const double t = ydot(viy, xdot(vix, o[0][k]));
     const double e2 = t * t;
     num += e2 * P.tab.shell[k * NSP + j];
     den += e2;
   }
-  // sums over the 16 lanes of the element
   num = row_bcast0(ysum4(xsum4(num)));
   den = row_bcast0(ysum4(xsum4(den)));
-  bool flag = (P.sensor == FRSG_SENSOR_ALWAYS) || (den > 0.0 && num / den > P.sensor_thr);
-  flag = flag && active;
+  const double onum = other_half(num), oden = other_half(den);
+  if (h) {
+    num = onum;
+    den = oden;
+  }
+  const bool flag = (P.sensor == FRSG_SENSOR_ALWAYS) || (den > 0.0 && num / den > P.sensor_thr);
   if (__ballot(flag) == 0) return 0;
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
+  for (int i = 0; i < 2; ++i) {
 #pragma unroll
     for (int k = 0; k < M; ++k) {
-      const double t = ydot(rvi.y, xdot(rvi.x, o[s][k])) * lam[k * NSP + j];
-      const double back = ydot(rv.y, xdot(rv.x, t));
-      if (flag) o[s][k] = back;
+      const double t = ydot(viy, xdot(vix, o[i][k])) * lam[k * NSP + j];
+      const double back = ydot(vy, xdot(vx, t));
+      if (flag) o[i][k] = back;
     }
   }
   return flag ? 1 : 0;
@@ -332,18 +386,18 @@ __device__ int sensor_filter_element(const KParams& P, double (&o)[4][M], int j,
 // the stage kernel
 // ---------------------------------------------------------------------------
 template <int M, int NQ>
-__global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(1, 1)))
-k_stage2d(KParams P, StageArgs A) {
-  __shared__ double sU[2][TE][NSP][4];
-  __shared__ double sF[2][TE][NSP][4];
-  __shared__ double sG[2][TE][NSP][4];
-  __shared__ double sH[2][16][NP][4];
-  __shared__ double sFs[TE][NSP][4];
+__global__ void __launch_bounds__(BLK2) k_stage2d(KParams P, StageArgs A, const double* __restrict__ Phi,
+                                                  const double* __restrict__ PhiT, const double* __restrict__ PWT,
+                                                  const double* __restrict__ in, const double* __restrict__ uin,
+                                                  double* out) {
+  __shared__ double sT[2][TE][NSP][4];  // element traces at its 16 flux points (by node parity)
+  __shared__ double sFs[TE][NSP][4];    // interface fluxes at those flux points
+  __shared__ double sH[NQ][16][NP][4];  // traces of elements outside the tile, every node
   __shared__ double sLam[M * NSP];
-  __shared__ double sRed[BLK / 64];
+  __shared__ double sRed[BLK2 / 64];
 
   const int tid = threadIdx.x;
-  const int le = tid >> 4, j = tid & 15;
+  const int le = tid >> 5, h = (tid >> 4) & 1, j = tid & 15;
   const int a = j & 3, b = j >> 2;
   const int lx = le & 3, ly = le >> 2;
   const int ntx = P.nx / 4;
@@ -351,58 +405,33 @@ k_stage2d(KParams P, StageArgs A) {
   // XCD a contiguous band of tiles (neighbouring halos then share its L2)
   const int ntiles = ntx * (P.ny / 4);
   int tile = blockIdx.x;
-  {
-    const int per = (ntiles + 7) / 8;
-    const int t2 = (tile % 8) * per + tile / 8;
-    if (ntiles % 8 == 0) tile = t2;
-  }
+  if (ntiles % 8 == 0) tile = (tile % 8) * (ntiles / 8) + tile / 8;
   const int tx = tile % ntx, ty = tile / ntx;
   const int ix = 4 * tx + lx, iy = 4 * ty + ly;
   const int e = iy * P.nx + ix;
   const long EN = (long)P.E * NSP;
   const double g = P.gamma;
-  const double* Phi = P.tab.Phi;
-  const double* PW = P.tab.PW;
   const double dt = (A.stage == 0) ? 0.0 : *P.dt;
 
-  // operator rows for this lane
-  Rot4 rl, rr, rw;
-  make_rot(P.tab.lL, a, b, rl);
-  make_rot(P.tab.lR, a, b, rr);
-  {
-    double wh[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) wh[c] = P.tab.w[c] * 0.5;
-    make_rot(wh, a, b, rw);
-  }
-  double dxr[NP], dyr[NP];
-#pragma unroll
-  for (int c = 0; c < NP; ++c) {
-    dxr[c] = A.Dt[a * NP + c];
-    dyr[c] = A.Dt[b * NP + c];
-  }
-  const double dhLa = P.tab.dhL[a], dhRa = P.tab.dhR[a], dhLb = P.tab.dhL[b], dhRb = P.tab.dhR[b];
-  const double iJx = 1.0 / P.Jx, iJy = 1.0 / P.Jy;
-
-  // filter factors (stage 3)
   if (A.stage == 3) {
-    for (int i = tid; i < M * NSP; i += BLK) {
+    for (int i = tid; i < M * NSP; i += BLK2) {
       const double f = P.tab.filt[i];
       sLam[i] = (P.filter == FRSG_FILTER_EXP) ? exp(-P.alpha * dt * f) : f;
     }
   }
 
-  // own coefficients
-  double m[4][M];
+  // own coefficients: variables 2h, 2h+1
+  double m[2][M];
 #pragma unroll
-  for (int s = 0; s < 4; ++s)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int k = 0; k < M; ++k) m[s][k] = A.in[((long)s * M + k) * EN + (long)e * NSP + j];
+    for (int k = 0; k < M; ++k) m[i][k] = in[((long)(2 * h + i) * M + k) * EN + (long)e * NSP + j];
 
-  // halo role: (face hf of the tile, flux point fp, state hs); modal trace of the outside neighbour
-  const int hf = tid >> 4, hfp = (tid >> 2) & 3, hs = tid & 3;
-  double th[M];
+  // traces of the elements around the tile at every node: combo (face hf, point fp, variable hs),
+  // two threads per combo, splitting the nodes by parity
   {
+    const int combo = tid >> 1, qpar = tid & 1;
+    const int hf = combo >> 4, hfp = (combo >> 2) & 3, hs = combo & 3;
     const int side = hf >> 2, pos = hf & 3;
     int nix, niy;
     const double* l;
@@ -417,22 +446,43 @@ k_stage2d(KParams P, StageArgs A) {
     if (niy < 0) { if (P.bc[2] == FRSG_BC_PERIODIC) niy += P.ny; else valid = false; }
     if (niy >= P.ny) { if (P.bc[3] == FRSG_BC_PERIODIC) niy -= P.ny; else valid = false; }
     const int ne = valid ? niy * P.nx + nix : 0;
+    double th[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) {
-      double acc = 0.0;
+      double t = 0.0;
       if (valid) {
-        const double* src = A.in + ((long)hs * M + k) * EN + (long)ne * NSP;
+        const double* src = in + ((long)hs * M + k) * EN + (long)ne * NSP;
 #pragma unroll
-        for (int c = 0; c < NP; ++c) acc += l[c] * src[along_x ? (c + NP * hfp) : (hfp + NP * c)];
+        for (int c = 0; c < NP; ++c) t += l[c] * src[along_x ? (c + NP * hfp) : (hfp + NP * c)];
       }
-      th[k] = acc;
+      th[k] = t;
+    }
+    for (int q = qpar; q < NQ; q += 2) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < M; ++k) t += th[k] * Phi[k * NQ + q];
+      sH[q][hf][hfp][hs] = t;
     }
   }
 
-  // face-point role of this lane: side = j >> 2 (x-lo, x-hi, y-lo, y-hi), flux point i = j & 3
+  // per-lane operator rows
+  LaneOps L;
+  double dx[4], dy[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    L.rlx[k] = P.tab.lL[(a + k) & 3];
+    L.rrx[k] = P.tab.lR[(a + k) & 3];
+    L.rly[k] = P.tab.lL[(b - k) & 3];
+    L.rry[k] = P.tab.lR[(b - k) & 3];
+    dx[k] = A.Dt[a * NP + ((a + k) & 3)];
+    dy[k] = A.Dt[b * NP + ((b - k) & 3)];
+  }
+  const double dhLa = P.tab.dhL[a], dhRa = P.tab.dhR[a], dhLb = P.tab.dhL[b], dhRb = P.tab.dhR[b];
+  const double iJx = 1.0 / P.Jx, iJy = 1.0 / P.Jy;
+
+  // face-point role: flux point j of this element, side = j >> 2 (x-lo, x-hi, y-lo, y-hi), i = j & 3
   const int fside = j >> 2, fi = j & 3;
-  int nbr_le = -1;  // neighbour inside the tile
-  int nbr_halo = -1;
+  int nbr_le = -1, nbr_halo = -1;
   bool boundary = false;
   if (fside == 0) {
     if (lx > 0) nbr_le = le - 1;
@@ -451,105 +501,100 @@ k_stage2d(KParams P, StageArgs A) {
     else if (iy == P.ny - 1 && P.bc[3] != FRSG_BC_PERIODIC) boundary = true;
     else nbr_halo = 12 + lx;
   }
-  // interpolation weights: own side and neighbour side of this face
-  const double* lown = (fside == 0 || fside == 2) ? P.tab.lL : P.tab.lR;
-  const double* lnbr = (fside == 0 || fside == 2) ? P.tab.lR : P.tab.lL;
-  double wown[4], wnbr[4];
+  // boundary rule of this lane's face (Sec. 2.1 boundary operator, ghost state per node)
+  const int gkind = P.bc[fside];
+  double gstate[4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    wown[c] = lown[c];
-    wnbr[c] = lnbr[c];
-  }
+  for (int s = 0; s < 4; ++s) gstate[s] = P.bc_state[fside][s];
+  const int gnormal = fside < 2 ? 1 : 2;
+  // the neighbour's flux point facing ours: x-lo <-> x-hi, y-lo <-> y-hi
+  const int mirror = (fside ^ 1) * 4 + fi;
+  const bool lo_side = (fside == 0 || fside == 2);
+  const int s0 = 2 * h, s1 = 2 * h + 1;
 
-  double acc[4][M];
+  double acc[2][M];
 #pragma unroll
-  for (int s = 0; s < 4; ++s)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int k = 0; k < M; ++k) acc[s][k] = 0.0;
+    for (int k = 0; k < M; ++k) acc[i][k] = 0.0;
 
   for (int q = 0; q < NQ; ++q) {
     const int par = q & 1;
-    // (1) nodal state and fluxes at this lane's solution point; halo traces
-    double U[4], F[4], G[4];
+    // (1) own pair at (j, q), all four variables, fluxes of the own pair, traces
+    double u2[2];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
+    for (int i = 0; i < 2; ++i) {
       double t = 0.0;
 #pragma unroll
-      for (int k = 0; k < M; ++k) t += m[s][k] * Phi[k * NQ + q];
-      U[s] = t;
+      for (int k = 0; k < M; ++k) t += m[i][k] * PhiT[q * M + k];
+      u2[i] = t;
     }
-    euler_fg(U, F, G, g);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      sU[par][le][j][s] = U[s];
-      sF[par][le][j][s] = F[s];
-      sG[par][le][j][s] = G[s];
-    }
+    double U[4];
+    full4(h, u2[0], u2[1], U);
+    double F2[2], G2[2];
     {
-      double t = 0.0;
+      const double ir = recip(U[0]);
+      const double p = (g - 1.0) * (U[3] - 0.5 * (U[1] * U[1] + U[2] * U[2]) * ir);
+      const double vx = U[1] * ir, vy = U[2] * ir;
+      if (h == 0) {
+        F2[0] = U[1];
+        G2[0] = U[2];
+        F2[1] = U[1] * vx + p;
+        G2[1] = U[1] * vy;
+      } else {
+        F2[0] = U[2] * vx;
+        G2[0] = U[2] * vy + p;
+        F2[1] = (U[3] + p) * vx;
+        G2[1] = (U[3] + p) * vy;
+      }
+    }
 #pragma unroll
-      for (int k = 0; k < M; ++k) t += th[k] * Phi[k * NQ + q];
-      sH[par][hf][hfp][hs] = t;
+    for (int i = 0; i < 2; ++i) {
+      const double txl = xdot(L.rlx, u2[i]), txr = xdot(L.rrx, u2[i]);
+      const double tyl = ydot(L.rly, u2[i]), tyr = ydot(L.rry, u2[i]);
+      if (a == 0) sT[par][le][0 + b][2 * h + i] = txl;
+      if (a == 1) sT[par][le][4 + b][2 * h + i] = txr;
+      if (b == 2) sT[par][le][8 + a][2 * h + i] = tyl;
+      if (b == 3) sT[par][le][12 + a][2 * h + i] = tyr;
     }
     __syncthreads();
 
-    // (2) interface flux at this lane's flux point
+    // (2) interface flux at flux point j (own pair of variables written)
     {
-      double own[4], nb[4];
+      double own[4], nb[4], gh[4];
+      const double* src = (nbr_le >= 0) ? &sT[par][nbr_le][mirror][0] : &sH[q][nbr_halo < 0 ? 0 : nbr_halo][fi][0];
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        double t = 0.0;
-#pragma unroll
-        for (int c = 0; c < NP; ++c) t += wown[c] * sU[par][le][fside < 2 ? (c + NP * fi) : (fi + NP * c)][s];
-        own[s] = t;
+        own[s] = sT[par][le][j][s];
+        nb[s] = src[s];
       }
-      if (nbr_le >= 0) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          double t = 0.0;
-#pragma unroll
-          for (int c = 0; c < NP; ++c)
-            t += wnbr[c] * sU[par][nbr_le][fside < 2 ? (c + NP * fi) : (fi + NP * c)][s];
-          nb[s] = t;
-        }
-      } else if (boundary) {
-        ghost<kEuler2>(P, fside, own, nb);
-      } else {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) nb[s] = sH[par][nbr_halo][fi][s];
+      for (int s = 0; s < 4; ++s) {
+        gh[s] = (gkind == FRSG_BC_DIRICHLET) ? gstate[s] : own[s];
+        if (gkind == FRSG_BC_REFLECT && s == gnormal) gh[s] = -gh[s];
+        nb[s] = boundary ? gh[s] : nb[s];
       }
       double Fs[4];
-      const bool lo = (fside == 0 || fside == 2);
-      if (fside < 2)
-        rusanov<kEuler2, 0>(lo ? nb : own, lo ? own : nb, Fs, 0.0, g);
-      else
-        rusanov<kEuler2, 1>(lo ? nb : own, lo ? own : nb, Fs, 0.0, g);
-#pragma unroll
-      for (int s = 0; s < 4; ++s) sFs[le][j][s] = Fs[s];
+      rusanov_e2(lo_side ? nb : own, lo_side ? own : nb, Fs, g, fside >> 1);
+      sFs[le][j][s0] = h ? Fs[2] : Fs[0];
+      sFs[le][j][s1] = h ? Fs[3] : Fs[1];
     }
-    __syncthreads();
+    // the interface fluxes of an element are written and read by the same wave
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-    // (3) nodal residual at this lane's solution point, projected onto the chaos
-    {
-      double R[4];
+    // (3) nodal residual of the own pair, projected onto the chaos
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        double ax = 0.0, ay = 0.0;
+    for (int i = 0; i < 2; ++i) {
+      const int s = 2 * h + i;
+      double ax = xdot(dx, F2[i]);
+      double ay = ydot(dy, G2[i]);
+      ax += sFs[le][0 + b][s] * dhLa + sFs[le][4 + b][s] * dhRa;
+      ay += sFs[le][8 + a][s] * dhLb + sFs[le][12 + a][s] * dhRb;
+      const double R = -ax * iJx - ay * iJy;
 #pragma unroll
-        for (int c = 0; c < NP; ++c) {
-          ax += dxr[c] * sF[par][le][c + NP * b][s];
-          ay += dyr[c] * sG[par][le][a + NP * c][s];
-        }
-        ax += sFs[le][0 + b][s] * dhLa + sFs[le][4 + b][s] * dhRa;
-        ay += sFs[le][8 + a][s] * dhLb + sFs[le][12 + a][s] * dhRb;
-        R[s] = -ax * iJx - ay * iJy;
-      }
-#pragma unroll
-      for (int k = 0; k < M; ++k) {
-        const double w = PW[k * NQ + q];
-#pragma unroll
-        for (int s = 0; s < 4; ++s) acc[s][k] += w * R[s];
-      }
+      for (int k = 0; k < M; ++k) acc[i][k] += PWT[q * M + k] * R;
     }
   }
 
@@ -557,91 +602,61 @@ k_stage2d(KParams P, StageArgs A) {
   const long base = (long)e * NSP + j;
   if (A.stage == 0) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int k = 0; k < M; ++k) A.out[((long)s * M + k) * EN + base] = acc[s][k];
+      for (int k = 0; k < M; ++k) out[((long)(2 * h + i) * M + k) * EN + base] = acc[i][k];
     return;
   }
-  // stage combination (acc becomes the output)
 #pragma unroll
-  for (int s = 0; s < 4; ++s)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int k = 0; k < M; ++k) {
-      const long idx = ((long)s * M + k) * EN + base;
-      const double uu = (A.cu != 0.0) ? A.u[idx] : 0.0;
-      acc[s][k] = A.cu * uu + A.cw * (m[s][k] + dt * acc[s][k]);
+      const long idx = ((long)(2 * h + i) * M + k) * EN + base;
+      const double uu = (A.cu != 0.0) ? uin[idx] : 0.0;
+      acc[i][k] = A.cu * uu + A.cw * (m[i][k] + dt * acc[i][k]);
     }
 
-  if (A.stage == 3 && P.filter != FRSG_FILTER_NONE) {
-    __syncthreads();  // sLam ready
-    Rot4 rvi, rv;
-    // x: row a of V^-1 acting on x; y: row b acting on y
-    {
-      double tx_[4], ty_[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        tx_[c] = P.tab.Vinv[a * NP + c];
-        ty_[c] = P.tab.Vinv[b * NP + c];
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        rvi.x[k] = tx_[(a + k) & 3];
-        rvi.y[k] = ty_[(b - k) & 3];
-      }
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        tx_[c] = P.tab.V[a * NP + c];
-        ty_[c] = P.tab.V[b * NP + c];
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        rv.x[k] = tx_[(a + k) & 3];
-        rv.y[k] = ty_[(b - k) & 3];
-      }
-    }
-    const int ff = sensor_filter_element<M>(P, acc, j, rvi, rv, sLam, true);
-    if (j == 0 && A.flag_filt) A.flag_filt[e] = (unsigned char)ff;
-  } else if (A.stage == 3 && j == 0 && A.flag_filt) {
-    A.flag_filt[e] = 0;
+  if (A.stage == 3) {
+    int ff = 0;
+    if (P.filter != FRSG_FILTER_NONE) ff = sensor_filter_pair<M>(P, acc, h, a, b, j, sLam);
+    if (tid % 32 == 0 && A.flag_filt) A.flag_filt[e] = (unsigned char)ff;
   }
-
   if (P.limiter) {
-    const int lf = limit_element<M, NQ>(P, acc, a, b, rw, rl, rr, A.cmax, true);
-    if (j == 0 && A.flag_lim) A.flag_lim[e] = (unsigned char)lf;
-  } else if (j == 0 && A.flag_lim) {
+    const int lf = limit_pair<M, NQ>(P, Phi, acc, h, a, b, L, A.cmax);
+    if (tid % 32 == 0 && A.flag_lim) A.flag_lim[e] = (unsigned char)lf;
+  } else if (tid % 32 == 0 && A.flag_lim) {
     A.flag_lim[e] = 0;
   }
 
 #pragma unroll
-  for (int s = 0; s < 4; ++s)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int k = 0; k < M; ++k) A.out[((long)s * M + k) * EN + base] = acc[s][k];
+    for (int k = 0; k < M; ++k) out[((long)(2 * h + i) * M + k) * EN + base] = acc[i][k];
 
   // CFL maximum of the new state for the next step
   if (A.stage == 3 && A.lam_next) {
     double rate = 0.0;
     for (int q = 0; q < NQ; ++q) {
-      double U[4];
+      double u2[2];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
+      for (int i = 0; i < 2; ++i) {
         double t = 0.0;
 #pragma unroll
-        for (int k = 0; k < M; ++k) t += acc[s][k] * Phi[k * NQ + q];
-        U[s] = t;
+        for (int k = 0; k < M; ++k) t += acc[i][k] * Phi[k * NQ + q];
+        u2[i] = t;
       }
+      double U[4];
+      full4(h, u2[0], u2[1], U);
       double r = speed<kEuler2, 0>(U, 0.0, g) / P.dx + speed<kEuler2, 1>(U, 0.0, g) / P.dy;
       if (!(r == r)) r = __longlong_as_double(0x7ff0000000000000ll);
       rate = fmax(rate, r);
     }
-    // wave then workgroup maximum
-    rate = ymax4(xmax4(rate));
-    rate = fmax(rate, __shfl_xor(rate, 16));
-    rate = fmax(rate, __shfl_xor(rate, 32));
+    for (int o = 32; o > 0; o >>= 1) rate = fmax(rate, __shfl_xor(rate, o));
     if ((tid & 63) == 0) sRed[tid >> 6] = rate;
     __syncthreads();
     if (tid == 0) {
       double r = sRed[0];
-      for (int w = 1; w < BLK / 64; ++w) r = fmax(r, sRed[w]);
+      for (int w = 1; w < BLK2 / 64; ++w) r = fmax(r, sRed[w]);
       atomicMax(A.lam_next, (unsigned long long)__double_as_longlong(r));
     }
   }
@@ -712,9 +727,6 @@ __global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
 template <int M, int NQ>
 static hipError_t launch_stage_t(const KParams& P, const FusedStage& S, hipStream_t s) {
   StageArgs A;
-  A.in = S.in;
-  A.u = S.u;
-  A.out = S.out;
   A.cu = S.cu;
   A.cw = S.cw;
   A.stage = S.stage;
@@ -724,7 +736,8 @@ static hipError_t launch_stage_t(const KParams& P, const FusedStage& S, hipStrea
   A.Dt = S.Dt;
   A.cmax = S.cmax;
   const int ntiles = (P.nx / 4) * (P.ny / 4);
-  hipLaunchKernelGGL((k_stage2d<M, NQ>), dim3(ntiles), dim3(BLK), 0, s, P, A);
+  hipLaunchKernelGGL((k_stage2d<M, NQ>), dim3(ntiles), dim3(BLK2), 0, s, P, A, P.tab.Phi, S.PhiT, S.PWT, S.in,
+                     S.u, S.out);
   return hipGetLastError();
 }
 

@@ -233,6 +233,13 @@ bool build_host_tables(const fr_sg_problem& P, HostTables& T, std::string& err) 
   T.cmax.assign(T.M, 0.0);
   for (int k = 0; k < T.M; ++k)
     for (int q = 0; q < T.Nq; ++q) T.cmax[k] = std::max(T.cmax[k], std::fabs(T.Phi[k * T.Nq + q]));
+  T.PhiT.assign((size_t)T.Nq * T.M, 0.0);
+  T.PWT.assign((size_t)T.Nq * T.M, 0.0);
+  for (int k = 0; k < T.M; ++k)
+    for (int q = 0; q < T.Nq; ++q) {
+      T.PhiT[q * T.M + k] = T.Phi[k * T.Nq + q];
+      T.PWT[q * T.M + k] = T.PW[k * T.Nq + q];
+    }
   T.swts.assign(nsp, 0.0);
   for (int j = 0; j < nsp; ++j)
     T.swts[j] = (dim == 1) ? T.w[j] / 2.0 : (T.w[j % n] / 2.0) * (T.w[j / n] / 2.0);
