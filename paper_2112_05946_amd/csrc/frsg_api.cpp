@@ -118,8 +118,12 @@ fr_sg_status validate(const fr_sg_problem& P, std::string& err) {
     err = "cfl must be positive";
     return FRSG_EINVAL;
   }
-  if (P.precision != FRSG_FP64) {
-    err = "only FRSG_FP64 is implemented";
+  if (P.precision != FRSG_FP64 && P.precision != FRSG_FP32_MIXED) {
+    err = "unknown precision";
+    return FRSG_EINVAL;
+  }
+  if (P.precision == FRSG_FP32_MIXED) {
+    err = "FRSG_FP32_MIXED is not available in this build";
     return FRSG_EUNSUPPORTED;
   }
   return FRSG_OK;
@@ -163,6 +167,8 @@ fr_sg_status timed(fr_sg_ctx* c, const char* name, double alg_bytes, const std::
 }
 
 double state_bytes(const fr_sg_ctx* c) { return 8.0 * c->S * c->T.M * (double)c->E * c->nsp; }
+
+int fp32(const fr_sg_ctx* c) { return c->prob.precision == FRSG_FP32_MIXED ? 1 : 0; }
 
 }  // namespace
 
@@ -271,6 +277,25 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
     probe.Nq = T.Nq;
     c->fused = fused2d_supported(probe);
   }
+  if (c->fused) {
+    std::vector<float> f32(2 * T.PhiT.size());
+    for (size_t i = 0; i < T.PhiT.size(); ++i) {
+      f32[i] = (float)T.PhiT[i];
+      f32[T.PhiT.size() + i] = (float)T.PWT[i];
+    }
+    float* d32 = nullptr;
+    he = hipMalloc(&d32, f32.size() * sizeof(float));
+    if (he == hipSuccess) he = hipMemcpy(d32, f32.data(), f32.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (he != hipSuccess) {
+      g_init_error = std::string("HIP error: ") + hipGetErrorString(he);
+      if (d32) (void)hipFree(d32);
+      (void)hipFree(c->dtab);
+      delete c;
+      return FRSG_EDEVICE;
+    }
+    c->dPhiT32 = d32;
+    c->dPWT32 = d32 + T.PhiT.size();
+  }
   const size_t state = (size_t)c->S * T.M * c->E * c->nsp;
   const size_t nodal = c->fused ? 0 : (size_t)c->S * T.Nq * c->E * c->nsp;
   const size_t corr = c->fused ? 0 : (size_t)c->S * T.Nq * c->E * (c->dim == 2 ? 4 * n : 2);
@@ -287,6 +312,7 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
   if (he != hipSuccess) {
     g_init_error = std::string("workspace allocation failed: ") + hipGetErrorString(he);
     (void)hipFree(c->dtab);
+    if (c->dPhiT32) (void)hipFree(c->dPhiT32);
     delete c;
     return FRSG_EDEVICE;
   }
@@ -295,6 +321,7 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
     g_init_error = std::string("HIP error: ") + hipGetErrorString(he);
     (void)hipFree(ws);
     (void)hipFree(c->dtab);
+    if (c->dPhiT32) (void)hipFree(c->dPhiT32);
     delete c;
     return FRSG_EDEVICE;
   }
@@ -424,7 +451,9 @@ fr_sg_status fr_sg_rhs(fr_sg_ctx* ctx, const double* u, double* dudt) {
     return FRSG_EINVAL;
   }
   if (ctx->fused) {
-    FusedStage S{u, u, dudt, 0.0, 1.0, 0, nullptr, nullptr, nullptr, ctx->dDt, ctx->dcmax, ctx->dPhiT, ctx->dPWT};
+    FusedStage S{u,          u,          dudt,         0.0,         1.0,           0,
+                 nullptr,    nullptr,    nullptr,      ctx->dDt,    ctx->dcmax,    ctx->dPhiT,
+                 ctx->dPWT,  fp32(ctx),  ctx->dPhiT32, ctx->dPWT32};
     return timed(ctx, "stage_rhs", 2 * state_bytes(ctx), [&] { return launch_fused_stage(ctx->kp, S, ctx->stream); });
   }
   fr_sg_status st = rhs_passes(ctx, u, 0);
@@ -498,12 +527,15 @@ static fr_sg_status step_fused(fr_sg_ctx* ctx, double* u, double dt, double* dt_
   uint8_t* f1 = flags ? flags + E : nullptr;
   uint8_t* f2 = flags ? flags + 2 * E : nullptr;
   uint8_t* f3 = flags ? flags + 3 * E : nullptr;
-  FusedStage s1{u, u, W.w1, 0.0, 1.0, 1, f0, nullptr, nullptr, ctx->dDt, ctx->dcmax, ctx->dPhiT, ctx->dPWT};
+  const int f32 = fp32(ctx);
+  FusedStage s1{u, u, W.w1, 0.0, 1.0, 1, f0, nullptr, nullptr, ctx->dDt, ctx->dcmax, ctx->dPhiT, ctx->dPWT,
+                f32, ctx->dPhiT32, ctx->dPWT32};
   if ((st = timed(ctx, "stage1", 2 * sb, [&] { return launch_fused_stage(K, s1, s); }))) return st;
-  FusedStage s2{W.w1, u, W.w2, 0.75, 0.25, 2, f1, nullptr, nullptr, ctx->dDt, ctx->dcmax, ctx->dPhiT, ctx->dPWT};
+  FusedStage s2{W.w1, u, W.w2, 0.75, 0.25, 2, f1, nullptr, nullptr, ctx->dDt, ctx->dcmax, ctx->dPhiT, ctx->dPWT,
+                f32, ctx->dPhiT32, ctx->dPWT32};
   if ((st = timed(ctx, "stage2", 3 * sb, [&] { return launch_fused_stage(K, s2, s); }))) return st;
   FusedStage s3{W.w2, u, u, 1.0 / 3.0, 2.0 / 3.0, 3, f3, f2, lam[cur ^ 1], ctx->dDt, ctx->dcmax, ctx->dPhiT,
-                ctx->dPWT};
+                ctx->dPWT, f32, ctx->dPhiT32, ctx->dPWT32};
   if ((st = timed(ctx, "stage3", 3 * sb, [&] { return launch_fused_stage(K, s3, s); }))) return st;
   ctx->lam_cur = cur ^ 1;
   ctx->lam_for = u;
@@ -620,6 +652,7 @@ fr_sg_status fr_sg_destroy(fr_sg_ctx* ctx) {
   for (hipEvent_t ev : ctx->events) (void)hipEventDestroy(ev);
   if (ctx->ws.w1) (void)hipFree(ctx->ws.w1);
   if (ctx->dtab) (void)hipFree(ctx->dtab);
+  if (ctx->dPhiT32) (void)hipFree(ctx->dPhiT32);
   delete ctx;
   return FRSG_OK;
 }

@@ -126,6 +126,8 @@ struct fr_sg_ctx {
   const double* dcmax = nullptr;
   const double* dPhiT = nullptr;
   const double* dPWT = nullptr;
+  float* dPhiT32 = nullptr;  // FP32 copies of the node-major tables
+  float* dPWT32 = nullptr;
   bool fused = false;
   int lam_cur = 0;              // which CFL accumulator holds the maximum of the current state
   const double* lam_for = nullptr;  // state whose maximum the previous step recorded (fr_sg_steps)
@@ -149,6 +151,9 @@ struct FusedStage {
   const double* cmax;
   const double* PhiT;  // [Nq][M] chaos basis at the nodes, node-major
   const double* PWT;   // [Nq][M] quadrature-weighted basis, node-major
+  int fp32;            // 1: node loop in FP32 (FP32-mixed precision)
+  const float* PhiT32;
+  const float* PWT32;
 };
 bool fused2d_supported(const KParams& P);
 hipError_t launch_fused_stage(const KParams& P, const FusedStage& S, hipStream_t s);

@@ -60,8 +60,12 @@ __device__ __forceinline__ double dpp(double v) {
   const int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), CTRL, 0xf, 0xf, true);
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, true));
+}
 
-// 1/x to double accuracy: hardware estimate refined by two Newton steps
+// 1/x to the accuracy of the type: hardware estimate refined by Newton steps
 __device__ __forceinline__ double recip(double x) {
   double r = __builtin_amdgcn_rcp(x);
   double e = fma(-x, r, 1.0);
@@ -69,27 +73,36 @@ __device__ __forceinline__ double recip(double x) {
   e = fma(-x, r, 1.0);
   return fma(r, e, r);
 }
+__device__ __forceinline__ float recip(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+__device__ __forceinline__ double sqrt_t(double x) { return sqrt(x); }
+__device__ __forceinline__ float sqrt_t(float x) { return sqrtf(x); }
+
 // value at point ((a + k) & 3, b)
-template <int K>
-__device__ __forceinline__ double xrot(double v) {
+template <int K, typename T>
+__device__ __forceinline__ T xrot(T v) {
   if constexpr (K == 0) return v;
   else if constexpr (K == 1) return dpp<0x39>(v);
   else if constexpr (K == 2) return dpp<0x4E>(v);
   else return dpp<0x93>(v);
 }
 // value at point (a, (b - k) & 3)
-template <int K>
-__device__ __forceinline__ double yrot(double v) {
+template <int K, typename T>
+__device__ __forceinline__ T yrot(T v) {
   if constexpr (K == 0) return v;
   else return dpp<0x120 + 4 * K>(v);
 }
 
 // sum_c w[c] v(c, b) with wx[k] = w[(a + k) & 3]
-__device__ __forceinline__ double xdot(const double* wx, double v) {
+template <typename T>
+__device__ __forceinline__ T xdot(const T* wx, T v) {
   return wx[0] * v + wx[1] * xrot<1>(v) + wx[2] * xrot<2>(v) + wx[3] * xrot<3>(v);
 }
 // sum_c w[c] v(a, c) with wy[k] = w[(b - k) & 3]
-__device__ __forceinline__ double ydot(const double* wy, double v) {
+template <typename T>
+__device__ __forceinline__ T ydot(const T* wy, T v) {
   return wy[0] * v + wy[1] * yrot<1>(v) + wy[2] * yrot<2>(v) + wy[3] * yrot<3>(v);
 }
 __device__ __forceinline__ double xmin4(double v) {
@@ -163,11 +176,15 @@ struct StageArgs {
 constexpr int BLK2 = 512;
 
 // value held by the partner lane (same point, other pair of variables)
-__device__ __forceinline__ double other_half(double v) { return __shfl_xor(v, 16); }
+template <typename T>
+__device__ __forceinline__ T other_half(T v) {
+  return __shfl_xor(v, 16);
+}
 
 // all four conserved variables from this lane's pair and the partner's pair
-__device__ __forceinline__ void full4(int h, double v0, double v1, double* U) {
-  const double o0 = other_half(v0), o1 = other_half(v1);
+template <typename T>
+__device__ __forceinline__ void full4(int h, T v0, T v1, T* U) {
+  const T o0 = other_half(v0), o1 = other_half(v1);
   U[0] = h ? o0 : v0;
   U[1] = h ? o1 : v1;
   U[2] = h ? v0 : o0;
@@ -175,23 +192,24 @@ __device__ __forceinline__ void full4(int h, double v0, double v1, double* U) {
 }
 
 // Lax-Friedrichs flux of the 2D Euler equations along direction dir (0: x, 1: y)
-__device__ __forceinline__ void rusanov_e2(const double* L, const double* R, double* Fs, double g, int dir) {
-  double fL[4], fR[4], sL, sR;
-  auto side = [&](const double* U, double* f, double& sp) {
-    const double ir = recip(U[0]);
-    const double p = (g - 1.0) * (U[3] - 0.5 * (U[1] * U[1] + U[2] * U[2]) * ir);
-    const double vn = (dir == 0 ? U[1] : U[2]) * ir;
+template <typename T>
+__device__ __forceinline__ void rusanov_e2(const T* L, const T* R, T* Fs, T g, int dir) {
+  T fL[4], fR[4], sL, sR;
+  auto side = [&](const T* U, T* f, T& sp) {
+    const T ir = recip(U[0]);
+    const T p = (g - T(1)) * (U[3] - T(0.5) * (U[1] * U[1] + U[2] * U[2]) * ir);
+    const T vn = (dir == 0 ? U[1] : U[2]) * ir;
     f[0] = dir == 0 ? U[1] : U[2];
-    f[1] = U[1] * vn + (dir == 0 ? p : 0.0);
-    f[2] = U[2] * vn + (dir == 0 ? 0.0 : p);
+    f[1] = U[1] * vn + (dir == 0 ? p : T(0));
+    f[2] = U[2] * vn + (dir == 0 ? T(0) : p);
     f[3] = (U[3] + p) * vn;
-    sp = fabs(vn) + sqrt(g * p * ir);
+    sp = fabs(vn) + sqrt_t(g * p * ir);
   };
   side(L, fL, sL);
   side(R, fR, sR);
-  const double lam = fmax(sL, sR);
+  const T lam = fmax(sL, sR);
 #pragma unroll
-  for (int s = 0; s < 4; ++s) Fs[s] = 0.5 * (fL[s] + fR[s]) - 0.5 * lam * (R[s] - L[s]);
+  for (int s = 0; s < 4; ++s) Fs[s] = T(0.5) * (fL[s] + fR[s]) - T(0.5) * lam * (R[s] - L[s]);
 }
 
 struct LaneOps {

@@ -59,7 +59,7 @@ def _init(lib, P):
     (lambda P: P.bc.__setitem__(0, 1), -1),            # unpaired periodic side
     (lambda P: P.bc.__setitem__(0, 9), -1),
     (lambda P: setattr(P, "filter", 5), -1),
-    (lambda P: setattr(P, "precision", 1), -2),
+    (lambda P: setattr(P, "precision", 7), -1),
 ])
 def test_invalid_problems_rejected_before_launch(lib, mutate, status):
     from paper_2112_05946_amd import binding, inputs
