@@ -71,14 +71,52 @@ def cpu_baseline(cfg_full):
                       (prob.nx, prob.ny, dof, el)}
 
 
+def timed_steps(torch, sol, u, steps, warmup):
+    """W untimed steps, then K timed steps bracketed by device synchronisation.
+
+    The library launches on the default stream, which is torch's current stream
+    here, so torch events bracket its kernels."""
+    dt_used = torch.empty(1, dtype=torch.float64, device=u.device)
+    flags = torch.empty(4 * sol.E, dtype=torch.uint8, device=u.device)
+    for _ in range(warmup):
+        sol.step(u, None, dt_used, flags)
+    sol.sync()
+    dts = torch.empty(steps, dtype=torch.float64, device=u.device)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    # K whole steps in one call: the CFL maximum of step n+1 is reduced in the
+    # end-of-step epilogue of step n (the first step reduces it separately)
+    sol.steps(u, steps, dts)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def pass_times(sol, u, steps):
+    """Per-pass device times (events recorded on the library's stream around each launch)."""
+    import torch
+    dts = torch.empty(steps, dtype=torch.float64, device=u.device)
+    sol.timing(True)
+    sol.steps(u, steps, dts)
+    passes = sol.timing_read()
+    sol.timing(False)
+    sol.sync()
+    return passes
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="shock_vortex")
-    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-mixed comparison run")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the multi-GPU halo exchange is not built); "
@@ -94,35 +132,13 @@ def main():
     cfg = inputs.CONFIGS[args.config]
     sol = Solver(cfg, precision=args.precision)
     u = sol.initial_state()
-    dt_used = torch.empty(1, dtype=torch.float64, device=u.device)
-    flags = torch.empty(4 * sol.E, dtype=torch.uint8, device=u.device)
-    for _ in range(args.warmup):
-        sol.step(u, None, dt_used, flags)
-    sol.sync()
-
-    # timed region: K whole steps, inputs resident in HBM
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record()
-    for _ in range(args.steps):
-        sol.step(u, None, dt_used, flags)
-    e1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1) / args.steps
-    sol.sync()
+    ms, wall = timed_steps(torch, sol, u, args.steps, args.warmup)
+    snapshot = u.clone()
     n_dof = int(sol.info["n_dof"])
     value = n_dof / (ms / 1e3)
 
     # per-pass device times over a second run of K steps (events around each launch)
-    sol.timing(True)
-    for _ in range(args.steps):
-        sol.step(u, None, dt_used, flags)
-    passes = sol.timing_read()
-    sol.timing(False)
-    sol.sync()
+    passes = pass_times(sol, u, args.steps)
     dom = max(passes, key=lambda k: passes[k][1])
     launches, tot_ms, alg = passes[dom]
     avg_s = tot_ms / launches / 1e3
@@ -130,17 +146,35 @@ def main():
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(dom, alg), "kernel": dom,
                 "alg_bytes_per_launch": alg, "avg_launch_ms": avg_s * 1e3}
+    sol.close()
+
+    # the other precision on the same workload: throughput and the L2 distance of
+    # its state from this run's after the same W + K steps
+    other = None
+    if args.precision == "fp64" and not args.no_fp32:
+        sol32 = Solver(cfg, precision="fp32")
+        u32 = sol32.initial_state()
+        ms32, _ = timed_steps(torch, sol32, u32, args.steps, args.warmup)
+        p32 = pass_times(sol32, u32.clone(), args.steps)
+        d32 = max(p32, key=lambda k: p32[k][1])
+        err = float(torch.linalg.vector_norm(u32 - snapshot) / torch.linalg.vector_norm(snapshot))
+        other = {"precision": "fp32_mixed", "value": n_dof / (ms32 / 1e3), "ms_per_step": ms32,
+                 "rel_l2_vs_fp64": err, "steps_compared": args.warmup + args.steps,
+                 "dominant_kernel_ms": p32[d32][1] / p32[d32][0],
+                 "passes_ms_per_step": {k: v[1] / args.steps for k, v in p32.items()}}
+        sol32.close()
 
     out = {
         "metric": METRIC, "value": value, "unit": "DOF-updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32 node loop, f64 state", "data": "synthetic",
         "config": {"workload": "%s %dx%d elements, p=%d, %d gPC modes (rdim %d), %d random nodes, %d states, "
                                "%d DOF" % (args.config, cfg["nx"], cfg.get("ny", 1), cfg["p"], sol.shape[1],
                                            cfg.get("rdim", 1), sol.info["n_nodes"], sol.shape[0], n_dof),
                    "precision": args.precision, "wall_s_timed": wall},
         "roofline": roofline,
         "passes_ms_per_step": {k: v[1] / args.steps for k, v in passes.items()},
+        "fp32_mixed": other,
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:

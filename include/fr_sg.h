@@ -74,6 +74,13 @@ typedef int32_t fr_sg_status;
 #define FRSG_SENSOR_ALWAYS 0
 #define FRSG_SENSOR_DETECTOR 1
 
+/* arithmetic of the right-hand side.  FRSG_FP64: everything in FP64.
+ * FRSG_FP32_MIXED: the per-node work of the right-hand side (chaos expansion at
+ * the node, fluxes, traces, interface fluxes, nodal residual and its Galerkin
+ * projection) in FP32; state storage, the Runge-Kutta combination, detector,
+ * filter, limiter and CFL reduction stay FP64.  Available where the fused 2D
+ * Euler path applies (FR degree 3, nx divisible by 4, ny by 2); elsewhere
+ * fr_sg_init returns FRSG_EUNSUPPORTED. */
 #define FRSG_FP64 0
 #define FRSG_FP32_MIXED 1
 

@@ -122,10 +122,6 @@ fr_sg_status validate(const fr_sg_problem& P, std::string& err) {
     err = "unknown precision";
     return FRSG_EINVAL;
   }
-  if (P.precision == FRSG_FP32_MIXED) {
-    err = "FRSG_FP32_MIXED is not available in this build";
-    return FRSG_EUNSUPPORTED;
-  }
   return FRSG_OK;
 }
 
@@ -275,7 +271,16 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
     probe.ny = c->dim == 2 ? P.ny : 1;
     probe.M = T.M;
     probe.Nq = T.Nq;
+    probe.E = P.nx * probe.ny;
     c->fused = fused2d_supported(probe);
+  }
+  if (P.precision == FRSG_FP32_MIXED && !c->fused) {
+    g_init_error =
+        "FRSG_FP32_MIXED runs on the fused 2D Euler path only (FR degree 3, nx % 4 == 0, ny % 2 == 0, "
+        "a compiled (M, Nq) pair)";
+    (void)hipFree(c->dtab);
+    delete c;
+    return FRSG_EUNSUPPORTED;
   }
   if (c->fused) {
     std::vector<float> f32(2 * T.PhiT.size());

@@ -45,8 +45,7 @@ namespace {
 
 constexpr int NP = 4;
 constexpr int NSP = 16;
-constexpr int TE = 16;      // elements per tile (4 x 4)
-constexpr int BLK = 256;    // threads per workgroup
+constexpr int BLK = 256;    // threads per workgroup of the element-wise kernels
 
 // ---------------------------------------------------------------------------
 // lane exchange within an element row of 16 lanes, lane r = a + 4 b
@@ -169,16 +168,32 @@ struct StageArgs {
   const double* cmax;        // [M] max_q |Phi_k(z_q)|
 };
 
-// Lane layout of a workgroup (one 4 x 4 tile of elements, 512 threads):
-//   tid = 32 le + 16 h + j,  j = a + 4 b;
+// Lane layout of a workgroup (one TX x TY tile of elements, 32 threads per element):
+//   tid = 32 le + 16 h + j,  j = a + 4 b,  le = lx + TX ly;
 // lane (le, h, j) owns conserved variables 2h and 2h+1 at solution point j of
-// local element le.  The 16 lanes with equal (le, h) form one DPP row.
-constexpr int BLK2 = 512;
+// local element le.  The 16 lanes with equal (le, h) form one DPP row, the two
+// rows of an element are partners, and the 32 lanes of an element sit in one
+// wave.
+constexpr int TX = 4, TY = 2;
+constexpr int TE = TX * TY;          // elements per tile
+constexpr int BLKS = 32 * TE;        // threads per stage workgroup
+constexpr int NHF = 2 * (TX + TY);   // element faces on the tile boundary
+static_assert(BLKS % 64 == 0, "an element's 32 lanes must share a wave");
 
-// value held by the partner lane (same point, other pair of variables)
-template <typename T>
-__device__ __forceinline__ T other_half(T v) {
-  return __shfl_xor(v, 16);
+// value held by the partner lane (same point, other pair of variables): the
+// 16-lane rows of each 32-lane half swap places.  Every lane of the wave must
+// be active.
+__device__ __forceinline__ unsigned other_half_u32(unsigned v) {
+  const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  return (threadIdx.x & 16) ? r[0] : r[1];
+}
+__device__ __forceinline__ float other_half(float v) {
+  return __uint_as_float(other_half_u32(__float_as_uint(v)));
+}
+__device__ __forceinline__ double other_half(double v) {
+  const unsigned long long x = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = other_half_u32((unsigned)x), hi = other_half_u32((unsigned)(x >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 // all four conserved variables from this lane's pair and the partner's pair
@@ -192,25 +207,36 @@ __device__ __forceinline__ void full4(int h, T v0, T v1, T* U) {
 }
 
 // Lax-Friedrichs flux of the 2D Euler equations along direction dir (0: x, 1: y)
+// between the own trace and the neighbour's; the neighbour is the left state
+// when nb_left.  f(L) + f(R) and the jump are formed so that the result does not
+// depend on which side computes it.
 template <typename T>
-__device__ __forceinline__ void rusanov_e2(const T* L, const T* R, T* Fs, T g, int dir) {
-  T fL[4], fR[4], sL, sR;
+__device__ __forceinline__ void rusanov_e2(const T* own, const T* nb, bool nb_left, T* Fs, T g, int dir) {
+  T fo[4], fn[4], so, sn;
   auto side = [&](const T* U, T* f, T& sp) {
     const T ir = recip(U[0]);
+    const T un = dir == 0 ? U[1] : U[2];
     const T p = (g - T(1)) * (U[3] - T(0.5) * (U[1] * U[1] + U[2] * U[2]) * ir);
-    const T vn = (dir == 0 ? U[1] : U[2]) * ir;
-    f[0] = dir == 0 ? U[1] : U[2];
+    const T vn = un * ir;
+    f[0] = un;
     f[1] = U[1] * vn + (dir == 0 ? p : T(0));
     f[2] = U[2] * vn + (dir == 0 ? T(0) : p);
     f[3] = (U[3] + p) * vn;
     sp = fabs(vn) + sqrt_t(g * p * ir);
   };
-  side(L, fL, sL);
-  side(R, fR, sR);
-  const T lam = fmax(sL, sR);
+  side(own, fo, so);
+  side(nb, fn, sn);
+  // 0.5 (f(L) + f(R)) - 0.5 lam (R - L), with R - L = +-(nb - own)
+  const T hl = nb_left ? T(-0.5) * fmax(so, sn) : T(0.5) * fmax(so, sn);
 #pragma unroll
-  for (int s = 0; s < 4; ++s) Fs[s] = T(0.5) * (fL[s] + fR[s]) - T(0.5) * lam * (R[s] - L[s]);
+  for (int s = 0; s < 4; ++s) Fs[s] = T(0.5) * (fo[s] + fn[s]) - hl * (nb[s] - own[s]);
 }
+
+// a pair of consecutive values, stored with one LDS access
+template <typename T>
+struct alignas(2 * sizeof(T)) Pair2 {
+  T x, y;
+};
 
 struct LaneOps {
   double rlx[4], rly[4], rrx[4], rry[4];  // rotated l(-1), l(+1) for x (row a) and y (row b)
@@ -400,64 +426,90 @@ __device__ int sensor_filter_pair(const KParams& P, double (&o)[2][M], int h, in
   return flag ? 1 : 0;
 }
 
+// Raw buffer access to a state array: one lane offset (VGPR) plus a uniform
+// offset per (variable, mode) (SGPR), so no per-coefficient address has to be
+// kept in registers.  Out-of-range offsets read 0 and drop stores.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t state_rsrc(const double* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0u, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, voff, soff, 0);
+}
+
 // ---------------------------------------------------------------------------
-// the stage kernel
+// the stage kernel; R is the type of the node loop (nodal values, fluxes,
+// residuals, projection), the epilogue runs in FP64
 // ---------------------------------------------------------------------------
-template <int M, int NQ>
-__global__ void __launch_bounds__(BLK2) k_stage2d(KParams P, StageArgs A, const double* __restrict__ Phi,
-                                                  const double* __restrict__ PhiT, const double* __restrict__ PWT,
+template <int M, int NQ, typename R>
+__global__ void __launch_bounds__(BLKS) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 2 : 3)))
+k_stage2d(KParams P, StageArgs A, const double* __restrict__ Phi,
+                                                  const R* __restrict__ PhiT, const R* __restrict__ PWT,
                                                   const double* __restrict__ in, const double* __restrict__ uin,
-                                                  double* out) {
-  __shared__ double sT[2][TE][NSP][4];  // element traces at its 16 flux points (by node parity)
-  __shared__ double sFs[TE][NSP][4];    // interface fluxes at those flux points
-  __shared__ double sH[NQ][16][NP][4];  // traces of elements outside the tile, every node
+                                                  const double* in_again, double* out) {
+  // in_again == in: the epilogue of the FP32 loop reads the FP64 input through
+  // it, so that the compiler cannot merge those loads with the ones at the top
+  // and keep the FP64 values live across the node loop
+  constexpr bool kFP64 = sizeof(R) == sizeof(double);
+  // element traces by slot: 0-15 are the flux points (x-lo row b, x-hi row b,
+  // y-lo column a, y-hi column a), 16-31 take the stores of lanes that own none
+  __shared__ Pair2<R> sT[2][TE][32][2];
+  __shared__ Pair2<R> sFs[TE][NSP][2];    // interface fluxes at the flux points
+  __shared__ R sH[NQ][NHF][NP][4];        // traces of elements outside the tile, every node
   __shared__ double sLam[M * NSP];
-  __shared__ double sRed[BLK2 / 64];
+  __shared__ double sRed[BLKS / 64];
 
   const int tid = threadIdx.x;
   const int le = tid >> 5, h = (tid >> 4) & 1, j = tid & 15;
   const int a = j & 3, b = j >> 2;
-  const int lx = le & 3, ly = le >> 2;
-  const int ntx = P.nx / 4;
+  const int lx = le % TX, ly = le / TX;
+  const int ntx = P.nx / TX;
   // XCD-aware order: consecutive workgroups go to different XCDs, so give each
   // XCD a contiguous band of tiles (neighbouring halos then share its L2)
-  const int ntiles = ntx * (P.ny / 4);
+  const int ntiles = ntx * (P.ny / TY);
   int tile = blockIdx.x;
   if (ntiles % 8 == 0) tile = (tile % 8) * (ntiles / 8) + tile / 8;
   const int tx = tile % ntx, ty = tile / ntx;
-  const int ix = 4 * tx + lx, iy = 4 * ty + ly;
+  const int ix = TX * tx + lx, iy = TY * ty + ly;
   const int e = iy * P.nx + ix;
   const long EN = (long)P.E * NSP;
-  const double g = P.gamma;
+  const R g = (R)P.gamma;
   const double dt = (A.stage == 0) ? 0.0 : *P.dt;
 
   if (A.stage == 3) {
-    for (int i = tid; i < M * NSP; i += BLK2) {
+    for (int i = tid; i < M * NSP; i += BLKS) {
       const double f = P.tab.filt[i];
       sLam[i] = (P.filter == FRSG_FILTER_EXP) ? exp(-P.alpha * dt * f) : f;
     }
   }
 
-  // own coefficients: variables 2h, 2h+1
-  double m[2][M];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int k = 0; k < M; ++k) m[i][k] = in[((long)(2 * h + i) * M + k) * EN + (long)e * NSP + j];
-
-  // traces of the elements around the tile at every node: combo (face hf, point fp, variable hs),
-  // two threads per combo, splitting the nodes by parity
+  // own coefficients: variables 2h, 2h+1 (the state is below 4 GiB, checked by the host)
+  const unsigned sbytes = (unsigned)(4 * M * EN * (long)sizeof(double));
+  const unsigned voff = (unsigned)(((long)(2 * h) * M * EN + (long)e * NSP + j) * (long)sizeof(double));
+  auto soff = [&](int i, int k) { return (unsigned)(((long)i * M + k) * EN * (long)sizeof(double)); };
+  R m[2][M];
   {
-    const int combo = tid >> 1, qpar = tid & 1;
-    const int hf = combo >> 4, hfp = (combo >> 2) & 3, hs = combo & 3;
-    const int side = hf >> 2, pos = hf & 3;
+    const auto rin = state_rsrc(in, sbytes);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int k = 0; k < M; ++k) m[i][k] = (R)bload(rin, voff, soff(i, k));
+  }
+
+  // traces of the elements around the tile at every node: one thread per
+  // (face hf, face point hfp, variable hs); faces: TY x-lo, TY x-hi, TX y-lo, TX y-hi
+  if (tid < NHF * NP * 4) {
+    const int hf = tid >> 4, hfp = (tid >> 2) & 3, hs = tid & 3;
     int nix, niy;
     const double* l;
     bool along_x;
-    if (side == 0) { nix = 4 * tx - 1; niy = 4 * ty + pos; l = P.tab.lR; along_x = true; }
-    else if (side == 1) { nix = 4 * tx + 4; niy = 4 * ty + pos; l = P.tab.lL; along_x = true; }
-    else if (side == 2) { nix = 4 * tx + pos; niy = 4 * ty - 1; l = P.tab.lR; along_x = false; }
-    else { nix = 4 * tx + pos; niy = 4 * ty + 4; l = P.tab.lL; along_x = false; }
+    if (hf < TY) { nix = TX * tx - 1; niy = TY * ty + hf; l = P.tab.lR; along_x = true; }
+    else if (hf < 2 * TY) { nix = TX * tx + TX; niy = TY * ty + hf - TY; l = P.tab.lL; along_x = true; }
+    else if (hf < 2 * TY + TX) { nix = TX * tx + hf - 2 * TY; niy = TY * ty - 1; l = P.tab.lR; along_x = false; }
+    else { nix = TX * tx + hf - 2 * TY - TX; niy = TY * ty + TY; l = P.tab.lL; along_x = false; }
     bool valid = true;
     if (nix < 0) { if (P.bc[0] == FRSG_BC_PERIODIC) nix += P.nx; else valid = false; }
     if (nix >= P.nx) { if (P.bc[1] == FRSG_BC_PERIODIC) nix -= P.nx; else valid = false; }
@@ -475,85 +527,86 @@ __global__ void __launch_bounds__(BLK2) k_stage2d(KParams P, StageArgs A, const 
       }
       th[k] = t;
     }
-    for (int q = qpar; q < NQ; q += 2) {
+#pragma unroll 1
+    for (int q = 0; q < NQ; ++q) {
       double t = 0.0;
 #pragma unroll
       for (int k = 0; k < M; ++k) t += th[k] * Phi[k * NQ + q];
-      sH[q][hf][hfp][hs] = t;
+      sH[q][hf][hfp][hs] = (R)t;
     }
   }
 
-  // per-lane operator rows
-  LaneOps L;
-  double dx[4], dy[4];
+  // per-lane operator rows: one x trace (lanes a = 0, 1) and one y trace
+  // (lanes b = 2, 3) per lane, by rotated Lagrange rows
+  R cx[4], cy[4], dx[4], dy[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    L.rlx[k] = P.tab.lL[(a + k) & 3];
-    L.rrx[k] = P.tab.lR[(a + k) & 3];
-    L.rly[k] = P.tab.lL[(b - k) & 3];
-    L.rry[k] = P.tab.lR[(b - k) & 3];
-    dx[k] = A.Dt[a * NP + ((a + k) & 3)];
-    dy[k] = A.Dt[b * NP + ((b - k) & 3)];
+    cx[k] = (R)(a == 0 ? P.tab.lL[(a + k) & 3] : P.tab.lR[(a + k) & 3]);
+    cy[k] = (R)(b == 2 ? P.tab.lL[(b - k) & 3] : P.tab.lR[(b - k) & 3]);
+    dx[k] = (R)A.Dt[a * NP + ((a + k) & 3)];
+    dy[k] = (R)A.Dt[b * NP + ((b - k) & 3)];
   }
-  const double dhLa = P.tab.dhL[a], dhRa = P.tab.dhR[a], dhLb = P.tab.dhL[b], dhRb = P.tab.dhR[b];
-  const double iJx = 1.0 / P.Jx, iJy = 1.0 / P.Jy;
+  const int xslot = (a < 2) ? 4 * a + b : 8 + 4 * a + b;
+  const int yslot = (b >= 2) ? 4 * b + a : 24 + 4 * b + a;
+  const R dhLa = (R)P.tab.dhL[a], dhRa = (R)P.tab.dhR[a], dhLb = (R)P.tab.dhL[b], dhRb = (R)P.tab.dhR[b];
+  const R iJx = (R)(1.0 / P.Jx), iJy = (R)(1.0 / P.Jy);
 
   // face-point role: flux point j of this element, side = j >> 2 (x-lo, x-hi, y-lo, y-hi), i = j & 3
   const int fside = j >> 2, fi = j & 3;
-  int nbr_le = -1, nbr_halo = -1;
+  int nbr_le = -1, nbr_halo = 0;
   bool boundary = false;
   if (fside == 0) {
     if (lx > 0) nbr_le = le - 1;
     else if (ix == 0 && P.bc[0] != FRSG_BC_PERIODIC) boundary = true;
     else nbr_halo = ly;
   } else if (fside == 1) {
-    if (lx < 3) nbr_le = le + 1;
+    if (lx < TX - 1) nbr_le = le + 1;
     else if (ix == P.nx - 1 && P.bc[1] != FRSG_BC_PERIODIC) boundary = true;
-    else nbr_halo = 4 + ly;
+    else nbr_halo = TY + ly;
   } else if (fside == 2) {
-    if (ly > 0) nbr_le = le - 4;
+    if (ly > 0) nbr_le = le - TX;
     else if (iy == 0 && P.bc[2] != FRSG_BC_PERIODIC) boundary = true;
-    else nbr_halo = 8 + lx;
+    else nbr_halo = 2 * TY + lx;
   } else {
-    if (ly < 3) nbr_le = le + 4;
+    if (ly < TY - 1) nbr_le = le + TX;
     else if (iy == P.ny - 1 && P.bc[3] != FRSG_BC_PERIODIC) boundary = true;
-    else nbr_halo = 12 + lx;
+    else nbr_halo = 2 * TY + TX + lx;
   }
   // boundary rule of this lane's face (Sec. 2.1 boundary operator, ghost state per node)
   const int gkind = P.bc[fside];
-  double gstate[4];
+  R gstate[4];
 #pragma unroll
-  for (int s = 0; s < 4; ++s) gstate[s] = P.bc_state[fside][s];
+  for (int s = 0; s < 4; ++s) gstate[s] = (R)P.bc_state[fside][s];
   const int gnormal = fside < 2 ? 1 : 2;
   // the neighbour's flux point facing ours: x-lo <-> x-hi, y-lo <-> y-hi
   const int mirror = (fside ^ 1) * 4 + fi;
   const bool lo_side = (fside == 0 || fside == 2);
-  const int s0 = 2 * h, s1 = 2 * h + 1;
 
-  double acc[2][M];
+  R acc[2][M];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int k = 0; k < M; ++k) acc[i][k] = 0.0;
+    for (int k = 0; k < M; ++k) acc[i][k] = R(0);
 
+#pragma unroll 1
   for (int q = 0; q < NQ; ++q) {
     const int par = q & 1;
     // (1) own pair at (j, q), all four variables, fluxes of the own pair, traces
-    double u2[2];
+    R u2[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      double t = 0.0;
+      R t = R(0);
 #pragma unroll
       for (int k = 0; k < M; ++k) t += m[i][k] * PhiT[q * M + k];
       u2[i] = t;
     }
-    double U[4];
+    R U[4];
     full4(h, u2[0], u2[1], U);
-    double F2[2], G2[2];
+    R F2[2], G2[2];
     {
-      const double ir = recip(U[0]);
-      const double p = (g - 1.0) * (U[3] - 0.5 * (U[1] * U[1] + U[2] * U[2]) * ir);
-      const double vx = U[1] * ir, vy = U[2] * ir;
+      const R ir = recip(U[0]);
+      const R p = (g - R(1)) * (U[3] - R(0.5) * (U[1] * U[1] + U[2] * U[2]) * ir);
+      const R vx = U[1] * ir, vy = U[2] * ir;
       if (h == 0) {
         F2[0] = U[1];
         G2[0] = U[2];
@@ -566,36 +619,26 @@ __global__ void __launch_bounds__(BLK2) k_stage2d(KParams P, StageArgs A, const 
         G2[1] = (U[3] + p) * vy;
       }
     }
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const double txl = xdot(L.rlx, u2[i]), txr = xdot(L.rrx, u2[i]);
-      const double tyl = ydot(L.rly, u2[i]), tyr = ydot(L.rry, u2[i]);
-      if (a == 0) sT[par][le][0 + b][2 * h + i] = txl;
-      if (a == 1) sT[par][le][4 + b][2 * h + i] = txr;
-      if (b == 2) sT[par][le][8 + a][2 * h + i] = tyl;
-      if (b == 3) sT[par][le][12 + a][2 * h + i] = tyr;
-    }
+    sT[par][le][xslot][h] = Pair2<R>{xdot(cx, u2[0]), xdot(cx, u2[1])};
+    sT[par][le][yslot][h] = Pair2<R>{ydot(cy, u2[0]), ydot(cy, u2[1])};
     __syncthreads();
 
     // (2) interface flux at flux point j (own pair of variables written)
     {
-      double own[4], nb[4], gh[4];
-      const double* src = (nbr_le >= 0) ? &sT[par][nbr_le][mirror][0] : &sH[q][nbr_halo < 0 ? 0 : nbr_halo][fi][0];
+      R own[4], nb[4];
+      const Pair2<R>* src = (nbr_le >= 0) ? sT[par][nbr_le][mirror] : (const Pair2<R>*)&sH[q][nbr_halo][fi][0];
+      const Pair2<R> o0 = sT[par][le][j][0], o1 = sT[par][le][j][1], n0 = src[0], n1 = src[1];
+      own[0] = o0.x; own[1] = o0.y; own[2] = o1.x; own[3] = o1.y;
+      nb[0] = n0.x; nb[1] = n0.y; nb[2] = n1.x; nb[3] = n1.y;
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        own[s] = sT[par][le][j][s];
-        nb[s] = src[s];
+        R gh = (gkind == FRSG_BC_DIRICHLET) ? gstate[s] : own[s];
+        if (gkind == FRSG_BC_REFLECT && s == gnormal) gh = -gh;
+        nb[s] = boundary ? gh : nb[s];
       }
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        gh[s] = (gkind == FRSG_BC_DIRICHLET) ? gstate[s] : own[s];
-        if (gkind == FRSG_BC_REFLECT && s == gnormal) gh[s] = -gh[s];
-        nb[s] = boundary ? gh[s] : nb[s];
-      }
-      double Fs[4];
-      rusanov_e2(lo_side ? nb : own, lo_side ? own : nb, Fs, g, fside >> 1);
-      sFs[le][j][s0] = h ? Fs[2] : Fs[0];
-      sFs[le][j][s1] = h ? Fs[3] : Fs[1];
+      R Fs[4];
+      rusanov_e2(own, nb, lo_side, Fs, g, fside >> 1);
+      sFs[le][j][h] = Pair2<R>{h ? Fs[2] : Fs[0], h ? Fs[3] : Fs[1]};
     }
     // the interface fluxes of an element are written and read by the same wave
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -603,44 +646,60 @@ __global__ void __launch_bounds__(BLK2) k_stage2d(KParams P, StageArgs A, const 
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
     // (3) nodal residual of the own pair, projected onto the chaos
+    {
+      const Pair2<R> fxl = sFs[le][0 + b][h], fxr = sFs[le][4 + b][h];
+      const Pair2<R> fyl = sFs[le][8 + a][h], fyr = sFs[le][12 + a][h];
+      const R r0 = -(xdot(dx, F2[0]) + fxl.x * dhLa + fxr.x * dhRa) * iJx -
+                   (ydot(dy, G2[0]) + fyl.x * dhLb + fyr.x * dhRb) * iJy;
+      const R r1 = -(xdot(dx, F2[1]) + fxl.y * dhLa + fxr.y * dhRa) * iJx -
+                   (ydot(dy, G2[1]) + fyl.y * dhLb + fyr.y * dhRb) * iJy;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int s = 2 * h + i;
-      double ax = xdot(dx, F2[i]);
-      double ay = ydot(dy, G2[i]);
-      ax += sFs[le][0 + b][s] * dhLa + sFs[le][4 + b][s] * dhRa;
-      ay += sFs[le][8 + a][s] * dhLb + sFs[le][12 + a][s] * dhRb;
-      const double R = -ax * iJx - ay * iJy;
-#pragma unroll
-      for (int k = 0; k < M; ++k) acc[i][k] += PWT[q * M + k] * R;
+      for (int k = 0; k < M; ++k) {
+        acc[0][k] += PWT[q * M + k] * r0;
+        acc[1][k] += PWT[q * M + k] * r1;
+      }
     }
   }
 
   // ----------------------------------------------------------------- epilogue
-  const long base = (long)e * NSP + j;
+  const auto rout = state_rsrc(out, sbytes);
   if (A.stage == 0) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int k = 0; k < M; ++k) out[((long)(2 * h + i) * M + k) * EN + base] = acc[i][k];
+      for (int k = 0; k < M; ++k) bstore((double)acc[i][k], rout, voff, soff(i, k));
     return;
   }
+  double o[2][M];
+  {
+    const auto ru = state_rsrc(uin, A.cu != 0.0 ? sbytes : 0u);
+    const auto rin2 = state_rsrc(in_again, sbytes);
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int k = 0; k < M; ++k) {
-      const long idx = ((long)(2 * h + i) * M + k) * EN + base;
-      const double uu = (A.cu != 0.0) ? uin[idx] : 0.0;
-      acc[i][k] = A.cu * uu + A.cw * (m[i][k] + dt * acc[i][k]);
-    }
+      for (int k = 0; k < M; ++k) {
+        const double uu = bload(ru, voff, soff(i, k));  // 0 from an empty range when cu = 0
+        // the FP64 input: kept in registers by the FP64 loop, re-read otherwise
+        const double mi = kFP64 ? (double)m[i][k] : bload(rin2, voff, soff(i, k));
+        o[i][k] = A.cu * uu + A.cw * (mi + dt * (double)acc[i][k]);
+      }
+  }
 
   if (A.stage == 3) {
     int ff = 0;
-    if (P.filter != FRSG_FILTER_NONE) ff = sensor_filter_pair<M>(P, acc, h, a, b, j, sLam);
+    if (P.filter != FRSG_FILTER_NONE) ff = sensor_filter_pair<M>(P, o, h, a, b, j, sLam);
     if (tid % 32 == 0 && A.flag_filt) A.flag_filt[e] = (unsigned char)ff;
   }
   if (P.limiter) {
-    const int lf = limit_pair<M, NQ>(P, Phi, acc, h, a, b, L, A.cmax);
+    LaneOps L;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      L.rlx[k] = P.tab.lL[(a + k) & 3];
+      L.rrx[k] = P.tab.lR[(a + k) & 3];
+      L.rly[k] = P.tab.lL[(b - k) & 3];
+      L.rry[k] = P.tab.lR[(b - k) & 3];
+    }
+    const int lf = limit_pair<M, NQ>(P, Phi, o, h, a, b, L, A.cmax);
     if (tid % 32 == 0 && A.flag_lim) A.flag_lim[e] = (unsigned char)lf;
   } else if (tid % 32 == 0 && A.flag_lim) {
     A.flag_lim[e] = 0;
@@ -649,10 +708,11 @@ __global__ void __launch_bounds__(BLK2) k_stage2d(KParams P, StageArgs A, const 
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int k = 0; k < M; ++k) out[((long)(2 * h + i) * M + k) * EN + base] = acc[i][k];
+    for (int k = 0; k < M; ++k) bstore(o[i][k], rout, voff, soff(i, k));
 
   // CFL maximum of the new state for the next step
   if (A.stage == 3 && A.lam_next) {
+    const double gd = P.gamma;
     double rate = 0.0;
     for (int q = 0; q < NQ; ++q) {
       double u2[2];
@@ -660,21 +720,21 @@ __global__ void __launch_bounds__(BLK2) k_stage2d(KParams P, StageArgs A, const 
       for (int i = 0; i < 2; ++i) {
         double t = 0.0;
 #pragma unroll
-        for (int k = 0; k < M; ++k) t += acc[i][k] * Phi[k * NQ + q];
+        for (int k = 0; k < M; ++k) t += o[i][k] * Phi[k * NQ + q];
         u2[i] = t;
       }
       double U[4];
       full4(h, u2[0], u2[1], U);
-      double r = speed<kEuler2, 0>(U, 0.0, g) / P.dx + speed<kEuler2, 1>(U, 0.0, g) / P.dy;
+      double r = speed<kEuler2, 0>(U, 0.0, gd) / P.dx + speed<kEuler2, 1>(U, 0.0, gd) / P.dy;
       if (!(r == r)) r = __longlong_as_double(0x7ff0000000000000ll);
       rate = fmax(rate, r);
     }
-    for (int o = 32; o > 0; o >>= 1) rate = fmax(rate, __shfl_xor(rate, o));
+    for (int w = 32; w > 0; w >>= 1) rate = fmax(rate, __shfl_xor(rate, w));
     if ((tid & 63) == 0) sRed[tid >> 6] = rate;
     __syncthreads();
     if (tid == 0) {
       double r = sRed[0];
-      for (int w = 1; w < BLK2 / 64; ++w) r = fmax(r, sRed[w]);
+      for (int w = 1; w < BLKS / 64; ++w) r = fmax(r, sRed[w]);
       atomicMax(A.lam_next, (unsigned long long)__double_as_longlong(r));
     }
   }
@@ -753,9 +813,13 @@ static hipError_t launch_stage_t(const KParams& P, const FusedStage& S, hipStrea
   A.lam_next = S.lam_next;
   A.Dt = S.Dt;
   A.cmax = S.cmax;
-  const int ntiles = (P.nx / 4) * (P.ny / 4);
-  hipLaunchKernelGGL((k_stage2d<M, NQ>), dim3(ntiles), dim3(BLK2), 0, s, P, A, P.tab.Phi, S.PhiT, S.PWT, S.in,
-                     S.u, S.out);
+  const int ntiles = (P.nx / TX) * (P.ny / TY);
+  if (S.fp32)
+    hipLaunchKernelGGL((k_stage2d<M, NQ, float>), dim3(ntiles), dim3(BLKS), 0, s, P, A, P.tab.Phi, S.PhiT32,
+                       S.PWT32, S.in, S.u, S.in, S.out);
+  else
+    hipLaunchKernelGGL((k_stage2d<M, NQ, double>), dim3(ntiles), dim3(BLKS), 0, s, P, A, P.tab.Phi, S.PhiT,
+                       S.PWT, S.in, S.u, S.in, S.out);
   return hipGetLastError();
 }
 
@@ -770,7 +834,9 @@ static hipError_t launch_cfl_t(const KParams& P, const double* u, unsigned long 
 #define FRSG_FUSED_SIZES(X) X(15, 25) X(10, 16) X(6, 9) X(3, 4) X(5, 5)
 
 bool fused2d_supported(const KParams& P) {
-  if (P.eq != kEuler2 || P.np1 != 4 || P.nx % 4 != 0 || P.ny % 4 != 0) return false;
+  if (P.eq != kEuler2 || P.np1 != 4 || P.nx % TX != 0 || P.ny % TY != 0) return false;
+  // raw buffer offsets are 32-bit: the state must stay below 4 GiB
+  if ((double)4 * P.M * P.E * NSP * sizeof(double) >= 4294967296.0) return false;
 #define X(MM, QQ) if (P.M == MM && P.Nq == QQ) return true;
   FRSG_FUSED_SIZES(X)
 #undef X

@@ -1,0 +1,134 @@
+"""FP32-mixed path (node loop of the fused 2D Euler stage kernel in FP32) against
+the FP64 oracle.
+
+FP32 changes the result, so the bar is an error bound instead of parity: the
+right-hand side of a fuzzed state within FP32_RHS_TOL relative L2 of the oracle,
+a step within FP32_STEP_TOL (the state moves by dt R, so the RHS error is scaled
+by dt |R| / |u|), dt within FP32_DT_TOL.  The FP64 epilogue takes the limiter
+and detector decisions on the FP32-perturbed state: a decision may differ from
+the oracle's only where the oracle's own margin is below FP32_TIE.
+"""
+
+import numpy as np
+import pytest
+
+from gpu_util import announce, oracle_for, rel_l2, solver_for, to_dev, to_np
+from oracle import fr as ofr
+from oracle import stabilize as ost
+from oracle import stepper as ostep
+from oracle.initial import project_initial
+from paper_2112_05946_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+FP32_RHS_TOL = 1e-4
+FP32_STEP_TOL = 1e-6
+FP32_DT_TOL = 1e-6
+FP32_TIE = 1e-5
+
+SV_TILED = inputs.small(inputs.SHOCK_VORTEX, 12, 8)
+SV_TY2 = inputs.small(inputs.SHOCK_VORTEX, 8, 6)
+SV_PERIODIC = dict(inputs.small(inputs.SHOCK_VORTEX, 8, 8), gpc_order=3, nq1d=4,
+                   bc=["periodic"] * 4, sensor="always", filter="l2")
+
+
+def _flags_close(prob, T, R, gflags, rflags, record):
+    diffs = 0
+    for pas in range(4):
+        bad = np.nonzero(gflags[pas] != rflags[pas])[0]
+        if len(bad) == 0:
+            continue
+        diffs += len(bad)
+        if pas == 2:
+            se, thr = ost.sensor_margin(prob, T, R, record[pas])
+            rel = np.abs(se[bad] - thr) / thr
+        else:
+            m, scale = ost.limiter_margin(prob, T, R, record[pas])
+            rel = np.abs(m[bad]) / scale[bad]
+        assert np.all(rel <= FP32_TIE), ("decision differs away from a tie", pas, bad[:5], rel[:5])
+    return diffs
+
+
+@pytest.mark.parametrize("label,cfg", [("tiled", SV_TILED), ("tile_rows_2", SV_TY2), ("periodic", SV_PERIODIC)])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_fp32_rhs_error(label, cfg, seed):
+    announce("fp32_rhs", label, seed)
+    prob, (T, R) = oracle_for(cfg)
+    u = inputs.fuzz_euler(2, R.M, prob.E, 16, seed)
+    ref = ofr.rhs(prob, T, R, u)
+    sol = solver_for(cfg, "fp32")
+    got = to_np(sol.rhs(to_dev(u)))
+    sol.sync()
+    err = rel_l2(got, ref)
+    print("[fp32] rhs rel L2 error %.3e" % err, flush=True)
+    assert err < FP32_RHS_TOL
+
+
+@pytest.mark.parametrize("label,cfg", [("tiled", SV_TILED), ("tile_rows_2", SV_TY2), ("periodic", SV_PERIODIC)])
+def test_fp32_steps_error(label, cfg):
+    announce("fp32_steps", label)
+    prob, (T, R) = oracle_for(cfg)
+    u0 = project_initial(prob, cfg["ic"], (T, R))
+    sol = solver_for(cfg, "fp32")
+    ud = to_dev(u0)
+    ref = u0.copy()
+    diffs = 0
+    for i in range(4):
+        rec = []
+        ref, rdt, rflags = ostep.step(prob, ref, None, (T, R), record=rec)
+        dtd, flags = sol.step(ud)
+        sol.sync()
+        assert abs(to_np(dtd)[0] - rdt) <= FP32_DT_TOL * rdt
+        diffs += _flags_close(prob, T, R, to_np(flags).reshape(4, prob.E), rflags, rec)
+        err = rel_l2(to_np(ud), ref)
+        print("[fp32] step %d rel L2 error %.3e, decisions differing %d" % (i, err, diffs), flush=True)
+        assert err < FP32_STEP_TOL * (i + 1)
+
+
+def test_fp32_limiter_exact_path():
+    """Near-vacuum state: the limiter acts; FP32 loop, FP64 limiter keeps the result realizable."""
+    cfg = dict(SV_TILED, bc=["periodic"] * 4)
+    announce("fp32_vacuum")
+    prob, (T, R) = oracle_for(cfg)
+    u = inputs.fuzz_euler(2, R.M, prob.E, 16, 6, vacuum_frac=0.15)
+    u, fl = ost.limit(prob, T, R, u)
+    assert fl.sum() > 0
+    sol = solver_for(cfg, "fp32")
+    ud = to_dev(u)
+    ref = u.copy()
+    for i in range(3):
+        rec = []
+        ref, _, rflags = ostep.step(prob, ref, 1e-5, (T, R), record=rec)
+        _, flags = sol.step(ud, 1e-5)
+        sol.sync()
+        _flags_close(prob, T, R, to_np(flags).reshape(4, prob.E), rflags, rec)
+        err = rel_l2(to_np(ud), ref)
+        print("[fp32] vacuum step %d rel L2 error %.3e" % (i, err), flush=True)
+        assert err < FP32_STEP_TOL * (i + 1)
+    # every element mean stays realizable
+    rho = ost.element_mean(prob, T, to_np(ud))
+    assert np.all(rho[0] > 0)
+
+
+def test_fp32_full_size_step():
+    """256 x 128 elements, 15 modes, 25 nodes: one FP32-mixed step against the oracle."""
+    cfg = inputs.SHOCK_VORTEX
+    announce("fp32_full_size")
+    prob, (T, R) = oracle_for(cfg)
+    u0 = project_initial(prob, cfg["ic"], (T, R))
+    ref, rdt, _ = ostep.step(prob, u0.copy(), None, (T, R))
+    sol = solver_for(cfg, "fp32")
+    ud = to_dev(u0)
+    dtd, _ = sol.step(ud)
+    sol.sync()
+    err = rel_l2(to_np(ud), ref)
+    print("[fp32] full-size step rel L2 error %.3e" % err, flush=True)
+    assert abs(to_np(dtd)[0] - rdt) <= FP32_DT_TOL * rdt
+    assert err < FP32_STEP_TOL
+
+
+def test_fp32_rejected_off_the_fused_path():
+    from paper_2112_05946_amd.binding import FrsgError
+    with pytest.raises(FrsgError) as ei:
+        solver_for(inputs.small(inputs.BURGERS, 16), "fp32")
+    assert ei.value.status == -2

@@ -187,14 +187,15 @@ def test_advection_full_horizon():
 
 
 # ---------------------------------------------------------------------------
-# fused 2D Euler path (p = 3, meshes in multiples of the 4 x 4 element tile)
+# fused 2D Euler path (p = 3, meshes in multiples of the 4 x 2 element tile)
 # ---------------------------------------------------------------------------
 SV_TILED = inputs.small(inputs.SHOCK_VORTEX, 12, 8)
+SV_TY2 = inputs.small(inputs.SHOCK_VORTEX, 8, 6)      # tile rows of 2, not of 4
 SV_PERIODIC = dict(inputs.small(inputs.SHOCK_VORTEX, 8, 8), gpc_order=3, nq1d=4,
                    bc=["periodic"] * 4, sensor="always", filter="l2")
 
 
-@pytest.mark.parametrize("label,cfg", [("tiled", SV_TILED), ("periodic", SV_PERIODIC)])
+@pytest.mark.parametrize("label,cfg", [("tiled", SV_TILED), ("tile_rows_2", SV_TY2), ("periodic", SV_PERIODIC)])
 @pytest.mark.parametrize("seed", [0, 1])
 def test_fused_rhs_fuzz(label, cfg, seed):
     announce("fused_rhs_fuzz", label, seed)
@@ -207,7 +208,7 @@ def test_fused_rhs_fuzz(label, cfg, seed):
     assert rel_l2(got, ref) < RTOL_FP64
 
 
-@pytest.mark.parametrize("label,cfg", [("tiled", SV_TILED), ("periodic", SV_PERIODIC)])
+@pytest.mark.parametrize("label,cfg", [("tiled", SV_TILED), ("tile_rows_2", SV_TY2), ("periodic", SV_PERIODIC)])
 def test_fused_steps_from_initial_state(label, cfg):
     announce("fused_steps", label)
     prob, (T, R) = oracle_for(cfg)
