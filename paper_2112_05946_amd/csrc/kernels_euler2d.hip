@@ -178,6 +178,9 @@ constexpr int TX = 4, TY = 2;
 constexpr int TE = TX * TY;          // elements per tile
 constexpr int BLKS = 32 * TE;        // threads per stage workgroup
 constexpr int NHF = 2 * (TX + TY);   // element faces on the tile boundary
+#ifndef FRSG_FP32_WAVES
+#define FRSG_FP32_WAVES 2  // waves per SIMD the FP32 node loop is compiled for (3 spills)
+#endif
 static_assert(BLKS % 64 == 0, "an element's 32 lanes must share a wave");
 
 // value held by the partner lane (same point, other pair of variables): the
@@ -445,7 +448,7 @@ __device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsig
 // residuals, projection), the epilogue runs in FP64
 // ---------------------------------------------------------------------------
 template <int M, int NQ, typename R>
-__global__ void __launch_bounds__(BLKS) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 2 : 3)))
+__global__ void __launch_bounds__(BLKS) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 2 : FRSG_FP32_WAVES)))
 k_stage2d(KParams P, StageArgs A, const double* __restrict__ Phi,
                                                   const R* __restrict__ PhiT, const R* __restrict__ PWT,
                                                   const double* __restrict__ in, const double* __restrict__ uin,
@@ -469,10 +472,21 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ Phi,
   const int ntx = P.nx / TX;
   // XCD-aware order: consecutive workgroups go to different XCDs, so give each
   // XCD a contiguous band of tiles (neighbouring halos then share its L2)
-  const int ntiles = ntx * (P.ny / TY);
+  const int nty = P.ny / TY, ntiles = ntx * nty;
   int tile = blockIdx.x;
   if (ntiles % 8 == 0) tile = (tile % 8) * (ntiles / 8) + tile / 8;
-  const int tx = tile % ntx, ty = tile / ntx;
+  // within that order, walk blocks of 8 x 8 tiles: the tiles resident on an XCD
+  // at one time then form a compact block, most of whose halo faces are read by
+  // tiles of the same block while the data is in L2
+  int tx, ty;
+  if (ntx % 8 == 0 && nty % 8 == 0) {
+    const int blk = tile >> 6, w = tile & 63, nbx = ntx / 8;
+    tx = (blk % nbx) * 8 + (w & 7);
+    ty = (blk / nbx) * 8 + (w >> 3);
+  } else {
+    tx = tile % ntx;
+    ty = tile / ntx;
+  }
   const int ix = TX * tx + lx, iy = TY * ty + ly;
   const int e = iy * P.nx + ix;
   const long EN = (long)P.E * NSP;
@@ -581,6 +595,7 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ Phi,
   // the neighbour's flux point facing ours: x-lo <-> x-hi, y-lo <-> y-hi
   const int mirror = (fside ^ 1) * 4 + fi;
   const bool lo_side = (fside == 0 || fside == 2);
+  const bool wave_at_boundary = __ballot(boundary) != 0;
 
   R acc[2][M];
 #pragma unroll
@@ -630,11 +645,13 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ Phi,
       const Pair2<R> o0 = sT[par][le][j][0], o1 = sT[par][le][j][1], n0 = src[0], n1 = src[1];
       own[0] = o0.x; own[1] = o0.y; own[2] = o1.x; own[3] = o1.y;
       nb[0] = n0.x; nb[1] = n0.y; nb[2] = n1.x; nb[3] = n1.y;
+      if (wave_at_boundary) {  // uniform: only waves with a domain-boundary face pay for the ghosts
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        R gh = (gkind == FRSG_BC_DIRICHLET) ? gstate[s] : own[s];
-        if (gkind == FRSG_BC_REFLECT && s == gnormal) gh = -gh;
-        nb[s] = boundary ? gh : nb[s];
+        for (int s = 0; s < 4; ++s) {
+          R gh = (gkind == FRSG_BC_DIRICHLET) ? gstate[s] : own[s];
+          if (gkind == FRSG_BC_REFLECT && s == gnormal) gh = -gh;
+          nb[s] = boundary ? gh : nb[s];
+        }
       }
       R Fs[4];
       rusanov_e2(own, nb, lo_side, Fs, g, fside >> 1);
@@ -712,10 +729,17 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ Phi,
 
   // CFL maximum of the new state for the next step
   if (A.stage == 3 && A.lam_next) {
-    const double gd = P.gamma;
-    double rate = 0.0;
-    for (int q = 0; q < NQ; ++q) {
-      double u2[2];
+    const double gd = P.gamma, idx = 1.0 / P.dx, idy = 1.0 / P.dy;
+    // (|vx| + c) / dx + (|vy| + c) / dy at one node; NaN counts as infinity
+    auto node_rate = [&](const double* U) {
+      const double ir = recip(U[0]);
+      const double vx = U[1] * ir, vy = U[2] * ir;
+      const double p = (gd - 1.0) * (U[3] - 0.5 * (U[1] * vx + U[2] * vy));
+      const double c = sqrt(gd * p * ir);
+      const double r = (fabs(vx) + c) * idx + (fabs(vy) + c) * idy;
+      return (r == r) ? r : __longlong_as_double(0x7ff0000000000000ll);
+    };
+    auto nodal = [&](int q, double* u2) {
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         double t = 0.0;
@@ -723,11 +747,27 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ Phi,
         for (int k = 0; k < M; ++k) t += o[i][k] * Phi[k * NQ + q];
         u2[i] = t;
       }
-      double U[4];
-      full4(h, u2[0], u2[1], U);
-      double r = speed<kEuler2, 0>(U, 0.0, gd) / P.dx + speed<kEuler2, 1>(U, 0.0, gd) / P.dy;
-      if (!(r == r)) r = __longlong_as_double(0x7ff0000000000000ll);
-      rate = fmax(rate, r);
+    };
+    double rate = 0.0;
+    // nodes in pairs: lane h = 0 completes node q, lane h = 1 node q + 1, each
+    // taking the partner's pair of variables at its node
+    int q = 0;
+    for (; q + 1 < NQ; q += 2) {
+      double a2[2], b2[2], U[4];
+      nodal(q, a2);
+      nodal(q + 1, b2);
+      const double r0 = other_half(h ? a2[0] : b2[0]), r1 = other_half(h ? a2[1] : b2[1]);
+      U[0] = h ? r0 : a2[0];
+      U[1] = h ? r1 : a2[1];
+      U[2] = h ? b2[0] : r0;
+      U[3] = h ? b2[1] : r1;
+      rate = fmax(rate, node_rate(U));
+    }
+    if (q < NQ) {
+      double a2[2], U[4];
+      nodal(q, a2);
+      full4(h, a2[0], a2[1], U);
+      rate = fmax(rate, node_rate(U));
     }
     for (int w = 32; w > 0; w >>= 1) rate = fmax(rate, __shfl_xor(rate, w));
     if ((tid & 63) == 0) sRed[tid >> 6] = rate;
