@@ -139,6 +139,61 @@ def roofline_for(passes, precision):
             "alg_bytes_per_launch": alg, "avg_launch_ms": avg_s * 1e3, "launches": launches}
 
 
+def adjoint_cost(torch, Solver, inputs):
+    """Adjoint/forward cost on the 4096-element Burgers problem (p = 3, 9 modes, 16 nodes):
+    500 steps at the CFL step of the initial state, held fixed."""
+    from paper_2112_05946_amd.adjoint import AdjointSolve, mean_square
+    cfg = inputs.BURGERS_ADJOINT
+    n, k = int(cfg["n_steps"]), int(cfg["checkpoint_every"])
+    sol = Solver(cfg)
+    u0 = sol.initial_state()
+    u = u0.clone()
+    dtd, flags = sol.step(u)
+    dt = float(dtd.item())
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    dts = torch.empty(1, dtype=torch.float64, device=u.device)
+    fl = torch.empty(4 * sol.E, dtype=torch.uint8, device=u.device)
+
+    def fwd():
+        for _ in range(n):
+            sol.step(u, dt, dts, fl)
+    fwd()  # warm-up
+    u.copy_(u0)
+    t_fwd = timed(fwd) / n
+    lam = torch.randn_like(u0)
+
+    def adj():
+        for _ in range(n):
+            sol.adjoint_step(u0, flags, dt, lam)
+    adj()
+    t_adj = timed(adj) / n
+    params = torch.tensor([0.0, float(cfg["gamma"]) if "gamma" in cfg else 1.4], dtype=torch.float64)
+
+    def grad():
+        x = u0.clone().requires_grad_(True)
+        J = mean_square(AdjointSolve.apply(x, params, sol, n, dt, k), sol)
+        J.backward()
+    grad()
+    t_grad = timed(grad) / n
+    sol.close()
+    dof = int(sol.info["n_dof"])
+    return {"workload": "burgers_adjoint %d elements, p=%d, %d modes, %d nodes, %d DOF, %d steps, checkpoint every %d"
+                        % (cfg["nx"], cfg["p"], sol.shape[1], sol.info["n_nodes"], dof, n, k),
+            "forward_ms_per_step": t_fwd, "adjoint_step_ms": t_adj, "adjoint_over_forward": t_adj / t_fwd,
+            "gradient_ms_per_step": t_grad, "gradient_over_forward": t_grad / t_fwd,
+            "note": "gradient = forward with checkpoints + backward (segment recompute + adjoint steps), per step"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +203,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-mixed comparison run")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost run")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the multi-GPU halo exchange is not built); "
@@ -193,6 +249,8 @@ def main():
                  "passes_ms_per_step": {k: v[1] / args.steps for k, v in p32.items()}}
         sol32.close()
 
+    adjoint = None if args.no_adjoint else adjoint_cost(torch, Solver, inputs)
+
     out = {
         "metric": METRIC, "value": value, "unit": "DOF-updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
@@ -204,6 +262,7 @@ def main():
         "roofline": roofline,
         "passes_ms_per_step": {k: v[1] / args.steps for k, v in passes.items()},
         "fp32_mixed": other,
+        "adjoint": adjoint,
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:

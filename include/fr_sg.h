@@ -177,6 +177,29 @@ fr_sg_status fr_sg_step(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, u
  * or NULL, laid out per step as in fr_sg_step. */
 fr_sg_status fr_sg_steps(fr_sg_ctx* ctx, double* u, int32_t nsteps, double* dt_used, uint8_t* flags);
 
+/* Discrete adjoint of one fr_sg_step (the paper has no adjoint; this is the
+ * exact transpose of the step as computed here: Sec. 3.2-3.4 right-hand side,
+ * the SSP-RK3 stages, the Sec. 4.1 filter) at frozen switch decisions and
+ * frozen dt:
+ *   lam <- (d u_{n+1} / d u_n)^T lam,
+ * where u_{n+1} = fr_sg_step(u_n, dt) produced the filter flags flags_n.  The
+ * stage states are recomputed from u_n with the forward passes.  The
+ * Lax-Friedrichs dissipation speed is differentiated through the side that
+ * attains the maximum.  Covers the scalar 1D equations (advection, Burgers);
+ * other problems return FRSG_EUNSUPPORTED.
+ * u_n: device state at the start of the step (not modified).
+ * flags_n: device uint8[4*E] of that step as written by fr_sg_step (row 2,
+ *   the filter decisions, is used); may be NULL when the problem has no filter.
+ * dt: the step's dt (> 0), as returned in dt_used.
+ * lam: device state-shaped array; in: adjoint of u_{n+1}, out: adjoint of u_n.
+ *   Must not alias u_n.
+ * dparams: device double[2] or NULL; [0] += d<lam_{n+1}, u_{n+1}>/d adv_speed
+ *   at fixed u_n and dt (zero for Burgers), [1] (gamma) is left unchanged.
+ * Asynchronous on the context's stream; uses the context's workspace, so calls
+ * on one context must not overlap. */
+fr_sg_status fr_sg_adjoint_step(fr_sg_ctx* ctx, const double* u_n, const uint8_t* flags_n, double dt, double* lam,
+                                double* dparams);
+
 /* Synchronise the stream and return (then clear) the latched device status:
  * FRSG_OK, FRSG_ENONFINITE or FRSG_ENOTREALIZABLE. */
 fr_sg_status fr_sg_sync(fr_sg_ctx* ctx);

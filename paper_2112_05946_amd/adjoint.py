@@ -1,0 +1,83 @@
+"""Reverse-mode differentiation of a run of FR-SG steps through the library's
+discrete adjoint (fr_sg_adjoint_step), with checkpointing.
+
+AdjointSolve.apply(u0, params, solver, n_steps, dt, k) runs n_steps SSP-RK3
+steps from u0 and returns u_T; its backward returns dJ/du0 and dJ/dparams for
+any scalar J of u_T built with torch.  params = [adv_speed, gamma] must be the
+solver's problem values (the steps use those); dt is fixed (None: the CFL step
+of each forward step, then held frozen in the backward pass).
+
+Checkpointing: the state is kept every k steps; the backward pass walks the
+segments in reverse, recomputes each segment's step-start states from its
+checkpoint with the same forward steps (bitwise the same arithmetic), then
+applies the adjoint steps in reverse.  Memory: n_steps/k + k states.
+
+Switch decisions (the detector's filter flags) and dt are those of the forward
+run; the derivative is that of the discrete map at those decisions.
+"""
+
+import math
+
+import numpy as np
+import torch
+
+
+class AdjointSolve(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, u0, params, solver, n_steps, dt=None, k=25):
+        pv = params.detach().cpu().numpy()
+        want = np.array([float(solver.cfg.get("adv_speed", 0.0)), float(solver.cfg.get("gamma", 1.4))])
+        if solver.cfg.get("equation") == "advection" and pv[0] != want[0]:
+            raise ValueError("params[0] must equal the solver's advection speed %r" % want[0])
+        k = max(1, int(k))
+        n = int(n_steps)
+        dev = u0.device
+        u = u0.detach().contiguous().clone()
+        flags = torch.empty((max(n, 1), 4 * solver.E), dtype=torch.uint8, device=dev)
+        dts = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+        ckpts = []
+        for i in range(n):
+            if i % k == 0:
+                ckpts.append(u.clone())
+            solver.step(u, dt, dts[i:i + 1], flags[i])
+        ctx.solver, ctx.n, ctx.k = solver, n, k
+        ctx.params_device = params.device
+        ctx.ckpts = ckpts
+        ctx.save_for_backward(flags, dts)
+        return u
+
+    @staticmethod
+    def backward(ctx, grad_u):
+        flags, dts = ctx.saved_tensors
+        solver, n, k = ctx.solver, ctx.n, ctx.k
+        lam = grad_u.detach().to(torch.float64).contiguous().clone()
+        dparams = torch.zeros(2, dtype=torch.float64, device=lam.device)
+        dt_host = dts.cpu().numpy()
+        scratch_dt = torch.empty(1, dtype=torch.float64, device=lam.device)
+        scratch_fl = torch.empty(4 * solver.E, dtype=torch.uint8, device=lam.device)
+        nseg = math.ceil(n / k)
+        for seg in reversed(range(nseg)):
+            start, end = seg * k, min(seg * k + k, n)
+            states = [ctx.ckpts[seg]]
+            u = ctx.ckpts[seg].clone()
+            for i in range(start, end - 1):
+                solver.step(u, float(dt_host[i]), scratch_dt, scratch_fl)
+                states.append(u.clone())
+            for i in reversed(range(start, end)):
+                solver.adjoint_step(states[i - start], flags[i], float(dt_host[i]), lam, dparams)
+        ctx.ckpts = None
+        return lam, dparams.to(ctx.params_device), None, None, None, None
+
+
+def quadrature_weights(solver):
+    """Legendre-Gauss weights of the solver's solution points (sum 2)."""
+    _, w = np.polynomial.legendre.leggauss(int(solver.cfg["p"]) + 1)
+    return torch.from_numpy(w).to(solver.device)
+
+
+def mean_square(u, solver):
+    """J = sum_e J_e sum_j w_j sum_k u[0, k, e, j]^2: the space integral of E[u^2]
+    (= E[u]^2 + Var[u]) for orthonormal chaos; 1D."""
+    dx = (float(solver.cfg["xhi"]) - float(solver.cfg["xlo"])) / int(solver.cfg["nx"])
+    w = quadrature_weights(solver)
+    return 0.5 * dx * torch.sum(u[0] * u[0] * w)

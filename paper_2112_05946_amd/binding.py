@@ -72,6 +72,7 @@ SYMBOLS = [
     ("fr_sg_rhs", ctypes.c_int32, [_VP, _VP, _VP]),
     ("fr_sg_step", ctypes.c_int32, [_VP, _VP, ctypes.c_double, _VP, _VP]),
     ("fr_sg_steps", ctypes.c_int32, [_VP, _VP, ctypes.c_int32, _VP, _VP]),
+    ("fr_sg_adjoint_step", ctypes.c_int32, [_VP, _VP, _VP, ctypes.c_double, _VP, _VP]),
     ("fr_sg_sync", ctypes.c_int32, [_VP]),
     ("fr_sg_timing_enable", ctypes.c_int32, [_VP, ctypes.c_int32]),
     ("fr_sg_timing_read", ctypes.c_int32, [_VP, ctypes.POINTER(PassTime), ctypes.c_int32,
@@ -241,6 +242,22 @@ class Solver:
         """nsteps in-place CFL steps; the CFL maximum of each later step comes from the step before."""
         self._state(u, "u")
         self._check(self.lib.fr_sg_steps(self._ctx, _ptr(u), int(nsteps), _ptr(dt_used), _ptr(flags)))
+
+    def adjoint_step(self, u_n, flags_n, dt, lam, dparams=None):
+        """lam <- (d u_{n+1}/d u_n)^T lam at the step's filter flags and dt (in place);
+        dparams (device float64[2] or None) accumulates d/d(adv_speed, gamma)."""
+        self._state(u_n, "u_n")
+        self._state(lam, "lam")
+        torch = self._torch
+        if flags_n is not None and (flags_n.dtype != torch.uint8 or flags_n.numel() != 4 * self.E
+                                    or flags_n.device != self.device or not flags_n.is_contiguous()):
+            raise ValueError("flags_n must be a contiguous uint8 device tensor of 4*E entries")
+        if dparams is not None and (dparams.dtype != torch.float64 or dparams.numel() != 2
+                                    or dparams.device != self.device):
+            raise ValueError("dparams must be a float64 device tensor of 2 entries")
+        self._check(self.lib.fr_sg_adjoint_step(self._ctx, _ptr(u_n), _ptr(flags_n), float(dt), _ptr(lam),
+                                                _ptr(dparams)))
+        return lam
 
     def timing(self, enable=True):
         self._check(self.lib.fr_sg_timing_enable(self._ctx, 1 if enable else 0))

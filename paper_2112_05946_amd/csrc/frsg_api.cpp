@@ -311,7 +311,22 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
   size_t o_gn = align_up(o_fn + nodal * 8);
   size_t o_co = align_up(o_gn + (c->dim == 2 ? nodal * 8 : 0));
   size_t o_sc = align_up(o_co + corr * 8);
-  size_t total = align_up(o_sc + 256);
+  // adjoint buffers, for the problems the adjoint covers (scalar 1D)
+  const bool adj = c->dim == 1 && c->S == 1;
+  size_t nadj_part = 0;
+  if (adj) {
+    KParams probe;
+    std::memset(&probe, 0, sizeof(probe));
+    probe.E = c->E;
+    probe.Nq = T.Nq;
+    nadj_part = (size_t)adjoint_partials(probe);
+  }
+  size_t o_avb = align_up(o_sc + 256);
+  size_t o_ab2 = align_up(o_avb + (adj ? state * 8 : 0));
+  size_t o_ab1 = align_up(o_ab2 + (adj ? state * 8 : 0));
+  size_t o_agt = align_up(o_ab1 + (adj ? state * 8 : 0));
+  size_t o_apt = align_up(o_agt + (adj ? (size_t)T.Nq * c->E * 2 * 8 : 0));
+  size_t total = align_up(o_apt + nadj_part * 8);
   char* ws = nullptr;
   he = hipMalloc(&ws, total);
   if (he != hipSuccess) {
@@ -337,6 +352,13 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
   c->ws.Gn = c->dim == 2 ? (double*)(ws + o_gn) : nullptr;
   c->ws.Corr = (double*)(ws + o_co);
   c->ws.scal = (double*)(ws + o_sc);
+  if (adj) {
+    c->ws.avb = (double*)(ws + o_avb);
+    c->ws.ab2 = (double*)(ws + o_ab2);
+    c->ws.ab1 = (double*)(ws + o_ab1);
+    c->ws.agT = (double*)(ws + o_agt);
+    c->ws.apart = (double*)(ws + o_apt);
+  }
   c->ws.bytes = total + blob.size() * sizeof(double);
 
   KParams& K = c->kp;
@@ -586,6 +608,70 @@ fr_sg_status fr_sg_steps(fr_sg_ctx* ctx, double* u, int32_t nsteps, double* dt_u
     if (st != FRSG_OK) return st;
   }
   return FRSG_OK;
+}
+
+fr_sg_status fr_sg_adjoint_step(fr_sg_ctx* ctx, const double* u_n, const uint8_t* flags_n, double dt, double* lam,
+                                double* dparams) {
+  if (!ctx) return FRSG_EINVAL;
+  if (!ctx->ws.avb) {
+    ctx->err = "the adjoint covers the scalar 1D equations (advection, Burgers) only";
+    return FRSG_EUNSUPPORTED;
+  }
+  if (!u_n || !lam || u_n == lam) {
+    ctx->err = "u_n and lam must be distinct device pointers";
+    return FRSG_EINVAL;
+  }
+  if (!(dt > 0.0) || !std::isfinite(dt)) {
+    ctx->err = "dt must be positive and finite";
+    return FRSG_EINVAL;
+  }
+  if (ctx->prob.filter != FRSG_FILTER_NONE && !flags_n) {
+    ctx->err = "flags_n is needed: the filter decisions of the forward step";
+    return FRSG_EINVAL;
+  }
+  const KParams& K = ctx->kp;
+  Workspace& W = ctx->ws;
+  hipStream_t s = ctx->stream;
+  const double sb = state_bytes(ctx);
+  fr_sg_status st;
+  FRSG_TRY_HIP(launch_set_scalars(K, dt, s), ctx);
+  // stage states of the forward step, recomputed with the forward passes (no
+  // limiter: the scalar equations do not use it)
+  if ((st = rhs_passes(ctx, u_n, 0)) != FRSG_OK) return st;
+  if ((st = timed(ctx, "adj_fwd_stage1", 2 * sb,
+                  [&] { return launch_project_stage(K, W.Un, u_n, u_n, W.w1, 0.0, 1.0, 0, s); })))
+    return st;
+  if ((st = rhs_passes(ctx, W.w1, 0)) != FRSG_OK) return st;
+  if ((st = timed(ctx, "adj_fwd_stage2", 3 * sb,
+                  [&] { return launch_project_stage(K, W.Un, u_n, W.w1, W.w2, 0.75, 0.25, 0, s); })))
+    return st;
+  // u+ = Filter(v): vb = Filter^T lam
+  if (ctx->prob.filter != FRSG_FILTER_NONE) {
+    if ((st = timed(ctx, "adj_filter", 2 * sb,
+                    [&] { return launch_filter_adjoint(K, lam, flags_n + 2 * (long)ctx->E, W.avb, s); })))
+      return st;
+  } else {
+    FRSG_TRY_HIP(hipMemcpyAsync(W.avb, lam, (size_t)sb, hipMemcpyDeviceToDevice, s), ctx);
+  }
+  // one transposed right-hand side: nodal values of the state, then the adjoint passes
+  auto vjp = [&](const char* name, const double* w, const double* g, const double* x0, const double* x1,
+                 const double* x2, double* out, double c0, double c1, double c2, double cg, double pscale) {
+    fr_sg_status r = timed(ctx, "adj_nodal", sb, [&] { return launch_nodal(K, w, W.Un, W.Fn, W.Gn, 0, s); });
+    if (r != FRSG_OK) return r;
+    return timed(ctx, name, 3 * sb, [&] {
+      return launch_rhs_adjoint(K, W.Un, g, W.Fn, W.Corr, W.agT, x0, x1, x2, out, c0, c1, c2, cg, W.apart, pscale,
+                                dparams, s);
+    });
+  };
+  // v = u/3 + 2/3 (w2 + dt R(w2)):   b2 = 2/3 vb + 2/3 dt R'(w2)^T vb
+  if ((st = vjp("adj_stage3", W.w2, W.avb, W.avb, nullptr, nullptr, W.ab2, 2.0 / 3.0, 0.0, 0.0, 2.0 / 3.0 * dt,
+                2.0 / 3.0 * dt)))
+    return st;
+  // w2 = 3/4 u + 1/4 (w1 + dt R(w1)):  b1 = 1/4 b2 + 1/4 dt R'(w1)^T b2
+  if ((st = vjp("adj_stage2", W.w1, W.ab2, W.ab2, nullptr, nullptr, W.ab1, 0.25, 0.0, 0.0, 0.25 * dt, 0.25 * dt)))
+    return st;
+  // w1 = u + dt R(u):  lam_n = vb/3 + 3/4 b2 + b1 + dt R'(u)^T b1
+  return vjp("adj_stage1", u_n, W.ab1, W.avb, W.ab2, W.ab1, lam, 1.0 / 3.0, 0.75, 1.0, dt, dt);
 }
 
 fr_sg_status fr_sg_sync(fr_sg_ctx* ctx) {

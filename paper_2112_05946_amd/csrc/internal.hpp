@@ -91,6 +91,12 @@ struct Workspace {
   double* Gn = nullptr;    // [S][Nq][E][nsp] nodal y-flux (2D)
   double* Corr = nullptr;  // [S][Nq][E][nface] interface-flux minus interpolated flux
   double* scal = nullptr;  // scalars: dt, lam bits, status
+  // adjoint (scalar 1D problems): stage adjoints, trace adjoints, partial sums
+  double* avb = nullptr;   // adjoint of the unfiltered end-of-step state
+  double* ab2 = nullptr;   // adjoint of w2
+  double* ab1 = nullptr;   // adjoint of w1
+  double* agT = nullptr;   // [Nq][E][2] adjoints of the traces at r = -1, +1
+  double* apart = nullptr; // per-block partial sums of the parameter derivative
   size_t bytes = 0;
 };
 
@@ -178,4 +184,13 @@ hipError_t launch_limiter(const KParams& P, double* u, unsigned char* flags, hip
 hipError_t launch_sensor_filter(const KParams& P, double* u, unsigned char* flags, hipStream_t s);
 hipError_t launch_fill_flags(unsigned char* flags, long n, hipStream_t s);
 hipError_t launch_copy_dt(const KParams& P, double* dt_used, hipStream_t s);
+
+// adjoint launchers (kernels_adjoint.hip)
+long adjoint_partials(const KParams& P);
+hipError_t launch_rhs_adjoint(const KParams& P, const double* Un, const double* g, double* GU, double* Gside,
+                              double* gT, const double* x0, const double* x1, const double* x2, double* out,
+                              double c0, double c1, double c2, double cg, double* part, double param_scale,
+                              double* dparam, hipStream_t s);
+hipError_t launch_filter_adjoint(const KParams& P, const double* g, const unsigned char* flags, double* out,
+                                 hipStream_t s);
 }  // namespace frsg

@@ -1,0 +1,286 @@
+// Discrete adjoint of the FR-SG step for the scalar 1D equations (linear
+// advection, Burgers): the transpose of the right-hand side at a given state,
+// applied to an adjoint vector, and the transpose of the detector-switched
+// modal filter at frozen flags.
+//
+// The forward right-hand side (Sec. 3.2-3.4, evaluated per random node and
+// Galerkin-projected, Sec. 2.1 Eq. discrete expectation value) is
+//
+//   R_k = sum_q PW[k,q] Rn_q,
+//   Rn_q[j] = -(1/J) ( sum_l Dt[j,l] f(U_q[l]) + F*_L,q h_L'(r_j) + F*_R,q h_R'(r_j) ),
+//   U_q[j] = sum_k Phi[k,q] u_k[j],   Dt = D - h_L' l(-1)^T - h_R' l(+1)^T,
+//
+// with F* the Lax-Friedrichs flux of the two traces at each face and node.
+// Its transpose applied to g is assembled in three passes:
+//
+//   adj_node  (q, e):   gR = PW^T g, d = -gR / J;  GL = h_L'.d, GR = h_R'.d
+//                       (adjoints of the element's left / right interface flux),
+//                       GU[l] = f'(U[l]) sum_j Dt[j,l] d[j];
+//   adj_face  (q, e):   transposed Lax-Friedrichs flux at the element's two faces
+//                       (adjoint of the face flux = GL of the element on the right
+//                       plus GR of the element on the left), giving the adjoints
+//                       gTm, gTp of the element's traces at r = -1, +1;
+//   adj_project (k, e, j): g_u = sum_q Phi[k,q] (GU + l_j(-1) gTm + l_j(+1) gTp),
+//                       combined with up to three vectors for the SSP-RK3 chain.
+//
+// The dissipation speed max(|f'(L)|, |f'(R)|) is differentiated through the
+// side attaining it (the left one on a tie).  The derivative with respect to the
+// advection speed is reduced per block and added, scaled, into one scalar.
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace frsg {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kMaxNp = 8;  // FR degree <= 7
+
+inline unsigned grid_for(long n, int block = kBlock) { return (unsigned)((n + block - 1) / block); }
+
+__device__ __forceinline__ double sgn(double x) { return (double)((x > 0.0) - (x < 0.0)); }
+
+// f'(U) of the scalar flux
+template <int EQ>
+__device__ __forceinline__ double dflux(double U, double adv) {
+  if constexpr (EQ == kAdvection) return adv;
+  else return U;
+}
+
+// transpose of F = (f(L) + f(R))/2 - lam (R - L)/2 applied to g; also d/da of g F
+template <int EQ>
+__device__ __forceinline__ void rusanov_adj(double L, double R, double g, double adv, double& gL, double& gR,
+                                            double& da) {
+  if constexpr (EQ == kAdvection) {
+    const double aa = fabs(adv);
+    gL = 0.5 * adv * g + 0.5 * aa * g;
+    gR = 0.5 * adv * g - 0.5 * aa * g;
+    da = g * (0.5 * (L + R) - 0.5 * sgn(adv) * (R - L));
+  } else {
+    const double sL = fabs(L), sR = fabs(R);
+    const double lam = fmax(sL, sR);
+    const double dlam = -0.5 * (R - L) * g;
+    gL = 0.5 * L * g + 0.5 * lam * g;
+    gR = 0.5 * R * g - 0.5 * lam * g;
+    if (sL >= sR)
+      gL += sgn(L) * dlam;
+    else
+      gR += sgn(R) * dlam;
+    da = 0.0;
+  }
+}
+
+// transpose of the ghost trace of a boundary side (outflow: copy, Dirichlet: constant)
+__device__ __forceinline__ double ghost_adj(const KParams& P, int side, double g) {
+  return P.bc[side] == FRSG_BC_OUTFLOW ? g : 0.0;
+}
+
+// ghost value of a boundary side for a scalar interior trace
+__device__ __forceinline__ double ghost_val(const KParams& P, int side, double t) {
+  return P.bc[side] == FRSG_BC_DIRICHLET ? P.bc_state[side][0] : t;
+}
+
+// ---------------------------------------------------------------------------
+// (q, e): nodal adjoint of the residual
+// ---------------------------------------------------------------------------
+template <int EQ>
+__global__ void __launch_bounds__(kBlock) k_adj_node(KParams P, const double* __restrict__ Un,
+                                                     const double* __restrict__ g, double* __restrict__ GU,
+                                                     double* __restrict__ Gside, double* __restrict__ part) {
+  __shared__ double sm[kBlock];
+  const int E = P.E, n = P.np1, Nq = P.Nq, M = P.M;
+  const long t = blockIdx.x * (long)kBlock + threadIdx.x;
+  double pa = 0.0;
+  if (t < (long)Nq * E) {
+    const int q = (int)(t / E), e = (int)(t - (long)q * E);
+    const long EN = (long)E * n;
+    double d[kMaxNp];
+    for (int j = 0; j < n; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < M; ++k) acc += P.tab.PW[k * Nq + q] * g[(long)k * EN + (long)e * n + j];
+      d[j] = -acc / P.Jx;
+    }
+    double GL = 0.0, GR = 0.0;
+    for (int j = 0; j < n; ++j) {
+      GL += P.tab.dhL[j] * d[j];
+      GR += P.tab.dhR[j] * d[j];
+    }
+    const double* U = Un + ((long)q * E + e) * n;
+    double* out = GU + ((long)q * E + e) * n;
+    for (int l = 0; l < n; ++l) {
+      double gF = 0.0;
+      for (int j = 0; j < n; ++j) gF += P.tab.D[j * n + l] * d[j];
+      gF = gF - P.tab.lL[l] * GL - P.tab.lR[l] * GR;
+      out[l] = dflux<EQ>(U[l], P.adv) * gF;
+      if constexpr (EQ == kAdvection) pa += gF * U[l];
+    }
+    Gside[((long)q * E + e) * 2 + 0] = GL;
+    Gside[((long)q * E + e) * 2 + 1] = GR;
+  }
+  if (part) {
+    const double s = block_reduce_sum(pa, sm);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// (q, e): transposed interface fluxes at the element's two faces
+// ---------------------------------------------------------------------------
+template <int EQ>
+__global__ void __launch_bounds__(kBlock) k_adj_face(KParams P, const double* __restrict__ Un,
+                                                     const double* __restrict__ Gside, double* __restrict__ gT,
+                                                     double* __restrict__ part) {
+  __shared__ double sm[kBlock];
+  const int E = P.E, n = P.np1, Nq = P.Nq;
+  const long t = blockIdx.x * (long)kBlock + threadIdx.x;
+  double pa = 0.0;
+  if (t < (long)Nq * E) {
+    const int q = (int)(t / E), e = (int)(t - (long)q * E);
+    const bool periodic = P.bc[0] == FRSG_BC_PERIODIC;
+    auto tr = [&](int el, const double* l) {
+      const double* U = Un + ((long)q * E + el) * n;
+      double acc = 0.0;
+      for (int j = 0; j < n; ++j) acc += l[j] * U[j];
+      return acc;
+    };
+    auto side = [&](int el, int s) { return Gside[((long)q * E + el) * 2 + s]; };
+    const double Tm = tr(e, P.tab.lL), Tp = tr(e, P.tab.lR);
+    double gTm, gTp;
+    {  // left face of e
+      const bool interior = e > 0 || periodic;
+      const int el = e > 0 ? e - 1 : E - 1;
+      const double UL = interior ? tr(el, P.tab.lR) : ghost_val(P, 0, Tm);
+      const double gF = side(e, 0) + (interior ? side(el, 1) : 0.0);
+      double gL, gR, da;
+      rusanov_adj<EQ>(UL, Tm, gF, P.adv, gL, gR, da);
+      gTm = gR + (interior ? 0.0 : ghost_adj(P, 0, gL));
+      pa += da;
+    }
+    {  // right face of e
+      const bool interior = e < E - 1 || periodic;
+      const int er = e < E - 1 ? e + 1 : 0;
+      const double UR = interior ? tr(er, P.tab.lL) : ghost_val(P, 1, Tp);
+      const double gF = side(e, 1) + (interior ? side(er, 0) : 0.0);
+      double gL, gR, da;
+      rusanov_adj<EQ>(Tp, UR, gF, P.adv, gL, gR, da);
+      gTp = gL + (interior ? 0.0 : ghost_adj(P, 1, gR));
+      if (!interior) pa += da;  // the last face of a non-periodic mesh has no element on its right
+    }
+    gT[((long)q * E + e) * 2 + 0] = gTm;
+    gT[((long)q * E + e) * 2 + 1] = gTp;
+  }
+  if (part) {
+    const double s = block_reduce_sum(pa, sm);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// (k, e, j): back to the modes, combined with the SSP-RK3 chain
+//   out = c0 x0 + c1 x1 + c2 x2 + cg * (dR/du)^T g
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_adj_project(KParams P, const double* __restrict__ GU,
+                                                        const double* __restrict__ gT, const double* x0,
+                                                        const double* x1, const double* x2, double* out, double c0,
+                                                        double c1, double c2, double cg) {
+  const int E = P.E, n = P.np1, Nq = P.Nq, M = P.M;
+  const long EN = (long)E * n;
+  const long t = blockIdx.x * (long)kBlock + threadIdx.x;
+  if (t >= (long)M * EN) return;
+  const int k = (int)(t / EN);
+  const long ej = t - (long)k * EN;
+  const int e = (int)(ej / n), j = (int)(ej - (long)e * n);
+  const double lLj = P.tab.lL[j], lRj = P.tab.lR[j];
+  double acc = 0.0;
+  for (int q = 0; q < Nq; ++q) {
+    const long qe = (long)q * E + e;
+    acc += P.tab.Phi[k * Nq + q] * (GU[qe * n + j] + lLj * gT[qe * 2 + 0] + lRj * gT[qe * 2 + 1]);
+  }
+  double v = cg * acc;
+  if (x0) v += c0 * x0[t];
+  if (x1) v += c1 * x1[t];
+  if (x2) v += c2 * x2[t];
+  out[t] = v;
+}
+
+// dparam[0] += scale * (sum of the partial sums), one thread, fixed order
+__global__ void k_adj_param(const double* __restrict__ part, int n, double scale, double* dparam) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += part[i];
+  dparam[0] += scale * s;
+}
+
+// ---------------------------------------------------------------------------
+// transposed filter on the flagged elements, identity elsewhere (Sec. 4.1 at
+// frozen switches): out = V^-T diag(Lambda) V^T g per chaos mode
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_filter_adj(KParams P, const double* __restrict__ g,
+                                                       const unsigned char* __restrict__ flags, double* out) {
+  const int E = P.E, n = P.np1, M = P.M;
+  const long EN = (long)E * n;
+  const long t = blockIdx.x * (long)kBlock + threadIdx.x;
+  if (t >= (long)M * E) return;
+  const int k = (int)(t / E), e = (int)(t - (long)k * E);
+  const double* src = g + (long)k * EN + (long)e * n;
+  double* dst = out + (long)k * EN + (long)e * n;
+  if (!flags[e]) {
+    for (int j = 0; j < n; ++j) dst[j] = src[j];
+    return;
+  }
+  const double dt = *P.dt;
+  double x[kMaxNp];
+  for (int l = 0; l < n; ++l) {  // Lambda (V^T g)
+    double acc = 0.0;
+    for (int j = 0; j < n; ++j) acc += P.tab.V[j * n + l] * src[j];
+    const double f = P.tab.filt[k * n + l];
+    x[l] = acc * (P.filter == FRSG_FILTER_EXP ? exp(-P.alpha * dt * f) : f);
+  }
+  for (int l = 0; l < n; ++l) {  // V^-T x
+    double acc = 0.0;
+    for (int m = 0; m < n; ++m) acc += P.tab.Vinv[m * n + l] * x[m];
+    dst[l] = acc;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+long adjoint_partials(const KParams& P) { return 2 * (long)grid_for((long)P.Nq * P.E); }
+
+hipError_t launch_rhs_adjoint(const KParams& P, const double* Un, const double* g, double* GU, double* Gside,
+                              double* gT, const double* x0, const double* x1, const double* x2, double* out,
+                              double c0, double c1, double c2, double cg, double* part, double param_scale,
+                              double* dparam, hipStream_t s) {
+  const long nqe = (long)P.Nq * P.E;
+  const unsigned gq = grid_for(nqe);
+  const bool want = P.eq == kAdvection && dparam && part;
+  double* p0 = want ? part : nullptr;
+  double* p1 = want ? part + gq : nullptr;
+  if (P.eq == kAdvection) {
+    hipLaunchKernelGGL(k_adj_node<kAdvection>, dim3(gq), dim3(kBlock), 0, s, P, Un, g, GU, Gside, p0);
+    hipLaunchKernelGGL(k_adj_face<kAdvection>, dim3(gq), dim3(kBlock), 0, s, P, Un, Gside, gT, p1);
+  } else if (P.eq == kBurgers) {
+    hipLaunchKernelGGL(k_adj_node<kBurgers>, dim3(gq), dim3(kBlock), 0, s, P, Un, g, GU, Gside, nullptr);
+    hipLaunchKernelGGL(k_adj_face<kBurgers>, dim3(gq), dim3(kBlock), 0, s, P, Un, Gside, gT, nullptr);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  const long total = (long)P.M * P.E * P.np1;
+  hipLaunchKernelGGL(k_adj_project, dim3(grid_for(total)), dim3(kBlock), 0, s, P, GU, gT, x0, x1, x2, out, c0, c1,
+                     c2, cg);
+  if (want) hipLaunchKernelGGL(k_adj_param, dim3(1), dim3(64), 0, s, part, (int)(2 * gq), param_scale, dparam);
+  return hipGetLastError();
+}
+
+hipError_t launch_filter_adjoint(const KParams& P, const double* g, const unsigned char* flags, double* out,
+                                 hipStream_t s) {
+  const long total = (long)P.M * P.E;
+  hipLaunchKernelGGL(k_filter_adj, dim3(grid_for(total)), dim3(kBlock), 0, s, P, g, flags, out);
+  return hipGetLastError();
+}
+
+}  // namespace frsg

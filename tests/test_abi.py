@@ -75,4 +75,5 @@ def test_null_arguments(lib):
     assert lib.fr_sg_query(None, None) == -1
     assert lib.fr_sg_rhs(None, None, None) == -1
     assert lib.fr_sg_step(None, None, 0.0, None, None) == -1
+    assert lib.fr_sg_adjoint_step(None, None, None, 1e-3, None, None) == -1
     assert lib.fr_sg_destroy(None) == 0
