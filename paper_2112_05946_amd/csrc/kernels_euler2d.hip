@@ -603,11 +603,9 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ Phi,
 #pragma unroll
     for (int k = 0; k < M; ++k) acc[i][k] = R(0);
 
-#pragma unroll 1
-  for (int q = 0; q < NQ; ++q) {
-    const int par = q & 1;
-    // (1) own pair at (j, q), all four variables, fluxes of the own pair, traces
-    R u2[2];
+  // own pair at (j, q): gPC expansion at the node; evaluated one node ahead,
+  // between the barrier and the interface flux, to cover the LDS latency there
+  auto expand = [&](int q, R* u2) {
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       R t = R(0);
@@ -615,6 +613,14 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ Phi,
       for (int k = 0; k < M; ++k) t += m[i][k] * PhiT[q * M + k];
       u2[i] = t;
     }
+  };
+  R u2[2];
+  expand(0, u2);
+
+#pragma unroll 1
+  for (int q = 0; q < NQ; ++q) {
+    const int par = q & 1;
+    // (1) all four variables at (j, q), fluxes of the own pair, traces
     R U[4];
     full4(h, u2[0], u2[1], U);
     R F2[2], G2[2];
@@ -643,6 +649,7 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ Phi,
       R own[4], nb[4];
       const Pair2<R>* src = (nbr_le >= 0) ? sT[par][nbr_le][mirror] : (const Pair2<R>*)&sH[q][nbr_halo][fi][0];
       const Pair2<R> o0 = sT[par][le][j][0], o1 = sT[par][le][j][1], n0 = src[0], n1 = src[1];
+      expand(q + 1 < NQ ? q + 1 : q, u2);  // next node, independent of the reads above
       own[0] = o0.x; own[1] = o0.y; own[2] = o1.x; own[3] = o1.y;
       nb[0] = n0.x; nb[1] = n0.y; nb[2] = n1.x; nb[3] = n1.y;
       if (wave_at_boundary) {  // uniform: only waves with a domain-boundary face pay for the ghosts
