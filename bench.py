@@ -139,6 +139,32 @@ def roofline_for(passes, precision):
             "alg_bytes_per_launch": alg, "avg_launch_ms": avg_s * 1e3, "launches": launches}
 
 
+def other_workloads(torch, Solver, inputs, steps):
+    """DOF-updates/s of the cache-resident 1D workloads (FP64, CFL steps in one call)."""
+    out = {}
+    for name in ("advection_sine", "burgers_sine", "sod_interface"):
+        cfg = inputs.CONFIGS[name]
+        sol = Solver(cfg)
+        u = sol.initial_state()
+        dts = torch.empty(steps, dtype=torch.float64, device=u.device)
+        sol.steps(u, 10, dts)
+        sol.sync()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sol.steps(u, steps, dts)
+        e1.record()
+        torch.cuda.synchronize()
+        sol.sync()
+        ms = e0.elapsed_time(e1) / steps
+        dof = int(sol.info["n_dof"])
+        out[name] = {"dof": dof, "ms_per_step": ms, "dof_updates_per_s": dof / (ms / 1e3),
+                     "shape": "%d el, p=%d, %d modes, %d nodes, %d states" % (cfg["nx"], cfg["p"], sol.shape[1],
+                                                                             sol.info["n_nodes"], sol.shape[0])}
+        sol.close()
+    return out
+
+
 def adjoint_cost(torch, Solver, inputs):
     """Adjoint/forward cost on the 4096-element Burgers problem (p = 3, 9 modes, 16 nodes):
     500 steps at the CFL step of the initial state, held fixed."""
@@ -204,6 +230,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-mixed comparison run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost run")
+    ap.add_argument("--no-others", action="store_true", help="skip the 1D workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the multi-GPU halo exchange is not built); "
@@ -250,6 +277,7 @@ def main():
         sol32.close()
 
     adjoint = None if args.no_adjoint else adjoint_cost(torch, Solver, inputs)
+    others = None if args.no_others else other_workloads(torch, Solver, inputs, 200)
 
     out = {
         "metric": METRIC, "value": value, "unit": "DOF-updates/s", "n_gpus": 1, "steps": args.steps,
@@ -263,6 +291,7 @@ def main():
         "passes_ms_per_step": {k: v[1] / args.steps for k, v in passes.items()},
         "fp32_mixed": other,
         "adjoint": adjoint,
+        "other_workloads": others,
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:

@@ -394,6 +394,7 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
   K.dt = c->ws.scal;
   K.lam_bits = (unsigned long long*)(c->ws.scal + 1);
   K.status = (unsigned*)(c->ws.scal + 2);  // scal[3] is the second CFL accumulator
+  c->fused1d = c->dim == 1 && fr1d_supported(K);
   *out = c;
   return FRSG_OK;
 }
@@ -483,6 +484,10 @@ fr_sg_status fr_sg_rhs(fr_sg_ctx* ctx, const double* u, double* dudt) {
                  ctx->dPWT,  fp32(ctx),  ctx->dPhiT32, ctx->dPWT32};
     return timed(ctx, "stage_rhs", 2 * state_bytes(ctx), [&] { return launch_fused_stage(ctx->kp, S, ctx->stream); });
   }
+  if (ctx->fused1d)
+    return timed(ctx, "stage_rhs", 2 * state_bytes(ctx), [&] {
+      return launch_stage1d(ctx->kp, u, u, u, dudt, 0.0, 1.0, 1, nullptr, ctx->stream);
+    });
   fr_sg_status st = rhs_passes(ctx, u, 0);
   if (st != FRSG_OK) return st;
   return timed(ctx, "project_rhs", state_bytes(ctx),
@@ -527,6 +532,61 @@ static fr_sg_status step_generic(fr_sg_ctx* ctx, double* u, double dt, double* d
   } else if (f2)
     FRSG_TRY_HIP(launch_fill_flags(f2, E, s), ctx);
   if ((st = fr_sg_limit(ctx, u, f3)) != FRSG_OK) return st;
+  if (dt_used) FRSG_TRY_HIP(launch_copy_dt(K, dt_used, s), ctx);
+  return FRSG_OK;
+}
+
+// The three stage states of the fused 1D path: w1 = u + dt R(u), w2 = 3/4 u + 1/4 (w1
+// + dt R(w1)), out = 1/3 u + 2/3 (w2 + dt R(w2)), each followed by the limiter (or a
+// flag clear) when lim is set; the third stage only when out is not null.
+static fr_sg_status stages_fused1d(fr_sg_ctx* ctx, const double* u, double* out, uint8_t* f0, uint8_t* f1,
+                                   uint8_t* f3, bool lim) {
+  const KParams& K = ctx->kp;
+  Workspace& W = ctx->ws;
+  hipStream_t s = ctx->stream;
+  const double sb = state_bytes(ctx);
+  const bool limiter = ctx->prob.limiter != 0;
+  fr_sg_status st;
+  if ((st = timed(ctx, "stage1", 2 * sb, [&] {
+         return launch_stage1d(K, u, u, u, W.w1, 0.0, 1.0, 0, (lim && !limiter) ? f0 : nullptr, s);
+       })))
+    return st;
+  if (lim && limiter && (st = fr_sg_limit(ctx, W.w1, f0)) != FRSG_OK) return st;
+  if ((st = timed(ctx, "stage2", 3 * sb, [&] {
+         return launch_stage1d(K, W.w1, u, W.w1, W.w2, 0.75, 0.25, 0, (lim && !limiter) ? f1 : nullptr, s);
+       })))
+    return st;
+  if (lim && limiter && (st = fr_sg_limit(ctx, W.w2, f1)) != FRSG_OK) return st;
+  if (!out) return FRSG_OK;
+  return timed(ctx, "stage3", 3 * sb, [&] {
+    return launch_stage1d(K, W.w2, u, W.w2, out, 1.0 / 3.0, 2.0 / 3.0, 0, (lim && !limiter) ? f3 : nullptr, s);
+  });
+}
+
+// fused 1D step: CFL pass (when dt <= 0), three stage kernels, filter, limiter
+static fr_sg_status step_fused1d(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, uint8_t* flags) {
+  const KParams& K = ctx->kp;
+  hipStream_t s = ctx->stream;
+  const int E = ctx->E;
+  const bool cfl = !(dt > 0.0);
+  uint8_t* f0 = flags ? flags : nullptr;
+  uint8_t* f1 = flags ? flags + E : nullptr;
+  uint8_t* f2 = flags ? flags + 2 * E : nullptr;
+  uint8_t* f3 = flags ? flags + 3 * E : nullptr;
+  fr_sg_status st;
+  FRSG_TRY_HIP(launch_set_scalars(K, cfl ? 0.0 : dt, s), ctx);
+  if (cfl) {
+    if ((st = timed(ctx, "cfl", state_bytes(ctx), [&] { return launch_cfl1d(K, u, s); }))) return st;
+    FRSG_TRY_HIP(launch_dt(K, 1, nullptr, s), ctx);
+  }
+  if ((st = stages_fused1d(ctx, u, u, f0, f1, f3, true)) != FRSG_OK) return st;
+  if (ctx->prob.filter != FRSG_FILTER_NONE) {
+    if ((st = timed(ctx, "sensor_filter", 2 * state_bytes(ctx), [&] { return launch_sensor_filter(K, u, f2, s); })))
+      return st;
+  } else if (f2) {
+    FRSG_TRY_HIP(launch_fill_flags(f2, E, s), ctx);
+  }
+  if (ctx->prob.limiter && (st = fr_sg_limit(ctx, u, f3)) != FRSG_OK) return st;
   if (dt_used) FRSG_TRY_HIP(launch_copy_dt(K, dt_used, s), ctx);
   return FRSG_OK;
 }
@@ -587,6 +647,7 @@ fr_sg_status fr_sg_step(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, u
   fr_sg_status st = check_step_args(ctx, u, dt);
   if (st != FRSG_OK) return st;
   if (ctx->fused) return step_fused(ctx, u, dt, dt_used, flags, false);
+  if (ctx->fused1d) return step_fused1d(ctx, u, dt, dt_used, flags);
   return step_generic(ctx, u, dt, dt_used, flags);
 }
 
@@ -603,6 +664,8 @@ fr_sg_status fr_sg_steps(fr_sg_ctx* ctx, double* u, int32_t nsteps, double* dt_u
     uint8_t* f = flags ? flags + i * fl : nullptr;
     if (ctx->fused)
       st = step_fused(ctx, u, 0.0, dtu, f, i > 0);
+    else if (ctx->fused1d)
+      st = step_fused1d(ctx, u, 0.0, dtu, f);
     else
       st = step_generic(ctx, u, 0.0, dtu, f);
     if (st != FRSG_OK) return st;
@@ -635,16 +698,20 @@ fr_sg_status fr_sg_adjoint_step(fr_sg_ctx* ctx, const double* u_n, const uint8_t
   const double sb = state_bytes(ctx);
   fr_sg_status st;
   FRSG_TRY_HIP(launch_set_scalars(K, dt, s), ctx);
-  // stage states of the forward step, recomputed with the forward passes (no
-  // limiter: the scalar equations do not use it)
-  if ((st = rhs_passes(ctx, u_n, 0)) != FRSG_OK) return st;
-  if ((st = timed(ctx, "adj_fwd_stage1", 2 * sb,
-                  [&] { return launch_project_stage(K, W.Un, u_n, u_n, W.w1, 0.0, 1.0, 0, s); })))
-    return st;
-  if ((st = rhs_passes(ctx, W.w1, 0)) != FRSG_OK) return st;
-  if ((st = timed(ctx, "adj_fwd_stage2", 3 * sb,
-                  [&] { return launch_project_stage(K, W.Un, u_n, W.w1, W.w2, 0.75, 0.25, 0, s); })))
-    return st;
+  // stage states of the forward step, recomputed with the same kernels as the
+  // forward step (no limiter: the scalar equations do not use it)
+  if (ctx->fused1d) {
+    if ((st = stages_fused1d(ctx, u_n, nullptr, nullptr, nullptr, nullptr, false)) != FRSG_OK) return st;
+  } else {
+    if ((st = rhs_passes(ctx, u_n, 0)) != FRSG_OK) return st;
+    if ((st = timed(ctx, "adj_fwd_stage1", 2 * sb,
+                    [&] { return launch_project_stage(K, W.Un, u_n, u_n, W.w1, 0.0, 1.0, 0, s); })))
+      return st;
+    if ((st = rhs_passes(ctx, W.w1, 0)) != FRSG_OK) return st;
+    if ((st = timed(ctx, "adj_fwd_stage2", 3 * sb,
+                    [&] { return launch_project_stage(K, W.Un, u_n, W.w1, W.w2, 0.75, 0.25, 0, s); })))
+      return st;
+  }
   // u+ = Filter(v): vb = Filter^T lam
   if (ctx->prob.filter != FRSG_FILTER_NONE) {
     if ((st = timed(ctx, "adj_filter", 2 * sb,

@@ -134,7 +134,8 @@ struct fr_sg_ctx {
   const double* dPWT = nullptr;
   float* dPhiT32 = nullptr;  // FP32 copies of the node-major tables
   float* dPWT32 = nullptr;
-  bool fused = false;
+  bool fused = false;            // fused 2D Euler stage kernel
+  bool fused1d = false;          // fused 1D stage kernel
   int lam_cur = 0;              // which CFL accumulator holds the maximum of the current state
   const double* lam_for = nullptr;  // state whose maximum the previous step recorded (fr_sg_steps)
   frsg::KParams kp;
@@ -184,6 +185,12 @@ hipError_t launch_limiter(const KParams& P, double* u, unsigned char* flags, hip
 hipError_t launch_sensor_filter(const KParams& P, double* u, unsigned char* flags, hipStream_t s);
 hipError_t launch_fill_flags(unsigned char* flags, long n, hipStream_t s);
 hipError_t launch_copy_dt(const KParams& P, double* dt_used, hipStream_t s);
+
+// fused 1D stage kernel (kernels_fr1d.hip)
+bool fr1d_supported(const KParams& P);
+hipError_t launch_stage1d(const KParams& P, const double* in, const double* u, const double* w, double* out, double cu,
+                          double cw, int rhs_only, unsigned char* clear_flags, hipStream_t s);
+hipError_t launch_cfl1d(const KParams& P, const double* u, hipStream_t s);
 
 // adjoint launchers (kernels_adjoint.hip)
 long adjoint_partials(const KParams& P);
