@@ -1,5 +1,6 @@
 // C ABI of the FR-SG hot path: problem validation, tables, workspace and the
 // orchestration of the HIP passes for the right-hand side and the SSP-RK3 step.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -319,7 +320,11 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
     std::memset(&probe, 0, sizeof(probe));
     probe.E = c->E;
     probe.Nq = T.Nq;
-    nadj_part = (size_t)adjoint_partials(probe);
+    probe.M = T.M;
+    probe.np1 = n;
+    probe.S = c->S;
+    probe.dim = c->dim;
+    nadj_part = (size_t)std::max(adjoint_partials(probe), adj1d_partials(probe));
   }
   size_t o_avb = align_up(o_sc + 256);
   size_t o_ab2 = align_up(o_avb + (adj ? state * 8 : 0));
@@ -721,8 +726,13 @@ fr_sg_status fr_sg_adjoint_step(fr_sg_ctx* ctx, const double* u_n, const uint8_t
     FRSG_TRY_HIP(hipMemcpyAsync(W.avb, lam, (size_t)sb, hipMemcpyDeviceToDevice, s), ctx);
   }
   // one transposed right-hand side: nodal values of the state, then the adjoint passes
+  const bool fused_adj = adj1d_fused_supported(K);
   auto vjp = [&](const char* name, const double* w, const double* g, const double* x0, const double* x1,
                  const double* x2, double* out, double c0, double c1, double c2, double cg, double pscale) {
+    if (fused_adj)
+      return timed(ctx, name, 3 * sb, [&] {
+        return launch_adj_stage1d(K, w, g, x0, x1, x2, out, c0, c1, c2, cg, W.apart, pscale, dparams, s);
+      });
     fr_sg_status r = timed(ctx, "adj_nodal", sb, [&] { return launch_nodal(K, w, W.Un, W.Fn, W.Gn, 0, s); });
     if (r != FRSG_OK) return r;
     return timed(ctx, name, 3 * sb, [&] {

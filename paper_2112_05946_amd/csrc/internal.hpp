@@ -198,6 +198,11 @@ hipError_t launch_rhs_adjoint(const KParams& P, const double* Un, const double* 
                               double* gT, const double* x0, const double* x1, const double* x2, double* out,
                               double c0, double c1, double c2, double cg, double* part, double param_scale,
                               double* dparam, hipStream_t s);
+bool adj1d_fused_supported(const KParams& P);
+long adj1d_partials(const KParams& P);
+hipError_t launch_adj_stage1d(const KParams& P, const double* w, const double* g, const double* x0, const double* x1,
+                              const double* x2, double* out, double c0, double c1, double c2, double cg, double* part,
+                              double param_scale, double* dparam, hipStream_t s);
 hipError_t launch_filter_adjoint(const KParams& P, const double* g, const unsigned char* flags, double* out,
                                  hipStream_t s);
 }  // namespace frsg

@@ -28,6 +28,8 @@
 // advection speed is reduced per block and added, scaled, into one scalar.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "internal.hpp"
 
@@ -244,11 +246,223 @@ __global__ void __launch_bounds__(kBlock) k_filter_adj(KParams P, const double* 
   }
 }
 
+// ---------------------------------------------------------------------------
+// fused transposed right-hand side for a block of EB elements (the same three
+// steps as k_adj_node / k_adj_face / k_adj_project, with the state and adjoint
+// coefficients of the block and one neighbour on each side staged in LDS)
+//   out = c0 x0 + c1 x1 + c2 x2 + cg (dR/dw)^T g
+// ---------------------------------------------------------------------------
+constexpr int kBlockA = 256;
+
+struct AdjStageArgs {
+  const double* w;  // state the right-hand side is linearised at
+  const double* g;  // adjoint vector
+  const double* x0;
+  const double* x1;
+  const double* x2;
+  double* out;
+  double c0, c1, c2, cg;
+  double* part;     // per-workgroup partial sums of d<g, R>/da (advection), or null
+  int EB;
+};
+
+template <int EQ, int N>
+__global__ void __launch_bounds__(kBlockA) k_adj_stage1d(KParams P, AdjStageArgs A) {
+  constexpr int n = N;
+  extern __shared__ double smem[];
+  __shared__ double sm[kBlockA];
+  const int E = P.E, M = P.M, Nq = P.Nq, EB = A.EB;
+  const int e0 = blockIdx.x * EB;
+  const int nloc = min(EB, E - e0);
+  const int nc = M * n;
+  const long EN = (long)E * n;
+  double* sW = smem;                         // [EB + 2][M][n]
+  double* sGc = sW + (EB + 2) * nc;          // [EB + 2][M][n]
+  double* sT = sGc + (EB + 2) * nc;          // [EB + 2][Nq][2] traces at r = -1, +1
+  double* sS = sT + (EB + 2) * Nq * 2;       // [EB + 2][Nq][2] adjoints of the left / right face fluxes
+  double* sU = sS + (EB + 2) * Nq * 2;       // [EB][n][Nq] nodal adjoint of the state
+  const bool periodic = P.bc[0] == FRSG_BC_PERIODIC;
+  const int tid = threadIdx.x;
+
+  const int span = (nloc + 2) * n;
+  for (int it = tid; it < M * span; it += kBlockA) {
+    const int k = it / span, rem = it - k * span;
+    const int ls = rem / n, j = rem - ls * n;
+    int e = e0 - 1 + ls;
+    if (e < 0) e = periodic ? E - 1 : 0;
+    if (e >= E) e = periodic ? 0 : E - 1;
+    const long src = (long)k * EN + (long)e * n + j;
+    sW[ls * nc + k * n + j] = A.w[src];
+    sGc[ls * nc + k * n + j] = A.g[src];
+  }
+  __syncthreads();
+
+  const int ls = tid / Nq, q = tid - ls * Nq;
+  const bool active = ls < nloc + 2;
+  const bool owned = active && ls >= 1 && ls <= nloc;
+  double U[n], GU[n];
+  double pa = 0.0;
+  double tm = 0.0, tp = 0.0;
+  if (active) {
+    const double* W = sW + ls * nc;
+    const double* Gc = sGc + ls * nc;
+    double d[n];
+#pragma unroll
+    for (int j = 0; j < n; ++j) {
+      double u = 0.0, gr = 0.0;
+      for (int k = 0; k < M; ++k) {
+        u += W[k * n + j] * P.tab.Phi[k * Nq + q];
+        gr += P.tab.PW[k * Nq + q] * Gc[k * n + j];
+      }
+      U[j] = u;
+      d[j] = -gr / P.Jx;
+    }
+    double GL = 0.0, GR = 0.0;
+#pragma unroll
+    for (int j = 0; j < n; ++j) {
+      GL += P.tab.dhL[j] * d[j];
+      GR += P.tab.dhR[j] * d[j];
+      tm += P.tab.lL[j] * U[j];
+      tp += P.tab.lR[j] * U[j];
+    }
+#pragma unroll
+    for (int l = 0; l < n; ++l) {
+      double gF = 0.0;
+#pragma unroll
+      for (int j = 0; j < n; ++j) gF += P.tab.D[j * n + l] * d[j];
+      gF = gF - P.tab.lL[l] * GL - P.tab.lR[l] * GR;
+      GU[l] = dflux<EQ>(U[l], P.adv) * gF;
+      if constexpr (EQ == kAdvection)
+        if (owned) pa += gF * U[l];
+    }
+    double* T = sT + ((long)ls * Nq + q) * 2;
+    T[0] = tm;
+    T[1] = tp;
+    double* G2 = sS + ((long)ls * Nq + q) * 2;
+    G2[0] = GL;
+    G2[1] = GR;
+  }
+  __syncthreads();
+
+  if (owned) {
+    const int e = e0 + ls - 1;
+    const double* Tl = sT + ((long)(ls - 1) * Nq + q) * 2;
+    const double* Tr = sT + ((long)(ls + 1) * Nq + q) * 2;
+    const double* Sl = sS + ((long)(ls - 1) * Nq + q) * 2;
+    const double* Sc = sS + ((long)ls * Nq + q) * 2;
+    const double* Sr = sS + ((long)(ls + 1) * Nq + q) * 2;
+    double gTm, gTp;
+    {  // left face
+      const bool interior = e > 0 || periodic;
+      const double UL = interior ? Tl[1] : ghost_val(P, 0, tm);
+      const double gF = Sc[0] + (interior ? Sl[1] : 0.0);
+      double gL, gR, da;
+      rusanov_adj<EQ>(UL, tm, gF, P.adv, gL, gR, da);
+      gTm = gR + (interior ? 0.0 : ghost_adj(P, 0, gL));
+      pa += da;
+    }
+    {  // right face
+      const bool interior = e < E - 1 || periodic;
+      const double UR = interior ? Tr[0] : ghost_val(P, 1, tp);
+      const double gF = Sc[1] + (interior ? Sr[0] : 0.0);
+      double gL, gR, da;
+      rusanov_adj<EQ>(tp, UR, gF, P.adv, gL, gR, da);
+      gTp = gL + (interior ? 0.0 : ghost_adj(P, 1, gR));
+      if (!interior) pa += da;
+    }
+#pragma unroll
+    for (int j = 0; j < n; ++j)
+      sU[((long)(ls - 1) * n + j) * Nq + q] = GU[j] + P.tab.lL[j] * gTm + P.tab.lR[j] * gTp;
+  }
+  if (A.part) {
+    const double sum = block_reduce_sum(pa, sm);
+    if (tid == 0) A.part[blockIdx.x] = sum;
+  } else {
+    __syncthreads();
+  }
+
+  const int ospan = nloc * n;
+  for (int it = tid; it < M * ospan; it += kBlockA) {
+    const int k = it / ospan, rem = it - k * ospan;
+    const int le = rem / n, j = rem - le * n;
+    const double* Gq = sU + ((long)le * n + j) * Nq;
+    double acc = 0.0;
+    for (int qq = 0; qq < Nq; ++qq) acc += P.tab.Phi[k * Nq + qq] * Gq[qq];
+    const long idx = (long)k * EN + (long)(e0 + le) * n + j;
+    double v = A.cg * acc;
+    if (A.x0) v += A.c0 * A.x0[idx];
+    if (A.x1) v += A.c1 * A.x1[idx];
+    if (A.x2) v += A.c2 * A.x2[idx];
+    A.out[idx] = v;
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+static void adj1d_shape(const KParams& P, int& EB, size_t& shmem) {
+  EB = kBlockA / P.Nq - 2;
+  if (EB < 1 || P.np1 > kMaxNp || P.S != 1 || P.dim != 1) {
+    EB = 0;
+    shmem = 0;
+    return;
+  }
+  const size_t nc = (size_t)P.M * P.np1;
+  shmem = sizeof(double) * (2 * (EB + 2) * nc + 4 * (size_t)(EB + 2) * P.Nq + (size_t)EB * P.np1 * P.Nq);
+  if (shmem > 48 * 1024) {
+    EB = 0;
+    shmem = 0;
+  }
+}
+
+bool adj1d_fused_supported(const KParams& P) {
+  int EB;
+  size_t sh;
+  adj1d_shape(P, EB, sh);
+  return EB > 0;
+}
+
+long adj1d_partials(const KParams& P) {
+  int EB;
+  size_t sh;
+  adj1d_shape(P, EB, sh);
+  return EB > 0 ? (P.E + EB - 1) / EB : 0;
+}
+
+hipError_t launch_adj_stage1d(const KParams& P, const double* w, const double* g, const double* x0, const double* x1,
+                              const double* x2, double* out, double c0, double c1, double c2, double cg, double* part,
+                              double param_scale, double* dparam, hipStream_t s) {
+  int EB;
+  size_t shmem;
+  adj1d_shape(P, EB, shmem);
+  if (EB == 0) return hipErrorInvalidValue;
+  const bool want = P.eq == kAdvection && dparam && part;
+  AdjStageArgs A{w, g, x0, x1, x2, out, c0, c1, c2, cg, want ? part : nullptr, EB};
+  const unsigned grid = (unsigned)((P.E + EB - 1) / EB);
+  auto go = [&](auto eq_tag) -> hipError_t {
+    constexpr int EQ = decltype(eq_tag)::value;
+    switch (P.np1) {
+#define FRSG_N(NN) \
+  case NN: hipLaunchKernelGGL((k_adj_stage1d<EQ, NN>), dim3(grid), dim3(kBlockA), shmem, s, P, A); break;
+      FRSG_N(2) FRSG_N(3) FRSG_N(4) FRSG_N(5) FRSG_N(6) FRSG_N(7) FRSG_N(8)
+#undef FRSG_N
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  };
+  hipError_t e;
+  if (P.eq == kAdvection)
+    e = go(std::integral_constant<int, kAdvection>{});
+  else if (P.eq == kBurgers)
+    e = go(std::integral_constant<int, kBurgers>{});
+  else
+    return hipErrorInvalidValue;
+  if (e != hipSuccess) return e;
+  if (want) hipLaunchKernelGGL(k_adj_param, dim3(1), dim3(64), 0, s, part, (int)grid, param_scale, dparam);
+  return hipGetLastError();
+}
 long adjoint_partials(const KParams& P) { return 2 * (long)grid_for((long)P.Nq * P.E); }
 
 hipError_t launch_rhs_adjoint(const KParams& P, const double* Un, const double* g, double* GU, double* Gside,

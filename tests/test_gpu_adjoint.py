@@ -31,6 +31,8 @@ def _state(cfg, prob, T, R, seed):
 CASES = [
     ("burgers_ragged", inputs.small(inputs.BURGERS, 37), 4e-4),
     ("burgers_no_filter", dict(inputs.small(inputs.BURGERS, 16), filter="none"), 4e-4),
+    # 100 random nodes: too many for the fused 1D kernels, so the multi-pass kernels run
+    ("burgers_multipass", dict(inputs.small(inputs.BURGERS, 9), gpc_order=4, nq1d=100), 4e-4),
     ("advection_periodic", dict(inputs.small(inputs.ADVECTION, 13), adv_speed=0.7, filter="exp", alpha=36.0,
                                 s=8.0, sensor="detector", s0=-2.0 * np.log10(3.0), kappa=4.0), 1e-3),
     ("advection_inflow_outflow", dict(inputs.small(inputs.ADVECTION, 11), adv_speed=-1.2,
