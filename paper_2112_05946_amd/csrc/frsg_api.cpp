@@ -259,6 +259,7 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
   tab.swts = b + off[13];
   c->dDt = b + off[14];
   c->dcmax = b + off[15];
+  tab.cmax = c->dcmax;
   c->dPhiT = b + off[16];
   c->dPWT = b + off[17];
 

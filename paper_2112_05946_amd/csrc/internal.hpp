@@ -64,6 +64,7 @@ struct DevTab {
   const double* filt;
   const double* shell;
   const double* swts;
+  const double* cmax;  // [M] max over the random nodes of |Phi_k|
 };
 
 // Everything a kernel needs about the problem, passed by value.

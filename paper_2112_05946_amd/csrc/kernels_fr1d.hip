@@ -179,23 +179,33 @@ __global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
     for (int it = tid; it < nloc; it += kBlock1) A.clear_flags[e0 + it] = 0;
 }
 
-// CFL maximum of a 1D state: (element, node) per thread, max over points
+// CFL maximum of a 1D state: a workgroup stages the coefficients of 256 / Nq
+// elements in LDS; thread (element, node q) takes the maximum over the points
 template <int EQ>
-__global__ void __launch_bounds__(kBlock1) k_cfl1d(KParams P, const double* __restrict__ u) {
+__global__ void __launch_bounds__(kBlock1) k_cfl1d(KParams P, const double* __restrict__ u, int EB) {
   constexpr int S = nstate<EQ>();
+  extern __shared__ double sC[];  // [EB][S][M][n]
   __shared__ double sm[kBlock1];
   const int E = P.E, n = P.np1, M = P.M, Nq = P.Nq;
   const long EN = (long)E * n;
-  const long t = blockIdx.x * (long)kBlock1 + threadIdx.x;
+  const int e0 = blockIdx.x * EB, nloc = min(EB, E - e0);
+  const int ncoef = S * M * n, span = nloc * n;
+  for (int it = threadIdx.x; it < S * M * span; it += kBlock1) {
+    const int sk = it / span, rem = it - sk * span;
+    const int le = rem / n, j = rem - le * n;
+    sC[le * ncoef + sk * n + j] = u[(long)sk * EN + (long)(e0 + le) * n + j];
+  }
+  __syncthreads();
+  const int le = threadIdx.x / Nq, q = threadIdx.x - le * Nq;
   double rate = 0.0;
-  if (t < (long)E * Nq) {
-    const int e = (int)(t / Nq), q = (int)(t - (long)e * Nq);
+  if (le < nloc) {
+    const double* C = sC + le * ncoef;
     for (int j = 0; j < n; ++j) {
       double U[S];
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         double acc = 0.0;
-        for (int k = 0; k < M; ++k) acc += u[((long)s * M + k) * EN + (long)e * n + j] * P.tab.Phi[k * Nq + q];
+        for (int k = 0; k < M; ++k) acc += C[(s * M + k) * n + j] * P.tab.Phi[k * Nq + q];
         U[s] = acc;
       }
       double r = speed<EQ, 0>(U, P.adv, P.gamma);
@@ -266,12 +276,14 @@ hipError_t launch_stage1d(const KParams& P, const double* in, const double* u, c
 }
 
 hipError_t launch_cfl1d(const KParams& P, const double* u, hipStream_t s) {
-  const long total = (long)P.E * P.Nq;
-  const unsigned grid = (unsigned)((total + kBlock1 - 1) / kBlock1);
+  const int EB = kBlock1 / P.Nq;  // >= 1 wherever the fused 1D path runs
+  if (EB < 1) return hipErrorInvalidValue;
+  const size_t shmem = sizeof(double) * (size_t)EB * P.S * P.M * P.np1;
+  const unsigned grid = (unsigned)((P.E + EB - 1) / EB);
   switch (P.eq) {
-    case kAdvection: hipLaunchKernelGGL(k_cfl1d<kAdvection>, dim3(grid), dim3(kBlock1), 0, s, P, u); break;
-    case kBurgers: hipLaunchKernelGGL(k_cfl1d<kBurgers>, dim3(grid), dim3(kBlock1), 0, s, P, u); break;
-    case kEuler1: hipLaunchKernelGGL(k_cfl1d<kEuler1>, dim3(grid), dim3(kBlock1), 0, s, P, u); break;
+    case kAdvection: hipLaunchKernelGGL(k_cfl1d<kAdvection>, dim3(grid), dim3(kBlock1), shmem, s, P, u, EB); break;
+    case kBurgers: hipLaunchKernelGGL(k_cfl1d<kBurgers>, dim3(grid), dim3(kBlock1), shmem, s, P, u, EB); break;
+    case kEuler1: hipLaunchKernelGGL(k_cfl1d<kEuler1>, dim3(grid), dim3(kBlock1), shmem, s, P, u, EB); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -335,16 +335,16 @@ __global__ void __launch_bounds__(kBlock) k_project_ic(KParams P, const double* 
 // ---------------------------------------------------------------------------
 constexpr int kElemBlock = 128;
 
+// The element's coefficients c(s, k, j) = C[(s * M + k) * cs + j]: staged in LDS
+// (cs = nsp) when they fit, else read in place from the state (cs = E * nsp).
 // nodal state at limiter point `pt` (solution points first, then face points)
 template <int EQ, int DIM>
-__device__ __forceinline__ void limiter_point(const KParams& P, const double* __restrict__ u, int e, int pt, int q,
-                                              double* U) {
+__device__ __forceinline__ void limiter_point(const KParams& P, const double* C, long cs, int pt, int q, double* U) {
   constexpr int S = nstate<EQ>();
   const int n = P.np1, nsp = P.nsp, M = P.M, Nq = P.Nq;
-  const long EN = (long)P.E * nsp;
   auto at_sp = [&](int s, int j) {
     double acc = 0.0;
-    for (int k = 0; k < M; ++k) acc += u[((long)s * M + k) * EN + (long)e * nsp + j] * P.tab.Phi[k * Nq + q];
+    for (int k = 0; k < M; ++k) acc += C[((long)s * M + k) * cs + j] * P.tab.Phi[k * Nq + q];
     return acc;
   };
   if (pt < nsp) {
@@ -375,17 +375,27 @@ __device__ __forceinline__ void limiter_point(const KParams& P, const double* __
 
 template <int EQ, int DIM>
 __global__ void __launch_bounds__(kElemBlock) k_limiter(KParams P, double* __restrict__ u,
-                                                        unsigned char* __restrict__ flags) {
+                                                        unsigned char* __restrict__ flags, int staged) {
   constexpr int S = nstate<EQ>();
+  extern __shared__ double sc[];  // [S][M][nsp] when staged
   __shared__ double sm[kElemBlock];
   const int e = blockIdx.x;
   const int nsp = P.nsp, M = P.M, Nq = P.Nq;
   const long EN = (long)P.E * nsp;
+  if (staged) {
+    for (int it = threadIdx.x; it < S * M * nsp; it += kElemBlock) {
+      const int sk = it / nsp, j = it - sk * nsp;
+      sc[it] = u[(long)sk * EN + (long)e * nsp + j];
+    }
+    __syncthreads();
+  }
+  const double* C = staged ? sc : u + (long)e * nsp;
+  const long cs = staged ? nsp : EN;
   double ub[S];
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     double acc = 0.0;
-    for (int j = 0; j < nsp; ++j) acc += u[((long)s * M) * EN + (long)e * nsp + j] * P.tab.swts[j];
+    for (int j = 0; j < nsp; ++j) acc += C[((long)s * M) * cs + j] * P.tab.swts[j];
     ub[s] = acc;
   }
   const double pb = pressure<EQ>(ub, P.gamma);
@@ -402,10 +412,72 @@ __global__ void __launch_bounds__(kElemBlock) k_limiter(KParams P, double* __res
   const double eps = fmin(1e-8, fmin(ub[0], pb));
   const int nfp = DIM == 1 ? 2 : 4 * P.np1;
   const int items = (nsp + nfp) * Nq;
+
+  // Decision from rigorous bounds first: at point pt the value at any node is
+  // a_0 + sum_{k>=1} a_k Phi_k(z_q), a_k the interpolated mode k, |Phi_k(z_q)|
+  // <= cmax_k.  If density and pressure bounds clear eps (with a relative
+  // margin for the rounding of the bounds) at every point, the node-by-node
+  // minimum clears it too and the element is left unchanged.
+  {
+    const int n = P.np1;
+    double safe = 1.0;
+    for (int pt = threadIdx.x; pt < nsp + nfp; pt += kElemBlock) {
+      double mn[S], vr[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        double mean = 0.0, var = 0.0;
+        for (int k = 0; k < M; ++k) {
+          const double* ck = C + ((long)s * M + k) * cs;
+          double a;
+          if (pt < nsp) {
+            a = ck[pt];
+          } else {
+            const int f = pt - nsp;
+            a = 0.0;
+            if constexpr (DIM == 1) {
+              const double* l = (f == 0) ? P.tab.lL : P.tab.lR;
+              for (int j = 0; j < n; ++j) a += l[j] * ck[j];
+            } else {
+              const int side = f / n, i = f % n;
+              const double* l = (side == 0 || side == 2) ? P.tab.lL : P.tab.lR;
+              for (int c = 0; c < n; ++c) a += l[c] * ck[side < 2 ? (c + n * i) : (i + n * c)];
+            }
+          }
+          if (k == 0)
+            mean = a;
+          else
+            var += fabs(a) * P.tab.cmax[k];
+        }
+        mn[s] = mean;
+        vr[s] = var;
+      }
+      const double rlo = mn[0] - vr[0];
+      const double tol_r = 1e-10 * (fabs(mn[0]) + vr[0]);
+      bool ok = rlo > eps + tol_r;
+      if (ok) {
+        double m2 = 0.0, ke = 0.0;
+#pragma unroll
+        for (int s = 1; s < S - 1; ++s) {
+          const double mx = fabs(mn[s]) + vr[s];
+          m2 += mx * mx;
+        }
+        ke = 0.5 * m2 / rlo;
+        const double elo = mn[S - 1] - vr[S - 1];
+        const double plo = (P.gamma - 1.0) * (elo - ke);
+        const double tol_p = 1e-10 * (P.gamma - 1.0) * (fabs(mn[S - 1]) + vr[S - 1] + ke);
+        ok = plo > eps + tol_p;
+      }
+      if (!ok) safe = 0.0;
+    }
+    if (block_reduce_min(safe, sm) > 0.5) {
+      if (threadIdx.x == 0 && flags) flags[e] = 0;
+      return;
+    }
+  }
   double rmin = INFINITY, pmin = INFINITY;
   for (int it = threadIdx.x; it < items; it += kElemBlock) {
     double U[S];
-    limiter_point<EQ, DIM>(P, u, e, it / Nq, it % Nq, U);
+    limiter_point<EQ, DIM>(P, C, cs, it / Nq, it % Nq, U);
     rmin = fmin(rmin, U[0]);
     pmin = fmin(pmin, pressure<EQ>(U, P.gamma));
   }
@@ -419,7 +491,7 @@ __global__ void __launch_bounds__(kElemBlock) k_limiter(KParams P, double* __res
   double bmin = 1.0;
   for (int it = threadIdx.x; it < items; it += kElemBlock) {
     double U[S];
-    limiter_point<EQ, DIM>(P, u, e, it / Nq, it % Nq, U);
+    limiter_point<EQ, DIM>(P, C, cs, it / Nq, it % Nq, U);
     U[0] = beta1 * (U[0] - ub[0]) + ub[0];
     if (pressure<EQ>(U, P.gamma) < eps) bmin = fmin(bmin, pressure_root<EQ>(ub, U, eps, P.gamma));
   }
@@ -431,7 +503,7 @@ __global__ void __launch_bounds__(kElemBlock) k_limiter(KParams P, double* __res
     const int s = it / (nsp * M);
     const long idx = ((long)s * M + k) * EN + (long)e * nsp + j;
     const double m0 = (k == 0) ? 1.0 : 0.0;
-    double v = u[idx];
+    double v = staged ? sc[it] : u[idx];
     if (s == 0) v = beta1 * (v - ub[0] * m0) + ub[0] * m0;
     v = beta2 * (v - ub[s] * m0) + ub[s] * m0;
     u[idx] = v;
@@ -606,10 +678,14 @@ hipError_t launch_project_ic(const KParams& P, const double* U0, double* u, hipS
 }
 
 hipError_t launch_limiter(const KParams& P, double* u, unsigned char* flags, hipStream_t s) {
+  // stage the element's coefficients in LDS when they fit in 32 KB
+  const size_t bytes = sizeof(double) * (size_t)P.S * P.M * P.nsp;
+  const int staged = bytes <= 32 * 1024 ? 1 : 0;
+  const size_t shmem = staged ? bytes : 0;
   if (P.eq == kEuler1)
-    hipLaunchKernelGGL((k_limiter<kEuler1, 1>), dim3(P.E), dim3(kElemBlock), 0, s, P, u, flags);
+    hipLaunchKernelGGL((k_limiter<kEuler1, 1>), dim3(P.E), dim3(kElemBlock), shmem, s, P, u, flags, staged);
   else if (P.eq == kEuler2)
-    hipLaunchKernelGGL((k_limiter<kEuler2, 2>), dim3(P.E), dim3(kElemBlock), 0, s, P, u, flags);
+    hipLaunchKernelGGL((k_limiter<kEuler2, 2>), dim3(P.E), dim3(kElemBlock), shmem, s, P, u, flags, staged);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
