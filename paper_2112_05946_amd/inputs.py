@@ -96,7 +96,9 @@ def initial_condition(name, x, y, z, gamma=GAMMA):
         p = np.where(left, 1.0, 0.1)
         return _cons1d(rho, np.zeros_like(rho), p, gamma)
     if name == "shock_vortex":
-        return shock_vortex_ic(x, y, z1, z[..., 1], gamma)
+        # one random dimension: only the vortex strength is uncertain
+        z2 = z[..., 1] if z.shape[-1] > 1 else np.zeros_like(z1)
+        return shock_vortex_ic(x, y, z1, z2, gamma)
     raise ValueError(name)
 
 

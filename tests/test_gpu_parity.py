@@ -247,3 +247,33 @@ def test_fused_multi_step_cfl_reuse():
     sol.sync()
     assert np.allclose(to_np(dts), rdts, rtol=1e-13, atol=0)
     assert rel_l2(to_np(ud), ref) < RTOL_FP64
+
+
+# every compiled (modes, nodes) pair of the fused kernel, one-tile meshes and
+# boundary combinations in which every halo face is a ghost or wraps to itself
+FUSED_EDGE = [
+    ("one_tile_periodic", dict(nx=4, ny=2, bc=["periodic"] * 4)),
+    ("one_tile_all_dirichlet", dict(nx=4, ny=2, bc=["dirichlet"] * 4)),
+    ("reflect_x_outflow_y", dict(nx=8, ny=4, bc=["reflect", "reflect", "outflow", "outflow"])),
+    ("order1_rdim2", dict(nx=8, ny=4, gpc_order=1, nq1d=2)),
+    ("order2_rdim2", dict(nx=8, ny=4, gpc_order=2, nq1d=3)),
+    ("order3_rdim2", dict(nx=8, ny=4, gpc_order=3, nq1d=4)),
+    ("order4_rdim1", dict(nx=8, ny=4, gpc_order=4, nq1d=5, rdim=1)),
+]
+
+
+@pytest.mark.parametrize("label,over", FUSED_EDGE)
+def test_fused_edge_cases(label, over):
+    announce("fused_edge", label)
+    base = inputs.small(inputs.SHOCK_VORTEX, 8, 4)
+    st = [[1.0, 0.4, -0.2, 2.6], [0.9, -0.1, 0.3, 2.2], [1.2, 0.2, 0.1, 3.0], [0.8, 0.0, -0.3, 2.0]]
+    cfg = dict(base, bc_state=st, **over)
+    prob, (T, R) = oracle_for(cfg)
+    u = inputs.fuzz_euler(2, R.M, prob.E, 16, 21)
+    sol = solver_for(cfg)
+    assert sol.info["n_modes"] == R.M
+    got = to_np(sol.rhs(to_dev(u)))
+    sol.sync()
+    assert rel_l2(got, ofr.rhs(prob, T, R, u)) < RTOL_FP64
+    u0 = project_initial(prob, cfg["ic"], (T, R))
+    _run_steps(cfg, u0, 2)
