@@ -25,6 +25,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "FR-SG DOF-updates/s, FP64 vs FP32-mixed at stated L2 err; adjoint/forward cost"
 HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_TFLOPS = 78.6
+FP32_VECTOR_TFLOPS = 157.3
+# algorithmic flops per DOF of one stage launch on the shock-vortex workload:
+# right-hand side 195 (chaos expansion and projection 2 x 2 N_q = 100, face
+# traces and Lax-Friedrichs fluxes 59, physical fluxes 12.5, derivative with the
+# Radau corrections 24) plus the stage combination (2 in stage 1, 5 in stages
+# 2-3: 4 on average)
+SV_FLOP_PER_DOF_LAUNCH = 199.0
 # symbol of the stage kernel for the shock-vortex sizes (15 modes, 25 nodes), per precision
 KERNEL_NAME = {"fp64": "k_stage2d<15, 25, double>", "fp32": "k_stage2d<15, 25, float>"}
 
@@ -59,19 +67,15 @@ def cpu_baseline(cfg_full):
     prob = Problem.from_config(cfg)
     T, R = build_tables(prob)
     u = project_initial(prob, cfg["ic"], (T, R))
-    threads = 1
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([1] + [int(i.get("num_threads", 1)) for i in threadpool_info()])
-    except Exception:
-        pass
-    t0 = time.perf_counter()
+    t0, c0 = time.perf_counter(), time.process_time()
     step(prob, u, None, (T, R))
-    el = time.perf_counter() - t0
+    el, cpu = time.perf_counter() - t0, time.process_time() - c0
     dof = prob.S * R.M * prob.E * prob.nsp
-    return {"value": dof / el, "unit": "DOF-updates/s", "cores": threads, "kind": "oracle",
-            "sample": "1 SSP-RK3 step of the same problem on a %dx%d mesh (%d DOF), %.1f s" %
-                      (prob.nx, prob.ny, dof, el)}
+    # threads actually used: process CPU time over wall time (NumPy's own threading)
+    cores = max(1, int(round(cpu / el)))
+    return {"value": dof / el, "unit": "DOF-updates/s", "cores": cores, "kind": "oracle",
+            "sample": "1 SSP-RK3 step of the same problem on a %dx%d mesh (%d DOF), %.1f s wall, %.1f s CPU" %
+                      (prob.nx, prob.ny, dof, el, cpu)}
 
 
 def timed_steps(torch, sol, u, steps, warmup):
@@ -137,6 +141,16 @@ def roofline_for(passes, precision):
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(kern, alg), "kernel": name,
             "alg_bytes_per_launch": alg, "avg_launch_ms": avg_s * 1e3, "launches": launches}
+
+
+def alu_roofline(roof, flop_per_dof, dof, precision):
+    """The same launches against the vector ALU peak: algorithmic flops per launch
+    (right-hand side plus stage combination, per DOF) over the average launch time."""
+    flops = flop_per_dof * dof
+    achieved = flops / (roof["avg_launch_ms"] / 1e3) / 1e12
+    peak = FP64_VECTOR_TFLOPS if precision == "fp64" else FP32_VECTOR_TFLOPS
+    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "flop_per_dof_per_launch": flop_per_dof}
 
 
 def other_workloads(torch, Solver, inputs, steps):
@@ -254,6 +268,8 @@ def main():
     # per-pass device times over a second run of K steps (events around each launch)
     passes = pass_times(sol, u, args.steps)
     roofline = roofline_for(passes, args.precision)
+    roof_alu = alu_roofline(roofline, SV_FLOP_PER_DOF_LAUNCH, int(sol.info["n_dof"]), args.precision) \
+        if args.config == "shock_vortex" else None
     sol.close()
 
     # the other precision on the same workload: throughput and the L2 distance of
@@ -288,6 +304,7 @@ def main():
                                            cfg.get("rdim", 1), sol.info["n_nodes"], sol.shape[0], n_dof),
                    "precision": args.precision, "wall_s_timed": wall},
         "roofline": roofline,
+        "roofline_alu": roof_alu,
         "passes_ms_per_step": {k: v[1] / args.steps for k, v in passes.items()},
         "fp32_mixed": other,
         "adjoint": adjoint,

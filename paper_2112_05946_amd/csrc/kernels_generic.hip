@@ -474,10 +474,49 @@ __global__ void __launch_bounds__(kElemBlock) k_limiter(KParams P, double* __res
       return;
     }
   }
+  // node-by-node test: the solution-point values at every node first go to an
+  // LDS table (all threads busy), face values interpolate from it
+  double* sN = sc + S * M * nsp;  // [S][nsp][Nq] when staged == 2
+  if (staged == 2) {
+    for (int it = threadIdx.x; it < S * nsp * Nq; it += kElemBlock) {
+      const int s = it / (nsp * Nq), rem = it - s * nsp * Nq;
+      const int j = rem / Nq, q = rem - j * Nq;
+      double acc = 0.0;
+      for (int k = 0; k < M; ++k) acc += C[((long)s * M + k) * cs + j] * P.tab.Phi[k * Nq + q];
+      sN[it] = acc;
+    }
+    __syncthreads();
+  }
+  auto point = [&](int pt, int q, double* U) {
+    if (staged != 2) {
+      limiter_point<EQ, DIM>(P, C, cs, pt, q, U);
+      return;
+    }
+    const int n = P.np1;
+    if (pt < nsp) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) U[s] = sN[((long)s * nsp + pt) * Nq + q];
+      return;
+    }
+    const int f = pt - nsp;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      double acc = 0.0;
+      if constexpr (DIM == 1) {
+        const double* l = (f == 0) ? P.tab.lL : P.tab.lR;
+        for (int j = 0; j < n; ++j) acc += l[j] * sN[((long)s * nsp + j) * Nq + q];
+      } else {
+        const int side = f / n, i = f % n;
+        const double* l = (side == 0 || side == 2) ? P.tab.lL : P.tab.lR;
+        for (int c = 0; c < n; ++c) acc += l[c] * sN[((long)s * nsp + (side < 2 ? (c + n * i) : (i + n * c))) * Nq + q];
+      }
+      U[s] = acc;
+    }
+  };
   double rmin = INFINITY, pmin = INFINITY;
   for (int it = threadIdx.x; it < items; it += kElemBlock) {
     double U[S];
-    limiter_point<EQ, DIM>(P, C, cs, it / Nq, it % Nq, U);
+    point(it / Nq, it % Nq, U);
     rmin = fmin(rmin, U[0]);
     pmin = fmin(pmin, pressure<EQ>(U, P.gamma));
   }
@@ -491,7 +530,7 @@ __global__ void __launch_bounds__(kElemBlock) k_limiter(KParams P, double* __res
   double bmin = 1.0;
   for (int it = threadIdx.x; it < items; it += kElemBlock) {
     double U[S];
-    limiter_point<EQ, DIM>(P, C, cs, it / Nq, it % Nq, U);
+    point(it / Nq, it % Nq, U);
     U[0] = beta1 * (U[0] - ub[0]) + ub[0];
     if (pressure<EQ>(U, P.gamma) < eps) bmin = fmin(bmin, pressure_root<EQ>(ub, U, eps, P.gamma));
   }
@@ -678,10 +717,12 @@ hipError_t launch_project_ic(const KParams& P, const double* U0, double* u, hipS
 }
 
 hipError_t launch_limiter(const KParams& P, double* u, unsigned char* flags, hipStream_t s) {
-  // stage the element's coefficients in LDS when they fit in 32 KB
+  // stage the element's coefficients in LDS when they fit in 32 KB (staged = 1),
+  // with the nodal table of the solution points as well when both fit in 48 KB (2)
   const size_t bytes = sizeof(double) * (size_t)P.S * P.M * P.nsp;
-  const int staged = bytes <= 32 * 1024 ? 1 : 0;
-  const size_t shmem = staged ? bytes : 0;
+  const size_t nodal = sizeof(double) * (size_t)P.S * P.nsp * P.Nq;
+  const int staged = bytes + nodal <= 48 * 1024 ? 2 : (bytes <= 32 * 1024 ? 1 : 0);
+  const size_t shmem = staged == 2 ? bytes + nodal : (staged ? bytes : 0);
   if (P.eq == kEuler1)
     hipLaunchKernelGGL((k_limiter<kEuler1, 1>), dim3(P.E), dim3(kElemBlock), shmem, s, P, u, flags, staged);
   else if (P.eq == kEuler2)
