@@ -277,3 +277,32 @@ def test_fused_edge_cases(label, over):
     assert rel_l2(got, ofr.rhs(prob, T, R, u)) < RTOL_FP64
     u0 = project_initial(prob, cfg["ic"], (T, R))
     _run_steps(cfg, u0, 2)
+
+
+@pytest.mark.parametrize("label,cfg", [("burgers", inputs.small(inputs.BURGERS, 21)),
+                                       ("sod", inputs.small(inputs.SOD, 30))])
+def test_steps_1d_matches_oracle(label, cfg):
+    """fr_sg_steps on the fused 1D path: per-step dt and flags, final state."""
+    import torch
+    announce("steps_1d", label)
+    prob, (T, R) = oracle_for(cfg)
+    u0 = project_initial(prob, cfg["ic"], (T, R))
+    n = 6
+    ref, rdts, rflags, recs = u0.copy(), [], [], []
+    for _ in range(n):
+        rec = []
+        ref, rdt, fl = ostep.step(prob, ref, None, (T, R), record=rec)
+        rdts.append(rdt)
+        rflags.append(fl)
+        recs.append(rec)
+    sol = solver_for(cfg)
+    ud = to_dev(u0)
+    dts = torch.empty(n, dtype=torch.float64, device=ud.device)
+    flags = torch.empty(n * 4 * prob.E, dtype=torch.uint8, device=ud.device)
+    sol.steps(ud, n, dts, flags)
+    sol.sync()
+    assert np.allclose(to_np(dts), rdts, rtol=1e-13, atol=0)
+    g = to_np(flags).reshape(n, 4, prob.E)
+    for i in range(n):
+        check_flags(prob, T, R, g[i], rflags[i], recs[i])
+    assert rel_l2(to_np(ud), ref) < RTOL_FP64
