@@ -306,3 +306,23 @@ def test_steps_1d_matches_oracle(label, cfg):
     for i in range(n):
         check_flags(prob, T, R, g[i], rflags[i], recs[i])
     assert rel_l2(to_np(ud), ref) < RTOL_FP64
+
+
+def test_burgers_adjoint_workload_full_horizon():
+    """4096 elements, 500 steps at the CFL step of the initial state held fixed, against the oracle."""
+    cfg = inputs.BURGERS_ADJOINT
+    announce("burgers_4096_500_steps")
+    prob, (T, R) = oracle_for(cfg)
+    u0 = project_initial(prob, cfg["ic"], (T, R))
+    dt = ostep.cfl_dt(prob, T, R, u0)
+    ref = u0.copy()
+    for _ in range(cfg["n_steps"]):
+        ref, _, _ = ostep.step(prob, ref, dt, (T, R))
+    sol = solver_for(cfg)
+    ud = to_dev(u0)
+    for _ in range(cfg["n_steps"]):
+        sol.step(ud, dt)
+    sol.sync()
+    err = rel_l2(to_np(ud), ref)
+    print("[full horizon] 500 steps rel L2 %.2e" % err, flush=True)
+    assert err < RTOL_FP64
