@@ -543,56 +543,58 @@ static fr_sg_status step_generic(fr_sg_ctx* ctx, double* u, double dt, double* d
 }
 
 // The three stage states of the fused 1D path: w1 = u + dt R(u), w2 = 3/4 u + 1/4 (w1
-// + dt R(w1)), out = 1/3 u + 2/3 (w2 + dt R(w2)), each followed by the limiter (or a
-// flag clear) when lim is set; the third stage only when out is not null.
+// + dt R(w1)), out = 1/3 u + 2/3 (w2 + dt R(w2)).  With lim set every stage output is
+// limited (Euler) or its limiter flags cleared, and the third stage also runs the
+// detector-switched filter and the CFL maximum of its output (into lam_next); the
+// third stage only runs when out is not null.
 static fr_sg_status stages_fused1d(fr_sg_ctx* ctx, const double* u, double* out, uint8_t* f0, uint8_t* f1,
-                                   uint8_t* f3, bool lim) {
+                                   uint8_t* f2, uint8_t* f3, bool lim, unsigned long long* lam_next) {
   const KParams& K = ctx->kp;
   Workspace& W = ctx->ws;
   hipStream_t s = ctx->stream;
   const double sb = state_bytes(ctx);
-  const bool limiter = ctx->prob.limiter != 0;
+  const int limiter = (lim && ctx->prob.limiter) ? 1 : 0;
+  const bool clear = lim && !limiter;
   fr_sg_status st;
   if ((st = timed(ctx, "stage1", 2 * sb, [&] {
-         return launch_stage1d(K, u, u, u, W.w1, 0.0, 1.0, 0, (lim && !limiter) ? f0 : nullptr, s);
+         return launch_stage1d(K, u, u, u, W.w1, 0.0, 1.0, 0, clear ? f0 : nullptr, s, limiter, 0, f0);
        })))
     return st;
-  if (lim && limiter && (st = fr_sg_limit(ctx, W.w1, f0)) != FRSG_OK) return st;
   if ((st = timed(ctx, "stage2", 3 * sb, [&] {
-         return launch_stage1d(K, W.w1, u, W.w1, W.w2, 0.75, 0.25, 0, (lim && !limiter) ? f1 : nullptr, s);
+         return launch_stage1d(K, W.w1, u, W.w1, W.w2, 0.75, 0.25, 0, clear ? f1 : nullptr, s, limiter, 0, f1);
        })))
     return st;
-  if (lim && limiter && (st = fr_sg_limit(ctx, W.w2, f1)) != FRSG_OK) return st;
   if (!out) return FRSG_OK;
   return timed(ctx, "stage3", 3 * sb, [&] {
-    return launch_stage1d(K, W.w2, u, W.w2, out, 1.0 / 3.0, 2.0 / 3.0, 0, (lim && !limiter) ? f3 : nullptr, s);
+    return launch_stage1d(K, W.w2, u, W.w2, out, 1.0 / 3.0, 2.0 / 3.0, 0, clear ? f3 : nullptr, s, limiter,
+                          lim ? 1 : 0, f3, f2, lam_next);
   });
 }
 
-// fused 1D step: CFL pass (when dt <= 0), three stage kernels, filter, limiter
-static fr_sg_status step_fused1d(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, uint8_t* flags) {
+// fused 1D step: CFL pass (dt <= 0 and no maximum from the previous step), three
+// stage kernels with the limiter, filter and next CFL maximum in their epilogues
+static fr_sg_status step_fused1d(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, uint8_t* flags,
+                                 bool reuse_cfl) {
   const KParams& K = ctx->kp;
+  Workspace& W = ctx->ws;
   hipStream_t s = ctx->stream;
   const int E = ctx->E;
-  const bool cfl = !(dt > 0.0);
+  unsigned long long* lam[2] = {(unsigned long long*)(W.scal + 1), (unsigned long long*)(W.scal + 3)};
+  const int cur = ctx->lam_cur;
+  fr_sg_status st;
+  if (dt > 0.0) {
+    FRSG_TRY_HIP(launch_set_dt(K, dt, nullptr, lam[cur ^ 1], s), ctx);
+  } else {
+    if (!reuse_cfl)
+      if ((st = timed(ctx, "cfl", state_bytes(ctx), [&] { return launch_cfl1d(K, u, lam[cur], s); }))) return st;
+    FRSG_TRY_HIP(launch_dt_from(K, lam[cur], lam[cur ^ 1], nullptr, s), ctx);
+  }
   uint8_t* f0 = flags ? flags : nullptr;
   uint8_t* f1 = flags ? flags + E : nullptr;
   uint8_t* f2 = flags ? flags + 2 * E : nullptr;
   uint8_t* f3 = flags ? flags + 3 * E : nullptr;
-  fr_sg_status st;
-  FRSG_TRY_HIP(launch_set_scalars(K, cfl ? 0.0 : dt, s), ctx);
-  if (cfl) {
-    if ((st = timed(ctx, "cfl", state_bytes(ctx), [&] { return launch_cfl1d(K, u, s); }))) return st;
-    FRSG_TRY_HIP(launch_dt(K, 1, nullptr, s), ctx);
-  }
-  if ((st = stages_fused1d(ctx, u, u, f0, f1, f3, true)) != FRSG_OK) return st;
-  if (ctx->prob.filter != FRSG_FILTER_NONE) {
-    if ((st = timed(ctx, "sensor_filter", 2 * state_bytes(ctx), [&] { return launch_sensor_filter(K, u, f2, s); })))
-      return st;
-  } else if (f2) {
-    FRSG_TRY_HIP(launch_fill_flags(f2, E, s), ctx);
-  }
-  if (ctx->prob.limiter && (st = fr_sg_limit(ctx, u, f3)) != FRSG_OK) return st;
+  if ((st = stages_fused1d(ctx, u, u, f0, f1, f2, f3, true, lam[cur ^ 1])) != FRSG_OK) return st;
+  ctx->lam_cur = cur ^ 1;
   if (dt_used) FRSG_TRY_HIP(launch_copy_dt(K, dt_used, s), ctx);
   return FRSG_OK;
 }
@@ -653,7 +655,7 @@ fr_sg_status fr_sg_step(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, u
   fr_sg_status st = check_step_args(ctx, u, dt);
   if (st != FRSG_OK) return st;
   if (ctx->fused) return step_fused(ctx, u, dt, dt_used, flags, false);
-  if (ctx->fused1d) return step_fused1d(ctx, u, dt, dt_used, flags);
+  if (ctx->fused1d) return step_fused1d(ctx, u, dt, dt_used, flags, false);
   return step_generic(ctx, u, dt, dt_used, flags);
 }
 
@@ -671,7 +673,7 @@ fr_sg_status fr_sg_steps(fr_sg_ctx* ctx, double* u, int32_t nsteps, double* dt_u
     if (ctx->fused)
       st = step_fused(ctx, u, 0.0, dtu, f, i > 0);
     else if (ctx->fused1d)
-      st = step_fused1d(ctx, u, 0.0, dtu, f);
+      st = step_fused1d(ctx, u, 0.0, dtu, f, i > 0);
     else
       st = step_generic(ctx, u, 0.0, dtu, f);
     if (st != FRSG_OK) return st;
@@ -707,7 +709,8 @@ fr_sg_status fr_sg_adjoint_step(fr_sg_ctx* ctx, const double* u_n, const uint8_t
   // stage states of the forward step, recomputed with the same kernels as the
   // forward step (no limiter: the scalar equations do not use it)
   if (ctx->fused1d) {
-    if ((st = stages_fused1d(ctx, u_n, nullptr, nullptr, nullptr, nullptr, false)) != FRSG_OK) return st;
+    if ((st = stages_fused1d(ctx, u_n, nullptr, nullptr, nullptr, nullptr, nullptr, false, nullptr)) != FRSG_OK)
+      return st;
   } else {
     if ((st = rhs_passes(ctx, u_n, 0)) != FRSG_OK) return st;
     if ((st = timed(ctx, "adj_fwd_stage1", 2 * sb,

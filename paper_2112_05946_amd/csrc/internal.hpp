@@ -189,9 +189,14 @@ hipError_t launch_copy_dt(const KParams& P, double* dt_used, hipStream_t s);
 
 // fused 1D stage kernel (kernels_fr1d.hip)
 bool fr1d_supported(const KParams& P);
+// limit: positivity limiter on the output (flag_lim); end_of_step: detector-
+// switched filter before the limiter (flag_filt) and the CFL maximum of the
+// output into lam_next (may be null)
 hipError_t launch_stage1d(const KParams& P, const double* in, const double* u, const double* w, double* out, double cu,
-                          double cw, int rhs_only, unsigned char* clear_flags, hipStream_t s);
-hipError_t launch_cfl1d(const KParams& P, const double* u, hipStream_t s);
+                          double cw, int rhs_only, unsigned char* clear_flags, hipStream_t s, int limit = 0,
+                          int end_of_step = 0, unsigned char* flag_lim = nullptr, unsigned char* flag_filt = nullptr,
+                          unsigned long long* lam_next = nullptr);
+hipError_t launch_cfl1d(const KParams& P, const double* u, unsigned long long* lam, hipStream_t s);
 
 // adjoint launchers (kernels_adjoint.hip)
 long adjoint_partials(const KParams& P);

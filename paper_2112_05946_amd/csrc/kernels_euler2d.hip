@@ -829,7 +829,7 @@ __global__ void __launch_bounds__(BLK) k_cfl2d(KParams P, const double* __restri
 
 __global__ void k_dt_from(KParams P, const unsigned long long* lam, unsigned long long* lam_reset, double* dt_used) {
   const double l = __longlong_as_double((long long)*lam);
-  const double dt = P.cfl / (P.np1 * l);
+  const double dt = (P.dim == 1 ? P.cfl * P.dx : P.cfl) / (P.np1 * l);  // 1D: CFL dx / ((p+1) lambda)
   if (!(dt > 0.0) || !isfinite(dt)) atomicOr(P.status, kStatusNonFinite);
   *P.dt = dt;
   if (dt_used) *dt_used = dt;

@@ -40,6 +40,11 @@ struct Stage1DArgs {
   int rhs_only;
   unsigned char* clear_flags;  // per element, set to 0 (no limiter); may be null
   int EB;                      // elements per workgroup
+  int limit;                   // apply the positivity limiter to the output (Euler)
+  int end_of_step;             // detector-switched filter before the limiter, CFL maximum after
+  unsigned char* flag_lim;     // per element: limiter acted (may be null)
+  unsigned char* flag_filt;    // per element: filter acted (may be null)
+  unsigned long long* lam_next;  // CFL accumulator of the output (end of step; may be null)
 };
 
 template <int EQ, int N>
@@ -162,8 +167,11 @@ __global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
   }
   __syncthreads();
 
-  // 4. projection and stage combination
+  // 4. projection and stage combination; with an epilogue the output stays in
+  // LDS (over the staged input, no longer needed) until the epilogue is done
   const double dt = A.rhs_only ? 0.0 : *P.dt;
+  const bool epi = A.limit || A.end_of_step;
+  double* sO = sC;  // [EB][S][M][n] output coefficients
   const int ospan = nloc * n;
   for (int it = tid; it < S * M * ospan; it += kBlock1) {
     const int sk = it / ospan, rem = it - sk * ospan;
@@ -173,16 +181,225 @@ __global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
     double acc = 0.0;
     for (int qq = 0; qq < Nq; ++qq) acc += P.tab.PW[k * Nq + qq] * Rq[qq];
     const long idx = (long)sk * EN + (long)(e0 + le) * n + j;
-    A.out[idx] = A.rhs_only ? acc : A.cu * A.u[idx] + A.cw * (A.w[idx] + dt * acc);
+    const double v = A.rhs_only ? acc : A.cu * A.u[idx] + A.cw * (A.w[idx] + dt * acc);
+    if (epi)
+      sO[le * ncoef + sk * n + j] = v;
+    else
+      A.out[idx] = v;
   }
   if (A.clear_flags)
     for (int it = tid; it < nloc; it += kBlock1) A.clear_flags[e0 + it] = 0;
+  if (!epi) return;
+  __syncthreads();
+
+  // 5. element epilogue: thread (owned element le, node q); per-(element, node)
+  // partial results go to sP (the trace buffer, free now) and are combined by
+  // every thread of the element in the same order
+  const bool own = active && ls >= 1 && ls <= nloc;
+  const int le = ls - 1;
+  double* O = sO + (own ? le : 0) * ncoef;
+  constexpr int PS = 2 * S;  // slots per (element, node) in the trace buffer
+  double* sP = sTr;          // [EB + 2][Nq][PS]
+  double* myP = sP + ((long)ls * Nq + q) * PS;
+  auto elemP = [&](int slot, int qq) { return sP[((long)ls * Nq + qq) * PS + slot]; };
+
+  // 5a. detector and modal filter (Sec. 4.2, 4.1): thread q owns chaos mode k = q
+  if (A.end_of_step && P.filter != FRSG_FILTER_NONE) {
+    const int k = q;
+    double ut[S][N];
+    double num = 0.0, den = 0.0;
+    if (own && k < M) {
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int m = 0; m < n; ++m) {
+          double acc = 0.0;
+#pragma unroll
+          for (int j = 0; j < n; ++j) acc += P.tab.Vinv[m * n + j] * O[(s * M + k) * n + j];
+          ut[s][m] = acc;
+        }
+#pragma unroll
+      for (int m = 0; m < n; ++m) {
+        const double e2 = ut[0][m] * ut[0][m];
+        num += e2 * P.tab.shell[k * n + m];
+        den += e2;
+      }
+    }
+    if (own) {
+      myP[0] = num;
+      myP[1] = den;
+    }
+    __syncthreads();
+    bool flag = false;
+    if (own) {
+      double tn = 0.0, td = 0.0;
+      for (int qq = 0; qq < M; ++qq) {
+        tn += elemP(0, qq);
+        td += elemP(1, qq);
+      }
+      flag = (P.sensor == FRSG_SENSOR_ALWAYS) || (td > 0.0 && tn / td > P.sensor_thr);
+      if (flag && k < M) {
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+          for (int j = 0; j < n; ++j) {
+            double acc = 0.0;
+#pragma unroll
+            for (int m = 0; m < n; ++m) {
+              const double f = P.tab.filt[k * n + m];
+              const double lam = (P.filter == FRSG_FILTER_EXP) ? exp(-P.alpha * dt * f) : f;
+              acc += P.tab.V[j * n + m] * (ut[s][m] * lam);
+            }
+            O[(s * M + k) * n + j] = acc;
+          }
+      }
+      if (q == 0 && A.flag_filt) A.flag_filt[e0 + le] = flag ? 1 : 0;
+    }
+    __syncthreads();
+  } else if (A.end_of_step && A.flag_filt) {
+    if (own && q == 0) A.flag_filt[e0 + le] = 0;
+  }
+
+  // 5b. positivity limiter (Sec. 4.3): minimum of density and pressure over the
+  // solution and face points at node q, then over the element's nodes
+  if constexpr (S > 1) {
+    if (A.limit) {
+      const double g = P.gamma;
+      double ub[S];
+      bool realizable = false;
+      double eps = 0.0;
+      // values at node q: the n solution points, then the two faces by interpolation
+      double Usp[S][N], Ufc[S][2];
+      auto point = [&](int pt, double* U) {  // pt < n: solution point; n, n+1: faces
+#pragma unroll
+        for (int s = 0; s < S; ++s) U[s] = pt < n ? Usp[s][pt] : Ufc[s][pt - n];
+      };
+      if (own) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+#pragma unroll
+          for (int j = 0; j < n; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < M; ++k) acc += O[(s * M + k) * n + j] * P.tab.Phi[k * Nq + q];
+            Usp[s][j] = acc;
+          }
+          double a = 0.0, b = 0.0;
+#pragma unroll
+          for (int j = 0; j < n; ++j) {
+            a += P.tab.lL[j] * Usp[s][j];
+            b += P.tab.lR[j] * Usp[s][j];
+          }
+          Ufc[s][0] = a;
+          Ufc[s][1] = b;
+        }
+      }
+      if (own) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          double acc = 0.0;
+#pragma unroll
+          for (int j = 0; j < n; ++j) acc += O[(s * M) * n + j] * P.tab.swts[j];
+          ub[s] = acc;
+        }
+        const double pb = pressure<EQ>(ub, g);
+        bool finite = true;
+#pragma unroll
+        for (int s = 0; s < S; ++s) finite = finite && isfinite(ub[s]);
+        realizable = ub[0] > 0.0 && pb > 0.0 && finite;
+        if (!realizable && q == 0) atomicOr(P.status, kStatusNotRealizable);
+        eps = fmin(1e-8, fmin(ub[0], pb));
+        double rmin = INFINITY, pmin = INFINITY;
+        if (realizable)
+#pragma unroll
+          for (int pt = 0; pt < n + 2; ++pt) {
+            double U[S];
+            point(pt, U);
+            rmin = fmin(rmin, U[0]);
+            pmin = fmin(pmin, pressure<EQ>(U, g));
+          }
+        myP[0] = rmin;
+        myP[1] = pmin;
+      }
+      __syncthreads();
+      bool on = false;
+      double beta1 = 1.0;
+      if (own && realizable) {
+        double rmin = INFINITY, pmin = INFINITY;
+        for (int qq = 0; qq < Nq; ++qq) {
+          rmin = fmin(rmin, elemP(0, qq));
+          pmin = fmin(pmin, elemP(1, qq));
+        }
+        on = fmin(rmin, pmin) < eps;
+        if (on) {
+          beta1 = (rmin >= eps) ? 1.0 : (ub[0] - eps) / (ub[0] - rmin);
+          double bmin = 1.0;
+#pragma unroll
+          for (int pt = 0; pt < n + 2; ++pt) {
+            double U[S];
+            point(pt, U);
+            U[0] = beta1 * (U[0] - ub[0]) + ub[0];
+            if (pressure<EQ>(U, g) < eps) bmin = fmin(bmin, pressure_root<EQ>(ub, U, eps, g));
+          }
+          myP[2] = bmin;
+        }
+      }
+      __syncthreads();
+      if (own && on) {
+        double beta2 = 1.0;
+        for (int qq = 0; qq < Nq; ++qq) beta2 = fmin(beta2, elemP(2, qq));
+        for (int it = q; it < S * M * n; it += Nq) {
+          const int s = it / (M * n), k = (it / n) % M;
+          const double m0 = (k == 0) ? 1.0 : 0.0;
+          double v = O[it];
+          if (s == 0) v = beta1 * (v - ub[0] * m0) + ub[0] * m0;
+          O[it] = beta2 * (v - ub[s] * m0) + ub[s] * m0;
+        }
+      }
+      if (own && q == 0 && A.flag_lim) A.flag_lim[e0 + le] = on ? 1 : 0;
+      __syncthreads();
+    }
+  }
+
+  // 5c. CFL maximum of the output for the next step
+  if (A.end_of_step && A.lam_next) {
+    __shared__ double sm[kBlock1];
+    double rate = 0.0;
+    if (own) {
+      for (int j = 0; j < n; ++j) {
+        double U[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          double acc = 0.0;
+          for (int k = 0; k < M; ++k) acc += O[(s * M + k) * n + j] * P.tab.Phi[k * Nq + q];
+          U[s] = acc;
+        }
+        double r = speed<EQ, 0>(U, P.adv, P.gamma);
+        if (!(r == r)) r = __longlong_as_double(0x7ff0000000000000ll);  // NaN -> +inf, dt -> 0
+        rate = fmax(rate, r);
+      }
+    }
+    sm[tid] = rate;
+    __syncthreads();
+    for (int o = kBlock1 / 2; o > 0; o >>= 1) {
+      if (tid < o) sm[tid] = fmax(sm[tid], sm[tid + o]);
+      __syncthreads();
+    }
+    if (tid == 0) atomicMax(A.lam_next, (unsigned long long)__double_as_longlong(sm[0]));
+  }
+
+  // 6. output
+  for (int it = tid; it < S * M * ospan; it += kBlock1) {
+    const int sk = it / ospan, rem = it - sk * ospan;
+    const int le2 = rem / n, j = rem - le2 * n;
+    A.out[(long)sk * EN + (long)(e0 + le2) * n + j] = sO[le2 * ncoef + sk * n + j];
+  }
 }
 
 // CFL maximum of a 1D state: a workgroup stages the coefficients of 256 / Nq
 // elements in LDS; thread (element, node q) takes the maximum over the points
 template <int EQ>
-__global__ void __launch_bounds__(kBlock1) k_cfl1d(KParams P, const double* __restrict__ u, int EB) {
+__global__ void __launch_bounds__(kBlock1) k_cfl1d(KParams P, const double* __restrict__ u, int EB,
+                                                   unsigned long long* lam) {
   constexpr int S = nstate<EQ>();
   extern __shared__ double sC[];  // [EB][S][M][n]
   __shared__ double sm[kBlock1];
@@ -219,8 +436,10 @@ __global__ void __launch_bounds__(kBlock1) k_cfl1d(KParams P, const double* __re
     if ((int)threadIdx.x < o) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + o]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) atomicMax(P.lam_bits, (unsigned long long)__double_as_longlong(sm[0]));
+  if (threadIdx.x == 0) atomicMax(lam, (unsigned long long)__double_as_longlong(sm[0]));
 }
+
+__global__ void k_zero_lam(unsigned long long* lam) { *lam = 0ull; }
 
 }  // namespace
 
@@ -249,12 +468,14 @@ bool fr1d_supported(const KParams& P) {
 }
 
 hipError_t launch_stage1d(const KParams& P, const double* in, const double* u, const double* w, double* out, double cu,
-                          double cw, int rhs_only, unsigned char* clear_flags, hipStream_t s) {
+                          double cw, int rhs_only, unsigned char* clear_flags, hipStream_t s, int limit,
+                          int end_of_step, unsigned char* flag_lim, unsigned char* flag_filt,
+                          unsigned long long* lam_next) {
   int EB;
   size_t shmem;
   fr1d_shape(P, EB, shmem);
   if (EB == 0) return hipErrorInvalidValue;
-  Stage1DArgs A{in, u, w, out, cu, cw, rhs_only, clear_flags, EB};
+  Stage1DArgs A{in, u, w, out, cu, cw, rhs_only, clear_flags, EB, limit, end_of_step, flag_lim, flag_filt, lam_next};
   const unsigned grid = (unsigned)((P.E + EB - 1) / EB);
   auto go = [&](auto eq_tag) -> hipError_t {
     constexpr int EQ = decltype(eq_tag)::value;
@@ -275,15 +496,16 @@ hipError_t launch_stage1d(const KParams& P, const double* in, const double* u, c
   }
 }
 
-hipError_t launch_cfl1d(const KParams& P, const double* u, hipStream_t s) {
+hipError_t launch_cfl1d(const KParams& P, const double* u, unsigned long long* lam, hipStream_t s) {
   const int EB = kBlock1 / P.Nq;  // >= 1 wherever the fused 1D path runs
   if (EB < 1) return hipErrorInvalidValue;
   const size_t shmem = sizeof(double) * (size_t)EB * P.S * P.M * P.np1;
   const unsigned grid = (unsigned)((P.E + EB - 1) / EB);
+  hipLaunchKernelGGL(k_zero_lam, dim3(1), dim3(1), 0, s, lam);
   switch (P.eq) {
-    case kAdvection: hipLaunchKernelGGL(k_cfl1d<kAdvection>, dim3(grid), dim3(kBlock1), shmem, s, P, u, EB); break;
-    case kBurgers: hipLaunchKernelGGL(k_cfl1d<kBurgers>, dim3(grid), dim3(kBlock1), shmem, s, P, u, EB); break;
-    case kEuler1: hipLaunchKernelGGL(k_cfl1d<kEuler1>, dim3(grid), dim3(kBlock1), shmem, s, P, u, EB); break;
+    case kAdvection: hipLaunchKernelGGL(k_cfl1d<kAdvection>, dim3(grid), dim3(kBlock1), shmem, s, P, u, EB, lam); break;
+    case kBurgers: hipLaunchKernelGGL(k_cfl1d<kBurgers>, dim3(grid), dim3(kBlock1), shmem, s, P, u, EB, lam); break;
+    case kEuler1: hipLaunchKernelGGL(k_cfl1d<kEuler1>, dim3(grid), dim3(kBlock1), shmem, s, P, u, EB, lam); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
