@@ -548,7 +548,9 @@ static fr_sg_status step_generic(fr_sg_ctx* ctx, double* u, double dt, double* d
 // detector-switched filter and the CFL maximum of its output (into lam_next); the
 // third stage only runs when out is not null.
 static fr_sg_status stages_fused1d(fr_sg_ctx* ctx, const double* u, double* out, uint8_t* f0, uint8_t* f1,
-                                   uint8_t* f2, uint8_t* f3, bool lim, unsigned long long* lam_next) {
+                                   uint8_t* f2, uint8_t* f3, bool lim, unsigned long long* lam_next,
+                                   int dt_source = 0, double dt_fixed = 0.0,
+                                   const unsigned long long* lam_in = nullptr, double* dt_used = nullptr) {
   const KParams& K = ctx->kp;
   Workspace& W = ctx->ws;
   hipStream_t s = ctx->stream;
@@ -557,7 +559,8 @@ static fr_sg_status stages_fused1d(fr_sg_ctx* ctx, const double* u, double* out,
   const bool clear = lim && !limiter;
   fr_sg_status st;
   if ((st = timed(ctx, "stage1", 2 * sb, [&] {
-         return launch_stage1d(K, u, u, u, W.w1, 0.0, 1.0, 0, clear ? f0 : nullptr, s, limiter, 0, f0);
+         return launch_stage1d(K, u, u, u, W.w1, 0.0, 1.0, 0, clear ? f0 : nullptr, s, limiter, 0, f0, nullptr,
+                               nullptr, dt_source, dt_fixed, lam_in, lam_next, dt_used);
        })))
     return st;
   if ((st = timed(ctx, "stage2", 3 * sb, [&] {
@@ -572,7 +575,8 @@ static fr_sg_status stages_fused1d(fr_sg_ctx* ctx, const double* u, double* out,
 }
 
 // fused 1D step: CFL pass (dt <= 0 and no maximum from the previous step), three
-// stage kernels with the limiter, filter and next CFL maximum in their epilogues
+// stage kernels with the limiter, filter and next CFL maximum in their epilogues;
+// the first stage derives and publishes dt
 static fr_sg_status step_fused1d(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, uint8_t* flags,
                                  bool reuse_cfl) {
   const KParams& K = ctx->kp;
@@ -582,20 +586,17 @@ static fr_sg_status step_fused1d(fr_sg_ctx* ctx, double* u, double dt, double* d
   unsigned long long* lam[2] = {(unsigned long long*)(W.scal + 1), (unsigned long long*)(W.scal + 3)};
   const int cur = ctx->lam_cur;
   fr_sg_status st;
-  if (dt > 0.0) {
-    FRSG_TRY_HIP(launch_set_dt(K, dt, nullptr, lam[cur ^ 1], s), ctx);
-  } else {
-    if (!reuse_cfl)
-      if ((st = timed(ctx, "cfl", state_bytes(ctx), [&] { return launch_cfl1d(K, u, lam[cur], s); }))) return st;
-    FRSG_TRY_HIP(launch_dt_from(K, lam[cur], lam[cur ^ 1], nullptr, s), ctx);
-  }
+  const bool fixed = dt > 0.0;
+  if (!fixed && !reuse_cfl)
+    if ((st = timed(ctx, "cfl", state_bytes(ctx), [&] { return launch_cfl1d(K, u, lam[cur], s); }))) return st;
   uint8_t* f0 = flags ? flags : nullptr;
   uint8_t* f1 = flags ? flags + E : nullptr;
   uint8_t* f2 = flags ? flags + 2 * E : nullptr;
   uint8_t* f3 = flags ? flags + 3 * E : nullptr;
-  if ((st = stages_fused1d(ctx, u, u, f0, f1, f2, f3, true, lam[cur ^ 1])) != FRSG_OK) return st;
+  if ((st = stages_fused1d(ctx, u, u, f0, f1, f2, f3, true, lam[cur ^ 1], fixed ? 1 : 2, fixed ? dt : 0.0,
+                           lam[cur], dt_used)) != FRSG_OK)
+    return st;
   ctx->lam_cur = cur ^ 1;
-  if (dt_used) FRSG_TRY_HIP(launch_copy_dt(K, dt_used, s), ctx);
   return FRSG_OK;
 }
 

@@ -191,11 +191,15 @@ hipError_t launch_copy_dt(const KParams& P, double* dt_used, hipStream_t s);
 bool fr1d_supported(const KParams& P);
 // limit: positivity limiter on the output (flag_lim); end_of_step: detector-
 // switched filter before the limiter (flag_filt) and the CFL maximum of the
-// output into lam_next (may be null)
+// output into lam_next (may be null).  dt_source: 0 reads the device dt; 1 uses
+// dt_fixed; 2 derives it from lam_in; with 1 or 2 the kernel also publishes dt
+// (device dt, dt_used) and zeroes lam_reset.
 hipError_t launch_stage1d(const KParams& P, const double* in, const double* u, const double* w, double* out, double cu,
                           double cw, int rhs_only, unsigned char* clear_flags, hipStream_t s, int limit = 0,
                           int end_of_step = 0, unsigned char* flag_lim = nullptr, unsigned char* flag_filt = nullptr,
-                          unsigned long long* lam_next = nullptr);
+                          unsigned long long* lam_next = nullptr, int dt_source = 0, double dt_fixed = 0.0,
+                          const unsigned long long* lam_in = nullptr, unsigned long long* lam_reset = nullptr,
+                          double* dt_used = nullptr);
 hipError_t launch_cfl1d(const KParams& P, const double* u, unsigned long long* lam, hipStream_t s);
 
 // adjoint launchers (kernels_adjoint.hip)

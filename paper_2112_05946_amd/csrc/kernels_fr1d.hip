@@ -45,6 +45,14 @@ struct Stage1DArgs {
   unsigned char* flag_lim;     // per element: limiter acted (may be null)
   unsigned char* flag_filt;    // per element: filter acted (may be null)
   unsigned long long* lam_next;  // CFL accumulator of the output (end of step; may be null)
+  // time step: dt_source 0 reads *P.dt; 1 takes dt_fixed; 2 computes it from the
+  // CFL accumulator lam_in.  With 1 or 2, workgroup 0 also stores it in *P.dt and
+  // dt_used, zeroes lam_reset and latches a non-finite or non-positive dt.
+  int dt_source;
+  double dt_fixed;
+  const unsigned long long* lam_in;
+  unsigned long long* lam_reset;
+  double* dt_used;
 };
 
 template <int EQ, int N>
@@ -169,7 +177,22 @@ __global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
 
   // 4. projection and stage combination; with an epilogue the output stays in
   // LDS (over the staged input, no longer needed) until the epilogue is done
-  const double dt = A.rhs_only ? 0.0 : *P.dt;
+  double dt;
+  if (A.rhs_only) {
+    dt = 0.0;
+  } else if (A.dt_source == 0) {
+    dt = *P.dt;
+  } else {
+    // dt = CFL dx / ((p+1) lambda_max) from the accumulated wave-speed maximum
+    dt = A.dt_source == 1 ? A.dt_fixed
+                          : P.cfl * P.dx / (P.np1 * __longlong_as_double((long long)*A.lam_in));
+    if (blockIdx.x == 0 && tid == 0) {
+      if (!(dt > 0.0) || !isfinite(dt)) atomicOr(P.status, kStatusNonFinite);
+      *P.dt = dt;
+      if (A.dt_used) *A.dt_used = dt;
+      if (A.lam_reset) *A.lam_reset = 0ull;
+    }
+  }
   const bool epi = A.limit || A.end_of_step;
   double* sO = sC;  // [EB][S][M][n] output coefficients
   const int ospan = nloc * n;
@@ -470,12 +493,15 @@ bool fr1d_supported(const KParams& P) {
 hipError_t launch_stage1d(const KParams& P, const double* in, const double* u, const double* w, double* out, double cu,
                           double cw, int rhs_only, unsigned char* clear_flags, hipStream_t s, int limit,
                           int end_of_step, unsigned char* flag_lim, unsigned char* flag_filt,
-                          unsigned long long* lam_next) {
+                          unsigned long long* lam_next, int dt_source, double dt_fixed,
+                          const unsigned long long* lam_in, unsigned long long* lam_reset, double* dt_used) {
   int EB;
   size_t shmem;
   fr1d_shape(P, EB, shmem);
   if (EB == 0) return hipErrorInvalidValue;
-  Stage1DArgs A{in, u, w, out, cu, cw, rhs_only, clear_flags, EB, limit, end_of_step, flag_lim, flag_filt, lam_next};
+  Stage1DArgs A{in,          u,       w,         out,         cu,         cw,        rhs_only,
+                clear_flags, EB,      limit,     end_of_step, flag_lim,   flag_filt, lam_next,
+                dt_source,   dt_fixed, lam_in,   lam_reset,   dt_used};
   const unsigned grid = (unsigned)((P.E + EB - 1) / EB);
   auto go = [&](auto eq_tag) -> hipError_t {
     constexpr int EQ = decltype(eq_tag)::value;
