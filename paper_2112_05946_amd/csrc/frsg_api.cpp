@@ -706,13 +706,15 @@ fr_sg_status fr_sg_adjoint_step(fr_sg_ctx* ctx, const double* u_n, const uint8_t
   hipStream_t s = ctx->stream;
   const double sb = state_bytes(ctx);
   fr_sg_status st;
-  FRSG_TRY_HIP(launch_set_scalars(K, dt, s), ctx);
   // stage states of the forward step, recomputed with the same kernels as the
-  // forward step (no limiter: the scalar equations do not use it)
+  // forward step (no limiter: the scalar equations do not use it); the first
+  // stage kernel publishes dt for the passes after it
   if (ctx->fused1d) {
-    if ((st = stages_fused1d(ctx, u_n, nullptr, nullptr, nullptr, nullptr, nullptr, false, nullptr)) != FRSG_OK)
+    if ((st = stages_fused1d(ctx, u_n, nullptr, nullptr, nullptr, nullptr, nullptr, false, nullptr, 1, dt)) !=
+        FRSG_OK)
       return st;
   } else {
+    FRSG_TRY_HIP(launch_set_scalars(K, dt, s), ctx);
     if ((st = rhs_passes(ctx, u_n, 0)) != FRSG_OK) return st;
     if ((st = timed(ctx, "adj_fwd_stage1", 2 * sb,
                     [&] { return launch_project_stage(K, W.Un, u_n, u_n, W.w1, 0.0, 1.0, 0, s); })))
