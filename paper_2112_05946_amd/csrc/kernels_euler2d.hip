@@ -6,21 +6,28 @@
 // 3.2-3.5) and the stage epilogue, reading each input coefficient from HBM
 // once and writing each output coefficient once:
 //
-//   * a workgroup owns a 4 x 4 tile of elements; thread (e, j) holds the 4 x M
-//     gPC coefficients of solution point j of element e in registers;
-//   * for each random node q: the gPC expansion at the node (Eq. polynomial
-//     chaos), the fluxes F, G there (Eq. local direct flux), solution traces at
-//     the 16 flux points of each element by Lagrange interpolation, the
-//     Lax-Friedrichs flux per node (Sec. 3.3), and the nodal residual
+//   * a workgroup owns a 4 x 2 tile of elements, 32 threads per element;
+//     thread (e, h, j) holds the M gPC coefficients of conserved variables 2h
+//     and 2h + 1 at solution point j of element e in registers, and
+//     accumulates their projected residual there;
+//   * random nodes go in pairs (q0, q1): each thread expands its own pair of
+//     variables at both nodes (Eq. polynomial chaos), then the two rows of an
+//     element trade halves so that rows h = 0 hold all four variables at q0
+//     and rows h = 1 at q1; at that node each thread evaluates the fluxes F,
+//     G (Eq. local direct flux), the solution trace at flux point j by
+//     Lagrange interpolation along its line, the Lax-Friedrichs flux there
+//     (Sec. 3.3) and the nodal residual
 //       R = -(1/Jx) [Dt F + F*_L h_L' + F*_R h_R']_x - (1/Jy) [...]_y,
 //     with Dt = D - h_L' l(-1)^T - h_R' l(+1)^T the derivative matrix that
 //     already subtracts the interpolated discontinuous flux at the faces
 //     (Sec. 3.4: the correction (F* - F^D) h' split into F* h' and -F^D h');
-//     R is Galerkin-projected on the fly (Eq. discrete expectation value),
-//     so the residual of the whole stage is never stored;
+//     the residuals are traded back and Galerkin-projected on the fly (Eq.
+//     discrete expectation value), so the residual of the stage is never
+//     stored;
 //   * traces of elements outside the tile come from their modal face traces,
-//     interpolated once per stage (the interpolation and the chaos expansion
-//     are both linear, so the order does not matter);
+//     interpolated once per stage and expanded at every node (the
+//     interpolation and the chaos expansion are both linear, so the order does
+//     not matter);
 //   * epilogue: SSP-RK3 combination, then the positivity limiter (Sec. 4.3) on
 //     stage outputs, or, after the third stage, the detector (Sec. 4.2), the
 //     modal filter (Sec. 4.1), the limiter and the CFL maximum of the new
@@ -32,9 +39,10 @@
 // threshold evaluate density and pressure node by node, so both routes give the
 // same decision as the node-by-node test.
 //
-// Exchanges inside an element use DPP: the 16 threads of an element form one
+// Exchanges inside an element: the 16 threads of an (element, h) form one
 // 16-lane DPP row, quad_perm rotations move along x (a) and row_ror:4k along y
-// (b).  Exchanges between elements of the tile go through LDS.
+// (b); the two rows of an element trade values with v_permlane16_swap.
+// Exchanges between elements of the tile go through LDS.
 #include <hip/hip_runtime.h>
 
 #include "device_common.hpp"
@@ -209,6 +217,31 @@ __device__ __forceinline__ void full4(int h, T v0, T v1, T* U) {
   U[3] = h ? v1 : o1;
 }
 
+// Exchange between the two 16-lane rows of each 32-lane half (v_permlane16_swap
+// of a and b): afterwards b in row 0 holds row 1's a and a in row 1 holds row
+// 0's b, while a in row 0 and b in row 1 keep their values.  Every lane of the
+// wave must be active.
+__device__ __forceinline__ void swap_rows_u32(unsigned& a, unsigned& b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+  a = r[0];
+  b = r[1];
+}
+__device__ __forceinline__ void swap_rows(float& a, float& b) {
+  unsigned x = __float_as_uint(a), y = __float_as_uint(b);
+  swap_rows_u32(x, y);
+  a = __uint_as_float(x);
+  b = __uint_as_float(y);
+}
+__device__ __forceinline__ void swap_rows(double& a, double& b) {
+  const unsigned long long x = (unsigned long long)__double_as_longlong(a);
+  const unsigned long long y = (unsigned long long)__double_as_longlong(b);
+  unsigned xl = (unsigned)x, xh = (unsigned)(x >> 32), yl = (unsigned)y, yh = (unsigned)(y >> 32);
+  swap_rows_u32(xl, yl);
+  swap_rows_u32(xh, yh);
+  a = __longlong_as_double((long long)(((unsigned long long)xh << 32) | xl));
+  b = __longlong_as_double((long long)(((unsigned long long)yh << 32) | yl));
+}
+
 // Lax-Friedrichs flux of the 2D Euler equations along direction dir (0: x, 1: y)
 // between the own trace and the neighbour's; the neighbour is the left state
 // when nb_left.  f(L) + f(R) and the jump are formed so that the result does not
@@ -235,10 +268,10 @@ __device__ __forceinline__ void rusanov_e2(const T* own, const T* nb, bool nb_le
   for (int s = 0; s < 4; ++s) Fs[s] = T(0.5) * (fo[s] + fn[s]) - hl * (nb[s] - own[s]);
 }
 
-// a pair of consecutive values, stored with one LDS access
+// the four conserved variables at one point, stored with one or two LDS accesses
 template <typename T>
-struct alignas(2 * sizeof(T)) Pair2 {
-  T x, y;
+struct alignas(4 * sizeof(T) > 16 ? 16 : 4 * sizeof(T)) Quad4 {
+  T v[4];
 };
 
 struct LaneOps {
@@ -249,7 +282,7 @@ struct LaneOps {
 // positivity limiter on one element (Sec. 4.3); o[i][k]: this lane's pair
 // ---------------------------------------------------------------------------
 template <int M, int NQ>
-__device__ int limit_pair(const KParams& P, const double* __restrict__ Phi, double (&o)[2][M], int h, int a, int b,
+__device__ int limit_pair(const KParams& P, const double* __restrict__ PhiT, double (&o)[2][M], int h, int a, int b,
                           const LaneOps& L, const double* cmax) {
   const double g = P.gamma;
   double rwx[4], rwy[4];
@@ -320,7 +353,7 @@ __device__ int limit_pair(const KParams& P, const double* __restrict__ Phi, doub
     for (int i = 0; i < 2; ++i) {
       double t = 0.0;
 #pragma unroll
-      for (int k = 0; k < M; ++k) t += o[i][k] * Phi[k * NQ + q];
+      for (int k = 0; k < M; ++k) t += o[i][k] * PhiT[q * M + k];
       u2[i] = t;
     }
     double U[4], T[4];
@@ -352,7 +385,7 @@ __device__ int limit_pair(const KParams& P, const double* __restrict__ Phi, doub
     for (int i = 0; i < 2; ++i) {
       double t = 0.0;
 #pragma unroll
-      for (int k = 0; k < M; ++k) t += o[i][k] * Phi[k * NQ + q];
+      for (int k = 0; k < M; ++k) t += o[i][k] * PhiT[q * M + k];
       u2[i] = t;
     }
     double T[4];
@@ -449,7 +482,7 @@ __device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsig
 // ---------------------------------------------------------------------------
 template <int M, int NQ, typename R>
 __global__ void __launch_bounds__(BLKS) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 2 : FRSG_FP32_WAVES)))
-k_stage2d(KParams P, StageArgs A, const double* __restrict__ Phi,
+k_stage2d(KParams P, StageArgs A, const double* __restrict__ PhiTd,
                                                   const R* __restrict__ PhiT, const R* __restrict__ PWT,
                                                   const double* __restrict__ in, const double* __restrict__ uin,
                                                   const double* in_again, double* out) {
@@ -457,12 +490,15 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ Phi,
   // it, so that the compiler cannot merge those loads with the ones at the top
   // and keep the FP64 values live across the node loop
   constexpr bool kFP64 = sizeof(R) == sizeof(double);
-  // element traces by slot: 0-15 are the flux points (x-lo row b, x-hi row b,
-  // y-lo column a, y-hi column a), 16-31 take the stores of lanes that own none
-  __shared__ Pair2<R> sT[2][TE][32][2];
-  __shared__ Pair2<R> sFs[TE][NSP][2];    // interface fluxes at the flux points
-  __shared__ R sH[NQ][NHF][NP][4];        // traces of elements outside the tile, every node
+  // per element and row h (node q0 or q1 of the pair in hand): nodal values at
+  // the solution points, traces at the flux points (x-lo row i, x-hi row i,
+  // y-lo column i, y-hi column i; two pairs in flight) and interface fluxes
+  __shared__ Quad4<R> sU[TE][2][NSP];
+  __shared__ Quad4<R> sT[2][TE][2][NSP];
+  __shared__ Quad4<R> sFs[TE][2][NSP];
+  __shared__ Quad4<R> sH[NQ][NHF][NP];    // traces of elements outside the tile, every node
   __shared__ double sLam[M * NSP];
+  __shared__ double sPhiT[NQ * M];
   __shared__ double sRed[BLKS / 64];
 
   const int tid = threadIdx.x;
@@ -500,6 +536,15 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ Phi,
     }
   }
 
+  // the basis table for the halo first (its loads are waited for first)
+  constexpr int NPHI = (NQ * M + BLKS - 1) / BLKS;
+  double phv[NPHI];
+  {
+    const auto rp = state_rsrc(PhiTd, (unsigned)(NQ * M * sizeof(double)));
+#pragma unroll
+    for (int r = 0; r < NPHI; ++r) phv[r] = bload(rp, (unsigned)((tid + r * BLKS) * sizeof(double)), 0u);
+  }
+
   // own coefficients: variables 2h, 2h+1 (the state is below 4 GiB, checked by the host)
   const unsigned sbytes = (unsigned)(4 * M * EN * (long)sizeof(double));
   const unsigned voff = (unsigned)(((long)(2 * h) * M * EN + (long)e * NSP + j) * (long)sizeof(double));
@@ -515,53 +560,69 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ Phi,
 
   // traces of the elements around the tile at every node: one thread per
   // (face hf, face point hfp, variable hs); faces: TY x-lo, TY x-hi, TX y-lo, TX y-hi
-  if (tid < NHF * NP * 4) {
-    const int hf = tid >> 4, hfp = (tid >> 2) & 3, hs = tid & 3;
+  const bool halo_thread = tid < NHF * NP * 4;
+  double hv[M][NP];  // the neighbour's coefficients along the face-normal lines
+  double lw[NP];     // Lagrange weights of the neighbour's face
+  {
+    const int hf = (tid >> 4) % NHF, hfp = (tid >> 2) & 3, hs = tid & 3;
     int nix, niy;
-    const double* l;
-    bool along_x;
-    if (hf < TY) { nix = TX * tx - 1; niy = TY * ty + hf; l = P.tab.lR; along_x = true; }
-    else if (hf < 2 * TY) { nix = TX * tx + TX; niy = TY * ty + hf - TY; l = P.tab.lL; along_x = true; }
-    else if (hf < 2 * TY + TX) { nix = TX * tx + hf - 2 * TY; niy = TY * ty - 1; l = P.tab.lR; along_x = false; }
-    else { nix = TX * tx + hf - 2 * TY - TX; niy = TY * ty + TY; l = P.tab.lL; along_x = false; }
-    bool valid = true;
+    bool along_x, from_lo;  // from_lo: the face is the neighbour's lo face (trace at -1)
+    if (hf < TY) { nix = TX * tx - 1; niy = TY * ty + hf; along_x = true; from_lo = false; }
+    else if (hf < 2 * TY) { nix = TX * tx + TX; niy = TY * ty + hf - TY; along_x = true; from_lo = true; }
+    else if (hf < 2 * TY + TX) { nix = TX * tx + hf - 2 * TY; niy = TY * ty - 1; along_x = false; from_lo = false; }
+    else { nix = TX * tx + hf - 2 * TY - TX; niy = TY * ty + TY; along_x = false; from_lo = true; }
+    bool valid = halo_thread;
     if (nix < 0) { if (P.bc[0] == FRSG_BC_PERIODIC) nix += P.nx; else valid = false; }
     if (nix >= P.nx) { if (P.bc[1] == FRSG_BC_PERIODIC) nix -= P.nx; else valid = false; }
     if (niy < 0) { if (P.bc[2] == FRSG_BC_PERIODIC) niy += P.ny; else valid = false; }
     if (niy >= P.ny) { if (P.bc[3] == FRSG_BC_PERIODIC) niy -= P.ny; else valid = false; }
+    // all loads first, without branches, so that they are in flight together; a
+    // face without a neighbour (domain boundary) reads element 0 instead, and
+    // its trace is never used: the lanes on that face take the ghost state
     const int ne = valid ? niy * P.nx + nix : 0;
+#pragma unroll
+    for (int c = 0; c < NP; ++c) lw[c] = from_lo ? P.tab.lL[c] : P.tab.lR[c];
+    const auto rh = state_rsrc(in, sbytes);
+    unsigned ho[NP];
+#pragma unroll
+    for (int c = 0; c < NP; ++c)
+      ho[c] = (unsigned)((((long)hs * M) * EN + (long)ne * NSP + (along_x ? c + NP * hfp : hfp + NP * c)) *
+                         (long)sizeof(double));
+    if (halo_thread) {  // uniform per wave
+#pragma unroll
+      for (int k = 0; k < M; ++k)
+#pragma unroll
+        for (int c = 0; c < NP; ++c) hv[k][c] = bload(rh, ho[c], soff(0, k));
+    }
+  }
+  // chaos basis at the nodes, node-major, for the expansion of the halo traces
+#pragma unroll
+  for (int r = 0; r < NPHI; ++r)
+    if (tid + r * BLKS < NQ * M) sPhiT[tid + r * BLKS] = phv[r];
+  __syncthreads();
+  if (halo_thread) {
+    const int hf = tid >> 4, hfp = (tid >> 2) & 3, hs = tid & 3;
     double th[M];
 #pragma unroll
-    for (int k = 0; k < M; ++k) {
-      double t = 0.0;
-      if (valid) {
-        const double* src = in + ((long)hs * M + k) * EN + (long)ne * NSP;
-#pragma unroll
-        for (int c = 0; c < NP; ++c) t += l[c] * src[along_x ? (c + NP * hfp) : (hfp + NP * c)];
-      }
-      th[k] = t;
-    }
+    for (int k = 0; k < M; ++k) th[k] = lw[0] * hv[k][0] + lw[1] * hv[k][1] + lw[2] * hv[k][2] + lw[3] * hv[k][3];
 #pragma unroll 1
     for (int q = 0; q < NQ; ++q) {
-      double t = 0.0;
+      double t0 = 0.0, t1 = 0.0;
 #pragma unroll
-      for (int k = 0; k < M; ++k) t += th[k] * Phi[k * NQ + q];
-      sH[q][hf][hfp][hs] = (R)t;
+      for (int k = 0; k < M; k += 2) t0 += th[k] * sPhiT[q * M + k];
+#pragma unroll
+      for (int k = 1; k < M; k += 2) t1 += th[k] * sPhiT[q * M + k];
+      sH[q][hf][hfp].v[hs] = (R)(t0 + t1);
     }
   }
 
-  // per-lane operator rows: one x trace (lanes a = 0, 1) and one y trace
-  // (lanes b = 2, 3) per lane, by rotated Lagrange rows
-  R cx[4], cy[4], dx[4], dy[4];
+  // per-lane rows of the modified derivative matrix, rotated for xdot / ydot
+  R dx[4], dy[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    cx[k] = (R)(a == 0 ? P.tab.lL[(a + k) & 3] : P.tab.lR[(a + k) & 3]);
-    cy[k] = (R)(b == 2 ? P.tab.lL[(b - k) & 3] : P.tab.lR[(b - k) & 3]);
     dx[k] = (R)A.Dt[a * NP + ((a + k) & 3)];
     dy[k] = (R)A.Dt[b * NP + ((b - k) & 3)];
   }
-  const int xslot = (a < 2) ? 4 * a + b : 8 + 4 * a + b;
-  const int yslot = (b >= 2) ? 4 * b + a : 24 + 4 * b + a;
   const R dhLa = (R)P.tab.dhL[a], dhRa = (R)P.tab.dhR[a], dhLb = (R)P.tab.dhL[b], dhRb = (R)P.tab.dhR[b];
   const R iJx = (R)(1.0 / P.Jx), iJy = (R)(1.0 / P.Jy);
 
@@ -597,14 +658,23 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ Phi,
   const bool lo_side = (fside == 0 || fside == 2);
   const bool wave_at_boundary = __ballot(boundary) != 0;
 
+  // the line of solution points through flux point j and its Lagrange weights
+  // (l(-1) on a lo side, l(+1) on a hi side)
+  int line[4];
+  R wl[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    line[c] = (fside < 2) ? c + NP * fi : fi + NP * c;
+    wl[c] = (R)(lo_side ? P.tab.lL[c] : P.tab.lR[c]);
+  }
+
   R acc[2][M];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int k = 0; k < M; ++k) acc[i][k] = R(0);
 
-  // own pair at (j, q): gPC expansion at the node; evaluated one node ahead,
-  // between the barrier and the interface flux, to cover the LDS latency there
+  // own pair at (j, q): gPC expansion at the node
   auto expand = [&](int q, R* u2) {
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -614,44 +684,77 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ Phi,
       u2[i] = t;
     }
   };
-  R u2[2];
-  expand(0, u2);
+  // Random nodes go in pairs (q0, q1 = q0 + 1).  Rows h = 0 work on node q0 and
+  // rows h = 1 on node q1 with all four variables of their point (fluxes,
+  // trace, interface flux, residual), so each of these is evaluated once per
+  // point and node; the expansion and the projection stay with the lane's own
+  // pair of variables at both nodes.  With an odd node count the last pair
+  // repeats its node and counts it once.
+  constexpr int NIT = (NQ + 1) / 2;
+  R ua[2], ub[2];  // own pair at q0 and at q1; the next pair's are expanded one step ahead
+  expand(0, ua);
+  expand(NQ > 1 ? 1 : 0, ub);
 
 #pragma unroll 1
-  for (int q = 0; q < NQ; ++q) {
-    const int par = q & 1;
-    // (1) all four variables at (j, q), fluxes of the own pair, traces
-    R U[4];
-    full4(h, u2[0], u2[1], U);
-    R F2[2], G2[2];
+  for (int t = 0; t < NIT; ++t) {
+    const int q0 = 2 * t;
+    const int q1 = (q0 + 1 < NQ) ? q0 + 1 : q0;
+    const int qh = h ? q1 : q0;
+    const int par = t & 1;
+    // (1) all four variables at (j, qh): row 0 takes the partner's pair at q0,
+    // row 1 the partner's pair at q1
+    R U[4] = {ua[0], ua[1], ub[0], ub[1]};
+    swap_rows(U[0], U[2]);
+    swap_rows(U[1], U[3]);
+    sU[le][h][j] = Quad4<R>{{U[0], U[1], U[2], U[3]}};
+    R F[4], G[4];
     {
       const R ir = recip(U[0]);
       const R p = (g - R(1)) * (U[3] - R(0.5) * (U[1] * U[1] + U[2] * U[2]) * ir);
       const R vx = U[1] * ir, vy = U[2] * ir;
-      if (h == 0) {
-        F2[0] = U[1];
-        G2[0] = U[2];
-        F2[1] = U[1] * vx + p;
-        G2[1] = U[1] * vy;
-      } else {
-        F2[0] = U[2] * vx;
-        G2[0] = U[2] * vy + p;
-        F2[1] = (U[3] + p) * vx;
-        G2[1] = (U[3] + p) * vy;
-      }
+      F[0] = U[1];
+      F[1] = U[1] * vx + p;
+      F[2] = U[2] * vx;
+      F[3] = (U[3] + p) * vx;
+      G[0] = U[2];
+      G[1] = U[1] * vy;
+      G[2] = U[2] * vy + p;
+      G[3] = (U[3] + p) * vy;
     }
-    sT[par][le][xslot][h] = Pair2<R>{xdot(cx, u2[0]), xdot(cx, u2[1])};
-    sT[par][le][yslot][h] = Pair2<R>{ydot(cy, u2[0]), ydot(cy, u2[1])};
+    // the nodal values of an element are written and read by the same wave
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    // (2) solution trace at flux point j, by Lagrange interpolation along its line
+    {
+      R T[4] = {R(0), R(0), R(0), R(0)};
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const Quad4<R> x = sU[le][h][line[c]];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) T[s] += wl[c] * x.v[s];
+      }
+      sT[par][le][h][j] = Quad4<R>{{T[0], T[1], T[2], T[3]}};
+    }
     __syncthreads();
 
-    // (2) interface flux at flux point j (own pair of variables written)
+    // (3) Lax-Friedrichs flux at flux point j and node qh
     {
+      const Quad4<R>* src = (nbr_le >= 0) ? &sT[par][nbr_le][h][mirror] : &sH[qh][nbr_halo][fi];
+      const Quad4<R> ow = sT[par][le][h][j], nq = *src;
+      // next pair, independent of the reads above
+      if (t + 1 < NIT) {
+        const int n0 = q0 + 2, n1 = (n0 + 1 < NQ) ? n0 + 1 : n0;
+        expand(n0, ua);
+        expand(n1, ub);
+      }
       R own[4], nb[4];
-      const Pair2<R>* src = (nbr_le >= 0) ? sT[par][nbr_le][mirror] : (const Pair2<R>*)&sH[q][nbr_halo][fi][0];
-      const Pair2<R> o0 = sT[par][le][j][0], o1 = sT[par][le][j][1], n0 = src[0], n1 = src[1];
-      expand(q + 1 < NQ ? q + 1 : q, u2);  // next node, independent of the reads above
-      own[0] = o0.x; own[1] = o0.y; own[2] = o1.x; own[3] = o1.y;
-      nb[0] = n0.x; nb[1] = n0.y; nb[2] = n1.x; nb[3] = n1.y;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        own[s] = ow.v[s];
+        nb[s] = nq.v[s];
+      }
       if (wave_at_boundary) {  // uniform: only waves with a domain-boundary face pay for the ghosts
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -662,25 +765,37 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ Phi,
       }
       R Fs[4];
       rusanov_e2(own, nb, lo_side, Fs, g, fside >> 1);
-      sFs[le][j][h] = Pair2<R>{h ? Fs[2] : Fs[0], h ? Fs[3] : Fs[1]};
+      sFs[le][h][j] = Quad4<R>{{Fs[0], Fs[1], Fs[2], Fs[3]}};
     }
     // the interface fluxes of an element are written and read by the same wave
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-    // (3) nodal residual of the own pair, projected onto the chaos
+    // (4) nodal residual at (j, qh), all four variables; then each lane takes
+    // its own pair at both nodes (variable 2h + i: r[i] at q0, r[2 + i] at q1)
+    // and projects it onto the chaos
     {
-      const Pair2<R> fxl = sFs[le][0 + b][h], fxr = sFs[le][4 + b][h];
-      const Pair2<R> fyl = sFs[le][8 + a][h], fyr = sFs[le][12 + a][h];
-      const R r0 = -(xdot(dx, F2[0]) + fxl.x * dhLa + fxr.x * dhRa) * iJx -
-                   (ydot(dy, G2[0]) + fyl.x * dhLb + fyr.x * dhRb) * iJy;
-      const R r1 = -(xdot(dx, F2[1]) + fxl.y * dhLa + fxr.y * dhRa) * iJx -
-                   (ydot(dy, G2[1]) + fyl.y * dhLb + fyr.y * dhRb) * iJy;
+      const Quad4<R> fxl = sFs[le][h][0 + b], fxr = sFs[le][h][4 + b];
+      const Quad4<R> fyl = sFs[le][h][8 + a], fyr = sFs[le][h][12 + a];
+      R r[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        r[s] = -(xdot(dx, F[s]) + fxl.v[s] * dhLa + fxr.v[s] * dhRa) * iJx -
+               (ydot(dy, G[s]) + fyl.v[s] * dhLb + fyr.v[s] * dhRb) * iJy;
+      swap_rows(r[0], r[2]);
+      swap_rows(r[1], r[3]);
 #pragma unroll
       for (int k = 0; k < M; ++k) {
-        acc[0][k] += PWT[q * M + k] * r0;
-        acc[1][k] += PWT[q * M + k] * r1;
+        acc[0][k] += PWT[q0 * M + k] * r[0];
+        acc[1][k] += PWT[q0 * M + k] * r[1];
+      }
+      if (q1 != q0) {
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+          acc[0][k] += PWT[q1 * M + k] * r[2];
+          acc[1][k] += PWT[q1 * M + k] * r[3];
+        }
       }
     }
   }
@@ -723,7 +838,7 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ Phi,
       L.rly[k] = P.tab.lL[(b - k) & 3];
       L.rry[k] = P.tab.lR[(b - k) & 3];
     }
-    const int lf = limit_pair<M, NQ>(P, Phi, o, h, a, b, L, A.cmax);
+    const int lf = limit_pair<M, NQ>(P, PhiTd, o, h, a, b, L, A.cmax);
     if (tid % 32 == 0 && A.flag_lim) A.flag_lim[e] = (unsigned char)lf;
   } else if (tid % 32 == 0 && A.flag_lim) {
     A.flag_lim[e] = 0;
@@ -751,7 +866,7 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ Phi,
       for (int i = 0; i < 2; ++i) {
         double t = 0.0;
 #pragma unroll
-        for (int k = 0; k < M; ++k) t += o[i][k] * Phi[k * NQ + q];
+        for (int k = 0; k < M; ++k) t += o[i][k] * PhiTd[q * M + k];
         u2[i] = t;
       }
     };
@@ -862,10 +977,10 @@ static hipError_t launch_stage_t(const KParams& P, const FusedStage& S, hipStrea
   A.cmax = S.cmax;
   const int ntiles = (P.nx / TX) * (P.ny / TY);
   if (S.fp32)
-    hipLaunchKernelGGL((k_stage2d<M, NQ, float>), dim3(ntiles), dim3(BLKS), 0, s, P, A, P.tab.Phi, S.PhiT32,
+    hipLaunchKernelGGL((k_stage2d<M, NQ, float>), dim3(ntiles), dim3(BLKS), 0, s, P, A, S.PhiT, S.PhiT32,
                        S.PWT32, S.in, S.u, S.in, S.out);
   else
-    hipLaunchKernelGGL((k_stage2d<M, NQ, double>), dim3(ntiles), dim3(BLKS), 0, s, P, A, P.tab.Phi, S.PhiT,
+    hipLaunchKernelGGL((k_stage2d<M, NQ, double>), dim3(ntiles), dim3(BLKS), 0, s, P, A, S.PhiT, S.PhiT,
                        S.PWT, S.in, S.u, S.in, S.out);
   return hipGetLastError();
 }
