@@ -332,7 +332,11 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
   size_t o_ab1 = align_up(o_ab2 + (adj ? state * 8 : 0));
   size_t o_agt = align_up(o_ab1 + (adj ? state * 8 : 0));
   size_t o_apt = align_up(o_agt + (adj ? (size_t)T.Nq * c->E * 2 * 8 : 0));
-  size_t total = align_up(o_apt + nadj_part * 8);
+  // fused 2D: two buffers of modal face traces on tile boundaries
+  const size_t ntr = c->fused ? fused2d_trace_count(P.nx, P.ny, T.M) : 0;
+  size_t o_tr0 = align_up(o_apt + nadj_part * 8);
+  size_t o_tr1 = align_up(o_tr0 + ntr * 8);
+  size_t total = align_up(o_tr1 + ntr * 8);
   char* ws = nullptr;
   he = hipMalloc(&ws, total);
   if (he != hipSuccess) {
@@ -364,6 +368,10 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
     c->ws.ab1 = (double*)(ws + o_ab1);
     c->ws.agT = (double*)(ws + o_agt);
     c->ws.apart = (double*)(ws + o_apt);
+  }
+  if (ntr) {
+    c->ws.tr[0] = (double*)(ws + o_tr0);
+    c->ws.tr[1] = (double*)(ws + o_tr1);
   }
   c->ws.bytes = total + blob.size() * sizeof(double);
 
@@ -600,10 +608,12 @@ static fr_sg_status step_fused1d(fr_sg_ctx* ctx, double* u, double dt, double* d
   return FRSG_OK;
 }
 
-// fused 2D Euler step: one kernel per stage.  reuse_cfl: take the CFL maximum of
-// u from the accumulator filled by the previous step's end-of-step pass.
+// fused 2D Euler step: one kernel per stage.  chained: u is the state the
+// previous step of the same call produced, so the CFL maximum of u comes from
+// the accumulator its end-of-step pass filled and the face traces of u from the
+// buffer its last launch wrote.
 static fr_sg_status step_fused(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, uint8_t* flags,
-                               bool reuse_cfl) {
+                               bool chained) {
   const KParams& K = ctx->kp;
   Workspace& W = ctx->ws;
   hipStream_t s = ctx->stream;
@@ -615,7 +625,7 @@ static fr_sg_status step_fused(fr_sg_ctx* ctx, double* u, double dt, double* dt_
   if (dt > 0.0) {
     FRSG_TRY_HIP(launch_set_dt(K, dt, nullptr, lam[cur ^ 1], s), ctx);
   } else {
-    if (!reuse_cfl)
+    if (!chained)
       if ((st = timed(ctx, "cfl", sb, [&] { return launch_fused_cfl(K, u, lam[cur], s); }))) return st;
     FRSG_TRY_HIP(launch_dt_from(K, lam[cur], lam[cur ^ 1], nullptr, s), ctx);
   }
@@ -624,15 +634,20 @@ static fr_sg_status step_fused(fr_sg_ctx* ctx, double* u, double dt, double* dt_
   uint8_t* f2 = flags ? flags + 2 * E : nullptr;
   uint8_t* f3 = flags ? flags + 3 * E : nullptr;
   const int f32 = fp32(ctx);
+  // each launch writes the face traces of its output into the buffer the
+  // previous launch did not write; stage 1 reads those of u only when the
+  // previous step of this call wrote them
+  const int tc = ctx->tr_cur;
   FusedStage s1{u, u, W.w1, 0.0, 1.0, 1, f0, nullptr, nullptr, ctx->dDt, ctx->dcmax, ctx->dPhiT, ctx->dPWT,
-                f32, ctx->dPhiT32, ctx->dPWT32};
+                f32, ctx->dPhiT32, ctx->dPWT32, chained ? W.tr[tc] : nullptr, W.tr[tc ^ 1]};
   if ((st = timed(ctx, "stage1", 2 * sb, [&] { return launch_fused_stage(K, s1, s); }))) return st;
   FusedStage s2{W.w1, u, W.w2, 0.75, 0.25, 2, f1, nullptr, nullptr, ctx->dDt, ctx->dcmax, ctx->dPhiT, ctx->dPWT,
-                f32, ctx->dPhiT32, ctx->dPWT32};
+                f32, ctx->dPhiT32, ctx->dPWT32, W.tr[tc ^ 1], W.tr[tc]};
   if ((st = timed(ctx, "stage2", 3 * sb, [&] { return launch_fused_stage(K, s2, s); }))) return st;
   FusedStage s3{W.w2, u, u, 1.0 / 3.0, 2.0 / 3.0, 3, f3, f2, lam[cur ^ 1], ctx->dDt, ctx->dcmax, ctx->dPhiT,
-                ctx->dPWT, f32, ctx->dPhiT32, ctx->dPWT32};
+                ctx->dPWT, f32, ctx->dPhiT32, ctx->dPWT32, W.tr[tc], W.tr[tc ^ 1]};
   if ((st = timed(ctx, "stage3", 3 * sb, [&] { return launch_fused_stage(K, s3, s); }))) return st;
+  ctx->tr_cur = tc ^ 1;
   ctx->lam_cur = cur ^ 1;
   ctx->lam_for = u;
   if (dt_used) FRSG_TRY_HIP(launch_copy_dt(K, dt_used, s), ctx);

@@ -98,6 +98,9 @@ struct Workspace {
   double* ab1 = nullptr;   // adjoint of w1
   double* agT = nullptr;   // [Nq][E][2] adjoints of the traces at r = -1, +1
   double* apart = nullptr; // per-block partial sums of the parameter derivative
+  // fused 2D: modal face traces on tile boundaries, written by one stage launch
+  // for the next (two buffers, used in turn)
+  double* tr[2] = {nullptr, nullptr};
   size_t bytes = 0;
 };
 
@@ -139,6 +142,7 @@ struct fr_sg_ctx {
   bool fused1d = false;          // fused 1D stage kernel
   int lam_cur = 0;              // which CFL accumulator holds the maximum of the current state
   const double* lam_for = nullptr;  // state whose maximum the previous step recorded (fr_sg_steps)
+  int tr_cur = 0;               // fused 2D: which face-trace buffer holds the traces of the current state
   frsg::KParams kp;
   frsg::Workspace ws;
   std::string err;
@@ -162,8 +166,12 @@ struct FusedStage {
   int fp32;            // 1: node loop in FP32 (FP32-mixed precision)
   const float* PhiT32;
   const float* PWT32;
+  const double* tr_in = nullptr;  // modal face traces of `in` on tile boundaries (null: from the state)
+  double* tr_out = nullptr;       // where to write those of `out` (may be null)
 };
 bool fused2d_supported(const KParams& P);
+// doubles of one modal face-trace buffer of the fused 2D kernel
+size_t fused2d_trace_count(int nx, int ny, int M);
 hipError_t launch_fused_stage(const KParams& P, const FusedStage& S, hipStream_t s);
 hipError_t launch_fused_cfl(const KParams& P, const double* u, unsigned long long* lam, hipStream_t s);
 hipError_t launch_dt_from(const KParams& P, const unsigned long long* lam, unsigned long long* lam_reset,

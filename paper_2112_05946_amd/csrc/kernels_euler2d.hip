@@ -174,6 +174,8 @@ struct StageArgs {
   unsigned long long* lam_next;  // stage 3: CFL accumulator of the new state (may be null)
   const double* Dt;          // 4 x 4 modified derivative matrix
   const double* cmax;        // [M] max_q |Phi_k(z_q)|
+  const double* tr_in;       // modal face traces of the input, or null: interpolate from the neighbours
+  double* tr_out;            // modal face traces of the output (may be null)
 };
 
 // Lane layout of a workgroup (one TX x TY tile of elements, 32 threads per element):
@@ -186,6 +188,10 @@ constexpr int TX = 4, TY = 2;
 constexpr int TE = TX * TY;          // elements per tile
 constexpr int BLKS = 32 * TE;        // threads per stage workgroup
 constexpr int NHF = 2 * (TX + TY);   // element faces on the tile boundary
+// modal face traces of one tile: per boundary face slot (x-lo rows, x-hi rows,
+// y-lo columns, y-hi columns), variable, face point and mode
+template <int M>
+constexpr int TRACE_PER_TILE = NHF * 4 * NP * M;
 #ifndef FRSG_FP32_WAVES
 #define FRSG_FP32_WAVES 2  // waves per SIMD the FP32 node loop is compiled for (3 spills)
 #endif
@@ -310,10 +316,8 @@ __device__ int limit_pair(const KParams& P, const double* __restrict__ PhiT, dou
     for (int k = 1; k < M; ++k) v += fabs(o[i][k]) * cmax[k];
     var[i] = v;
   }
-  auto safe = [&](double m0, double m1, double v0, double v1) {
-    double mn[4], vr[4];
-    full4(h, m0, m1, mn);
-    full4(h, v0, v1, vr);
+  // decision at one location from all four variables' means and bounds
+  auto safe = [&](const double* mn, const double* vr) {
     const double rlo = mn[0] - vr[0];
     const double elo = mn[3] - vr[3];
     const double mx = fabs(mn[1]) + vr[1];
@@ -333,11 +337,37 @@ __device__ int limit_pair(const KParams& P, const double* __restrict__ PhiT, dou
     bx[k] = fabs(L.rrx[k]);
     by[k] = fabs(L.rry[k]);
   }
-  bool ok = safe(mean[0], mean[1], var[0], var[1]);
-  ok = safe(xdot(L.rlx, mean[0]), xdot(L.rlx, mean[1]), xdot(ax, var[0]), xdot(ax, var[1])) && ok;
-  ok = safe(xdot(L.rrx, mean[0]), xdot(L.rrx, mean[1]), xdot(bx, var[0]), xdot(bx, var[1])) && ok;
-  ok = safe(ydot(L.rly, mean[0]), ydot(L.rly, mean[1]), ydot(ay, var[0]), ydot(ay, var[1])) && ok;
-  ok = safe(ydot(L.rry, mean[0]), ydot(L.rry, mean[1]), ydot(by, var[0]), ydot(by, var[1])) && ok;
+  // own pair's mean and bound at the solution point and at the four face
+  // points of its row (x) and column (y)
+  double lm[5][2], lv[5][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    lm[0][i] = mean[i];
+    lv[0][i] = var[i];
+    lm[1][i] = xdot(L.rlx, mean[i]);
+    lv[1][i] = xdot(ax, var[i]);
+    lm[2][i] = xdot(L.rrx, mean[i]);
+    lv[2][i] = xdot(bx, var[i]);
+    lm[3][i] = ydot(L.rly, mean[i]);
+    lv[3][i] = ydot(ay, var[i]);
+    lm[4][i] = ydot(L.rry, mean[i]);
+    lv[4][i] = ydot(by, var[i]);
+  }
+  // locations in pairs: row 0 tests location A, row 1 location B, each with
+  // all four variables after one exchange (every lane takes part in each)
+  auto test_pair = [&](int A, int B) {
+    double mn[4] = {lm[A][0], lm[A][1], lm[B][0], lm[B][1]};
+    double vr[4] = {lv[A][0], lv[A][1], lv[B][0], lv[B][1]};
+    swap_rows(mn[0], mn[2]);
+    swap_rows(mn[1], mn[3]);
+    swap_rows(vr[0], vr[2]);
+    swap_rows(vr[1], vr[3]);
+    return safe(mn, vr);
+  };
+  const bool t01 = test_pair(0, 1);
+  const bool t23 = test_pair(2, 3);
+  const bool t40 = test_pair(4, 0);
+  const bool ok = t01 && t23 && t40;
   // element-wide decision
   double okd = ok ? 1.0 : 0.0;
   okd = ymin4(xmin4(okd));
@@ -493,10 +523,23 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ PhiTd,
   // per element and row h (node q0 or q1 of the pair in hand): nodal values at
   // the solution points, traces at the flux points (x-lo row i, x-hi row i,
   // y-lo column i, y-hi column i; two pairs in flight) and interface fluxes
-  __shared__ Quad4<R> sU[TE][2][NSP];
-  __shared__ Quad4<R> sT[2][TE][2][NSP];
-  __shared__ Quad4<R> sFs[TE][2][NSP];
-  __shared__ Quad4<R> sH[NQ][NHF][NP];    // traces of elements outside the tile, every node
+  // (traces of elements outside the tile at every node in sH); the epilogue
+  // reuses the space to stage the new state for its face traces
+  struct LoopLds {
+    Quad4<R> sU[TE][2][NSP];
+    Quad4<R> sT[2][TE][2][NSP];
+    Quad4<R> sFs[TE][2][NSP];
+    Quad4<R> sH[NQ][NHF][NP];
+  };
+  union StageLds {
+    LoopLds loop;
+    double sO[TE][4][NSP][M];
+  };
+  __shared__ StageLds lds;
+  auto& sU = lds.loop.sU;
+  auto& sT = lds.loop.sT;
+  auto& sFs = lds.loop.sFs;
+  auto& sH = lds.loop.sH;
   __shared__ double sLam[M * NSP];
   __shared__ double sPhiT[NQ * M];
   __shared__ double sRed[BLKS / 64];
@@ -561,8 +604,7 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ PhiTd,
   // traces of the elements around the tile at every node: one thread per
   // (face hf, face point hfp, variable hs); faces: TY x-lo, TY x-hi, TX y-lo, TX y-hi
   const bool halo_thread = tid < NHF * NP * 4;
-  double hv[M][NP];  // the neighbour's coefficients along the face-normal lines
-  double lw[NP];     // Lagrange weights of the neighbour's face
+  double th[M];  // modal trace of this thread's neighbour variable at its face point
   {
     const int hf = (tid >> 4) % NHF, hfp = (tid >> 2) & 3, hs = tid & 3;
     int nix, niy;
@@ -577,22 +619,44 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ PhiTd,
     if (niy < 0) { if (P.bc[2] == FRSG_BC_PERIODIC) niy += P.ny; else valid = false; }
     if (niy >= P.ny) { if (P.bc[3] == FRSG_BC_PERIODIC) niy -= P.ny; else valid = false; }
     // all loads first, without branches, so that they are in flight together; a
-    // face without a neighbour (domain boundary) reads element 0 instead, and
-    // its trace is never used: the lanes on that face take the ghost state
-    const int ne = valid ? niy * P.nx + nix : 0;
+    // face without a neighbour (domain boundary) reads tile or element 0
+    // instead, and its trace is never used: the lanes on that face take the
+    // ghost state
+    if (A.tr_in) {  // uniform: the traces were written by the launch that wrote the input
+      // the neighbour tile's face slot that faces this one (x-lo halo <- x-hi slot, ...)
+      const int slot = hf < TY ? TY + hf
+                     : hf < 2 * TY ? hf - TY
+                     : hf < 2 * TY + TX ? hf + TX
+                     : hf - TX;
+      const int nt = valid ? (niy / TY) * ntx + nix / TX : 0;
+      const auto rtr = state_rsrc(A.tr_in, (unsigned)((long)ntiles * TRACE_PER_TILE<M> * (long)sizeof(double)));
+      const unsigned to = (unsigned)(((long)nt * TRACE_PER_TILE<M> + ((slot * 4 + hs) * NP + hfp) * M) *
+                                     (long)sizeof(double));
+      if (halo_thread) {  // uniform per wave
 #pragma unroll
-    for (int c = 0; c < NP; ++c) lw[c] = from_lo ? P.tab.lL[c] : P.tab.lR[c];
-    const auto rh = state_rsrc(in, sbytes);
-    unsigned ho[NP];
+        for (int k = 0; k < M; ++k) th[k] = bload(rtr, to, (unsigned)(k * sizeof(double)));
+      }
+    } else {
+      const int ne = valid ? niy * P.nx + nix : 0;
+      double lw[NP];
 #pragma unroll
-    for (int c = 0; c < NP; ++c)
-      ho[c] = (unsigned)((((long)hs * M) * EN + (long)ne * NSP + (along_x ? c + NP * hfp : hfp + NP * c)) *
-                         (long)sizeof(double));
-    if (halo_thread) {  // uniform per wave
+      for (int c = 0; c < NP; ++c) lw[c] = from_lo ? P.tab.lL[c] : P.tab.lR[c];
+      const auto rh = state_rsrc(in, sbytes);
+      unsigned ho[NP];
 #pragma unroll
-      for (int k = 0; k < M; ++k)
+      for (int c = 0; c < NP; ++c)
+        ho[c] = (unsigned)((((long)hs * M) * EN + (long)ne * NSP + (along_x ? c + NP * hfp : hfp + NP * c)) *
+                           (long)sizeof(double));
+      if (halo_thread) {  // uniform per wave
+        double hv[M][NP];
 #pragma unroll
-        for (int c = 0; c < NP; ++c) hv[k][c] = bload(rh, ho[c], soff(0, k));
+        for (int k = 0; k < M; ++k)
+#pragma unroll
+          for (int c = 0; c < NP; ++c) hv[k][c] = bload(rh, ho[c], soff(0, k));
+#pragma unroll
+        for (int k = 0; k < M; ++k)
+          th[k] = lw[0] * hv[k][0] + lw[1] * hv[k][1] + lw[2] * hv[k][2] + lw[3] * hv[k][3];
+      }
     }
   }
   // chaos basis at the nodes, node-major, for the expansion of the halo traces
@@ -602,9 +666,6 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ PhiTd,
   __syncthreads();
   if (halo_thread) {
     const int hf = tid >> 4, hfp = (tid >> 2) & 3, hs = tid & 3;
-    double th[M];
-#pragma unroll
-    for (int k = 0; k < M; ++k) th[k] = lw[0] * hv[k][0] + lw[1] * hv[k][1] + lw[2] * hv[k][2] + lw[3] * hv[k][3];
 #pragma unroll 1
     for (int q = 0; q < NQ; ++q) {
       double t0 = 0.0, t1 = 0.0;
@@ -849,6 +910,43 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ PhiTd,
 #pragma unroll
     for (int k = 0; k < M; ++k) bstore(o[i][k], rout, voff, soff(i, k));
 
+  // modal face traces of the new state on the tile's boundary faces, for the
+  // next launch's neighbours: the same interpolation, in the same order, as
+  // their own prologue would take from the stored state
+  if (A.tr_out) {  // uniform
+    __syncthreads();  // the node loop's LDS is free
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int k = 0; k < M; ++k) lds.sO[le][2 * h + i][j][k] = o[i][k];
+    __syncthreads();
+    const int tile_id = ty * ntx + tx;
+    const auto rtr = state_rsrc(A.tr_out, (unsigned)((long)ntiles * TRACE_PER_TILE<M> * (long)sizeof(double)));
+    const unsigned tbase = (unsigned)((long)tile_id * TRACE_PER_TILE<M> * (long)sizeof(double));
+    constexpr int NR = (TRACE_PER_TILE<M> + BLKS - 1) / BLKS;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int oi = tid + r * BLKS;  // ((slot * 4 + s) * NP + point) * M + mode
+      if (oi < TRACE_PER_TILE<M>) {
+        const int k = oi % M, fp = (oi / M) % NP, sv = (oi / (M * NP)) % 4, slot = oi / (M * NP * 4);
+        int ex, ey;
+        bool ax, lo;
+        if (slot < TY) { ex = 0; ey = slot; ax = true; lo = true; }
+        else if (slot < 2 * TY) { ex = TX - 1; ey = slot - TY; ax = true; lo = false; }
+        else if (slot < 2 * TY + TX) { ex = slot - 2 * TY; ey = 0; ax = false; lo = true; }
+        else { ex = slot - 2 * TY - TX; ey = TY - 1; ax = false; lo = false; }
+        const int el = ex + TX * ey;
+        double v[NP], w[NP];
+#pragma unroll
+        for (int c = 0; c < NP; ++c) {
+          v[c] = lds.sO[el][sv][ax ? c + NP * fp : fp + NP * c][k];
+          w[c] = lo ? P.tab.lL[c] : P.tab.lR[c];
+        }
+        bstore(w[0] * v[0] + w[1] * v[1] + w[2] * v[2] + w[3] * v[3], rtr, tbase + (unsigned)(oi * sizeof(double)), 0u);
+      }
+    }
+  }
+
   // CFL maximum of the new state for the next step
   if (A.stage == 3 && A.lam_next) {
     const double gd = P.gamma, idx = 1.0 / P.dx, idy = 1.0 / P.dy;
@@ -875,14 +973,12 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ PhiTd,
     // taking the partner's pair of variables at its node
     int q = 0;
     for (; q + 1 < NQ; q += 2) {
-      double a2[2], b2[2], U[4];
+      double a2[2], b2[2];
       nodal(q, a2);
       nodal(q + 1, b2);
-      const double r0 = other_half(h ? a2[0] : b2[0]), r1 = other_half(h ? a2[1] : b2[1]);
-      U[0] = h ? r0 : a2[0];
-      U[1] = h ? r1 : a2[1];
-      U[2] = h ? b2[0] : r0;
-      U[3] = h ? b2[1] : r1;
+      double U[4] = {a2[0], a2[1], b2[0], b2[1]};
+      swap_rows(U[0], U[2]);
+      swap_rows(U[1], U[3]);
       rate = fmax(rate, node_rate(U));
     }
     if (q < NQ) {
@@ -975,6 +1071,8 @@ static hipError_t launch_stage_t(const KParams& P, const FusedStage& S, hipStrea
   A.lam_next = S.lam_next;
   A.Dt = S.Dt;
   A.cmax = S.cmax;
+  A.tr_in = S.tr_in;
+  A.tr_out = S.tr_out;
   const int ntiles = (P.nx / TX) * (P.ny / TY);
   if (S.fp32)
     hipLaunchKernelGGL((k_stage2d<M, NQ, float>), dim3(ntiles), dim3(BLKS), 0, s, P, A, S.PhiT, S.PhiT32,
@@ -994,6 +1092,10 @@ static hipError_t launch_cfl_t(const KParams& P, const double* u, unsigned long 
 }
 
 #define FRSG_FUSED_SIZES(X) X(15, 25) X(10, 16) X(6, 9) X(3, 4) X(5, 5)
+
+size_t fused2d_trace_count(int nx, int ny, int M) {
+  return (size_t)(nx / TX) * (size_t)(ny / TY) * (size_t)(NHF * 4 * NP) * (size_t)M;
+}
 
 bool fused2d_supported(const KParams& P) {
   if (P.eq != kEuler2 || P.np1 != 4 || P.nx % TX != 0 || P.ny % TY != 0) return false;
