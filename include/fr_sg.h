@@ -26,8 +26,10 @@
  * Ownership: the caller owns every state, right-hand-side, adjoint, flag and
  * time-step buffer.  The library owns the context, its operator tables and a
  * workspace allocated once by fr_sg_init (two stage states plus nodal
- * scratch; fr_sg_query reports its size) and freed by fr_sg_destroy.  No
- * other call allocates device memory.
+ * scratch, or, on the fused 2D path, two buffers of modal face traces on
+ * tile boundaries that each stage launch writes for the next; fr_sg_query
+ * reports its size) and freed by fr_sg_destroy.  No other call allocates
+ * device memory.
  *
  * Errors: invalid or unsupported problems are rejected by fr_sg_init before
  * any launch.  Non-finite or non-realizable states met on the device are
@@ -172,7 +174,11 @@ fr_sg_status fr_sg_step(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, u
 /* nsteps CFL steps in a row (dt from the CFL condition at the start of each
  * step), in place.  The wave-speed maximum of the first step is computed from
  * u; that of every later step is taken in the previous step's end-of-step
- * pass, so a time loop makes no extra pass over the state for it.
+ * pass, so a time loop makes no extra pass over the state for it.  On the
+ * fused 2D path the face traces of the neighbours that a stage needs come
+ * from the previous launch in the same way (the first stage of the call
+ * interpolates them from u); the result equals nsteps fr_sg_step calls with
+ * the same time steps bit for bit. 
  * dt_used: device double[nsteps] or NULL; flags: device uint8[nsteps * 4 * E]
  * or NULL, laid out per step as in fr_sg_step. */
 fr_sg_status fr_sg_steps(fr_sg_ctx* ctx, double* u, int32_t nsteps, double* dt_used, uint8_t* flags);
