@@ -541,7 +541,8 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ PhiTd,
   auto& sFs = lds.loop.sFs;
   auto& sH = lds.loop.sH;
   __shared__ double sLam[M * NSP];
-  __shared__ double sPhiT[NQ * M];
+  constexpr int NQP = (NQ + 1) & ~1;  // rows padded to whole 16-byte pairs
+  __shared__ __attribute__((aligned(16))) double sPhiK[M][NQP];  // chaos basis, mode-major
   __shared__ double sRed[BLKS / 64];
 
   const int tid = threadIdx.x;
@@ -659,22 +660,25 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ PhiTd,
       }
     }
   }
-  // chaos basis at the nodes, node-major, for the expansion of the halo traces
+  // chaos basis at the nodes, mode-major, for the expansion of the halo traces
 #pragma unroll
-  for (int r = 0; r < NPHI; ++r)
-    if (tid + r * BLKS < NQ * M) sPhiT[tid + r * BLKS] = phv[r];
+  for (int r = 0; r < NPHI; ++r) {
+    const int i = tid + r * BLKS;  // node-major index q * M + k
+    if (i < NQ * M) sPhiK[i % M][i / M] = phv[r];
+  }
   __syncthreads();
   if (halo_thread) {
+    // all nodes at once, mode by mode: independent accumulators, one pass over the table
     const int hf = tid >> 4, hfp = (tid >> 2) & 3, hs = tid & 3;
-#pragma unroll 1
-    for (int q = 0; q < NQ; ++q) {
-      double t0 = 0.0, t1 = 0.0;
+    double tq[NQ];
 #pragma unroll
-      for (int k = 0; k < M; k += 2) t0 += th[k] * sPhiT[q * M + k];
+    for (int q = 0; q < NQ; ++q) tq[q] = 0.0;
 #pragma unroll
-      for (int k = 1; k < M; k += 2) t1 += th[k] * sPhiT[q * M + k];
-      sH[q][hf][hfp].v[hs] = (R)(t0 + t1);
-    }
+    for (int k = 0; k < M; ++k)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) tq[q] += th[k] * sPhiK[k][q];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) sH[q][hf][hfp].v[hs] = (R)tq[q];
   }
 
   // per-lane rows of the modified derivative matrix, rotated for xdot / ydot
