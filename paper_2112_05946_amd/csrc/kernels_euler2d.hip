@@ -279,6 +279,13 @@ template <typename T>
 struct alignas(4 * sizeof(T) > 16 ? 16 : 4 * sizeof(T)) Quad4 {
   T v[4];
 };
+// two of the four conserved variables at one point: the nodal values, traces
+// and interface fluxes of an element are kept as two planes (variables 0-1,
+// variables 2-3) so that 16 consecutive points fill whole rows of LDS banks
+template <typename T>
+struct alignas(2 * sizeof(T)) Half2 {
+  T x, y;
+};
 
 struct LaneOps {
   double rlx[4], rly[4], rrx[4], rry[4];  // rotated l(-1), l(+1) for x (row a) and y (row b)
@@ -526,9 +533,9 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ PhiTd,
   // (traces of elements outside the tile at every node in sH); the epilogue
   // reuses the space to stage the new state for its face traces
   struct LoopLds {
-    Quad4<R> sU[TE][2][NSP];
-    Quad4<R> sT[2][TE][2][NSP];
-    Quad4<R> sFs[TE][2][NSP];
+    Half2<R> sU[TE][2][2][NSP];     // [element][row h][plane][point]
+    Half2<R> sT[2][TE][2][2][NSP];  // [pair parity][element][row h][plane][flux point]
+    Half2<R> sFs[TE][2][2][NSP];
     Quad4<R> sH[NQ][NHF][NP];
   };
   union StageLds {
@@ -771,7 +778,8 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ PhiTd,
     R U[4] = {ua[0], ua[1], ub[0], ub[1]};
     swap_rows(U[0], U[2]);
     swap_rows(U[1], U[3]);
-    sU[le][h][j] = Quad4<R>{{U[0], U[1], U[2], U[3]}};
+    sU[le][h][0][j] = Half2<R>{U[0], U[1]};
+    sU[le][h][1][j] = Half2<R>{U[2], U[3]};
     R F[4], G[4];
     {
       const R ir = recip(U[0]);
@@ -796,30 +804,31 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ PhiTd,
       R T[4] = {R(0), R(0), R(0), R(0)};
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const Quad4<R> x = sU[le][h][line[c]];
-#pragma unroll
-        for (int s = 0; s < 4; ++s) T[s] += wl[c] * x.v[s];
+        const Half2<R> x0 = sU[le][h][0][line[c]], x1 = sU[le][h][1][line[c]];
+        T[0] += wl[c] * x0.x;
+        T[1] += wl[c] * x0.y;
+        T[2] += wl[c] * x1.x;
+        T[3] += wl[c] * x1.y;
       }
-      sT[par][le][h][j] = Quad4<R>{{T[0], T[1], T[2], T[3]}};
+      sT[par][le][h][0][j] = Half2<R>{T[0], T[1]};
+      sT[par][le][h][1][j] = Half2<R>{T[2], T[3]};
     }
     __syncthreads();
 
     // (3) Lax-Friedrichs flux at flux point j and node qh
     {
-      const Quad4<R>* src = (nbr_le >= 0) ? &sT[par][nbr_le][h][mirror] : &sH[qh][nbr_halo][fi];
-      const Quad4<R> ow = sT[par][le][h][j], nq = *src;
+      const Half2<R>* src0 = (nbr_le >= 0) ? &sT[par][nbr_le][h][0][mirror]
+                                           : reinterpret_cast<const Half2<R>*>(&sH[qh][nbr_halo][fi]);
+      const Half2<R>* src1 = (nbr_le >= 0) ? &sT[par][nbr_le][h][1][mirror] : src0 + 1;
+      const Half2<R> ow0 = sT[par][le][h][0][j], ow1 = sT[par][le][h][1][j], nq0 = *src0, nq1 = *src1;
       // next pair, independent of the reads above
       if (t + 1 < NIT) {
         const int n0 = q0 + 2, n1 = (n0 + 1 < NQ) ? n0 + 1 : n0;
         expand(n0, ua);
         expand(n1, ub);
       }
-      R own[4], nb[4];
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        own[s] = ow.v[s];
-        nb[s] = nq.v[s];
-      }
+      R own[4] = {ow0.x, ow0.y, ow1.x, ow1.y};
+      R nb[4] = {nq0.x, nq0.y, nq1.x, nq1.y};
       if (wave_at_boundary) {  // uniform: only waves with a domain-boundary face pay for the ghosts
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -830,7 +839,8 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ PhiTd,
       }
       R Fs[4];
       rusanov_e2(own, nb, lo_side, Fs, g, fside >> 1);
-      sFs[le][h][j] = Quad4<R>{{Fs[0], Fs[1], Fs[2], Fs[3]}};
+      sFs[le][h][0][j] = Half2<R>{Fs[0], Fs[1]};
+      sFs[le][h][1][j] = Half2<R>{Fs[2], Fs[3]};
     }
     // the interface fluxes of an element are written and read by the same wave
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -841,13 +851,17 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ PhiTd,
     // its own pair at both nodes (variable 2h + i: r[i] at q0, r[2 + i] at q1)
     // and projects it onto the chaos
     {
-      const Quad4<R> fxl = sFs[le][h][0 + b], fxr = sFs[le][h][4 + b];
-      const Quad4<R> fyl = sFs[le][h][8 + a], fyr = sFs[le][h][12 + a];
+      const Half2<R> fxl0 = sFs[le][h][0][0 + b], fxr0 = sFs[le][h][0][4 + b];
+      const Half2<R> fyl0 = sFs[le][h][0][8 + a], fyr0 = sFs[le][h][0][12 + a];
+      const Half2<R> fxl1 = sFs[le][h][1][0 + b], fxr1 = sFs[le][h][1][4 + b];
+      const Half2<R> fyl1 = sFs[le][h][1][8 + a], fyr1 = sFs[le][h][1][12 + a];
+      const R fxl[4] = {fxl0.x, fxl0.y, fxl1.x, fxl1.y}, fxr[4] = {fxr0.x, fxr0.y, fxr1.x, fxr1.y};
+      const R fyl[4] = {fyl0.x, fyl0.y, fyl1.x, fyl1.y}, fyr[4] = {fyr0.x, fyr0.y, fyr1.x, fyr1.y};
       R r[4];
 #pragma unroll
       for (int s = 0; s < 4; ++s)
-        r[s] = -(xdot(dx, F[s]) + fxl.v[s] * dhLa + fxr.v[s] * dhRa) * iJx -
-               (ydot(dy, G[s]) + fyl.v[s] * dhLb + fyr.v[s] * dhRb) * iJy;
+        r[s] = -(xdot(dx, F[s]) + fxl[s] * dhLa + fxr[s] * dhRa) * iJx -
+               (ydot(dy, G[s]) + fyl[s] * dhLb + fyr[s] * dhRb) * iJy;
       swap_rows(r[0], r[2]);
       swap_rows(r[1], r[3]);
 #pragma unroll
