@@ -19,7 +19,14 @@ Filters (Sec. 4.1): u~* = Lambda o u~ and back to nodal with V.
   (App. A);
 * L2 (Sec. 4.1.2, Eq. filter function, Eq. l2 strength):
   lambda = 1 / (1 + alpha1 sum_d j_d^2 (j_d+1)^2 + alpha2 |k|^2 (|k|+1)^2),
-  alpha1 = 1/(eps1 N_p^2 (N_p-1)^2), alpha2 = 1/(eps2 N_c^2 (N_c+1)^2).
+  alpha1 = 1/(eps1 N_p^2 (N_p-1)^2), alpha2 = 1/(eps2 N_c^2 (N_c+1)^2);
+* Lasso (Sec. 4.1.3, Eq. LassoFilterFunction, Eq. fStrength), one physical and
+  one random dimension: per element and conserved variable,
+    u~*_{j,k} = ReLU(1 - (a1 j(j+1) + a2 k(k+1)) ||Psi_j Phi_k||_1 / |u~_{j,k}|) u~_{j,k},
+    a1 = |u~_{N_p-1,0}| / (N_p (N_p-1) ||Psi_{N_p-1} Phi_0||_1),
+    a2 = |u~_{0,N_c}| / (N_c (N_c+1) ||Psi_0 Phi_{N_c}||_1),
+  with ||Psi_j Phi_k||_1 = ||Psi_j||_1 ||Phi_k||_1 (both under their
+  probability measures); a zero coefficient stays zero.
 
 Limiter (Sec. 4.3): per element, mean state u_bar over element x random space,
 eps = min(1e-8, rho_bar, p_bar); if the minimum of density or pressure over
@@ -35,7 +42,7 @@ carries the mean).
 import numpy as np
 
 from .fr import euler_pressure, nodal_at_face_points, nodal_at_solution_points
-from .tables import sensor_threshold
+from .tables import legendre_l1_norms, sensor_threshold
 
 
 class NotRealizable(ArithmeticError):
@@ -122,14 +129,47 @@ def filter_strength(prob, T, R, dt):
     return lam
 
 
+def lasso_norms(prob, T, R):
+    """||Psi_j Phi_k||_1, indexed [k, j] (one physical, one random dimension)."""
+    check_lasso(prob)
+    lx = legendre_l1_norms(T.n)
+    lz = legendre_l1_norms(R.M)
+    return np.outer(lz, lx)
+
+
+def check_lasso(prob):
+    if prob.dim != 1 or prob.rdim != 1:
+        raise ValueError("the Lasso filter is defined here for one physical and one random dimension")
+
+
+def lasso_modal(prob, T, R, ut):
+    """Eq. LassoFilterFunction with the strengths of Eq. fStrength, on spatial-
+    modal coefficients ut[s, k, e, j] (k = chaos degree); returns the filtered ones."""
+    nrm = lasso_norms(prob, T, R)
+    Np, Nc = T.n, R.M - 1
+    j = np.arange(Np, dtype=np.float64)
+    k = np.arange(R.M, dtype=np.float64)
+    au = np.abs(ut)
+    a1 = au[:, 0, :, Np - 1] / (float(Np * (Np - 1)) * nrm[0, Np - 1])   # [s, e]
+    a2 = au[:, Nc, :, 0] / (float(Nc * (Nc + 1)) * nrm[Nc, 0]) if Nc > 0 else np.zeros_like(a1)
+    pen = (a1[:, None, :, None] * (j * (j + 1.0))[None, None, None, :]
+           + a2[:, None, :, None] * (k * (k + 1.0))[None, :, None, None]) * nrm[None, :, None, :]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        f = np.where(au > 0.0, 1.0 - pen / au, 0.0)
+    return np.maximum(f, 0.0) * ut
+
+
 def sensor_filter(prob, T, R, u, dt):
     """Sensor-gated filter; returns (u_filtered, flags)."""
     if prob.filter == "none":
         return u.copy(), np.zeros(u.shape[2], dtype=bool)
     flags = sensor_flags(prob, T, R, u)
-    lam = filter_strength(prob, T, R, dt)
     ut = to_spatial_modal(prob, T, u)
-    uf = to_nodal(prob, T, ut * lam[None, :, None, :])
+    if prob.filter == "lasso":
+        uf = to_nodal(prob, T, lasso_modal(prob, T, R, ut))
+    else:
+        lam = filter_strength(prob, T, R, dt)
+        uf = to_nodal(prob, T, ut * lam[None, :, None, :])
     out = u.copy()
     out[:, :, flags, :] = uf[:, :, flags, :]
     return out, flags

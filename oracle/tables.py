@@ -73,6 +73,26 @@ def gauss_legendre(n):
     return x, w
 
 
+def legendre_l1_norms(n):
+    """||sqrt(2j+1) P_j||_1 under dr/2 on [-1, 1], j = 0..n-1 (the L1 norms of the
+    orthonormal Legendre functions that enter the Lasso filter, Sec. 4.1.3).
+
+    |P_j| is integrated piece by piece between consecutive roots of P_j, where
+    it has one sign, by a Gauss-Legendre rule of j+1 points on each piece
+    (exact for a polynomial of degree j)."""
+    out = np.zeros(n)
+    for j in range(n):
+        roots = gauss_legendre(j)[0] if j > 0 else np.zeros(0)
+        cuts = np.concatenate(([-1.0], roots, [1.0]))
+        xg, wg = gauss_legendre(j + 1)
+        total = 0.0
+        for lo, hi in zip(cuts[:-1], cuts[1:]):
+            x = 0.5 * (hi - lo) * xg + 0.5 * (hi + lo)
+            total += abs(0.5 * (hi - lo) * np.dot(wg, legendre_values(j, x)[j]))
+        out[j] = math.sqrt(2 * j + 1) * 0.5 * total
+    return out
+
+
 def lagrange_values(r_nodes, x):
     """l_j(x) for the Lagrange basis on r_nodes (Sec. 3.2); shape (len(x), N)."""
     r_nodes = np.asarray(r_nodes, dtype=np.float64)
