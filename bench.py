@@ -156,7 +156,7 @@ def alu_roofline(roof, flop_per_dof, dof, precision):
 def other_workloads(torch, Solver, inputs, steps):
     """DOF-updates/s of the cache-resident 1D workloads (FP64, CFL steps in one call)."""
     out = {}
-    for name in ("advection_sine", "burgers_sine", "sod_interface"):
+    for name in ("advection_sine", "burgers_sine", "sod_interface", "burgers_lasso", "sod_lasso"):
         cfg = inputs.CONFIGS[name]
         sol = Solver(cfg)
         u = sol.initial_state()

@@ -67,10 +67,16 @@ typedef int32_t fr_sg_status;
 #define FRSG_BC_OUTFLOW 2     /* ghost = interior trace                           */
 #define FRSG_BC_REFLECT 3     /* ghost = interior trace, normal momentum negated  */
 
-/* modal filter (Sec. 4.1.1 exponential, Sec. 4.1.2 L2) */
+/* modal filter (Sec. 4.1.1 exponential, Sec. 4.1.2 L2, Sec. 4.1.3 Lasso).
+ * FRSG_FILTER_LASSO: the soft threshold of Eq. LassoFilterFunction with the
+ * strengths of Eq. fStrength taken per element and conserved variable from the
+ * highest pure spatial and pure chaos coefficients (which it sets to zero);
+ * one physical and one random dimension only (dim 1, rdim 1), no adjoint
+ * (fr_sg_init returns FRSG_EUNSUPPORTED otherwise, fr_sg_adjoint_step too). */
 #define FRSG_FILTER_NONE 0
 #define FRSG_FILTER_EXP 1
 #define FRSG_FILTER_L2 2
+#define FRSG_FILTER_LASSO 3
 
 /* filter switch: every element, or the modal-decay detector of Sec. 4.2 */
 #define FRSG_SENSOR_ALWAYS 0

@@ -21,7 +21,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "EDEVICE", -4: "ENONFIN
           -6: "EABI"}
 EQUATION = {"advection": 0, "burgers": 1, "euler1d": 2, "euler2d": 3}
 BC = {"periodic": 0, "dirichlet": 1, "outflow": 2, "reflect": 3}
-FILTER = {"none": 0, "exp": 1, "l2": 2}
+FILTER = {"none": 0, "exp": 1, "l2": 2, "lasso": 3}
 SENSOR = {"always": 0, "detector": 1}
 PRECISION = {"fp64": 0, "fp32": 1}
 

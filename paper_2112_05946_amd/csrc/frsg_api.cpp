@@ -83,9 +83,13 @@ fr_sg_status validate(const fr_sg_problem& P, std::string& err) {
       err = "periodic boundaries must be paired";
       return FRSG_EINVAL;
     }
-  if (P.filter < FRSG_FILTER_NONE || P.filter > FRSG_FILTER_L2) {
+  if (P.filter < FRSG_FILTER_NONE || P.filter > FRSG_FILTER_LASSO) {
     err = "unknown filter";
     return FRSG_EINVAL;
+  }
+  if (P.filter == FRSG_FILTER_LASSO && (dim != 1 || P.rdim != 1)) {
+    err = "the Lasso filter is available for one physical and one random dimension";
+    return FRSG_EUNSUPPORTED;
   }
   if (P.filter == FRSG_FILTER_EXP && !(P.alpha >= 0.0 && P.s > 0.0)) {
     err = "exponential filter needs alpha >= 0 and s > 0";
@@ -711,6 +715,10 @@ fr_sg_status fr_sg_adjoint_step(fr_sg_ctx* ctx, const double* u_n, const uint8_t
   if (!(dt > 0.0) || !std::isfinite(dt)) {
     ctx->err = "dt must be positive and finite";
     return FRSG_EINVAL;
+  }
+  if (ctx->prob.filter == FRSG_FILTER_LASSO) {
+    ctx->err = "the adjoint covers the linear filters (exponential, L2), not the Lasso filter";
+    return FRSG_EUNSUPPORTED;
   }
   if (ctx->prob.filter != FRSG_FILTER_NONE && !flags_n) {
     ctx->err = "flags_n is needed: the filter decisions of the forward step";

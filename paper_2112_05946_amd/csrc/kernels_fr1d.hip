@@ -248,6 +248,18 @@ __global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
         den += e2;
       }
     }
+    // Lasso strengths (Eq. fStrength) need |u~| of the highest pure spatial
+    // mode (owned by thread k = 0) and of the highest chaos mode at spatial
+    // mode 0 (thread k = M - 1); they pass through sR, free since step 4
+    double* la = sR + (long)(own ? le : 0) * 2 * S;
+    if (P.filter == FRSG_FILTER_LASSO && own) {
+      if (k == 0)
+#pragma unroll
+        for (int s = 0; s < S; ++s) la[s] = fabs(ut[s][n - 1]);
+      if (k == M - 1)
+#pragma unroll
+        for (int s = 0; s < S; ++s) la[S + s] = fabs(ut[s][0]);
+    }
     if (own) {
       myP[0] = num;
       myP[1] = den;
@@ -262,19 +274,43 @@ __global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
       }
       flag = (P.sensor == FRSG_SENSOR_ALWAYS) || (td > 0.0 && tn / td > P.sensor_thr);
       if (flag && k < M) {
+        if (P.filter == FRSG_FILTER_LASSO) {
+          // Eq. LassoFilterFunction: soft threshold of every (spatial, chaos)
+          // coefficient; filt holds ||Psi_m Phi_k||_1
 #pragma unroll
-        for (int s = 0; s < S; ++s)
-#pragma unroll
-          for (int j = 0; j < n; ++j) {
-            double acc = 0.0;
+          for (int s = 0; s < S; ++s) {
+            const double a1 = la[s] / ((double)(n * (n - 1)) * P.tab.filt[n - 1]);
+            const double a2 = (M > 1) ? la[S + s] / ((double)((M - 1) * M) * P.tab.filt[(M - 1) * n]) : 0.0;
 #pragma unroll
             for (int m = 0; m < n; ++m) {
-              const double f = P.tab.filt[k * n + m];
-              const double lam = (P.filter == FRSG_FILTER_EXP) ? exp(-P.alpha * dt * f) : f;
-              acc += P.tab.V[j * n + m] * (ut[s][m] * lam);
+              const double pen = (a1 * (double)(m * (m + 1)) + a2 * (double)(k * (k + 1))) * P.tab.filt[k * n + m];
+              const double au = fabs(ut[s][m]);
+              const double f = (au > 0.0) ? 1.0 - pen / au : 0.0;
+              ut[s][m] = (f > 0.0 ? f : 0.0) * ut[s][m];
             }
-            O[(s * M + k) * n + j] = acc;
+#pragma unroll
+            for (int j = 0; j < n; ++j) {
+              double acc = 0.0;
+#pragma unroll
+              for (int m = 0; m < n; ++m) acc += P.tab.V[j * n + m] * ut[s][m];
+              O[(s * M + k) * n + j] = acc;
+            }
           }
+        } else {
+#pragma unroll
+          for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int j = 0; j < n; ++j) {
+              double acc = 0.0;
+#pragma unroll
+              for (int m = 0; m < n; ++m) {
+                const double f = P.tab.filt[k * n + m];
+                const double lam = (P.filter == FRSG_FILTER_EXP) ? exp(-P.alpha * dt * f) : f;
+                acc += P.tab.V[j * n + m] * (ut[s][m] * lam);
+              }
+              O[(s * M + k) * n + j] = acc;
+            }
+        }
       }
       if (q == 0 && A.flag_filt) A.flag_filt[e0 + le] = flag ? 1 : 0;
     }

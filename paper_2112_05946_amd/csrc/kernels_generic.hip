@@ -606,6 +606,19 @@ __global__ void __launch_bounds__(kElemBlock) k_sensor_filter(KParams P, double*
     const double* src = ut + (long)sk * nsp;
     auto lam = [&](int m) {
       const double f = P.tab.filt[k * nsp + m];
+      if (P.filter == FRSG_FILTER_LASSO) {
+        // Eq. LassoFilterFunction with the strengths of Eq. fStrength (one
+        // physical and one random dimension); f = ||Psi_m Phi_k||_1
+        const int s = sk / M;
+        const double a1 = fabs(ut[(long)s * M * nsp + n - 1]) / ((double)(n * (n - 1)) * P.tab.filt[n - 1]);
+        const double a2 =
+            M > 1 ? fabs(ut[((long)s * M + M - 1) * nsp]) / ((double)((M - 1) * M) * P.tab.filt[(M - 1) * nsp])
+                  : 0.0;
+        const double pen = (a1 * (double)(m * (m + 1)) + a2 * (double)(k * (k + 1))) * f;
+        const double au = fabs(src[m]);
+        const double g = au > 0.0 ? 1.0 - pen / au : 0.0;
+        return g > 0.0 ? g : 0.0;
+      }
       return P.filter == FRSG_FILTER_EXP ? exp(-P.alpha * dt * f) : f;
     };
     double acc = 0.0;

@@ -55,6 +55,31 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
   }
 }
 
+// ||sqrt(2j+1) P_j||_1 under dr/2 on [-1, 1]: P_j keeps one sign between
+// consecutive roots, so it is integrated piece by piece with a (j+1)-point
+// Gauss rule (exact for degree j) and the absolute values are summed
+double legendre_l1(int j) {
+  std::vector<double> cut(1, -1.0), gx, gw, xr, wr;
+  if (j > 0) {
+    gauss_legendre(j, xr, wr);
+    cut.insert(cut.end(), xr.begin(), xr.end());
+  }
+  cut.push_back(1.0);
+  gauss_legendre(j + 1, gx, gw);
+  std::vector<double> P(j + 1);
+  double total = 0.0;
+  for (size_t i = 0; i + 1 < cut.size(); ++i) {
+    const double h = 0.5 * (cut[i + 1] - cut[i]), c = 0.5 * (cut[i + 1] + cut[i]);
+    double piece = 0.0;
+    for (int g = 0; g < j + 1; ++g) {
+      legendre(j, c + h * gx[g], P.data());
+      piece += gw[g] * P[j];
+    }
+    total += std::fabs(h * piece);
+  }
+  return std::sqrt(2.0 * j + 1.0) * 0.5 * total;
+}
+
 double lagrange(const std::vector<double>& r, int j, double x) {
   double v = 1.0;
   for (size_t m = 0; m < r.size(); ++m)
@@ -223,6 +248,10 @@ bool build_host_tables(const fr_sg_problem& P, HostTables& T, std::string& err) 
         for (int d = 0; d < dim; ++d) sx += (long)dj[d] * dj[d] * (dj[d] + 1) * (dj[d] + 1);
         double pen = a1 * (double)sx + a2 * kk * kk * (kk + 1) * (kk + 1);
         T.filt[k * nsp + j] = 1.0 / (1.0 + pen);
+      } else if (P.filter == FRSG_FILTER_LASSO) {
+        // ||Psi_j Phi_k||_1 (one physical, one random dimension): the kernels
+        // form the data-dependent factors from it
+        T.filt[k * nsp + j] = legendre_l1(j) * legendre_l1(kk);
       }
     }
   }

@@ -150,7 +150,12 @@ SHOCK_VORTEX = dict(
 
 BURGERS_ADJOINT = dict(BURGERS, name="burgers_adjoint", nx=4096, n_steps=500, checkpoint_every=25)
 
-CONFIGS = {c["name"]: c for c in (ADVECTION, BURGERS, SOD, SHOCK_VORTEX, BURGERS_ADJOINT)}
+# the Burgers and Sod workloads with the Lasso filter (Sec. 4.1.3) on every
+# element in place of the detector-gated exponential and L2 filters
+BURGERS_LASSO = dict(BURGERS, name="burgers_lasso", filter="lasso", sensor="always")
+SOD_LASSO = dict(SOD, name="sod_lasso", filter="lasso", sensor="always")
+
+CONFIGS = {c["name"]: c for c in (ADVECTION, BURGERS, SOD, SHOCK_VORTEX, BURGERS_ADJOINT, BURGERS_LASSO, SOD_LASSO)}
 
 
 def small(cfg, nx, ny=None, **kw):

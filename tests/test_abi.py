@@ -77,3 +77,16 @@ def test_null_arguments(lib):
     assert lib.fr_sg_step(None, None, 0.0, None, None) == -1
     assert lib.fr_sg_adjoint_step(None, None, None, 1e-3, None, None) == -1
     assert lib.fr_sg_destroy(None) == 0
+
+
+@pytest.mark.parametrize("base,over", [
+    ("SHOCK_VORTEX", dict(filter="lasso", nx=4, ny=2)),     # two physical dimensions
+    ("BURGERS", dict(filter="lasso", rdim=2, nq1d=10)),     # two random dimensions
+])
+def test_lasso_scope_rejected_before_launch(lib, base, over):
+    """The Lasso filter is provided for one physical and one random dimension."""
+    from paper_2112_05946_amd import binding, inputs
+    P = binding.problem_from_config(dict(getattr(inputs, base), **over))
+    st, ctx, msg = _init(lib, P)
+    assert st == -2, msg
+    assert not ctx.value and "Lasso" in msg

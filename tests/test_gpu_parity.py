@@ -148,7 +148,8 @@ def test_step_euler_vacuum_fuzz():
 
 
 @pytest.mark.parametrize("label,cfg", [("advection", inputs.ADVECTION), ("burgers", inputs.BURGERS),
-                                       ("sod", inputs.SOD)])
+                                       ("sod", inputs.SOD), ("burgers_lasso", inputs.BURGERS_LASSO),
+                                       ("sod_lasso", inputs.SOD_LASSO)])
 def test_full_size_1d_steps(label, cfg):
     """Full configuration sizes, two CFL steps from the initial state."""
     announce("full_size", label)
