@@ -38,6 +38,8 @@ def _check(prob):
         raise ValueError("the adjoint covers the scalar 1D equations (advection, Burgers)")
     if prob.limiter:
         raise ValueError("the adjoint has no limiter (the scalar equations do not use it)")
+    if prob.flux != "rusanov":
+        raise ValueError("the adjoint covers the Lax-Friedrichs flux")
     if prob.filter == "lasso":
         raise ValueError("the adjoint covers the linear filters (exponential, L2), not the Lasso filter")
 

@@ -11,7 +11,8 @@ Sec. 3.2-3.5):
 3. interpolate the solution to the element faces per node (Lagrange
    interpolation, Sec. 3.2) and form the interactive flux there with the
    Lax-Friedrichs (Rusanov) solver, per node, with the dissipation speed the
-   larger spectral radius of the two traces (Sec. 3.3), then project it;
+   larger spectral radius of the two traces (Sec. 3.3), or with the HLL
+   solver (Euler equations), then project it;
 4. interpolate the projected discontinuous flux polynomial to the faces
    (Eq. discontinuous flux polynomial);
 5. total-flux derivative at the solution points: sum_l f_l l_l'(r_j) plus the
@@ -99,6 +100,38 @@ def rusanov(prob, UL, UR, direction):
     return 0.5 * (fL + fR) - 0.5 * lam[None] * (UR - UL)
 
 
+def hll(prob, UL, UR, direction):
+    """HLL interactive flux per node for the Euler equations (named in Tables 5 and 6;
+    the paper gives no formula).  Two waves bound the Riemann fan, with Davis's
+    estimates S_L = min(u_L - c_L, u_R - c_R), S_R = max(u_L + c_L, u_R + c_R)
+    (u the velocity normal to the face, c the sound speed); between them one
+    constant state conserves the fan, which gives
+      F = f_L                                   if S_L >= 0,
+      F = f_R                                   if S_R <= 0,
+      F = (S_R f_L - S_L f_R + S_L S_R (U_R - U_L)) / (S_R - S_L) otherwise."""
+    if not prob.equation.startswith("euler"):
+        raise ValueError("the HLL flux is provided for the Euler equations")
+    dim = 1 if prob.equation == "euler1d" else 2
+    flux = flux_x if direction == 0 else flux_y
+    fL, fR = flux(prob, UL), flux(prob, UR)
+    uL = UL[1 + direction] / UL[0]
+    uR = UR[1 + direction] / UR[0]
+    cL = np.sqrt(prob.gamma * euler_pressure(UL, prob.gamma, dim) / UL[0])
+    cR = np.sqrt(prob.gamma * euler_pressure(UR, prob.gamma, dim) / UR[0])
+    SL = np.minimum(uL - cL, uR - cR)
+    SR = np.maximum(uL + cL, uR + cR)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        mid = (SR[None] * fL - SL[None] * fR + (SL * SR)[None] * (UR - UL)) / (SR - SL)[None]
+    return np.where((SL >= 0.0)[None], fL, np.where((SR <= 0.0)[None], fR, mid))
+
+
+def interactive_flux(prob, UL, UR, direction):
+    """The configured interactive flux (Sec. 3.3): Lax-Friedrichs, or HLL for Euler."""
+    if prob.flux == "hll":
+        return hll(prob, UL, UR, direction)
+    return rusanov(prob, UL, UR, direction)
+
+
 # ----------------------------------------------------------------------------
 # boundary ghosts and face pairing
 # ----------------------------------------------------------------------------
@@ -157,7 +190,7 @@ def _rhs_1d(prob, T, R, u):
     Um = np.einsum("j,sqej->sqe", T.lL, U)
     Up = np.einsum("j,sqej->sqe", T.lR, U)
     left, right = face_pairs(prob, Um, Up, axis=2, sides=(0, 1))
-    Fstar = np.einsum("kq,sqf->skf", R.PW, rusanov(prob, left, right, 0))
+    Fstar = np.einsum("kq,sqf->skf", R.PW, interactive_flux(prob, left, right, 0))
     # 4. discontinuous flux polynomial at the faces
     fDL = np.einsum("j,skej->ske", T.lL, fh)
     fDR = np.einsum("j,skej->ske", T.lR, fh)
@@ -182,7 +215,7 @@ def _rhs_2d(prob, T, R, u):
     Um = np.einsum("a,sqyxba->sqyxb", T.lL, U)
     Up = np.einsum("a,sqyxba->sqyxb", T.lR, U)
     left, right = face_pairs(prob, Um, Up, axis=3, sides=(0, 1))
-    Fx = np.einsum("kq,sqyfb->skyfb", R.PW, rusanov(prob, left, right, 0))
+    Fx = np.einsum("kq,sqyfb->skyfb", R.PW, interactive_flux(prob, left, right, 0))
     fDL = np.einsum("a,skyxba->skyxb", T.lL, fh)
     fDR = np.einsum("a,skyxba->skyxb", T.lR, fh)
     dx_part = np.einsum("ac,skyxbc->skyxba", T.D, fh)
@@ -194,7 +227,7 @@ def _rhs_2d(prob, T, R, u):
     Vm = np.einsum("b,sqyxba->sqyxa", T.lL, U)
     Vp = np.einsum("b,sqyxba->sqyxa", T.lR, U)
     left, right = face_pairs(prob, Vm, Vp, axis=2, sides=(2, 3))
-    Gy = np.einsum("kq,sqfxa->skfxa", R.PW, rusanov(prob, left, right, 1))
+    Gy = np.einsum("kq,sqfxa->skfxa", R.PW, interactive_flux(prob, left, right, 1))
     gDL = np.einsum("b,skyxba->skyxa", T.lL, gh)
     gDR = np.einsum("b,skyxba->skyxa", T.lR, gh)
     dy_part = np.einsum("bc,skyxca->skyxba", T.D, gh)

@@ -30,6 +30,7 @@ class Problem:
     bc_state: List[List[float]] = field(default_factory=lambda: [[0.0] * 4 for _ in range(4)])
     adv_speed: float = 1.0
     gamma: float = 1.4
+    flux: str = "rusanov"
     filter: str = "none"
     alpha: float = 36.0
     s: float = 8.0
