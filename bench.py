@@ -154,9 +154,11 @@ def alu_roofline(roof, flop_per_dof, dof, precision):
 
 
 def other_workloads(torch, Solver, inputs, steps):
-    """DOF-updates/s of the cache-resident 1D workloads (FP64, CFL steps in one call)."""
+    """DOF-updates/s of the other workloads (FP64, CFL steps in one call): the cache-resident 1D
+    problems, with the Lasso filter and the HLL flux, and the shock-vortex problem with HLL."""
     out = {}
-    for name in ("advection_sine", "burgers_sine", "sod_interface", "burgers_lasso", "sod_lasso"):
+    for name in ("advection_sine", "burgers_sine", "sod_interface", "burgers_lasso", "sod_lasso", "sod_hll",
+                 "shock_vortex_hll"):
         cfg = inputs.CONFIGS[name]
         sol = Solver(cfg)
         u = sol.initial_state()
@@ -173,7 +175,9 @@ def other_workloads(torch, Solver, inputs, steps):
         ms = e0.elapsed_time(e1) / steps
         dof = int(sol.info["n_dof"])
         out[name] = {"dof": dof, "ms_per_step": ms, "dof_updates_per_s": dof / (ms / 1e3),
-                     "shape": "%d el, p=%d, %d modes, %d nodes, %d states" % (cfg["nx"], cfg["p"], sol.shape[1],
+                     "shape": "%s el, p=%d, %d modes, %d nodes, %d states" % (
+                         "%dx%d" % (cfg["nx"], cfg["ny"]) if cfg["equation"] == "euler2d" else str(cfg["nx"]),
+                         cfg["p"], sol.shape[1],
                                                                              sol.info["n_nodes"], sol.shape[0])}
         sol.close()
     return out

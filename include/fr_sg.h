@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define FRSG_ABI_VERSION 1
+#define FRSG_ABI_VERSION 2
 
 typedef int32_t fr_sg_status;
 #define FRSG_OK 0
@@ -66,6 +66,14 @@ typedef int32_t fr_sg_status;
 #define FRSG_BC_DIRICHLET 1   /* ghost = bc_state[side] (conservative variables) */
 #define FRSG_BC_OUTFLOW 2     /* ghost = interior trace                           */
 #define FRSG_BC_REFLECT 3     /* ghost = interior trace, normal momentum negated  */
+
+/* interactive flux at the element faces (Sec. 3.3), per random node.
+ * FRSG_FLUX_HLL: the two-wave HLL solver with Davis's wave speeds
+ * S_L = min(u_L - c_L, u_R - c_R), S_R = max(u_L + c_L, u_R + c_R), which the
+ * paper names for its Euler runs (Tables 5, 6); Euler equations only
+ * (fr_sg_init returns FRSG_EUNSUPPORTED for the scalar equations). */
+#define FRSG_FLUX_RUSANOV 0
+#define FRSG_FLUX_HLL 1
 
 /* modal filter (Sec. 4.1.1 exponential, Sec. 4.1.2 L2, Sec. 4.1.3 Lasso).
  * FRSG_FILTER_LASSO: the soft threshold of Eq. LassoFilterFunction with the
@@ -113,6 +121,7 @@ typedef struct fr_sg_problem {
   int32_t limiter;         /* 1: positivity-preserving limiter (Euler only)           */
   double cfl;              /* dt = cfl dx / ((p+1) lambda_max) (1D); 2D analogue      */
   int32_t precision;       /* FRSG_FP64 or FRSG_FP32_MIXED                            */
+  int32_t flux;            /* FRSG_FLUX_RUSANOV (Lax-Friedrichs) or FRSG_FLUX_HLL     */
 } fr_sg_problem;
 
 typedef struct fr_sg_info {

@@ -84,6 +84,37 @@ __device__ __forceinline__ void rusanov(const R* L, const R* Rt, R* Fs, R adv, R
   for (int s = 0; s < S; ++s) Fs[s] = R(0.5) * (fL[s] + fR[s]) - R(0.5) * lam * (Rt[s] - L[s]);
 }
 
+// HLL interactive flux (Euler): two waves with Davis's speed estimates bound
+// the Riemann fan, one constant state between them conserves it
+template <int EQ, int DIR, typename R>
+__device__ __forceinline__ void hll(const R* L, const R* Rt, R* Fs, R gamma) {
+  constexpr int S = nstate<EQ>();
+  R fL[S], fR[S];
+  flux<EQ, DIR>(L, fL, R(0), gamma);
+  flux<EQ, DIR>(Rt, fR, R(0), gamma);
+  const R uL = L[1 + DIR] / L[0], uR = Rt[1 + DIR] / Rt[0];
+  const R cL = sqrt(gamma * pressure<EQ>(L, gamma) / L[0]);
+  const R cR = sqrt(gamma * pressure<EQ>(Rt, gamma) / Rt[0]);
+  const R SL = fmin(uL - cL, uR - cR), SR = fmax(uL + cL, uR + cR);
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+    Fs[s] = (SL >= R(0)) ? fL[s]
+          : (SR <= R(0)) ? fR[s]
+                         : (SR * fL[s] - SL * fR[s] + (SL * SR) * (Rt[s] - L[s])) / (SR - SL);
+}
+
+// the configured interactive flux (Sec. 3.3): Lax-Friedrichs, or HLL for Euler
+template <int EQ, int DIR, typename R>
+__device__ __forceinline__ void interface_flux(int kind, const R* L, const R* Rt, R* Fs, R adv, R gamma) {
+  if constexpr (EQ == kEuler1 || EQ == kEuler2) {
+    if (kind == FRSG_FLUX_HLL) {
+      hll<EQ, DIR>(L, Rt, Fs, gamma);
+      return;
+    }
+  }
+  rusanov<EQ, DIR>(L, Rt, Fs, adv, gamma);
+}
+
 // ghost trace outside boundary `side` (0 x-lo, 1 x-hi, 2 y-lo, 3 y-hi)
 template <int EQ, typename R>
 __device__ __forceinline__ void ghost(const KParams& P, int side, const R* in, R* out) {

@@ -83,6 +83,14 @@ fr_sg_status validate(const fr_sg_problem& P, std::string& err) {
       err = "periodic boundaries must be paired";
       return FRSG_EINVAL;
     }
+  if (P.flux != FRSG_FLUX_RUSANOV && P.flux != FRSG_FLUX_HLL) {
+    err = "unknown interactive flux";
+    return FRSG_EINVAL;
+  }
+  if (P.flux == FRSG_FLUX_HLL && P.equation < FRSG_EULER1D) {
+    err = "the HLL flux is available for the Euler equations";
+    return FRSG_EUNSUPPORTED;
+  }
   if (P.filter < FRSG_FILTER_NONE || P.filter > FRSG_FILTER_LASSO) {
     err = "unknown filter";
     return FRSG_EINVAL;
@@ -404,6 +412,7 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
   if (c->dim == 1) K.bc[2] = K.bc[3] = FRSG_BC_PERIODIC;
   K.cfl = P.cfl;
   K.filter = P.filter;
+  K.flux = P.flux;
   K.sensor = P.sensor;
   K.limiter = P.limiter;
   K.alpha = P.alpha;

@@ -77,6 +77,7 @@ struct KParams {
   double bc_state[4][4];
   double cfl;
   int filter, sensor, limiter;
+  int flux;  // FRSG_FLUX_*
   double alpha, sensor_thr;
   DevTab tab;
   unsigned* status;

@@ -274,6 +274,43 @@ __device__ __forceinline__ void rusanov_e2(const T* own, const T* nb, bool nb_le
   for (int s = 0; s < 4; ++s) Fs[s] = T(0.5) * (fo[s] + fn[s]) - hl * (nb[s] - own[s]);
 }
 
+// HLL flux of the 2D Euler equations along direction dir between the own trace
+// and the neighbour's (the left state when nb_left): Davis's wave speeds
+// S_L = min(u_L - c_L, u_R - c_R), S_R = max(u_L + c_L, u_R + c_R).  Both
+// elements of a face pass the same left and right states, so they get the
+// same result.
+template <typename T>
+__device__ __forceinline__ void hll_e2(const T* own, const T* nb, bool nb_left, T* Fs, T g, int dir) {
+  T Lv[4], Rv[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    Lv[s] = nb_left ? nb[s] : own[s];
+    Rv[s] = nb_left ? own[s] : nb[s];
+  }
+  T fL[4], fR[4], uL, uR, cL, cR;
+  auto side = [&](const T* U, T* f, T& un, T& c) {
+    const T ir = recip(U[0]);
+    const T mn = dir == 0 ? U[1] : U[2];
+    const T p = (g - T(1)) * (U[3] - T(0.5) * (U[1] * U[1] + U[2] * U[2]) * ir);
+    const T vn = mn * ir;
+    f[0] = mn;
+    f[1] = U[1] * vn + (dir == 0 ? p : T(0));
+    f[2] = U[2] * vn + (dir == 0 ? T(0) : p);
+    f[3] = (U[3] + p) * vn;
+    un = vn;
+    c = sqrt_t(g * p * ir);
+  };
+  side(Lv, fL, uL, cL);
+  side(Rv, fR, uR, cR);
+  const T SL = fmin(uL - cL, uR - cR), SR = fmax(uL + cL, uR + cR);
+  const T iw = recip(SR - SL);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const T mid = (SR * fL[s] - SL * fR[s] + (SL * SR) * (Rv[s] - Lv[s])) * iw;
+    Fs[s] = (SL >= T(0)) ? fL[s] : (SR <= T(0)) ? fR[s] : mid;
+  }
+}
+
 // the four conserved variables at one point, stored with one or two LDS accesses
 template <typename T>
 struct alignas(4 * sizeof(T) > 16 ? 16 : 4 * sizeof(T)) Quad4 {
@@ -517,7 +554,7 @@ __device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsig
 // the stage kernel; R is the type of the node loop (nodal values, fluxes,
 // residuals, projection), the epilogue runs in FP64
 // ---------------------------------------------------------------------------
-template <int M, int NQ, typename R>
+template <int M, int NQ, typename R, int FLUX>
 __global__ void __launch_bounds__(BLKS) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 2 : FRSG_FP32_WAVES)))
 k_stage2d(KParams P, StageArgs A, const double* __restrict__ PhiTd,
                                                   const R* __restrict__ PhiT, const R* __restrict__ PWT,
@@ -838,7 +875,10 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ PhiTd,
         }
       }
       R Fs[4];
-      rusanov_e2(own, nb, lo_side, Fs, g, fside >> 1);
+      if constexpr (FLUX == FRSG_FLUX_HLL)
+        hll_e2(own, nb, lo_side, Fs, g, fside >> 1);
+      else
+        rusanov_e2(own, nb, lo_side, Fs, g, fside >> 1);
       sFs[le][h][0][j] = Half2<R>{Fs[0], Fs[1]};
       sFs[le][h][1][j] = Half2<R>{Fs[2], Fs[3]};
     }
@@ -1092,12 +1132,21 @@ static hipError_t launch_stage_t(const KParams& P, const FusedStage& S, hipStrea
   A.tr_in = S.tr_in;
   A.tr_out = S.tr_out;
   const int ntiles = (P.nx / TX) * (P.ny / TY);
-  if (S.fp32)
-    hipLaunchKernelGGL((k_stage2d<M, NQ, float>), dim3(ntiles), dim3(BLKS), 0, s, P, A, S.PhiT, S.PhiT32,
-                       S.PWT32, S.in, S.u, S.in, S.out);
-  else
-    hipLaunchKernelGGL((k_stage2d<M, NQ, double>), dim3(ntiles), dim3(BLKS), 0, s, P, A, S.PhiT, S.PhiT,
-                       S.PWT, S.in, S.u, S.in, S.out);
+  if (S.fp32) {
+    if (P.flux == FRSG_FLUX_HLL)
+      hipLaunchKernelGGL((k_stage2d<M, NQ, float, FRSG_FLUX_HLL>), dim3(ntiles), dim3(BLKS), 0, s, P, A, S.PhiT,
+                         S.PhiT32, S.PWT32, S.in, S.u, S.in, S.out);
+    else
+      hipLaunchKernelGGL((k_stage2d<M, NQ, float, FRSG_FLUX_RUSANOV>), dim3(ntiles), dim3(BLKS), 0, s, P, A, S.PhiT,
+                         S.PhiT32, S.PWT32, S.in, S.u, S.in, S.out);
+  } else {
+    if (P.flux == FRSG_FLUX_HLL)
+      hipLaunchKernelGGL((k_stage2d<M, NQ, double, FRSG_FLUX_HLL>), dim3(ntiles), dim3(BLKS), 0, s, P, A, S.PhiT,
+                         S.PhiT, S.PWT, S.in, S.u, S.in, S.out);
+    else
+      hipLaunchKernelGGL((k_stage2d<M, NQ, double, FRSG_FLUX_RUSANOV>), dim3(ntiles), dim3(BLKS), 0, s, P, A,
+                         S.PhiT, S.PhiT, S.PWT, S.in, S.u, S.in, S.out);
+  }
   return hipGetLastError();
 }
 

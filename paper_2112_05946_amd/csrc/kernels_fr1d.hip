@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
 #pragma unroll
       for (int s = 0; s < S; ++s) UL[s] = Tl[S + s];
     }
-    rusanov<EQ, 0>(UL, Tc, FL, P.adv, P.gamma);
+    interface_flux<EQ, 0>(P.flux, UL, Tc, FL, P.adv, P.gamma);
     // right face: right state = neighbour's r = -1 trace, or the ghost of our r = +1 trace
     if (e == E - 1 && !periodic) {
       ghost<EQ>(P, 1, Tc + S, UR);
@@ -152,7 +152,7 @@ __global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
 #pragma unroll
       for (int s = 0; s < S; ++s) UR[s] = Tr[s];
     }
-    rusanov<EQ, 0>(Tc + S, UR, FR, P.adv, P.gamma);
+    interface_flux<EQ, 0>(P.flux, Tc + S, UR, FR, P.adv, P.gamma);
     const double iJ = 1.0 / P.Jx;
 #pragma unroll
     for (int s = 0; s < S; ++s) {

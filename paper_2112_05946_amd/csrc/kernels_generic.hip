@@ -160,7 +160,7 @@ __global__ void __launch_bounds__(kBlock) k_faces_1d(KParams P, const double* __
     trace(Un, f, P.tab.lL, UR);
   }
   double Fs[S];
-  rusanov<EQ, 0>(UL, UR, Fs, P.adv, P.gamma);
+  interface_flux<EQ, 0>(P.flux, UL, UR, Fs, P.adv, P.gamma);
   if (f >= 1) {
     trace(Fn, f - 1, P.tab.lR, tmp);
 #pragma unroll
@@ -228,7 +228,7 @@ __global__ void __launch_bounds__(kBlock) k_faces_2d(KParams P, const double* __
     trace(Un, elem(f), P.tab.lL, UR);
   }
   double Fs[S];
-  rusanov<EQ, DIR>(UL, UR, Fs, P.adv, P.gamma);
+  interface_flux<EQ, DIR>(P.flux, UL, UR, Fs, P.adv, P.gamma);
   const int nface_slots = 4 * n;
   if (f >= 1) {
     const int e = elem(f - 1);

@@ -155,7 +155,13 @@ BURGERS_ADJOINT = dict(BURGERS, name="burgers_adjoint", nx=4096, n_steps=500, ch
 BURGERS_LASSO = dict(BURGERS, name="burgers_lasso", filter="lasso", sensor="always")
 SOD_LASSO = dict(SOD, name="sod_lasso", filter="lasso", sensor="always")
 
-CONFIGS = {c["name"]: c for c in (ADVECTION, BURGERS, SOD, SHOCK_VORTEX, BURGERS_ADJOINT, BURGERS_LASSO, SOD_LASSO)}
+# the Sod and shock-vortex workloads with the HLL interactive flux the paper
+# uses for them (Tables 5, 6) in place of Lax-Friedrichs
+SOD_HLL = dict(SOD, name="sod_hll", flux="hll")
+SHOCK_VORTEX_HLL = dict(SHOCK_VORTEX, name="shock_vortex_hll", flux="hll")
+
+CONFIGS = {c["name"]: c for c in (ADVECTION, BURGERS, SOD, SHOCK_VORTEX, BURGERS_ADJOINT, BURGERS_LASSO, SOD_LASSO,
+                                  SOD_HLL, SHOCK_VORTEX_HLL)}
 
 
 def small(cfg, nx, ny=None, **kw):

@@ -90,3 +90,14 @@ def test_lasso_scope_rejected_before_launch(lib, base, over):
     st, ctx, msg = _init(lib, P)
     assert st == -2, msg
     assert not ctx.value and "Lasso" in msg
+
+
+def test_hll_needs_the_euler_equations(lib):
+    from paper_2112_05946_amd import binding, inputs
+    P = binding.problem_from_config(dict(inputs.BURGERS, flux="hll"))
+    st, ctx, msg = _init(lib, P)
+    assert st == -2 and "HLL" in msg
+    P = binding.problem_from_config(inputs.BURGERS)
+    P.flux = 7
+    st, ctx, msg = _init(lib, P)
+    assert st == -1 and not ctx.value
