@@ -177,8 +177,7 @@ def other_workloads(torch, Solver, inputs, steps):
         out[name] = {"dof": dof, "ms_per_step": ms, "dof_updates_per_s": dof / (ms / 1e3),
                      "shape": "%s el, p=%d, %d modes, %d nodes, %d states" % (
                          "%dx%d" % (cfg["nx"], cfg["ny"]) if cfg["equation"] == "euler2d" else str(cfg["nx"]),
-                         cfg["p"], sol.shape[1],
-                                                                             sol.info["n_nodes"], sol.shape[0])}
+                         cfg["p"], sol.shape[1], sol.info["n_nodes"], sol.shape[0])}
         sol.close()
     return out
 
