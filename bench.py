@@ -34,7 +34,8 @@ FP32_VECTOR_TFLOPS = 157.3
 # 2-3: 4 on average)
 SV_FLOP_PER_DOF_LAUNCH = 199.0
 # symbol of the stage kernel for the shock-vortex sizes (15 modes, 25 nodes), per precision
-KERNEL_NAME = {"fp64": "k_stage2d<15, 25, double>", "fp32": "k_stage2d<15, 25, float>"}
+# the stage kernel's instances for the headline workload (Lax-Friedrichs flux)
+KERNEL_NAME = {"fp64": "k_stage2d<15, 25, double, 0>", "fp32": "k_stage2d<15, 25, float, 0>"}
 
 
 def traffic_for(kernel, alg_bytes):
