@@ -31,6 +31,7 @@ class Problem:
     adv_speed: float = 1.0
     gamma: float = 1.4
     flux: str = "rusanov"
+    integrator: str = "ssprk3"
     filter: str = "none"
     alpha: float = 36.0
     s: float = 8.0
