@@ -156,10 +156,11 @@ def alu_roofline(roof, flop_per_dof, dof, precision):
 
 def other_workloads(torch, Solver, inputs, steps):
     """DOF-updates/s of the other workloads (FP64, CFL steps in one call): the cache-resident 1D
-    problems, with the Lasso filter and the HLL flux, and the shock-vortex problem with HLL."""
+    problems, with the Lasso filter, the HLL flux and the Bogacki-Shampine integrator, and the
+    shock-vortex problem with HLL, alone and with Bogacki-Shampine."""
     out = {}
     for name in ("advection_sine", "burgers_sine", "sod_interface", "burgers_lasso", "sod_lasso", "sod_hll",
-                 "shock_vortex_hll"):
+                 "shock_vortex_hll", "sod_hll_bs3", "shock_vortex_hll_bs3"):
         cfg = inputs.CONFIGS[name]
         sol = Solver(cfg)
         u = sol.initial_state()

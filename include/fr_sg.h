@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define FRSG_ABI_VERSION 2
+#define FRSG_ABI_VERSION 3
 
 typedef int32_t fr_sg_status;
 #define FRSG_OK 0
@@ -74,6 +74,21 @@ typedef int32_t fr_sg_status;
  * (fr_sg_init returns FRSG_EUNSUPPORTED for the scalar equations). */
 #define FRSG_FLUX_RUSANOV 0
 #define FRSG_FLUX_HLL 1
+
+/* time integrator.  FRSG_SSPRK3: three-stage SSP Runge-Kutta (Shu-Osher form),
+ * the limiter after each stage, the sensor-gated filter and the limiter at the
+ * end (the fused kernels run it with the stage work in one launch per stage).
+ * The others are the explicit integrators the paper's tables name, at the same
+ * CFL step (no error control): FRSG_RK4 (classical, Table 1),
+ * FRSG_RK_BS3 (Bogacki-Shampine 3(2), Tables 5, 6), FRSG_RK_TSIT5 (Tsitouras
+ * 5(4), Table 4); stage states Y_i = Lim(u + dt sum_j a_ij K_j), then
+ * u <- Lim(Filter(u + dt sum_i b_i K_i)).  They keep one right-hand-side buffer
+ * per stage in the workspace and run the right-hand side, the stage
+ * combination and the limiter as separate passes; no adjoint. */
+#define FRSG_SSPRK3 0
+#define FRSG_RK4 1
+#define FRSG_RK_BS3 2
+#define FRSG_RK_TSIT5 3
 
 /* modal filter (Sec. 4.1.1 exponential, Sec. 4.1.2 L2, Sec. 4.1.3 Lasso).
  * FRSG_FILTER_LASSO: the soft threshold of Eq. LassoFilterFunction with the
@@ -122,6 +137,7 @@ typedef struct fr_sg_problem {
   double cfl;              /* dt = cfl dx / ((p+1) lambda_max) (1D); 2D analogue      */
   int32_t precision;       /* FRSG_FP64 or FRSG_FP32_MIXED                            */
   int32_t flux;            /* FRSG_FLUX_RUSANOV (Lax-Friedrichs) or FRSG_FLUX_HLL     */
+  int32_t integrator;      /* FRSG_SSPRK3, FRSG_RK4, FRSG_RK_BS3, FRSG_RK_TSIT5       */
 } fr_sg_problem;
 
 typedef struct fr_sg_info {

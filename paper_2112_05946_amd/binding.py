@@ -16,13 +16,14 @@ from . import inputs
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfrsg.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 STATUS = {0: "OK", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "EDEVICE", -4: "ENONFINITE", -5: "ENOTREALIZABLE",
           -6: "EABI"}
 EQUATION = {"advection": 0, "burgers": 1, "euler1d": 2, "euler2d": 3}
 BC = {"periodic": 0, "dirichlet": 1, "outflow": 2, "reflect": 3}
 FILTER = {"none": 0, "exp": 1, "l2": 2, "lasso": 3}
 FLUX = {"rusanov": 0, "hll": 1}
+INTEGRATOR = {"ssprk3": 0, "rk4": 1, "bs3": 2, "tsit5": 3}
 SENSOR = {"always": 0, "detector": 1}
 PRECISION = {"fp64": 0, "fp32": 1}
 
@@ -45,7 +46,7 @@ class Problem(ctypes.Structure):
         ("eps1", ctypes.c_double), ("eps2", ctypes.c_double),
         ("sensor", ctypes.c_int32), ("s0", ctypes.c_double), ("kappa", ctypes.c_double),
         ("limiter", ctypes.c_int32), ("cfl", ctypes.c_double), ("precision", ctypes.c_int32),
-        ("flux", ctypes.c_int32),
+        ("flux", ctypes.c_int32), ("integrator", ctypes.c_int32),
     ]
 
 
@@ -125,6 +126,7 @@ def problem_from_config(cfg, precision="fp64"):
     P.gamma = float(cfg.get("gamma", 1.4))
     P.filter = FILTER[cfg.get("filter", "none")]
     P.flux = FLUX[cfg.get("flux", "rusanov")]
+    P.integrator = INTEGRATOR[cfg.get("integrator", "ssprk3")]
     P.alpha = float(cfg.get("alpha", 36.0))
     P.s = float(cfg.get("s", 8.0))
     P.eps1 = float(cfg.get("eps1", 0.6))

@@ -25,6 +25,38 @@ thread_local std::string g_init_error;
 
 int nstates(int eq) { return eq <= FRSG_BURGERS ? 1 : (eq == FRSG_EULER1D ? 3 : 4); }
 
+// Explicit Runge-Kutta tableaux of the paper's integrators (RK4, Table 1;
+// Tsitouras 5(4), Table 4; Bogacki-Shampine 3(2), Tables 5, 6), used at the
+// CFL step: the propagating weights only (the first-same-as-last stage of the
+// embedded pairs serves the error estimate and is left out).
+struct Tableau {
+  int s;
+  double A[kRkMaxTerms][kRkMaxTerms];
+  double b[kRkMaxTerms];
+};
+const Tableau kRK4 = {4,
+                      {{0}, {0.5}, {0.0, 0.5}, {0.0, 0.0, 1.0}},
+                      {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0}};
+const Tableau kBS3 = {3, {{0}, {0.5}, {0.0, 0.75}}, {2.0 / 9.0, 1.0 / 3.0, 4.0 / 9.0}};
+const Tableau kTsit5 = {6,
+                        {{0},
+                         {0.161},
+                         {-0.008480655492356989, 0.335480655492357},
+                         {2.897153057105493, -6.359448489975075, 4.3622954328695815},
+                         {5.325864828439257, -11.748883564062828, 7.4955393428898365, -0.09249506636175525},
+                         {5.86145544294642, -12.92096931784711, 8.159367898576159, -0.071584973281401,
+                          -0.028269050394068383}},
+                        {0.09646076681806523, 0.01, 0.4798896504144996, 1.379008574103742, -3.290069515436081,
+                         2.324710524099774}};
+const Tableau* tableau_of(int integrator) {
+  switch (integrator) {
+    case FRSG_RK4: return &kRK4;
+    case FRSG_RK_BS3: return &kBS3;
+    case FRSG_RK_TSIT5: return &kTsit5;
+    default: return nullptr;
+  }
+}
+
 fr_sg_status validate(const fr_sg_problem& P, std::string& err) {
   if (P.abi_version != FRSG_ABI_VERSION) {
     err = "abi_version mismatch";
@@ -83,6 +115,10 @@ fr_sg_status validate(const fr_sg_problem& P, std::string& err) {
       err = "periodic boundaries must be paired";
       return FRSG_EINVAL;
     }
+  if (P.integrator < FRSG_SSPRK3 || P.integrator > FRSG_RK_TSIT5) {
+    err = "unknown integrator";
+    return FRSG_EINVAL;
+  }
   if (P.flux != FRSG_FLUX_RUSANOV && P.flux != FRSG_FLUX_HLL) {
     err = "unknown interactive flux";
     return FRSG_EINVAL;
@@ -348,7 +384,11 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
   const size_t ntr = c->fused ? fused2d_trace_count(P.nx, P.ny, T.M) : 0;
   size_t o_tr0 = align_up(o_apt + nadj_part * 8);
   size_t o_tr1 = align_up(o_tr0 + ntr * 8);
-  size_t total = align_up(o_tr1 + ntr * 8);
+  // tableau integrators: one right-hand-side buffer per stage
+  const Tableau* tab_rk = tableau_of(P.integrator);
+  const int nrk = tab_rk ? tab_rk->s : 0;
+  size_t o_rk = align_up(o_tr1 + ntr * 8);
+  size_t total = align_up(o_rk + (size_t)nrk * align_up(state * 8));
   char* ws = nullptr;
   he = hipMalloc(&ws, total);
   if (he != hipSuccess) {
@@ -381,6 +421,7 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
     c->ws.agT = (double*)(ws + o_agt);
     c->ws.apart = (double*)(ws + o_apt);
   }
+  for (int i = 0; i < nrk; ++i) c->ws.rk[i] = (double*)(ws + o_rk + (size_t)i * align_up(state * 8));
   if (ntr) {
     c->ws.tr[0] = (double*)(ws + o_tr0);
     c->ws.tr[1] = (double*)(ws + o_tr1);
@@ -499,12 +540,19 @@ static fr_sg_status rhs_passes(fr_sg_ctx* ctx, const double* in, int do_cfl) {
   return timed(ctx, "resid", 0.0, [&] { return launch_resid(K, W.Fn, W.Gn, W.Corr, W.Un, s); });
 }
 
+static fr_sg_status rhs_into(fr_sg_ctx* ctx, const double* u, double* dudt);
+
 fr_sg_status fr_sg_rhs(fr_sg_ctx* ctx, const double* u, double* dudt) {
   if (!ctx) return FRSG_EINVAL;
   if (!u || !dudt || u == dudt) {
     ctx->err = "u and dudt must be distinct device pointers";
     return FRSG_EINVAL;
   }
+  return rhs_into(ctx, u, dudt);
+}
+
+// the right-hand side of u into dudt with the path's kernels (no CFL maximum)
+static fr_sg_status rhs_into(fr_sg_ctx* ctx, const double* u, double* dudt) {
   if (ctx->fused) {
     FusedStage S{u,          u,          dudt,         0.0,         1.0,           0,
                  nullptr,    nullptr,    nullptr,      ctx->dDt,    ctx->dcmax,    ctx->dPhiT,
@@ -667,6 +715,89 @@ static fr_sg_status step_fused(fr_sg_ctx* ctx, double* u, double dt, double* dt_
   return FRSG_OK;
 }
 
+// One step of a tableau integrator (RK4, Bogacki-Shampine 3(2), Tsitouras 5(4)):
+//   K_1 = R(u), Y_i = Lim(u + dt sum_{j<i} a_ij K_j), K_i = R(Y_i),
+//   u <- Lim(Filter(u + dt sum_i b_i K_i)),
+// with the path's right-hand-side kernels, the stage combination kernel and the
+// element-wise limiter and sensor/filter passes.  Flags: row 0 = limiter acted
+// on any stage state, row 1 = 0, rows 2 and 3 as for SSP-RK3.
+static fr_sg_status step_rk(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, uint8_t* flags) {
+  const KParams& K = ctx->kp;
+  Workspace& W = ctx->ws;
+  hipStream_t s = ctx->stream;
+  const Tableau& tb = *tableau_of(ctx->prob.integrator);
+  const int E = ctx->E;
+  const long n = (long)ctx->S * ctx->kp.M * E * ctx->nsp;
+  const double sb = state_bytes(ctx);
+  unsigned long long* lam = (unsigned long long*)(W.scal + 1);
+  fr_sg_status st;
+  // dt on the device: fixed, or from the CFL maximum of u
+  if (dt > 0.0) {
+    if (ctx->fused || ctx->fused1d)
+      FRSG_TRY_HIP(launch_set_dt(K, dt, nullptr, nullptr, s), ctx);
+    else
+      FRSG_TRY_HIP(launch_set_scalars(K, dt, s), ctx);
+  } else if (ctx->fused) {
+    if ((st = timed(ctx, "cfl", sb, [&] { return launch_fused_cfl(K, u, lam, s); }))) return st;
+    FRSG_TRY_HIP(launch_dt_from(K, lam, nullptr, nullptr, s), ctx);
+  } else if (ctx->fused1d) {
+    if ((st = timed(ctx, "cfl", sb, [&] { return launch_cfl1d(K, u, lam, s); }))) return st;
+    FRSG_TRY_HIP(launch_dt_from(K, lam, nullptr, nullptr, s), ctx);
+  } else {
+    FRSG_TRY_HIP(launch_set_scalars(K, 0.0, s), ctx);
+    if ((st = timed(ctx, "nodal", sb, [&] { return launch_nodal(K, u, W.Un, W.Fn, W.Gn, 1, s); }))) return st;
+    FRSG_TRY_HIP(launch_dt(K, ctx->dim, nullptr, s), ctx);
+  }
+  uint8_t* f0 = flags ? flags : nullptr;
+  uint8_t* scratch = (uint8_t*)W.w2;  // per-stage limiter flags, OR-ed into row 0
+  if (f0) FRSG_TRY_HIP(launch_fill_flags(f0, E, s), ctx);
+  if (flags) FRSG_TRY_HIP(launch_fill_flags(flags + E, E, s), ctx);
+  double* Y = W.w1;
+  for (int i = 0; i < tb.s; ++i) {
+    const double* in = u;
+    if (i > 0) {
+      RkTerms T;
+      T.n = 0;
+      for (int j = 0; j < i; ++j)
+        if (tb.A[i][j] != 0.0) {
+          T.K[T.n] = W.rk[j];
+          T.a[T.n] = tb.A[i][j];
+          ++T.n;
+        }
+      if ((st = timed(ctx, "rk_stage", (T.n + 2) * sb,
+                      [&] { return launch_rk_combine(u, T, K.dt, Y, n, s); })))
+        return st;
+      if (ctx->prob.limiter) {
+        if ((st = fr_sg_limit(ctx, Y, f0 ? scratch : nullptr)) != FRSG_OK) return st;
+        if (f0) FRSG_TRY_HIP(launch_or_flags(f0, scratch, E, s), ctx);
+      }
+      in = Y;
+    }
+    if ((st = rhs_into(ctx, in, W.rk[i])) != FRSG_OK) return st;
+  }
+  RkTerms T;
+  T.n = 0;
+  for (int i = 0; i < tb.s; ++i)
+    if (tb.b[i] != 0.0) {
+      T.K[T.n] = W.rk[i];
+      T.a[T.n] = tb.b[i];
+      ++T.n;
+    }
+  if ((st = timed(ctx, "rk_update", (T.n + 2) * sb, [&] { return launch_rk_combine(u, T, K.dt, u, n, s); })))
+    return st;
+  uint8_t* f2 = flags ? flags + 2 * E : nullptr;
+  uint8_t* f3 = flags ? flags + 3 * E : nullptr;
+  if (ctx->prob.filter != FRSG_FILTER_NONE) {
+    if ((st = timed(ctx, "sensor_filter", 2 * sb, [&] { return launch_sensor_filter(K, u, f2, s); }))) return st;
+  } else if (f2) {
+    FRSG_TRY_HIP(launch_fill_flags(f2, E, s), ctx);
+  }
+  if ((st = fr_sg_limit(ctx, u, f3)) != FRSG_OK) return st;
+  ctx->lam_for = nullptr;
+  if (dt_used) FRSG_TRY_HIP(launch_copy_dt(K, dt_used, s), ctx);
+  return FRSG_OK;
+}
+
 static fr_sg_status check_step_args(fr_sg_ctx* ctx, double* u, double dt) {
   if (!ctx) return FRSG_EINVAL;
   if (!u) {
@@ -683,6 +814,7 @@ static fr_sg_status check_step_args(fr_sg_ctx* ctx, double* u, double dt) {
 fr_sg_status fr_sg_step(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, uint8_t* flags) {
   fr_sg_status st = check_step_args(ctx, u, dt);
   if (st != FRSG_OK) return st;
+  if (ctx->prob.integrator != FRSG_SSPRK3) return step_rk(ctx, u, dt, dt_used, flags);
   if (ctx->fused) return step_fused(ctx, u, dt, dt_used, flags, false);
   if (ctx->fused1d) return step_fused1d(ctx, u, dt, dt_used, flags, false);
   return step_generic(ctx, u, dt, dt_used, flags);
@@ -699,7 +831,9 @@ fr_sg_status fr_sg_steps(fr_sg_ctx* ctx, double* u, int32_t nsteps, double* dt_u
   for (int i = 0; i < nsteps; ++i) {
     double* dtu = dt_used ? dt_used + i : nullptr;
     uint8_t* f = flags ? flags + i * fl : nullptr;
-    if (ctx->fused)
+    if (ctx->prob.integrator != FRSG_SSPRK3)
+      st = step_rk(ctx, u, 0.0, dtu, f);
+    else if (ctx->fused)
       st = step_fused(ctx, u, 0.0, dtu, f, i > 0);
     else if (ctx->fused1d)
       st = step_fused1d(ctx, u, 0.0, dtu, f, i > 0);
@@ -724,6 +858,10 @@ fr_sg_status fr_sg_adjoint_step(fr_sg_ctx* ctx, const double* u_n, const uint8_t
   if (!(dt > 0.0) || !std::isfinite(dt)) {
     ctx->err = "dt must be positive and finite";
     return FRSG_EINVAL;
+  }
+  if (ctx->prob.integrator != FRSG_SSPRK3) {
+    ctx->err = "the adjoint covers the SSP-RK3 step";
+    return FRSG_EUNSUPPORTED;
   }
   if (ctx->prob.filter == FRSG_FILTER_LASSO) {
     ctx->err = "the adjoint covers the linear filters (exponential, L2), not the Lasso filter";

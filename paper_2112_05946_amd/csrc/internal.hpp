@@ -85,6 +85,8 @@ struct KParams {
   double* dt;                    // device time step of the current step
 };
 
+constexpr int kRkMaxTerms = 8;  // stages of the largest tableau integrator, and more
+
 struct Workspace {
   double* w1 = nullptr;
   double* w2 = nullptr;
@@ -102,6 +104,8 @@ struct Workspace {
   // fused 2D: modal face traces on tile boundaries, written by one stage launch
   // for the next (two buffers, used in turn)
   double* tr[2] = {nullptr, nullptr};
+  // tableau integrators: one right-hand-side buffer per stage
+  double* rk[kRkMaxTerms] = {nullptr};
   size_t bytes = 0;
 };
 
@@ -194,6 +198,15 @@ hipError_t launch_project_ic(const KParams& P, const double* U0, double* u, hipS
 hipError_t launch_limiter(const KParams& P, double* u, unsigned char* flags, hipStream_t s);
 hipError_t launch_sensor_filter(const KParams& P, double* u, unsigned char* flags, hipStream_t s);
 hipError_t launch_fill_flags(unsigned char* flags, long n, hipStream_t s);
+// explicit Runge-Kutta stage combination: out = u + dt sum_j a[j] K[j] (flat state of n doubles)
+struct RkTerms {
+  const double* K[kRkMaxTerms];
+  double a[kRkMaxTerms];
+  int n;
+};
+hipError_t launch_rk_combine(const double* u, const RkTerms& T, const double* dt, double* out, long n,
+                             hipStream_t s);
+hipError_t launch_or_flags(unsigned char* dst, const unsigned char* src, long n, hipStream_t s);
 hipError_t launch_copy_dt(const KParams& P, double* dt_used, hipStream_t s);
 
 // fused 1D stage kernel (kernels_fr1d.hip)

@@ -159,9 +159,13 @@ SOD_LASSO = dict(SOD, name="sod_lasso", filter="lasso", sensor="always")
 # uses for them (Tables 5, 6) in place of Lax-Friedrichs
 SOD_HLL = dict(SOD, name="sod_hll", flux="hll")
 SHOCK_VORTEX_HLL = dict(SHOCK_VORTEX, name="shock_vortex_hll", flux="hll")
+# ... and with the Bogacki-Shampine integrator as well (the paper's settings in
+# Tables 5 and 6), at the CFL step
+SOD_HLL_BS3 = dict(SOD, name="sod_hll_bs3", flux="hll", integrator="bs3")
+SHOCK_VORTEX_HLL_BS3 = dict(SHOCK_VORTEX, name="shock_vortex_hll_bs3", flux="hll", integrator="bs3")
 
 CONFIGS = {c["name"]: c for c in (ADVECTION, BURGERS, SOD, SHOCK_VORTEX, BURGERS_ADJOINT, BURGERS_LASSO, SOD_LASSO,
-                                  SOD_HLL, SHOCK_VORTEX_HLL)}
+                                  SOD_HLL, SHOCK_VORTEX_HLL, SOD_HLL_BS3, SHOCK_VORTEX_HLL_BS3)}
 
 
 def small(cfg, nx, ny=None, **kw):

@@ -101,3 +101,11 @@ def test_hll_needs_the_euler_equations(lib):
     P.flux = 7
     st, ctx, msg = _init(lib, P)
     assert st == -1 and not ctx.value
+
+
+def test_unknown_integrator_rejected(lib):
+    from paper_2112_05946_amd import binding, inputs
+    P = binding.problem_from_config(inputs.BURGERS)
+    P.integrator = 9
+    st, ctx, msg = _init(lib, P)
+    assert st == -1 and "integrator" in msg

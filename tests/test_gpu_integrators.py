@@ -1,0 +1,91 @@
+"""The paper's explicit integrators (RK4, Bogacki-Shampine 3(2), Tsitouras
+5(4)) at the CFL step on the GPU against the oracle: every right-hand-side
+path (fused 1D, multi-pass 1D, fused 2D, generic 2D), with filters, the
+limiter and the HLL flux."""
+
+import numpy as np
+import pytest
+
+from gpu_util import RTOL_FP64, announce, oracle_for, rel_l2, solver_for, to_dev, to_np
+from oracle import stepper as ostep
+from oracle.initial import project_initial
+from paper_2112_05946_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ("burgers_rk4_fused", dict(inputs.small(inputs.BURGERS, 24), integrator="rk4")),
+    ("burgers_tsit5_multipass", dict(inputs.small(inputs.BURGERS, 10), integrator="tsit5", nq1d=100)),
+    ("sod_bs3_hll_fused", dict(inputs.small(inputs.SOD, 40), integrator="bs3", flux="hll")),
+    ("sod_tsit5_lasso", dict(inputs.small(inputs.SOD, 30), integrator="tsit5", filter="lasso", sensor="always")),
+    ("sv_bs3_hll_fused", dict(inputs.small(inputs.SHOCK_VORTEX, 12, 8), integrator="bs3", flux="hll")),
+    ("sv_rk4_generic", dict(inputs.small(inputs.SHOCK_VORTEX, 7, 5), integrator="rk4")),
+    ("advection_tsit5", dict(inputs.small(inputs.ADVECTION, 16), integrator="tsit5")),
+]
+
+
+@pytest.mark.parametrize("label,cfg", CASES)
+def test_integrator_steps_match_oracle(label, cfg):
+    announce("integrator_steps", label)
+    prob, (T, R) = oracle_for(cfg)
+    u0 = project_initial(prob, cfg["ic"], (T, R))
+    sol = solver_for(cfg)
+    ud = to_dev(u0)
+    ref = u0.copy()
+    for i in range(3):
+        ref, rdt, rflags = ostep.step(prob, ref, None, (T, R))
+        dtd, flags = sol.step(ud)
+        sol.sync()
+        g = to_np(flags).reshape(4, prob.E)
+        assert abs(to_np(dtd)[0] - rdt) <= 1e-13 * rdt
+        assert np.array_equal(g[2], rflags[2]) and np.array_equal(g[3], rflags[3])
+        assert np.array_equal(g[0], rflags[0]) and not g[1].any()
+        err = rel_l2(to_np(ud), ref)
+        print("[rk] %s step %d rel-L2 %.2e" % (label, i, err), flush=True)
+        assert err < RTOL_FP64
+
+
+def test_integrator_chained_steps():
+    import torch
+    cfg = dict(inputs.small(inputs.SOD, 24), integrator="bs3", flux="hll")
+    announce("integrator_chained")
+    prob, (T, R) = oracle_for(cfg)
+    u0 = project_initial(prob, cfg["ic"], (T, R))
+    ref = u0.copy()
+    rdts = []
+    for _ in range(6):
+        ref, rdt, _ = ostep.step(prob, ref, None, (T, R))
+        rdts.append(rdt)
+    sol = solver_for(cfg)
+    ud = to_dev(u0)
+    dts = torch.empty(6, dtype=torch.float64, device=ud.device)
+    sol.steps(ud, 6, dts)
+    sol.sync()
+    assert np.allclose(to_np(dts), rdts, rtol=1e-13, atol=0)
+    assert rel_l2(to_np(ud), ref) < RTOL_FP64
+
+
+def test_integrator_full_size_shock_vortex_step():
+    """The paper's setting for the 2D problem (Table 6): HLL flux, Bogacki-Shampine."""
+    cfg = dict(inputs.SHOCK_VORTEX, integrator="bs3", flux="hll")
+    announce("integrator_full_size")
+    prob, (T, R) = oracle_for(cfg)
+    u0 = project_initial(prob, cfg["ic"], (T, R))
+    ref, rdt, _ = ostep.step(prob, u0, None, (T, R))
+    sol = solver_for(cfg)
+    ud = to_dev(u0)
+    dtd, _ = sol.step(ud)
+    sol.sync()
+    assert abs(to_np(dtd)[0] - rdt) <= 1e-13 * rdt
+    assert rel_l2(to_np(ud), ref) < RTOL_FP64
+
+
+def test_integrator_has_no_adjoint():
+    from paper_2112_05946_amd.binding import FrsgError
+    cfg = dict(inputs.small(inputs.BURGERS, 8), integrator="rk4")
+    sol = solver_for(cfg)
+    u = sol.initial_state()
+    flags = sol.step(u.clone(), 1e-4)[1]
+    with pytest.raises(FrsgError) as ei:
+        sol.adjoint_step(u, flags, 1e-4, u.clone())
+    assert ei.value.status == -2
