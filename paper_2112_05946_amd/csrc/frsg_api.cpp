@@ -523,6 +523,10 @@ fr_sg_status fr_sg_limit(fr_sg_ctx* ctx, double* u, uint8_t* flags) {
     ctx->err = "null pointer";
     return FRSG_EINVAL;
   }
+  if (ctx->prob.limiter && ctx->fused)
+    return timed(ctx, "limiter", 2 * state_bytes(ctx), [&] {
+      return launch_fused_post(ctx->kp, ctx->dPhiT, ctx->dcmax, u, 0, 1, nullptr, flags, ctx->stream);
+    });
   if (ctx->prob.limiter)
     return timed(ctx, "limiter", 2 * state_bytes(ctx), [&] { return launch_limiter(ctx->kp, u, flags, ctx->stream); });
   if (flags) FRSG_TRY_HIP(launch_fill_flags(flags, ctx->E, ctx->stream), ctx);
@@ -787,12 +791,25 @@ static fr_sg_status step_rk(fr_sg_ctx* ctx, double* u, double dt, double* dt_use
     return st;
   uint8_t* f2 = flags ? flags + 2 * E : nullptr;
   uint8_t* f3 = flags ? flags + 3 * E : nullptr;
-  if (ctx->prob.filter != FRSG_FILTER_NONE) {
-    if ((st = timed(ctx, "sensor_filter", 2 * sb, [&] { return launch_sensor_filter(K, u, f2, s); }))) return st;
-  } else if (f2) {
-    FRSG_TRY_HIP(launch_fill_flags(f2, E, s), ctx);
+  const bool filt = ctx->prob.filter != FRSG_FILTER_NONE;
+  if (ctx->fused) {
+    // filter and limiter in one element-wise pass
+    if (!filt && f2) FRSG_TRY_HIP(launch_fill_flags(f2, E, s), ctx);
+    if (!ctx->prob.limiter && f3) FRSG_TRY_HIP(launch_fill_flags(f3, E, s), ctx);
+    if (filt || ctx->prob.limiter)
+      if ((st = timed(ctx, "filter_limiter", 2 * sb, [&] {
+             return launch_fused_post(K, ctx->dPhiT, ctx->dcmax, u, filt ? 1 : 0, ctx->prob.limiter ? 1 : 0,
+                                      filt ? f2 : nullptr, ctx->prob.limiter ? f3 : nullptr, s);
+           })))
+        return st;
+  } else {
+    if (filt) {
+      if ((st = timed(ctx, "sensor_filter", 2 * sb, [&] { return launch_sensor_filter(K, u, f2, s); }))) return st;
+    } else if (f2) {
+      FRSG_TRY_HIP(launch_fill_flags(f2, E, s), ctx);
+    }
+    if ((st = fr_sg_limit(ctx, u, f3)) != FRSG_OK) return st;
   }
-  if ((st = fr_sg_limit(ctx, u, f3)) != FRSG_OK) return st;
   ctx->lam_for = nullptr;
   if (dt_used) FRSG_TRY_HIP(launch_copy_dt(K, dt_used, s), ctx);
   return FRSG_OK;

@@ -179,6 +179,9 @@ bool fused2d_supported(const KParams& P);
 size_t fused2d_trace_count(int nx, int ny, int M);
 hipError_t launch_fused_stage(const KParams& P, const FusedStage& S, hipStream_t s);
 hipError_t launch_fused_cfl(const KParams& P, const double* u, unsigned long long* lam, hipStream_t s);
+// sensor-gated filter and/or limiter in place, with the fused kernel's tile layout
+hipError_t launch_fused_post(const KParams& P, const double* PhiTd, const double* cmax, double* u, int do_filter,
+                             int do_limit, unsigned char* flag_filt, unsigned char* flag_lim, hipStream_t s);
 hipError_t launch_dt_from(const KParams& P, const unsigned long long* lam, unsigned long long* lam_reset,
                           double* dt_used, hipStream_t s);
 hipError_t launch_set_dt(const KParams& P, double dt, double* dt_used, unsigned long long* lam_reset, hipStream_t s);

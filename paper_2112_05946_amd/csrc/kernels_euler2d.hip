@@ -1057,6 +1057,64 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ PhiTd,
 }
 
 // ---------------------------------------------------------------------------
+// Element-wise passes on a state with the stage kernel's lane layout: the
+// sensor-gated filter (Sec. 4.1, 4.2) and/or the positivity limiter (Sec. 4.3),
+// in that order, in place.  Used where they are not fused into a stage (the
+// tableau integrators, fr_sg_limit).
+// ---------------------------------------------------------------------------
+template <int M, int NQ>
+__global__ void __launch_bounds__(BLKS) __attribute__((amdgpu_waves_per_eu(2)))
+k_post2d(KParams P, const double* __restrict__ PhiTd, const double* __restrict__ cmax, double* u, int do_filter,
+         int do_limit, unsigned char* flag_filt, unsigned char* flag_lim) {
+  __shared__ double sLam[M * NSP];
+  const int tid = threadIdx.x;
+  const int le = tid >> 5, h = (tid >> 4) & 1, j = tid & 15;
+  const int a = j & 3, b = j >> 2;
+  const int lx = le % TX, ly = le / TX;
+  const int ntx = P.nx / TX;
+  const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
+  const int e = (TY * ty + ly) * P.nx + TX * tx + lx;
+  const long EN = (long)P.E * NSP;
+  if (do_filter) {
+    const double dt = *P.dt;
+    for (int i = tid; i < M * NSP; i += BLKS) {
+      const double f = P.tab.filt[i];
+      sLam[i] = (P.filter == FRSG_FILTER_EXP) ? exp(-P.alpha * dt * f) : f;
+    }
+    __syncthreads();
+  }
+  const unsigned sbytes = (unsigned)(4 * M * EN * (long)sizeof(double));
+  const unsigned voff = (unsigned)(((long)(2 * h) * M * EN + (long)e * NSP + j) * (long)sizeof(double));
+  auto soff = [&](int i, int k) { return (unsigned)(((long)i * M + k) * EN * (long)sizeof(double)); };
+  const auto ru = state_rsrc(u, sbytes);
+  double o[2][M];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int k = 0; k < M; ++k) o[i][k] = bload(ru, voff, soff(i, k));
+  if (do_filter) {
+    const int ff = sensor_filter_pair<M>(P, o, h, a, b, j, sLam);
+    if (tid % 32 == 0 && flag_filt) flag_filt[e] = (unsigned char)ff;
+  }
+  if (do_limit) {
+    LaneOps L;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      L.rlx[k] = P.tab.lL[(a + k) & 3];
+      L.rrx[k] = P.tab.lR[(a + k) & 3];
+      L.rly[k] = P.tab.lL[(b - k) & 3];
+      L.rry[k] = P.tab.lR[(b - k) & 3];
+    }
+    const int lf = limit_pair<M, NQ>(P, PhiTd, o, h, a, b, L, cmax);
+    if (tid % 32 == 0 && flag_lim) flag_lim[e] = (unsigned char)lf;
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int k = 0; k < M; ++k) bstore(o[i][k], ru, voff, soff(i, k));
+}
+
+// ---------------------------------------------------------------------------
 // CFL maximum of a state (used when no previous step recorded it)
 // ---------------------------------------------------------------------------
 template <int M, int NQ>
@@ -1176,6 +1234,24 @@ bool fused2d_supported(const KParams& P) {
 
 hipError_t launch_fused_stage(const KParams& P, const FusedStage& S, hipStream_t s) {
 #define X(MM, QQ) if (P.M == MM && P.Nq == QQ) return launch_stage_t<MM, QQ>(P, S, s);
+  FRSG_FUSED_SIZES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+template <int M, int NQ>
+static hipError_t launch_post_t(const KParams& P, const double* PhiTd, const double* cmax, double* u, int do_filter,
+                                int do_limit, unsigned char* flag_filt, unsigned char* flag_lim, hipStream_t s) {
+  const int ntiles = (P.nx / TX) * (P.ny / TY);
+  hipLaunchKernelGGL((k_post2d<M, NQ>), dim3(ntiles), dim3(BLKS), 0, s, P, PhiTd, cmax, u, do_filter, do_limit,
+                     flag_filt, flag_lim);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_post(const KParams& P, const double* PhiTd, const double* cmax, double* u, int do_filter,
+                             int do_limit, unsigned char* flag_filt, unsigned char* flag_lim, hipStream_t s) {
+#define X(MM, QQ) \
+  if (P.M == MM && P.Nq == QQ) return launch_post_t<MM, QQ>(P, PhiTd, cmax, u, do_filter, do_limit, flag_filt, flag_lim, s);
   FRSG_FUSED_SIZES(X)
 #undef X
   return hipErrorInvalidValue;

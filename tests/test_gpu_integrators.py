@@ -89,3 +89,24 @@ def test_integrator_has_no_adjoint():
     with pytest.raises(FrsgError) as ei:
         sol.adjoint_step(u, flags, 1e-4, u.clone())
     assert ei.value.status == -2
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_fused_limit_pass_matches_oracle(seed):
+    """fr_sg_limit on the fused 2D path (element-wise pass with the stage kernel's
+    lane layout), near-vacuum elements so that the limiter acts."""
+    import torch
+    from oracle import stabilize as ost
+    cfg = inputs.small(inputs.SHOCK_VORTEX, 12, 8)
+    announce("fused_limit_pass", seed)
+    prob, (T, R) = oracle_for(cfg)
+    u = inputs.fuzz_euler(2, R.M, prob.E, prob.nsp, seed, vacuum_frac=0.25)
+    ref, rflags = ost.limit(prob, T, R, u)
+    assert rflags.sum() > 0
+    sol = solver_for(cfg)
+    ud = to_dev(u)
+    flags = torch.zeros(prob.E, dtype=torch.uint8, device=ud.device)
+    sol.limit(ud, flags)
+    sol.sync()
+    assert np.array_equal(to_np(flags).astype(bool), rflags)
+    assert rel_l2(to_np(ud), ref) < RTOL_FP64
