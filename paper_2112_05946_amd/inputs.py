@@ -14,6 +14,10 @@ Workloads are shaped like the paper's experiments (Sec. 5):
                           u0 = 1 + 0.5 sin(pi x) + 0.2 z sin(pi x) on periodic [0, 2];
 * ``sod_interface``       1D Euler Sod tube with uncertain interface
                           x0 = 0.5 + 0.05 z (Sec. 5.3, second case);
+* ``wave_propagation``    the convergence study of Sec. 5.1 (Tables 1-3):
+                          u_t + u_x = 0 on periodic [-1, 1] with
+                          u0 = xi(z) sin(pi x), xi = 1 + 0.1 z ~ U(0.9, 1.1);
+                          exact solution xi(z) sin(pi (x - t));
 * ``shock_vortex``        2D Euler stationary Mach 1.1 normal shock at x = 0.5
                           and an isentropic vortex of strength 0.3 + 0.05 z1
                           centred at (0.25 + 0.02 z2, 0.5) (Sec. 5.4 setup with
@@ -88,6 +92,8 @@ def initial_condition(name, x, y, z, gamma=GAMMA):
     z1 = z[..., 0]
     if name == "advection_sine":
         return np.sin(2.0 * np.pi * (x + 0.1 * z1))[None]
+    if name == "wave_propagation":
+        return ((1.0 + 0.1 * z1) * np.sin(np.pi * x))[None]
     if name == "burgers_sine":
         return (1.0 + 0.5 * np.sin(np.pi * x) + 0.2 * z1 * np.sin(np.pi * x))[None]
     if name == "sod_interface":
@@ -164,7 +170,31 @@ SHOCK_VORTEX_HLL = dict(SHOCK_VORTEX, name="shock_vortex_hll", flux="hll")
 SOD_HLL_BS3 = dict(SOD, name="sod_hll_bs3", flux="hll", integrator="bs3")
 SHOCK_VORTEX_HLL_BS3 = dict(SHOCK_VORTEX, name="shock_vortex_hll_bs3", flux="hll", integrator="bs3")
 
-CONFIGS = {c["name"]: c for c in (ADVECTION, BURGERS, SOD, SHOCK_VORTEX, BURGERS_ADJOINT, BURGERS_LASSO, SOD_LASSO,
+# the convergence study of Sec. 5.1: Table 1's setup (N_c = 5, N_q = 9,
+# Lax-Friedrichs, RK4, periodic, no filter) on 4..64 elements, measured at
+# t = 2.  Its CFL number 0.1 is read as dt = 0.1 dx / |a|; with the CFL rule
+# dt = cfl dx / ((p + 1) lambda_max) used here that is cfl = 0.1 (p + 1).
+WAVE_DX = (0.5, 0.25, 0.125, 0.0625, 0.03125)
+WAVE_T = 2.0
+
+
+def wave_propagation(n_points, nx):
+    """Table 1 setup with N_p = n_points solution points on nx elements."""
+    return dict(
+        name="wave_propagation", equation="advection", ic="wave_propagation",
+        nx=nx, xlo=-1.0, xhi=1.0, p=n_points - 1, gpc_order=5, nq1d=9, rdim=1,
+        bc=["periodic"] * 4, adv_speed=1.0, flux="rusanov", integrator="rk4",
+        filter="none", limiter=False, cfl=0.1 * n_points, t_end=WAVE_T)
+
+
+def wave_exact(x, t, z):
+    """Exact solution of the wave-propagation problem at points x, time t, random z."""
+    return (1.0 + 0.1 * z) * np.sin(np.pi * (x - t))
+
+
+WAVE = wave_propagation(3, 64)
+
+CONFIGS = {c["name"]: c for c in (ADVECTION, WAVE, BURGERS, SOD, SHOCK_VORTEX, BURGERS_ADJOINT, BURGERS_LASSO, SOD_LASSO,
                                   SOD_HLL, SHOCK_VORTEX_HLL, SOD_HLL_BS3, SHOCK_VORTEX_HLL_BS3)}
 
 
