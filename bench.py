@@ -184,6 +184,22 @@ def other_workloads(torch, Solver, inputs, steps):
     return out
 
 
+def convergence_study():
+    """The wave-propagation study of Sec. 5.1 on the library (RK4, dt = 0.1 dx, t = 2): errors of
+    the expectation and orders per norm for N_p = 3 and 4 on 4..64 elements, the largest
+    deviation from the paper's Tables 2-3, and the step time on 64 elements."""
+    from paper_2112_05946_amd.convergence import NORMS, PAPER, wave_table
+    out = {"t": 2.0, "integrator": "rk4", "dt": "0.1 dx"}
+    for n in (3, 4):
+        tab = wave_table(n)
+        dev = max(abs(tab[nm][i] / PAPER[n][nm][i] - 1.0) for nm in NORMS for i in range(len(tab["dx"])))
+        out["np%d" % n] = {"dx": tab["dx"], "l1": tab["l1"], "l1_order": tab["l1_order"],
+                           "l2_order": tab["l2_order"], "linf_order": tab["linf_order"],
+                           "max_rel_dev_from_paper": dev, "ms_per_step_64el": tab["ms_per_step"][-1],
+                           "dof_64el": tab["dof"][-1]}
+    return out
+
+
 def adjoint_cost(torch, Solver, inputs):
     """Adjoint/forward cost on the 4096-element Burgers problem (p = 3, 9 modes, 16 nodes):
     500 steps at the CFL step of the initial state, held fixed."""
@@ -250,6 +266,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-mixed comparison run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost run")
     ap.add_argument("--no-others", action="store_true", help="skip the 1D workloads")
+    ap.add_argument("--no-convergence", action="store_true", help="skip the wave-propagation convergence study")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the multi-GPU halo exchange is not built); "
@@ -304,6 +321,7 @@ def main():
 
     adjoint = None if args.no_adjoint else adjoint_cost(torch, Solver, inputs)
     others = None if args.no_others else other_workloads(torch, Solver, inputs, 200)
+    convergence = None if args.no_convergence else convergence_study()
 
     out = {
         "metric": METRIC, "value": value, "unit": "DOF-updates/s", "n_gpus": 1, "steps": args.steps,
@@ -319,6 +337,7 @@ def main():
         "fp32_mixed": other,
         "adjoint": adjoint,
         "other_workloads": others,
+        "wave_propagation_convergence": convergence,
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:

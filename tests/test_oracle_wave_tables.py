@@ -17,42 +17,22 @@ scheme does not have (it is the same at any smaller step), presumably the
 error of the paper's own time integration; they are pinned more loosely.
 """
 
-import json
 import math
-import os
 
 import numpy as np
 import pytest
 
-from oracle.initial import project_initial, solution_point_coords
+from oracle.initial import project_initial
 from oracle.problem import Problem
-from oracle.stepper import cfl_dt, step
+from oracle.stepper import cfl_dt
 from oracle.tables import build_tables
 from paper_2112_05946_amd import inputs
-
-GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "wave_propagation_tables.json")
-TABLES = {3: "table2_np3", 4: "table3_np4"}
-NORMS = ("l1", "l2", "linf")
-
-
-def _gold():
-    with open(GOLDEN) as f:
-        return json.load(f)
+from wave_ref import NORMS, TABLES, gold as _gold, oracle_wave
 
 
 def oracle_wave_errors(n_points, nx):
-    """Run the Table 1 setup to t = 2 with the oracle; return (l1, l2, linf), final state."""
-    prob = Problem.from_config(inputs.wave_propagation(n_points, nx))
-    T, R = build_tables(prob)
-    u = project_initial(prob, "wave_propagation", (T, R))
-    dt = cfl_dt(prob, T, R, u)
-    n = max(1, int(round(inputs.WAVE_T / dt)))
-    dt = inputs.WAVE_T / n
-    for _ in range(n):
-        u, _, flags = step(prob, u, dt, (T, R))
-    x, _ = solution_point_coords(prob, T)
-    e = u[0, 0] - np.sin(np.pi * (x - inputs.WAVE_T))
-    return (prob.dx * np.abs(e).sum(), prob.dx * math.sqrt(np.sum(e * e)), prob.dx * np.abs(e).max()), u
+    errs, u, _ = oracle_wave(n_points, nx)
+    return errs, u
 
 
 def test_fixture_orders_follow_its_errors():
