@@ -174,6 +174,9 @@ def face_pairs(prob, Tminus, Tplus, axis, sides):
 # ----------------------------------------------------------------------------
 
 def rhs(prob, T, R, u):
+    if prob.element == "tri":
+        from .tri import rhs_tri
+        return rhs_tri(prob, T, R, u)
     if prob.dim == 1:
         return _rhs_1d(prob, T, R, u)
     return _rhs_2d(prob, T, R, u)

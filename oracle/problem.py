@@ -43,6 +43,11 @@ class Problem:
     limiter: bool = False
     cfl: float = 0.3
     t_end: float = 0.0
+    # "quad": the nx x ny Cartesian mesh; "tri": the triangle mesh `mesh`
+    # (dict of xy [E, 3, 2], nbr [E, 3], nbr_face [E, 3], as made by the shared
+    # input module), 2D Euler only
+    element: str = "quad"
+    mesh: dict = None
 
     @property
     def dim(self):
@@ -54,10 +59,14 @@ class Problem:
 
     @property
     def E(self):
+        if self.element == "tri":
+            return len(self.mesh["xy"])
         return self.nx * (self.ny if self.dim == 2 else 1)
 
     @property
     def nsp(self):
+        if self.element == "tri":
+            return (self.p + 1) * (self.p + 2) // 2
         return (self.p + 1) ** self.dim
 
     @property

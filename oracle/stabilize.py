@@ -163,6 +163,8 @@ def sensor_filter(prob, T, R, u, dt):
     """Sensor-gated filter; returns (u_filtered, flags)."""
     if prob.filter == "none":
         return u.copy(), np.zeros(u.shape[2], dtype=bool)
+    if prob.element == "tri":
+        raise NotImplementedError("sensor and filter on triangles")
     flags = sensor_flags(prob, T, R, u)
     ut = to_spatial_modal(prob, T, u)
     if prob.filter == "lasso":
@@ -254,6 +256,8 @@ def limit(prob, T, R, u):
     flags = np.zeros(E, dtype=bool)
     if not prob.limiter:
         return u.copy(), flags
+    if prob.element == "tri":
+        raise NotImplementedError("positivity limiter on triangles")
     dim = prob.dim
     out = u.copy()
     ubar = element_mean(prob, T, u)  # [s, e]

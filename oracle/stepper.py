@@ -111,6 +111,9 @@ def explicit_rk(u, dt, R, tableau, L=lambda w: (w, None), F=lambda w: (w, None),
 
 
 def cfl_dt(prob, T, R, u):
+    if prob.element == "tri":
+        from .tri import cfl_dt_tri
+        return cfl_dt_tri(prob, T, R, u)
     U = nodal_at_solution_points(R, u)
     n = prob.p + 1
     if prob.dim == 1:

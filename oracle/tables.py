@@ -217,6 +217,9 @@ def build_random_tables(order, rdim, nq1d):
 
 
 def build_tables(problem):
+    if problem.element == "tri":
+        from .tri import build_tri_tables
+        return build_tri_tables(problem.p), build_random_tables(problem.gpc_order, problem.rdim, problem.nq1d)
     return build_fr_tables(problem.p), build_random_tables(problem.gpc_order, problem.rdim, problem.nq1d)
 
 

@@ -207,6 +207,78 @@ def small(cfg, nx, ny=None, **kw):
 
 
 # ----------------------------------------------------------------------------
+# triangle meshes (Sec. 3.1: straight-sided triangles, each the image of the
+# isosceles right reference triangle)
+# ----------------------------------------------------------------------------
+
+def tri_mesh_rectangle(nx, ny, xlo=0.0, xhi=1.0, ylo=0.0, yhi=1.0, periodic=(True, True), perturb=0.0, seed=0):
+    """Triangulation of [xlo, xhi] x [ylo, yhi]: nx x ny cells, each cut along its
+    lower-right to upper-left diagonal into two counter-clockwise triangles.
+
+    Cell (i, j) with corners A (lower left), B (lower right), C (upper right),
+    D (upper left) gives element 2 (j nx + i) = (A, B, D) and element
+    2 (j nx + i) + 1 = (C, D, B).  Face f of an element joins its vertices f and
+    (f + 1) mod 3.  With perturb > 0 every vertex not on a non-periodic
+    boundary moves by a seeded uniform offset of at most perturb times the cell
+    size in each coordinate (the same offset for all periodic copies of a vertex).
+
+    Returns dict(xy [E, 3, 2] vertex coordinates, nbr [E, 3] neighbour element
+    across each face or -1 - side for a boundary face (side 0 x-lo, 1 x-hi,
+    2 y-lo, 3 y-hi), nbr_face [E, 3] the neighbour's face index or -1).
+    """
+    dx, dy = (xhi - xlo) / nx, (yhi - ylo) / ny
+    rng = np.random.default_rng(seed)
+    off = rng.uniform(-perturb, perturb, (ny + 1, nx + 1, 2)) * np.array([dx, dy])
+    px, py = periodic
+    if px:
+        off[:, nx] = off[:, 0]
+    else:
+        off[:, 0] = 0.0
+        off[:, nx] = 0.0
+    if py:
+        off[ny, :] = off[0, :]
+    else:
+        off[0, :] = 0.0
+        off[ny, :] = 0.0
+
+    def vert(i, j):
+        return np.array([xlo + i * dx, ylo + j * dy]) + off[j, i]
+
+    E = 2 * nx * ny
+    xy = np.zeros((E, 3, 2))
+    nbr = np.zeros((E, 3), dtype=np.int32)
+    nbf = np.zeros((E, 3), dtype=np.int32)
+    cell = lambda i, j: 2 * (j * nx + i)
+    for j in range(ny):
+        for i in range(nx):
+            e0, e1 = cell(i, j), cell(i, j) + 1
+            A, B, C, D = vert(i, j), vert(i + 1, j), vert(i + 1, j + 1), vert(i, j + 1)
+            xy[e0] = (A, B, D)
+            xy[e1] = (C, D, B)
+            # e0: face 0 A-B (bottom), face 1 B-D (diagonal), face 2 D-A (left)
+            if j > 0 or py:
+                nbr[e0, 0], nbf[e0, 0] = cell(i, (j - 1) % ny) + 1, 0
+            else:
+                nbr[e0, 0], nbf[e0, 0] = -1 - 2, -1
+            nbr[e0, 1], nbf[e0, 1] = e1, 1
+            if i > 0 or px:
+                nbr[e0, 2], nbf[e0, 2] = cell((i - 1) % nx, j) + 1, 2
+            else:
+                nbr[e0, 2], nbf[e0, 2] = -1 - 0, -1
+            # e1: face 0 C-D (top), face 1 D-B (diagonal), face 2 B-C (right)
+            if j < ny - 1 or py:
+                nbr[e1, 0], nbf[e1, 0] = cell(i, (j + 1) % ny), 0
+            else:
+                nbr[e1, 0], nbf[e1, 0] = -1 - 3, -1
+            nbr[e1, 1], nbf[e1, 1] = e0, 1
+            if i < nx - 1 or px:
+                nbr[e1, 2], nbf[e1, 2] = cell((i + 1) % nx, j), 2
+            else:
+                nbr[e1, 2], nbf[e1, 2] = -1 - 1, -1
+    return dict(xy=xy, nbr=nbr, nbr_face=nbf)
+
+
+# ----------------------------------------------------------------------------
 # seeded random modal states (fuzz inputs)
 # ----------------------------------------------------------------------------
 
