@@ -17,9 +17,12 @@
  *   M    gPC modes (N_c + 1 in 1D random space; (N_c+1)(N_c+2)/2 for the
  *        total-degree set in 2D random space, graded order
  *        (0,0),(1,0),(0,1),(2,0),(1,1),(0,2),...),
- *   E    elements, row-major e = iy * nx + ix,
+ *   E    elements, row-major e = iy * nx + ix (or the triangles in the
+ *        caller's order, element = FRSG_ELEM_TRI),
  *   N_sp solution points per element, (p+1)^dim, j = a + (p+1) * b with a
- *        the x index; points are Legendre-Gauss in each direction.
+ *        the x index; points are Legendre-Gauss in each direction.  On
+ *        triangles N_sp = (p+1)(p+2)/2 warp-and-blend points (see
+ *        FRSG_ELEM_TRI).
  * i.e. the gPC coefficients (Sec. 2.1, Eq. polynomial chaos) held at the FR
  * solution points (Sec. 3.2) of each element.
  *
@@ -44,7 +47,7 @@
 extern "C" {
 #endif
 
-#define FRSG_ABI_VERSION 3
+#define FRSG_ABI_VERSION 4
 
 typedef int32_t fr_sg_status;
 #define FRSG_OK 0
@@ -115,6 +118,35 @@ typedef int32_t fr_sg_status;
 #define FRSG_FP64 0
 #define FRSG_FP32_MIXED 1
 
+/* element shape (Sec. 3.1).  FRSG_ELEM_QUAD: the nx x ny Cartesian mesh of
+ * [xlo, xhi] x [ylo, yhi] (or nx line elements in 1D).  FRSG_ELEM_TRI: an
+ * unstructured mesh of n_tri straight-sided triangles, each the image of the
+ * isosceles right reference triangle (-1,-1), (1,-1), (-1,1) under
+ * x = lam1 x1 + lam2 x2 + lam3 x3 (Sec. 3.1), 2D Euler only.  Its FR form is
+ * that of Sec. 3.5: solution points are the warp-and-blend nodes (equispaced
+ * lattice warped so that the edge nodes are Legendre-Gauss-Lobatto points;
+ * rows of constant s bottom to top, r increasing in a row), p+1
+ * Legendre-Gauss flux points per face, and the vector correction fields are
+ * the ones that make FR equal to nodal DG (normal component 1 at their own
+ * flux point and 0 at the others, zero moments against vector polynomials of
+ * degree p-1), whose divergence is the DG lifting.  FR degree 1..4.  Mesh
+ * arrays (host memory, read during fr_sg_init only, copied):
+ *   tri_xy[n_tri][3][2]   vertex coordinates, counter-clockwise;
+ *   tri_nbr[n_tri][3]     across face f (vertex f to vertex f+1 mod 3): the
+ *                         neighbouring triangle, or -1 - side for a boundary
+ *                         face whose ghost state follows bc[side] (side 0..3;
+ *                         that bc must not be FRSG_BC_PERIODIC: periodicity is
+ *                         expressed by the neighbour links themselves);
+ *   tri_nbr_face[n_tri][3] the neighbour's face index (ignored on boundary
+ *                         faces); links must be mutual.
+ * Reflection mirrors the velocity about the face.  CFL step:
+ * dt = cfl / ((p+1) max(lambda / d_e)) with lambda = |v| + c over the nodes
+ * and points of element e and d_e its inscribed-circle diameter.  Not yet
+ * available on triangles: filters, the limiter, FP32-mixed, the adjoint
+ * (fr_sg_init returns FRSG_EUNSUPPORTED). */
+#define FRSG_ELEM_QUAD 0
+#define FRSG_ELEM_TRI 1
+
 typedef struct fr_sg_problem {
   int32_t abi_version;     /* FRSG_ABI_VERSION                                        */
   int32_t equation;        /* FRSG_ADVECTION .. FRSG_EULER2D                          */
@@ -138,6 +170,11 @@ typedef struct fr_sg_problem {
   int32_t precision;       /* FRSG_FP64 or FRSG_FP32_MIXED                            */
   int32_t flux;            /* FRSG_FLUX_RUSANOV (Lax-Friedrichs) or FRSG_FLUX_HLL     */
   int32_t integrator;      /* FRSG_SSPRK3, FRSG_RK4, FRSG_RK_BS3, FRSG_RK_TSIT5       */
+  int32_t element;         /* FRSG_ELEM_QUAD or FRSG_ELEM_TRI                         */
+  int32_t n_tri;           /* triangles (FRSG_ELEM_TRI; nx, ny, domain ignored)       */
+  const double* tri_xy;    /* host, [n_tri][3][2]                                     */
+  const int32_t* tri_nbr;  /* host, [n_tri][3]                                        */
+  const int32_t* tri_nbr_face; /* host, [n_tri][3]                                    */
 } fr_sg_problem;
 
 typedef struct fr_sg_info {

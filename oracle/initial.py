@@ -17,6 +17,9 @@ from .tables import build_tables
 
 def solution_point_coords(prob, T):
     """Physical coordinates of every solution point: x[e, j], y[e, j]."""
+    if prob.element == "tri":
+        from .tri import solution_point_coords_tri
+        return solution_point_coords_tri(prob, T)
     xc = prob.xlo + (np.arange(prob.nx) + 0.5) * prob.dx
     if prob.dim == 1:
         x = xc[:, None] + 0.5 * prob.dx * T.r[None, :]

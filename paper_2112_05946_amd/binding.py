@@ -16,7 +16,7 @@ from . import inputs
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfrsg.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 STATUS = {0: "OK", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "EDEVICE", -4: "ENONFINITE", -5: "ENOTREALIZABLE",
           -6: "EABI"}
 EQUATION = {"advection": 0, "burgers": 1, "euler1d": 2, "euler2d": 3}
@@ -26,6 +26,7 @@ FLUX = {"rusanov": 0, "hll": 1}
 INTEGRATOR = {"ssprk3": 0, "rk4": 1, "bs3": 2, "tsit5": 3}
 SENSOR = {"always": 0, "detector": 1}
 PRECISION = {"fp64": 0, "fp32": 1}
+ELEMENT = {"quad": 0, "tri": 1}
 
 
 class FrsgError(RuntimeError):
@@ -47,6 +48,8 @@ class Problem(ctypes.Structure):
         ("sensor", ctypes.c_int32), ("s0", ctypes.c_double), ("kappa", ctypes.c_double),
         ("limiter", ctypes.c_int32), ("cfl", ctypes.c_double), ("precision", ctypes.c_int32),
         ("flux", ctypes.c_int32), ("integrator", ctypes.c_int32),
+        ("element", ctypes.c_int32), ("n_tri", ctypes.c_int32),
+        ("tri_xy", ctypes.c_void_p), ("tri_nbr", ctypes.c_void_p), ("tri_nbr_face", ctypes.c_void_p),
     ]
 
 
@@ -137,6 +140,20 @@ def problem_from_config(cfg, precision="fp64"):
     P.limiter = 1 if cfg.get("limiter", False) else 0
     P.cfl = float(cfg.get("cfl", 0.3))
     P.precision = PRECISION[precision]
+    P.element = ELEMENT[cfg.get("element", "quad")]
+    if P.element == ELEMENT["tri"]:
+        # host arrays read by fr_sg_init only; the struct keeps them alive until then
+        mesh = cfg["mesh"]
+        xy = np.ascontiguousarray(mesh["xy"], dtype=np.float64)
+        nb = np.ascontiguousarray(mesh["nbr"], dtype=np.int32)
+        nf = np.ascontiguousarray(mesh["nbr_face"], dtype=np.int32)
+        if xy.shape != (len(xy), 3, 2) or nb.shape != (len(xy), 3) or nf.shape != (len(xy), 3):
+            raise ValueError("triangle mesh arrays must be xy [E, 3, 2], nbr [E, 3], nbr_face [E, 3]")
+        P.n_tri = len(xy)
+        P.tri_xy = xy.ctypes.data
+        P.tri_nbr = nb.ctypes.data
+        P.tri_nbr_face = nf.ctypes.data
+        P._mesh_arrays = (xy, nb, nf)
     return P
 
 

@@ -71,13 +71,37 @@ fr_sg_status validate(const fr_sg_problem& P, std::string& err) {
     err = "fr_degree must be in 1..7";
     return P.fr_degree < 1 ? FRSG_EINVAL : FRSG_EUNSUPPORTED;
   }
-  if (P.nx < 1 || (dim == 2 && P.ny < 1)) {
-    err = "element counts must be positive";
+  if (P.element != FRSG_ELEM_QUAD && P.element != FRSG_ELEM_TRI) {
+    err = "unknown element shape";
     return FRSG_EINVAL;
   }
-  if (!(P.xhi > P.xlo) || (dim == 2 && !(P.yhi > P.ylo))) {
-    err = "empty domain";
-    return FRSG_EINVAL;
+  const bool tri = P.element == FRSG_ELEM_TRI;
+  if (tri) {
+    if (P.equation != FRSG_EULER2D) {
+      err = "triangles carry the 2D Euler equations";
+      return FRSG_EUNSUPPORTED;
+    }
+    if (P.n_tri < 1 || !P.tri_xy || !P.tri_nbr || !P.tri_nbr_face) {
+      err = "a triangle mesh needs n_tri >= 1 and its vertex and neighbour arrays";
+      return FRSG_EINVAL;
+    }
+    if (P.fr_degree > kTriMaxDeg) {
+      err = "fr_degree must be in 1..4 on triangles";
+      return FRSG_EUNSUPPORTED;
+    }
+    if (P.filter != FRSG_FILTER_NONE || P.limiter || P.precision != FRSG_FP64) {
+      err = "filters, the limiter and FP32-mixed are not available on triangles";
+      return FRSG_EUNSUPPORTED;
+    }
+  } else {
+    if (P.nx < 1 || (dim == 2 && P.ny < 1)) {
+      err = "element counts must be positive";
+      return FRSG_EINVAL;
+    }
+    if (!(P.xhi > P.xlo) || (dim == 2 && !(P.yhi > P.ylo))) {
+      err = "empty domain";
+      return FRSG_EINVAL;
+    }
   }
   if (P.rdim != 1 && P.rdim != 2) {
     err = "rdim must be 1 or 2";
@@ -93,8 +117,9 @@ fr_sg_status validate(const fr_sg_problem& P, std::string& err) {
     err = "too many gPC modes or random nodes";
     return FRSG_EUNSUPPORTED;
   }
-  const long E = (long)P.nx * (dim == 2 ? P.ny : 1);
-  const long nsp = dim == 2 ? (long)(P.fr_degree + 1) * (P.fr_degree + 1) : P.fr_degree + 1;
+  const long E = tri ? (long)P.n_tri : (long)P.nx * (dim == 2 ? P.ny : 1);
+  const long nsp = tri ? (long)(P.fr_degree + 1) * (P.fr_degree + 2) / 2
+                       : (dim == 2 ? (long)(P.fr_degree + 1) * (P.fr_degree + 1) : P.fr_degree + 1);
   if (E * nsp * Nq > (1l << 31) / 4) {
     err = "problem too large for 32-bit node indexing";
     return FRSG_EUNSUPPORTED;
@@ -110,7 +135,7 @@ fr_sg_status validate(const fr_sg_problem& P, std::string& err) {
       return FRSG_EUNSUPPORTED;
     }
   }
-  for (int d = 0; d < dim; ++d)
+  for (int d = 0; d < (tri ? 0 : dim); ++d)
     if ((P.bc[2 * d] == FRSG_BC_PERIODIC) != (P.bc[2 * d + 1] == FRSG_BC_PERIODIC)) {
       err = "periodic boundaries must be paired";
       return FRSG_EINVAL;
@@ -248,11 +273,21 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
     return FRSG_EINVAL;
   }
   const fr_sg_problem& P = c->prob;
+  c->is_tri = P.element == FRSG_ELEM_TRI;
+  if (c->is_tri && !build_tri_tables(P, c->tri, err)) {
+    g_init_error = err;
+    delete c;
+    return FRSG_EINVAL;
+  }
+  // the mesh arrays are the caller's and are read during this call only
+  c->prob.tri_xy = nullptr;
+  c->prob.tri_nbr = nullptr;
+  c->prob.tri_nbr_face = nullptr;
   c->dim = P.equation == FRSG_EULER2D ? 2 : 1;
   c->S = nstates(P.equation);
-  c->E = P.nx * (c->dim == 2 ? P.ny : 1);
+  c->E = c->is_tri ? P.n_tri : P.nx * (c->dim == 2 ? P.ny : 1);
   const int n = P.fr_degree + 1;
-  c->nsp = c->dim == 2 ? n * n : n;
+  c->nsp = c->is_tri ? c->tri.np : (c->dim == 2 ? n * n : n);
   const HostTables& T = c->T;
 
   // one device buffer for all tables
@@ -322,7 +357,30 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
     probe.M = T.M;
     probe.Nq = T.Nq;
     probe.E = P.nx * probe.ny;
-    c->fused = fused2d_supported(probe);
+    c->fused = !c->is_tri && fused2d_supported(probe);
+  }
+  if (c->is_tri) {
+    // triangle operators and geometry: one double buffer and the neighbour table
+    const TriTables& R = c->tri;
+    std::vector<double> tb;
+    tb.insert(tb.end(), R.Dr.begin(), R.Dr.end());
+    tb.insert(tb.end(), R.Ds.begin(), R.Ds.end());
+    tb.insert(tb.end(), R.Lf.begin(), R.Lf.end());
+    tb.insert(tb.end(), R.lift.begin(), R.lift.end());
+    tb.insert(tb.end(), R.geo.begin(), R.geo.end());
+    he = hipMalloc(&c->dtri, tb.size() * sizeof(double));
+    if (he == hipSuccess) he = hipMemcpy(c->dtri, tb.data(), tb.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (he == hipSuccess) he = hipMalloc(&c->dtri_nbr, R.nbr.size() * sizeof(int));
+    if (he == hipSuccess)
+      he = hipMemcpy(c->dtri_nbr, R.nbr.data(), R.nbr.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (he != hipSuccess) {
+      g_init_error = std::string("HIP error: ") + hipGetErrorString(he);
+      if (c->dtri) (void)hipFree(c->dtri);
+      if (c->dtri_nbr) (void)hipFree(c->dtri_nbr);
+      (void)hipFree(c->dtab);
+      delete c;
+      return FRSG_EDEVICE;
+    }
   }
   if (P.precision == FRSG_FP32_MIXED && !c->fused) {
     g_init_error =
@@ -353,7 +411,8 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
   }
   const size_t state = (size_t)c->S * T.M * c->E * c->nsp;
   const size_t nodal = c->fused ? 0 : (size_t)c->S * T.Nq * c->E * c->nsp;
-  const size_t corr = c->fused ? 0 : (size_t)c->S * T.Nq * c->E * (c->dim == 2 ? 4 * n : 2);
+  const size_t corr = c->fused ? 0
+                      : (size_t)c->S * T.Nq * c->E * (c->is_tri ? 3 * c->tri.nfp : (c->dim == 2 ? 4 * n : 2));
   size_t o_w1 = 0;
   size_t o_w2 = align_up(o_w1 + state * 8);
   size_t o_un = align_up(o_w2 + state * 8);
@@ -393,6 +452,8 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
   he = hipMalloc(&ws, total);
   if (he != hipSuccess) {
     g_init_error = std::string("workspace allocation failed: ") + hipGetErrorString(he);
+    if (c->dtri) (void)hipFree(c->dtri);
+    if (c->dtri_nbr) (void)hipFree(c->dtri_nbr);
     (void)hipFree(c->dtab);
     if (c->dPhiT32) (void)hipFree(c->dPhiT32);
     delete c;
@@ -402,6 +463,8 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
   if (he != hipSuccess) {
     g_init_error = std::string("HIP error: ") + hipGetErrorString(he);
     (void)hipFree(ws);
+    if (c->dtri) (void)hipFree(c->dtri);
+    if (c->dtri_nbr) (void)hipFree(c->dtri_nbr);
     (void)hipFree(c->dtab);
     if (c->dPhiT32) (void)hipFree(c->dPhiT32);
     delete c;
@@ -427,21 +490,25 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
     c->ws.tr[1] = (double*)(ws + o_tr1);
   }
   c->ws.bytes = total + blob.size() * sizeof(double);
+  if (c->is_tri)
+    c->ws.bytes += (c->tri.Dr.size() + c->tri.Ds.size() + c->tri.Lf.size() + c->tri.lift.size() + c->tri.geo.size()) *
+                       sizeof(double) +
+                   c->tri.nbr.size() * sizeof(int);
 
   KParams& K = c->kp;
   std::memset(&K, 0, sizeof(K));
   K.eq = P.equation;
   K.dim = c->dim;
   K.E = c->E;
-  K.nx = P.nx;
-  K.ny = c->dim == 2 ? P.ny : 1;
+  K.nx = c->is_tri ? 1 : P.nx;
+  K.ny = (c->dim == 2 && !c->is_tri) ? P.ny : 1;
   K.nsp = c->nsp;
   K.M = T.M;
   K.Nq = T.Nq;
   K.S = c->S;
   K.np1 = n;
-  K.dx = (P.xhi - P.xlo) / P.nx;
-  K.dy = c->dim == 2 ? (P.yhi - P.ylo) / P.ny : 1.0;
+  K.dx = c->is_tri ? 1.0 : (P.xhi - P.xlo) / P.nx;
+  K.dy = (c->dim == 2 && !c->is_tri) ? (P.yhi - P.ylo) / P.ny : 1.0;
   K.Jx = K.dx / 2.0;
   K.Jy = K.dy / 2.0;
   K.adv = P.adv_speed;
@@ -459,6 +526,18 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
   K.alpha = P.alpha;
   K.sensor_thr = std::pow(10.0, P.s0 - (2.0 * P.kappa / M_PI) * std::asin(0.98));
   K.tab = tab;
+  if (c->is_tri) {
+    const TriTables& R = c->tri;
+    K.tri = 1;
+    K.nfp = R.nfp;
+    const double* b2 = c->dtri;
+    K.tri_Dr = b2;
+    K.tri_Ds = K.tri_Dr + R.Dr.size();
+    K.tri_Lf = K.tri_Ds + R.Ds.size();
+    K.tri_lift = K.tri_Lf + R.Lf.size();
+    K.tri_geo = K.tri_lift + R.lift.size();
+    K.tri_nbr = c->dtri_nbr;
+  }
   K.dt = c->ws.scal;
   K.lam_bits = (unsigned long long*)(c->ws.scal + 1);
   K.status = (unsigned*)(c->ws.scal + 2);  // scal[3] is the second CFL accumulator
@@ -492,6 +571,18 @@ fr_sg_status fr_sg_points(const fr_sg_ctx* ctx, double* x, double* y, double* z)
   const KParams& K = ctx->kp;
   const int n = K.np1;
   const fr_sg_problem& P = ctx->prob;
+  if (ctx->is_tri) {
+    // physical coordinates of the solution points, computed at init (Sec. 3.1 map)
+    const TriTables& R = ctx->tri;
+    for (int e = 0; e < K.E; ++e)
+      for (int j = 0; j < R.np; ++j) {
+        if (x) x[(long)e * R.np + j] = R.xy_pts[((long)e * R.np + j) * 2];
+        if (y) y[(long)e * R.np + j] = R.xy_pts[((long)e * R.np + j) * 2 + 1];
+      }
+    if (z)
+      for (size_t i = 0; i < ctx->T.z.size(); ++i) z[i] = ctx->T.z[i];
+    return FRSG_OK;
+  }
   for (int e = 0; e < K.E; ++e) {
     const int ix = e % K.nx, iy = e / K.nx;
     const double xc = P.xlo + (ix + 0.5) * K.dx;
@@ -538,6 +629,14 @@ static fr_sg_status rhs_passes(fr_sg_ctx* ctx, const double* in, int do_cfl) {
   Workspace& W = ctx->ws;
   hipStream_t s = ctx->stream;
   fr_sg_status st;
+  if (ctx->is_tri) {
+    if ((st = timed(ctx, "nodal", state_bytes(ctx), [&] { return launch_nodal(K, in, W.Un, W.Fn, W.Gn, 0, s); })))
+      return st;
+    if (do_cfl && (st = timed(ctx, "cfl", 0.0, [&] { return launch_cfl_tri(K, W.Un, s); }))) return st;
+    if ((st = timed(ctx, "faces", 0.0, [&] { return launch_faces_tri(K, W.Un, W.Fn, W.Gn, W.Corr, s); })))
+      return st;
+    return timed(ctx, "resid", 0.0, [&] { return launch_resid_tri(K, W.Fn, W.Gn, W.Corr, W.Un, s); });
+  }
   if ((st = timed(ctx, "nodal", state_bytes(ctx), [&] { return launch_nodal(K, in, W.Un, W.Fn, W.Gn, do_cfl, s); })))
     return st;
   if ((st = timed(ctx, "faces", 0.0, [&] { return launch_faces(K, W.Un, W.Fn, W.Gn, W.Corr, s); }))) return st;
@@ -749,7 +848,9 @@ static fr_sg_status step_rk(fr_sg_ctx* ctx, double* u, double dt, double* dt_use
     FRSG_TRY_HIP(launch_dt_from(K, lam, nullptr, nullptr, s), ctx);
   } else {
     FRSG_TRY_HIP(launch_set_scalars(K, 0.0, s), ctx);
-    if ((st = timed(ctx, "nodal", sb, [&] { return launch_nodal(K, u, W.Un, W.Fn, W.Gn, 1, s); }))) return st;
+    if ((st = timed(ctx, "nodal", sb, [&] { return launch_nodal(K, u, W.Un, W.Fn, W.Gn, ctx->is_tri ? 0 : 1, s); })))
+      return st;
+    if (ctx->is_tri && (st = timed(ctx, "cfl", 0.0, [&] { return launch_cfl_tri(K, W.Un, s); }))) return st;
     FRSG_TRY_HIP(launch_dt(K, ctx->dim, nullptr, s), ctx);
   }
   uint8_t* f0 = flags ? flags : nullptr;
@@ -1015,6 +1116,8 @@ fr_sg_status fr_sg_destroy(fr_sg_ctx* ctx) {
   if (ctx->ws.w1) (void)hipFree(ctx->ws.w1);
   if (ctx->dtab) (void)hipFree(ctx->dtab);
   if (ctx->dPhiT32) (void)hipFree(ctx->dPhiT32);
+  if (ctx->dtri) (void)hipFree(ctx->dtri);
+  if (ctx->dtri_nbr) (void)hipFree(ctx->dtri_nbr);
   delete ctx;
   return FRSG_OK;
 }

@@ -45,6 +45,33 @@ struct HostTables {
 };
 
 bool build_host_tables(const fr_sg_problem& P, HostTables& T, std::string& err);
+// n-point Gauss-Legendre rule (weights sum 2); Gauss-Jordan inverse of an n x n matrix
+void gauss_rule(int n, std::vector<double>& x, std::vector<double>& w);
+bool invert_matrix(int n, const std::vector<double>& A, std::vector<double>& Ainv);
+
+// ---------------------------------------------------------------------------
+// triangles (element = FRSG_ELEM_TRI): reference operators and per-element geometry
+// ---------------------------------------------------------------------------
+constexpr int kTriMaxDeg = 4;                                   // p <= 4
+constexpr int kTriMaxNp = (kTriMaxDeg + 1) * (kTriMaxDeg + 2) / 2;  // 15 solution points
+constexpr int kTriGeo = 16;                                     // doubles of geometry per triangle
+// geometry record of a triangle: dr/dx, dr/dy, ds/dx, ds/dy, det (= area / 2),
+// unit outward normals (nx, ny) of faces 0..2, the factors (face length /
+// reference face length / det) of faces 0..2, inscribed-circle diameter
+enum : int { kGeoRx = 0, kGeoRy, kGeoSx, kGeoSy, kGeoDet, kGeoN0 = 5, kGeoSc0 = 11, kGeoDin = 14 };
+struct TriTables {
+  int p = 0, np = 0, nfp = 0;
+  std::vector<double> r, s;        // solution points on the reference triangle
+  std::vector<double> Dr, Ds;      // [np][np]: d l_i/dr, d l_i/ds at point j (row j)
+  std::vector<double> Lf;          // [3 nfp][np]: l_i at the flux points, face-major
+  std::vector<double> lift;        // [np][3 nfp]: divergence of the correction fields
+  std::vector<double> mean_w;      // [np]: element mean = sum_j mean_w[j] u_j
+  std::vector<double> geo;         // [E][kTriGeo]
+  std::vector<int> nbr;            // [E][6]: neighbour element (or -1 - side), then neighbour face
+  std::vector<double> xy_pts;      // [E][np][2]: physical solution-point coordinates
+};
+// reference tables for degree p, mesh checks and geometry from the problem's arrays
+bool build_tri_tables(const fr_sg_problem& P, TriTables& T, std::string& err);
 
 // ---------------------------------------------------------------------------
 // device-side view of the tables (one allocation, sub-arrays by offset)
@@ -80,6 +107,14 @@ struct KParams {
   int flux;  // FRSG_FLUX_*
   double alpha, sensor_thr;
   DevTab tab;
+  // triangles (element = FRSG_ELEM_TRI; tri = 0 on quadrilateral meshes)
+  int tri, nfp;
+  const double* tri_Dr;    // [N_p][N_p]
+  const double* tri_Ds;
+  const double* tri_Lf;    // [3 nfp][N_p]
+  const double* tri_lift;  // [N_p][3 nfp]
+  const double* tri_geo;   // [E][kTriGeo]
+  const int* tri_nbr;      // [E][6]
   unsigned* status;
   unsigned long long* lam_bits;  // CFL accumulator (bit pattern of a positive double)
   double* dt;                    // device time step of the current step
@@ -131,6 +166,10 @@ struct fr_sg_ctx {
   int events_used = 0;
   std::vector<PassRecord> pending;
   frsg::HostTables T;
+  frsg::TriTables tri;           // triangle operators and geometry (element = FRSG_ELEM_TRI)
+  bool is_tri = false;
+  double* dtri = nullptr;        // device copies of the triangle tables and geometry
+  int* dtri_nbr = nullptr;
   hipStream_t stream = nullptr;
   int dim = 1;
   int S = 1;
@@ -201,6 +240,13 @@ hipError_t launch_project_ic(const KParams& P, const double* U0, double* u, hipS
 hipError_t launch_limiter(const KParams& P, double* u, unsigned char* flags, hipStream_t s);
 hipError_t launch_sensor_filter(const KParams& P, double* u, unsigned char* flags, hipStream_t s);
 hipError_t launch_fill_flags(unsigned char* flags, long n, hipStream_t s);
+// triangle passes (kernels_tri.hip): interactive-flux jumps [S][Nq][E][3 nfp],
+// nodal residual into Rn, CFL maximum of the nodal values into P.lam_bits
+hipError_t launch_faces_tri(const KParams& P, const double* Un, const double* Fn, const double* Gn, double* Jump,
+                            hipStream_t s);
+hipError_t launch_resid_tri(const KParams& P, const double* Fn, const double* Gn, const double* Jump, double* Rn,
+                            hipStream_t s);
+hipError_t launch_cfl_tri(const KParams& P, const double* Un, hipStream_t s);
 // explicit Runge-Kutta stage combination: out = u + dt sum_j a[j] K[j] (flat state of n doubles)
 struct RkTerms {
   const double* K[kRkMaxTerms];

@@ -122,6 +122,9 @@ bool invert(int n, const std::vector<double>& A, std::vector<double>& Ainv) {
 
 }  // namespace
 
+void gauss_rule(int n, std::vector<double>& x, std::vector<double>& w) { gauss_legendre(n, x, w); }
+bool invert_matrix(int n, const std::vector<double>& A, std::vector<double>& Ainv) { return invert(n, A, Ainv); }
+
 bool build_host_tables(const fr_sg_problem& P, HostTables& T, std::string& err) {
   const int p = P.fr_degree;
   const int n = p + 1;

@@ -87,6 +87,26 @@ def shock_vortex_ic(x, y, z1, z2, gamma=GAMMA):
     return _cons2d(rho, u0 + du, dv, p, gamma)
 
 
+def vortex_ic(x, y, z1, z2, gamma=GAMMA):
+    """The isentropic vortex of Sec. 5.4 (strength 0.3 + 0.05 z1, mu = 0.204,
+    r_c = 0.05) centred at (0.5 + 0.02 z2, 0.5) in the uniform Mach 1.1 upstream
+    state of the shock-vortex problem, without the shock (periodic [0, 1]^2)."""
+    up, _ = shock_states(gamma=gamma)
+    zeta = 0.3 + 0.05 * z1
+    dx, dy = x - (0.5 + 0.02 * z2), y - 0.5
+    r = np.sqrt(dx * dx + dy * dy)
+    eta = r / SV_RC
+    amp = zeta * eta * np.exp(SV_MU * (1.0 - eta * eta))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        st = np.where(r > 0, dy / np.where(r > 0, r, 1.0), 0.0)
+        ct = np.where(r > 0, dx / np.where(r > 0, r, 1.0), 0.0)
+    dT = -(gamma - 1.0) * zeta * zeta / (4.0 * SV_MU * gamma) * np.exp(2.0 * SV_MU * (1.0 - eta * eta))
+    T0 = up[3] / up[0]
+    T = T0 + dT
+    rho = up[0] * (T / T0) ** (1.0 / (gamma - 1.0))
+    return _cons2d(rho, up[1] + amp * st, -amp * ct, rho * T, gamma)
+
+
 def initial_condition(name, x, y, z, gamma=GAMMA):
     """Conservative initial data at points x, y (same shape) and random z[..., rdim]."""
     z1 = z[..., 0]
@@ -101,6 +121,13 @@ def initial_condition(name, x, y, z, gamma=GAMMA):
         rho = np.where(left, 1.0, 0.125)
         p = np.where(left, 1.0, 0.1)
         return _cons1d(rho, np.zeros_like(rho), p, gamma)
+    if name == "tri_density_wave":
+        # rho = 1 + 0.2 sin(2 pi (x + y)), velocity (1 + 0.1 z1, 0.5), p = 1
+        rho = 1.0 + 0.2 * np.sin(2.0 * np.pi * (x + y))
+        return _cons2d(rho, 1.0 + 0.1 * z1, 0.5 + 0.0 * x, 1.0 + 0.0 * x, gamma)
+    if name == "tri_vortex":
+        z2 = z[..., 1] if z.shape[-1] > 1 else np.zeros_like(z1)
+        return vortex_ic(x, y, z1, z2, gamma)
     if name == "shock_vortex":
         # one random dimension: only the vortex strength is uncertain
         z2 = z[..., 1] if z.shape[-1] > 1 else np.zeros_like(z1)
@@ -193,6 +220,28 @@ def wave_exact(x, t, z):
 
 
 WAVE = wave_propagation(3, 64)
+
+
+def tri_vortex(n, p=3, perturb=0.1, seed=1):
+    """The vortex of Sec. 5.4 without the shock, advected through the periodic unit
+    square on 2 n^2 perturbed triangles: FR degree p, two random dimensions with
+    total-degree-4 chaos (15 modes) on 5 x 5 nodes, Lax-Friedrichs, SSP-RK3, CFL 0.3."""
+    return dict(
+        name="tri_vortex", equation="euler2d", ic="tri_vortex", element="tri",
+        mesh=tri_mesh_rectangle(n, n, perturb=perturb, seed=seed), nx=1, ny=1,
+        p=p, gpc_order=4, nq1d=5, rdim=2, bc=["outflow"] * 4, gamma=GAMMA,
+        filter="none", limiter=False, cfl=0.3, t_end=0.1)
+
+
+def tri_density_wave(n, p=2, perturb=0.15, seed=7, gpc_order=3, nq1d=4):
+    """Density wave rho = 1 + 0.2 sin(2 pi (x + y)) carried by the velocity
+    (1 + 0.1 z, 0.5) at unit pressure, periodic unit square, 2 n^2 perturbed
+    triangles; exact solution rho(x - (1 + 0.1 z) t, y - t/2)."""
+    return dict(
+        name="tri_density_wave", equation="euler2d", ic="tri_density_wave", element="tri",
+        mesh=tri_mesh_rectangle(n, n, perturb=perturb, seed=seed), nx=1, ny=1,
+        p=p, gpc_order=gpc_order, nq1d=nq1d, rdim=1, bc=["outflow"] * 4, gamma=GAMMA,
+        filter="none", limiter=False, cfl=0.1, t_end=0.05)
 
 CONFIGS = {c["name"]: c for c in (ADVECTION, WAVE, BURGERS, SOD, SHOCK_VORTEX, BURGERS_ADJOINT, BURGERS_LASSO, SOD_LASSO,
                                   SOD_HLL, SHOCK_VORTEX_HLL, SOD_HLL_BS3, SHOCK_VORTEX_HLL_BS3)}

@@ -109,3 +109,50 @@ def test_unknown_integrator_rejected(lib):
     P.integrator = 9
     st, ctx, msg = _init(lib, P)
     assert st == -1 and "integrator" in msg
+
+
+def _tri_problem(**over):
+    from paper_2112_05946_amd import binding, inputs
+    cfg = dict(inputs.tri_density_wave(3), **over)
+    return binding.problem_from_config(cfg), cfg
+
+
+@pytest.mark.parametrize("over,status", [
+    (dict(equation="burgers"), -2),
+    (dict(filter="exp"), -2),
+    (dict(limiter=True), -2),
+    (dict(p=5), -2),
+])
+def test_tri_unsupported_combinations(lib, over, status):
+    P, _ = _tri_problem(**over)
+    st, ctx, msg = _init(lib, P)
+    assert st == status, msg
+    assert not ctx.value and msg
+
+
+def test_tri_invalid_meshes_rejected_before_launch(lib):
+    from paper_2112_05946_amd import binding, inputs
+    base = inputs.tri_density_wave(3)
+
+    def try_mesh(mesh, bc=None):
+        cfg = dict(base, mesh=mesh)
+        if bc:
+            cfg["bc"] = bc
+        P = binding.problem_from_config(cfg)
+        return _init(lib, P)
+
+    m = {k: v.copy() for k, v in base["mesh"].items()}
+    m["xy"][4] = m["xy"][4][::-1]                       # clockwise
+    st, ctx, msg = try_mesh(m)
+    assert st == -1 and "clockwise" in msg and not ctx.value
+    m = {k: v.copy() for k, v in base["mesh"].items()}
+    m["nbr_face"][0, 1] = 2                              # link not mutual
+    st, ctx, msg = try_mesh(m)
+    assert st == -1 and "mutual" in msg
+    m = inputs.tri_mesh_rectangle(3, 3, periodic=(False, True))
+    st, ctx, msg = try_mesh(m, bc=["periodic"] * 4)      # boundary faces on periodic sides
+    assert st == -1 and "periodic" in msg
+    P, _ = _tri_problem()
+    P.n_tri = 0
+    st, ctx, msg = _init(lib, P)
+    assert st == -1

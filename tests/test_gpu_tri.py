@@ -1,0 +1,158 @@
+"""Triangle path (element = FRSG_ELEM_TRI, 2D Euler) on the GPU against the
+oracle: right-hand side and steps on periodic and bounded perturbed meshes,
+every FR degree 1..4, both interactive fluxes, one and two random dimensions;
+the full-size vortex workload on sampled elements and by free-stream and
+conservation properties."""
+
+import numpy as np
+import pytest
+
+from gpu_util import RTOL_FP64, announce, rel_l2, solver_for, to_dev, to_np
+from oracle import stepper as ostep
+from oracle import tri as otri
+from oracle.initial import project_initial
+from oracle.problem import Problem
+from oracle.tables import build_tables
+from paper_2112_05946_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _cfg(n, p, flux="rusanov", rdim=1, bounded=False, integrator="ssprk3", perturb=0.2, seed=3, m=None):
+    periodic = (False, False) if bounded else (True, True)
+    mesh = inputs.tri_mesh_rectangle(n, m or n, periodic=periodic, perturb=perturb, seed=seed)
+    bc = ["dirichlet", "outflow", "reflect", "reflect"] if bounded else ["outflow"] * 4
+    st = inputs._cons2d(*[np.array(v) for v in (1.0, 1.302, 0.0, 1.0)])
+    return dict(name="tri_test", equation="euler2d", ic="tri_vortex", element="tri", mesh=mesh, nx=1, ny=1,
+                p=p, gpc_order=2 if rdim == 1 else 2, nq1d=3, rdim=rdim, bc=bc,
+                bc_state=[[float(v) for v in st]] + [[0.0] * 4] * 3, gamma=inputs.GAMMA, flux=flux,
+                integrator=integrator, filter="none", limiter=False, cfl=0.3)
+
+
+RHS_CASES = [
+    ("p1_lf", _cfg(4, 1)),
+    ("p2_hll", _cfg(5, 2, flux="hll", m=3)),
+    ("p3_lf_rdim2", _cfg(4, 3, rdim=2)),
+    ("p4_lf", _cfg(3, 4)),
+    ("p3_bounded_hll", _cfg(5, 3, flux="hll", bounded=True, m=4)),
+    ("p2_bounded_lf_rdim2", _cfg(4, 2, bounded=True, rdim=2)),
+]
+
+
+@pytest.mark.parametrize("label,cfg", RHS_CASES)
+def test_tri_rhs_fuzz(label, cfg):
+    announce("tri_rhs", label)
+    prob = Problem.from_config(cfg)
+    T, R = build_tables(prob)
+    u = inputs.fuzz_euler(2, R.M, prob.E, T.n, seed=17)
+    ref = otri.rhs_tri(prob, T, R, u)
+    sol = solver_for(cfg)
+    got = to_np(sol.rhs(to_dev(u)))
+    sol.sync()
+    assert got.shape == ref.shape
+    assert rel_l2(got, ref) < RTOL_FP64, rel_l2(got, ref)
+
+
+@pytest.mark.parametrize("label,cfg", RHS_CASES[:3])
+def test_tri_points_and_initial_state(label, cfg):
+    announce("tri_points", label)
+    prob = Problem.from_config(cfg)
+    T, R = build_tables(prob)
+    sol = solver_for(cfg)
+    x, y, _ = sol.points()
+    X, Y = otri.solution_point_coords_tri(prob, T)
+    assert np.max(np.abs(x - X)) < 1e-14 and np.max(np.abs(y - Y)) < 1e-14
+    u0 = to_np(sol.initial_state())
+    ref = project_initial(prob, cfg["ic"], (T, R))
+    assert rel_l2(u0, ref) < RTOL_FP64
+
+
+@pytest.mark.parametrize("label,cfg", [
+    ("p2_ssprk3", _cfg(4, 2)),
+    ("p3_hll_bounded", _cfg(4, 3, flux="hll", bounded=True)),
+    ("p3_rk4", _cfg(4, 3, integrator="rk4")),
+    ("p1_bs3_rdim2", _cfg(5, 1, rdim=2, integrator="bs3")),
+])
+def test_tri_steps_match_oracle(label, cfg):
+    announce("tri_steps", label)
+    prob = Problem.from_config(cfg)
+    T, R = build_tables(prob)
+    u = project_initial(prob, cfg["ic"], (T, R))
+    sol = solver_for(cfg)
+    ud = to_dev(u)
+    for i in range(3):
+        u, rdt, _ = ostep.step(prob, u, None, (T, R))
+        dtd, flags = sol.step(ud)
+        sol.sync()
+        assert abs(to_np(dtd)[0] / rdt - 1.0) < 1e-13, (i, to_np(dtd)[0], rdt)
+        assert not to_np(flags).any()
+        assert rel_l2(to_np(ud), u) < RTOL_FP64, (i, rel_l2(to_np(ud), u))
+    # fr_sg_steps over the same path
+    ud2 = to_dev(project_initial(prob, cfg["ic"], (T, R)))
+    sol.steps(ud2, 3)
+    sol.sync()
+    assert rel_l2(to_np(ud2), u) < RTOL_FP64
+
+
+def _local_problem(cfg, e):
+    """Element e with its three neighbours (their outer faces open): the oracle's
+    right-hand side of e on this four-element mesh is e's on the whole mesh."""
+    mesh = cfg["mesh"]
+    nb, nf = mesh["nbr"][e], mesh["nbr_face"][e]
+    ids = [e] + [int(n) for n in nb]
+    xy = mesh["xy"][ids]
+    nbr = np.full((4, 3), -1 - 1, dtype=np.int32)   # outflow ghosts on the neighbours' other faces
+    nbf = np.full((4, 3), -1, dtype=np.int32)
+    for f in range(3):
+        nbr[0, f], nbf[0, f] = 1 + f, nf[f]
+        nbr[1 + f, nf[f]], nbf[1 + f, nf[f]] = 0, f
+    local = dict(cfg, mesh=dict(xy=xy, nbr=nbr, nbr_face=nbf), bc=["outflow"] * 4)
+    return Problem.from_config(local), ids
+
+
+def test_tri_vortex_full_size_sampled_and_properties():
+    cfg = inputs.tri_vortex(128)
+    announce("tri_vortex_full", cfg["mesh"]["xy"].shape[0])
+    sol = solver_for(cfg)
+    u = sol.initial_state()
+    r = to_np(sol.rhs(u))
+    sol.sync()
+    uh = to_np(u)
+    prob = Problem.from_config(cfg)
+    T, R = build_tables(prob)
+    # sampled elements: the oracle's right-hand side of each on its local patch
+    # (half of them inside the vortex, where the right-hand side is not rounding noise).
+    # Bar: relative L2 over the sampled elements together, 1e-11: the right-hand side
+    # of this near-uniform Mach 1.1 flow on elements of width 1/128 is what is left
+    # when flux divergence and corrections of size ~1e3 cancel to values of 0.05..8,
+    # so two evaluation orders differ by ~1e-16 of those terms, ~1e-12 of the result.
+    # The fuzz-state cases above hold the 1e-12 bar.
+    rng = np.random.default_rng(0)
+    X, Y = otri.solution_point_coords_tri(prob, T)
+    near = np.nonzero(np.hypot(X.mean(1) - 0.5, Y.mean(1) - 0.5) < 0.15)[0]
+    picks = np.concatenate([rng.choice(near, 24, replace=False), rng.choice(prob.E, 24, replace=False)])
+    got, want = [], []
+    for e in picks:
+        lp, ids = _local_problem(cfg, int(e))
+        want.append(otri.rhs_tri(lp, T, R, uh[:, :, ids])[:, :, 0])
+        got.append(r[:, :, e])
+    err = rel_l2(np.array(got), np.array(want))
+    print("[tri_vortex] sampled rel L2", err, flush=True)
+    assert err < 1e-11, err
+    # conservation over the periodic mesh
+    G = otri.geometry(cfg["mesh"]["xy"])
+    tot = np.einsum("skej,j,e->sk", r, T.mean_w, 2 * G.det)
+    scale = np.einsum("skej,j,e->sk", np.abs(r), np.abs(T.mean_w), 2 * G.det)
+    assert np.max(np.abs(tot)) < 1e-12 * np.max(scale), (np.max(np.abs(tot)), np.max(scale))
+    # free stream: a uniform state with random variation has a zero right-hand side
+    st = inputs._cons2d(*[np.array(v) for v in (1.0, 1.302, 0.0, 1.0)])
+    uf = np.zeros_like(uh)
+    uf[:, 0] = np.asarray(st)[:, None, None]
+    uf[1, 1] = 0.01
+    rf = to_np(sol.rhs(to_dev(uf)))
+    sol.sync()
+    assert np.max(np.abs(rf)) < 1e-10
+    # one CFL step stays finite and realizable
+    dtd, _ = sol.step(u)
+    sol.sync()
+    assert np.isfinite(to_np(u)).all() and to_np(dtd)[0] > 0
