@@ -156,12 +156,13 @@ def alu_roofline(roof, flop_per_dof, dof, precision):
 
 def other_workloads(torch, Solver, inputs, steps):
     """DOF-updates/s of the other workloads (FP64, CFL steps in one call): the cache-resident 1D
-    problems, with the Lasso filter, the HLL flux and the Bogacki-Shampine integrator, and the
-    shock-vortex problem with HLL, alone and with Bogacki-Shampine."""
+    problems, with the Lasso filter, the HLL flux and the Bogacki-Shampine integrator, the
+    shock-vortex problem with HLL, alone and with Bogacki-Shampine, and the vortex on 32768
+    perturbed triangles (p = 3, 15 modes, 25 nodes)."""
     out = {}
     for name in ("advection_sine", "burgers_sine", "sod_interface", "burgers_lasso", "sod_lasso", "sod_hll",
-                 "shock_vortex_hll", "sod_hll_bs3", "shock_vortex_hll_bs3"):
-        cfg = inputs.CONFIGS[name]
+                 "shock_vortex_hll", "sod_hll_bs3", "shock_vortex_hll_bs3", "tri_vortex"):
+        cfg = inputs.tri_vortex(128) if name == "tri_vortex" else inputs.CONFIGS[name]
         sol = Solver(cfg)
         u = sol.initial_state()
         dts = torch.empty(steps, dtype=torch.float64, device=u.device)
@@ -178,6 +179,7 @@ def other_workloads(torch, Solver, inputs, steps):
         dof = int(sol.info["n_dof"])
         out[name] = {"dof": dof, "ms_per_step": ms, "dof_updates_per_s": dof / (ms / 1e3),
                      "shape": "%s el, p=%d, %d modes, %d nodes, %d states" % (
+                         "%d triangles" % sol.E if cfg.get("element") == "tri" else
                          "%dx%d" % (cfg["nx"], cfg["ny"]) if cfg["equation"] == "euler2d" else str(cfg["nx"]),
                          cfg["p"], sol.shape[1], sol.info["n_nodes"], sol.shape[0])}
         sol.close()
