@@ -409,10 +409,21 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
     c->dPhiT32 = d32;
     c->dPWT32 = d32 + T.PhiT.size();
   }
+  if (c->is_tri) {
+    KParams probe;
+    std::memset(&probe, 0, sizeof(probe));
+    probe.eq = P.equation;
+    probe.nfp = c->tri.nfp;
+    probe.M = T.M;
+    probe.Nq = T.Nq;
+    c->fused_tri = tri_fused_supported(probe);
+  }
   const size_t state = (size_t)c->S * T.M * c->E * c->nsp;
-  const size_t nodal = c->fused ? 0 : (size_t)c->S * T.Nq * c->E * c->nsp;
-  const size_t corr = c->fused ? 0
+  const bool no_nodal = c->fused || c->fused_tri;
+  const size_t nodal = no_nodal ? 0 : (size_t)c->S * T.Nq * c->E * c->nsp;
+  const size_t corr = no_nodal ? 0
                       : (size_t)c->S * T.Nq * c->E * (c->is_tri ? 3 * c->tri.nfp : (c->dim == 2 ? 4 * n : 2));
+  const size_t ntm = c->fused_tri ? (size_t)c->S * T.M * c->E * 3 * c->tri.nfp : 0;
   size_t o_w1 = 0;
   size_t o_w2 = align_up(o_w1 + state * 8);
   size_t o_un = align_up(o_w2 + state * 8);
@@ -447,7 +458,8 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
   const Tableau* tab_rk = tableau_of(P.integrator);
   const int nrk = tab_rk ? tab_rk->s : 0;
   size_t o_rk = align_up(o_tr1 + ntr * 8);
-  size_t total = align_up(o_rk + (size_t)nrk * align_up(state * 8));
+  size_t o_tm = align_up(o_rk + (size_t)nrk * align_up(state * 8));
+  size_t total = align_up(o_tm + ntm * 8);
   char* ws = nullptr;
   he = hipMalloc(&ws, total);
   if (he != hipSuccess) {
@@ -485,6 +497,7 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
     c->ws.apart = (double*)(ws + o_apt);
   }
   for (int i = 0; i < nrk; ++i) c->ws.rk[i] = (double*)(ws + o_rk + (size_t)i * align_up(state * 8));
+  if (ntm) c->ws.Tm = (double*)(ws + o_tm);
   if (ntr) {
     c->ws.tr[0] = (double*)(ws + o_tr0);
     c->ws.tr[1] = (double*)(ws + o_tr1);
@@ -656,6 +669,10 @@ fr_sg_status fr_sg_rhs(fr_sg_ctx* ctx, const double* u, double* dudt) {
 
 // the right-hand side of u into dudt with the path's kernels (no CFL maximum)
 static fr_sg_status rhs_into(fr_sg_ctx* ctx, const double* u, double* dudt) {
+  if (ctx->fused_tri)
+    return timed(ctx, "stage_rhs", 2 * state_bytes(ctx), [&] {
+      return launch_stage_tri(ctx->kp, u, u, u, dudt, 0.0, 1.0, 1, ctx->ws.Tm, ctx->stream);
+    });
   if (ctx->fused) {
     FusedStage S{u,          u,          dudt,         0.0,         1.0,           0,
                  nullptr,    nullptr,    nullptr,      ctx->dDt,    ctx->dcmax,    ctx->dPhiT,
@@ -685,10 +702,29 @@ static fr_sg_status step_generic(fr_sg_ctx* ctx, double* u, double dt, double* d
   fr_sg_status st;
 
   FRSG_TRY_HIP(launch_set_scalars(K, cfl ? 0.0 : dt, s), ctx);
+  const double sb = state_bytes(ctx);
+  if (ctx->fused_tri) {
+    // triangles: one fused launch per stage (after its trace pass); no filter or limiter
+    if (cfl) {
+      if ((st = timed(ctx, "cfl", sb, [&] { return launch_cfl_tri_modal(K, u, s); }))) return st;
+      FRSG_TRY_HIP(launch_dt(K, ctx->dim, nullptr, s), ctx);
+    }
+    if ((st = timed(ctx, "stage1", 2 * sb,
+                    [&] { return launch_stage_tri(K, u, u, u, W.w1, 0.0, 1.0, 0, W.Tm, s); })))
+      return st;
+    if ((st = timed(ctx, "stage2", 3 * sb,
+                    [&] { return launch_stage_tri(K, W.w1, u, W.w1, W.w2, 0.75, 0.25, 0, W.Tm, s); })))
+      return st;
+    if ((st = timed(ctx, "stage3", 3 * sb,
+                    [&] { return launch_stage_tri(K, W.w2, u, W.w2, u, 1.0 / 3.0, 2.0 / 3.0, 0, W.Tm, s); })))
+      return st;
+    if (flags) FRSG_TRY_HIP(launch_fill_flags(flags, 4l * E, s), ctx);
+    if (dt_used) FRSG_TRY_HIP(launch_copy_dt(K, dt_used, s), ctx);
+    return FRSG_OK;
+  }
   // stage 1: w1 = Lim(u + dt R(u)); the CFL maximum is taken in the same pass over u
   if ((st = rhs_passes(ctx, u, cfl ? 1 : 0)) != FRSG_OK) return st;
   if (cfl) FRSG_TRY_HIP(launch_dt(K, ctx->dim, nullptr, s), ctx);
-  const double sb = state_bytes(ctx);
   if ((st = timed(ctx, "project_stage1", 2 * sb,
                   [&] { return launch_project_stage(K, W.Un, u, u, W.w1, 0.0, 1.0, 0, s); })))
     return st;
@@ -846,6 +882,10 @@ static fr_sg_status step_rk(fr_sg_ctx* ctx, double* u, double dt, double* dt_use
   } else if (ctx->fused1d) {
     if ((st = timed(ctx, "cfl", sb, [&] { return launch_cfl1d(K, u, lam, s); }))) return st;
     FRSG_TRY_HIP(launch_dt_from(K, lam, nullptr, nullptr, s), ctx);
+  } else if (ctx->fused_tri) {
+    FRSG_TRY_HIP(launch_set_scalars(K, 0.0, s), ctx);
+    if ((st = timed(ctx, "cfl", sb, [&] { return launch_cfl_tri_modal(K, u, s); }))) return st;
+    FRSG_TRY_HIP(launch_dt(K, ctx->dim, nullptr, s), ctx);
   } else {
     FRSG_TRY_HIP(launch_set_scalars(K, 0.0, s), ctx);
     if ((st = timed(ctx, "nodal", sb, [&] { return launch_nodal(K, u, W.Un, W.Fn, W.Gn, ctx->is_tri ? 0 : 1, s); })))

@@ -129,6 +129,7 @@ struct Workspace {
   double* Fn = nullptr;    // [S][Nq][E][nsp] nodal x-flux
   double* Gn = nullptr;    // [S][Nq][E][nsp] nodal y-flux (2D)
   double* Corr = nullptr;  // [S][Nq][E][nface] interface-flux minus interpolated flux
+  double* Tm = nullptr;    // fused triangles: modal traces [S][M][E][3 nfp] of the stage input
   double* scal = nullptr;  // scalars: dt, lam bits, status
   // adjoint (scalar 1D problems): stage adjoints, trace adjoints, partial sums
   double* avb = nullptr;   // adjoint of the unfiltered end-of-step state
@@ -168,6 +169,7 @@ struct fr_sg_ctx {
   frsg::HostTables T;
   frsg::TriTables tri;           // triangle operators and geometry (element = FRSG_ELEM_TRI)
   bool is_tri = false;
+  bool fused_tri = false;        // fused triangle stage kernel
   double* dtri = nullptr;        // device copies of the triangle tables and geometry
   int* dtri_nbr = nullptr;
   hipStream_t stream = nullptr;
@@ -247,6 +249,13 @@ hipError_t launch_faces_tri(const KParams& P, const double* Un, const double* Fn
 hipError_t launch_resid_tri(const KParams& P, const double* Fn, const double* Gn, const double* Jump, double* Rn,
                             hipStream_t s);
 hipError_t launch_cfl_tri(const KParams& P, const double* Un, hipStream_t s);
+// fused triangle stage (p = 1..4 and the (M, Nq) pairs of the fused 2D kernel): a trace pass
+// over `in` into Tm ([S][M][E][3 nfp]), then out = cu u + cw (w + dt R(in)), or R(in) with rhs_only
+bool tri_fused_supported(const KParams& P);
+hipError_t launch_stage_tri(const KParams& P, const double* in, const double* u, const double* w, double* out,
+                            double cu, double cw, int rhs_only, double* Tm, hipStream_t s);
+// CFL maximum of a modal state on triangles into P.lam_bits
+hipError_t launch_cfl_tri_modal(const KParams& P, const double* u, hipStream_t s);
 // explicit Runge-Kutta stage combination: out = u + dt sum_j a[j] K[j] (flat state of n doubles)
 struct RkTerms {
   const double* K[kRkMaxTerms];

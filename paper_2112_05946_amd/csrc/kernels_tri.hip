@@ -206,4 +206,273 @@ hipError_t launch_cfl_tri(const KParams& P, const double* Un, hipStream_t s) {
   return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// fused stage kernel: one launch per Runge-Kutta stage on triangles
+// ---------------------------------------------------------------------------
+// Each element gets 4 x SLOTS threads, thread (state s, slot): slot < N_p is
+// solution point j, slot < 3 nfp is flux point fk.  A thread keeps its own
+// chaos coefficients of state s at point j, the neighbour's modal trace at flux
+// point fk and the projection accumulators of (s, j) in registers; per random
+// node it expands both, and the element's nodal values, fluxes, traces and face
+// jumps pass through LDS.  The residual is projected on the fly and combined
+// with the stage inputs in the epilogue, so a stage reads the state once and
+// writes it once; the neighbours' modal traces come from a trace pass
+// (E x 3 nfp x S x M doubles) over the stage input.
+namespace {
+
+template <int PD>
+struct TriShape {
+  static constexpr int NPT = (PD + 1) * (PD + 2) / 2;
+  static constexpr int NFP = PD + 1;
+  static constexpr int NF = 3 * NFP;
+  static constexpr int SLOTS = NPT > NF ? NPT : NF;
+  static constexpr int TPE = 4 * SLOTS;           // threads per element
+  static constexpr int EPB = 256 / TPE;           // elements per block
+};
+
+// modal traces of every element at its flux points: Tm[s][k][e][fk] = sum_j Lf[fk][j] u[s][k][e][j]
+template <int PD>
+__global__ void __launch_bounds__(256) k_trace_tri(KParams P, const double* __restrict__ u, double* __restrict__ Tm) {
+  using Sh = TriShape<PD>;
+  const long n = 4l * P.M * P.E;
+  const long t = blockIdx.x * 256l + threadIdx.x;
+  if (t >= n) return;
+  double v[Sh::NPT];
+#pragma unroll
+  for (int j = 0; j < Sh::NPT; ++j) v[j] = u[t * Sh::NPT + j];
+#pragma unroll
+  for (int fk = 0; fk < Sh::NF; ++fk) {
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < Sh::NPT; ++j) acc += P.tri_Lf[fk * Sh::NPT + j] * v[j];
+    Tm[t * Sh::NF + fk] = acc;
+  }
+}
+
+template <int PD, int M, int NQ>
+__global__ void __launch_bounds__(256) k_stage_tri(KParams P, const double* __restrict__ in, const double* u,
+                                                   const double* w, double* out, double cu, double cw, int rhs_only,
+                                                   const double* __restrict__ Tm) {
+  using Sh = TriShape<PD>;
+  constexpr int NPT = Sh::NPT, NFP = Sh::NFP, NF = Sh::NF, SLOTS = Sh::SLOTS, EPB = Sh::EPB;
+  __shared__ double sU[EPB][4][NPT], sF[EPB][4][NPT], sG[EPB][4][NPT];
+  __shared__ double sUL[EPB][4][NF], sUR[EPB][4][NF], sJ[EPB][4][NF];
+  __shared__ double sDr[NPT * NPT], sDs[NPT * NPT], sLf[NF * NPT], sLift[NPT * NF];
+  for (int i = threadIdx.x; i < NPT * NPT; i += 256) {
+    sDr[i] = P.tri_Dr[i];
+    sDs[i] = P.tri_Ds[i];
+  }
+  for (int i = threadIdx.x; i < NF * NPT; i += 256) {
+    sLf[i] = P.tri_Lf[i];
+    sLift[i] = P.tri_lift[i];
+  }
+  const int E = P.E;
+  const int el = threadIdx.x / Sh::TPE;
+  const int rem = threadIdx.x % Sh::TPE;
+  const int s = rem / SLOTS, slot = rem % SLOTS;
+  const int e = blockIdx.x * EPB + el;
+  const bool active = el < EPB && e < E;
+  const int le = active ? el : 0;
+  const bool pt = active && slot < NPT;
+  const bool fp = active && slot < NF;
+  const long EN = (long)E * NPT;
+
+  // per-element geometry and the face this thread's flux point lies on
+  const double* geo = P.tri_geo + (long)(active ? e : 0) * kTriGeo;
+  const double rx = geo[kGeoRx], ry = geo[kGeoRy], sx = geo[kGeoSx], sy = geo[kGeoSy];
+  const int f = fp ? slot / NFP : 0, kk = fp ? slot % NFP : 0;
+  const double fnx = geo[kGeoN0 + 2 * f], fny = geo[kGeoN0 + 2 * f + 1], fsc = geo[kGeoSc0 + f];
+  const int nb = fp ? P.tri_nbr[(long)e * 6 + f] : -1;
+  const int g = fp ? P.tri_nbr[(long)e * 6 + 3 + f] : 0;
+
+  double uc[M], tn[M], acc[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    uc[k] = pt ? in[((long)s * M + k) * EN + (long)e * NPT + slot] : 0.0;
+    tn[k] = (fp && nb >= 0) ? Tm[(((long)s * M + k) * E + nb) * NF + g * NFP + (NFP - 1 - kk)] : 0.0;
+    acc[k] = 0.0;
+  }
+  __syncthreads();
+
+  for (int q = 0; q < NQ; ++q) {
+    // A: own nodal value at point j, neighbour trace at flux point fk
+    if (pt) {
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < M; ++k) v += P.tab.Phi[k * NQ + q] * uc[k];
+      sU[le][s][slot] = v;
+    }
+    if (fp && nb >= 0) {
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < M; ++k) v += P.tab.Phi[k * NQ + q] * tn[k];
+      sUR[le][s][slot] = v;
+    }
+    __syncthreads();
+    // B1: physical fluxes at the solution points, one state per thread
+    if (pt) {
+      const double r0 = sU[le][0][slot], m1 = sU[le][1][slot], m2 = sU[le][2][slot], en = sU[le][3][slot];
+      const double vx = m1 / r0, vy = m2 / r0;
+      const double p = (P.gamma - 1.0) * (en - 0.5 * (m1 * m1 + m2 * m2) / r0);
+      double Fs, Gs;
+      if (s == 0) {
+        Fs = m1;
+        Gs = m2;
+      } else if (s == 1) {
+        Fs = m1 * vx + p;
+        Gs = m1 * vy;
+      } else if (s == 2) {
+        Fs = m2 * vx;
+        Gs = m2 * vy + p;
+      } else {
+        Fs = (en + p) * vx;
+        Gs = (en + p) * vy;
+      }
+      sF[le][s][slot] = Fs;
+      sG[le][s][slot] = Gs;
+    }
+    __syncthreads();
+    // B2a: own trace and interpolated normal flux at flux point fk
+    double FDs = 0.0;
+    if (fp) {
+      double ul = 0.0, fx = 0.0, fy = 0.0;
+#pragma unroll
+      for (int j = 0; j < NPT; ++j) {
+        const double l = sLf[slot * NPT + j];
+        ul += l * sU[le][s][j];
+        fx += l * sF[le][s][j];
+        fy += l * sG[le][s][j];
+      }
+      sUL[le][s][slot] = ul;
+      FDs = fnx * fx + fny * fy;
+    }
+    __syncthreads();
+    // B2b: interactive flux along the normal (each thread its own state), jump
+    if (fp) {
+      double L[4], R[4], Fst[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) L[c] = sUL[le][c][slot];
+      if (nb >= 0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) R[c] = sUR[le][c][slot];
+      } else {
+        ghost_n(P, -1 - nb, L, fnx, fny, R);
+      }
+      flux_n(P.flux, L, R, fnx, fny, P.gamma, Fst);
+      sJ[le][s][slot] = (Fst[s] - FDs) * fsc;
+    }
+    __syncthreads();
+    // C: nodal residual of state s at point j, projected onto the chaos
+    if (pt) {
+      double dr = 0.0, ds = 0.0, c = 0.0;
+#pragma unroll
+      for (int i = 0; i < NPT; ++i) {
+        const double Fi = sF[le][s][i], Gi = sG[le][s][i];
+        dr += sDr[slot * NPT + i] * (rx * Fi + ry * Gi);
+        ds += sDs[slot * NPT + i] * (sx * Fi + sy * Gi);
+      }
+#pragma unroll
+      for (int m = 0; m < NF; ++m) c += sLift[slot * NF + m] * sJ[le][s][m];
+      const double R = -(dr + ds + c);
+#pragma unroll
+      for (int k = 0; k < M; ++k) acc[k] += P.tab.PW[k * NQ + q] * R;
+    }
+  }
+  if (!pt) return;
+  const double dt = rhs_only ? 0.0 : *P.dt;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const long idx = ((long)s * M + k) * EN + (long)e * NPT + slot;
+    out[idx] = rhs_only ? acc[k] : cu * u[idx] + cw * (w[idx] + dt * acc[k]);
+  }
+}
+
+// CFL maximum of a modal state: (|v| + c) / d_e over solution points and nodes
+__global__ void __launch_bounds__(256) k_cfl_tri_modal(KParams P, const double* __restrict__ u) {
+  __shared__ double sm[256];
+  const int np = P.nsp, E = P.E, M = P.M, Nq = P.Nq;
+  const long EN = (long)E * np;
+  const long t = blockIdx.x * 256l + threadIdx.x;
+  double rate = 0.0;
+  if (t < EN) {
+    const int e = (int)(t / np);
+    const double din = P.tri_geo[(long)e * kTriGeo + kGeoDin];
+    for (int q = 0; q < Nq; ++q) {
+      double U[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        double v = 0.0;
+        for (int k = 0; k < M; ++k) v += P.tab.Phi[k * Nq + q] * u[((long)s * M + k) * EN + t];
+        U[s] = v;
+      }
+      const double p = euler2_p(U, P.gamma);
+      double r = (sqrt(U[1] * U[1] + U[2] * U[2]) / U[0] + sqrt(P.gamma * p / U[0])) / din;
+      if (!(r == r)) r = __longlong_as_double(0x7ff0000000000000ll);
+      rate = fmax(rate, r);
+    }
+  }
+  sm[threadIdx.x] = rate;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(P.lam_bits, (unsigned long long)__double_as_longlong(sm[0]));
+}
+
+template <int PD, int M, int NQ>
+hipError_t go_stage_tri(const KParams& P, const double* in, const double* u, const double* w, double* out, double cu,
+                        double cw, int rhs_only, const double* Tm, hipStream_t s) {
+  using Sh = TriShape<PD>;
+  const long nt = 4l * M * P.E;
+  hipLaunchKernelGGL((k_trace_tri<PD>), dim3(blocks(nt)), dim3(256), 0, s, P, in, const_cast<double*>(Tm));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const unsigned grid = (unsigned)((P.E + Sh::EPB - 1) / Sh::EPB);
+  hipLaunchKernelGGL((k_stage_tri<PD, M, NQ>), dim3(grid), dim3(256), 0, s, P, in, u, w, out, cu, cw, rhs_only, Tm);
+  return hipGetLastError();
+}
+
+template <int PD>
+hipError_t dispatch_mq(const KParams& P, const double* in, const double* u, const double* w, double* out, double cu,
+                       double cw, int rhs_only, const double* Tm, hipStream_t s) {
+#define FRSG_TRI_MQ(MM, QQ) \
+  if (P.M == MM && P.Nq == QQ) return go_stage_tri<PD, MM, QQ>(P, in, u, w, out, cu, cw, rhs_only, Tm, s);
+  FRSG_TRI_MQ(15, 25) FRSG_TRI_MQ(10, 16) FRSG_TRI_MQ(6, 9) FRSG_TRI_MQ(5, 5) FRSG_TRI_MQ(3, 4)
+#undef FRSG_TRI_MQ
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+bool tri_fused_supported(const KParams& P) {
+  if (P.eq != FRSG_EULER2D || P.nfp < 2 || P.nfp > 5) return false;
+  const int mq[5][2] = {{15, 25}, {10, 16}, {6, 9}, {5, 5}, {3, 4}};
+  for (auto& x : mq)
+    if (P.M == x[0] && P.Nq == x[1]) return true;
+  return false;
+}
+
+// one stage: trace pass over `in` (into Tm), then out = cu u + cw (w + dt R(in)), or R(in)
+// with rhs_only
+hipError_t launch_stage_tri(const KParams& P, const double* in, const double* u, const double* w, double* out,
+                            double cu, double cw, int rhs_only, double* Tm, hipStream_t s) {
+  if (!tri_fused_supported(P)) return hipErrorInvalidValue;
+  switch (P.nfp - 1) {
+    case 1: return dispatch_mq<1>(P, in, u, w, out, cu, cw, rhs_only, Tm, s);
+    case 2: return dispatch_mq<2>(P, in, u, w, out, cu, cw, rhs_only, Tm, s);
+    case 3: return dispatch_mq<3>(P, in, u, w, out, cu, cw, rhs_only, Tm, s);
+    case 4: return dispatch_mq<4>(P, in, u, w, out, cu, cw, rhs_only, Tm, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_cfl_tri_modal(const KParams& P, const double* u, hipStream_t s) {
+  if (P.eq != FRSG_EULER2D) return hipErrorInvalidValue;
+  const long n = (long)P.E * P.nsp;
+  hipLaunchKernelGGL(k_cfl_tri_modal, dim3(blocks(n)), dim3(256), 0, s, P, u);
+  return hipGetLastError();
+}
+
 }  // namespace frsg

@@ -18,19 +18,26 @@ from paper_2112_05946_amd import inputs
 pytestmark = pytest.mark.gpu
 
 
-def _cfg(n, p, flux="rusanov", rdim=1, bounded=False, integrator="ssprk3", perturb=0.2, seed=3, m=None):
+def _cfg(n, p, flux="rusanov", rdim=1, bounded=False, integrator="ssprk3", perturb=0.2, seed=3, m=None, gpc=2, nq=3):
     periodic = (False, False) if bounded else (True, True)
     mesh = inputs.tri_mesh_rectangle(n, m or n, periodic=periodic, perturb=perturb, seed=seed)
     bc = ["dirichlet", "outflow", "reflect", "reflect"] if bounded else ["outflow"] * 4
     st = inputs._cons2d(*[np.array(v) for v in (1.0, 1.302, 0.0, 1.0)])
     return dict(name="tri_test", equation="euler2d", ic="tri_vortex", element="tri", mesh=mesh, nx=1, ny=1,
-                p=p, gpc_order=2 if rdim == 1 else 2, nq1d=3, rdim=rdim, bc=bc,
+                p=p, gpc_order=gpc, nq1d=nq, rdim=rdim, bc=bc,
                 bc_state=[[float(v) for v in st]] + [[0.0] * 4] * 3, gamma=inputs.GAMMA, flux=flux,
                 integrator=integrator, filter="none", limiter=False, cfl=0.3)
 
 
+# (M, N_q) = (3, 3): the multi-pass triangle kernels; (6, 9), (3, 4), (5, 5), (15, 25):
+# the fused triangle stage kernel
 RHS_CASES = [
     ("p1_lf", _cfg(4, 1)),
+    ("fused_p1_hll_rdim2", _cfg(4, 1, flux="hll", rdim=2, m=5)),
+    ("fused_p2_lf_m3q4", _cfg(5, 2, nq=4)),
+    ("fused_p3_bounded_hll_m5q5", _cfg(4, 3, flux="hll", bounded=True, gpc=4, nq=5)),
+    ("fused_p4_lf_rdim2", _cfg(3, 4, rdim=2)),
+    ("fused_p3_bounded_lf_m15q25", _cfg(3, 3, bounded=True, rdim=2, gpc=4, nq=5)),
     ("p2_hll", _cfg(5, 2, flux="hll", m=3)),
     ("p3_lf_rdim2", _cfg(4, 3, rdim=2)),
     ("p4_lf", _cfg(3, 4)),
@@ -72,6 +79,9 @@ def test_tri_points_and_initial_state(label, cfg):
     ("p3_hll_bounded", _cfg(4, 3, flux="hll", bounded=True)),
     ("p3_rk4", _cfg(4, 3, integrator="rk4")),
     ("p1_bs3_rdim2", _cfg(5, 1, rdim=2, integrator="bs3")),
+    ("fused_p3_ssprk3_rdim2", _cfg(4, 3, rdim=2)),
+    ("fused_p2_hll_bounded_m5q5", _cfg(4, 2, flux="hll", bounded=True, gpc=4, nq=5)),
+    ("fused_p3_tsit5_m3q4", _cfg(4, 3, integrator="tsit5", nq=4)),
 ])
 def test_tri_steps_match_oracle(label, cfg):
     announce("tri_steps", label)
