@@ -250,14 +250,35 @@ __global__ void __launch_bounds__(256) k_trace_tri(KParams P, const double* __re
   }
 }
 
+// broadcast lane C of each group of four lanes (DPP quad permutation, all lanes active)
+template <int C>
+__device__ __forceinline__ double quad_bcast(double v) {
+  constexpr int ctrl = C * 85;  // quad_perm(C, C, C, C)
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)x, ctrl, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), ctrl, 0xf, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ void quad_gather(double v, double* all) {
+  all[0] = quad_bcast<0>(v);
+  all[1] = quad_bcast<1>(v);
+  all[2] = quad_bcast<2>(v);
+  all[3] = quad_bcast<3>(v);
+}
+
+// Lane layout: lane = 4 slot + s within an element's 4 x SLOTS lanes, so the four
+// conserved variables of one point sit in one group of four lanes and trade values
+// by DPP instead of LDS.  Per node two barriers: after the nodal values and
+// contravariant fluxes (double-buffered by node parity) and after the face jumps.
 template <int PD, int M, int NQ>
 __global__ void __launch_bounds__(256) k_stage_tri(KParams P, const double* __restrict__ in, const double* u,
                                                    const double* w, double* out, double cu, double cw, int rhs_only,
                                                    const double* __restrict__ Tm) {
   using Sh = TriShape<PD>;
-  constexpr int NPT = Sh::NPT, NFP = Sh::NFP, NF = Sh::NF, SLOTS = Sh::SLOTS, EPB = Sh::EPB;
-  __shared__ double sU[EPB][4][NPT], sF[EPB][4][NPT], sG[EPB][4][NPT];
-  __shared__ double sUL[EPB][4][NF], sUR[EPB][4][NF], sJ[EPB][4][NF];
+  constexpr int NPT = Sh::NPT, NFP = Sh::NFP, NF = Sh::NF, EPB = Sh::EPB;
+  __shared__ double sU[2][EPB][4][NPT], sFr[2][EPB][4][NPT], sGs[2][EPB][4][NPT];
+  __shared__ double sJ[EPB][4][NF];
   __shared__ double sDr[NPT * NPT], sDs[NPT * NPT], sLf[NF * NPT], sLift[NPT * NF];
   for (int i = threadIdx.x; i < NPT * NPT; i += 256) {
     sDr[i] = P.tri_Dr[i];
@@ -270,7 +291,7 @@ __global__ void __launch_bounds__(256) k_stage_tri(KParams P, const double* __re
   const int E = P.E;
   const int el = threadIdx.x / Sh::TPE;
   const int rem = threadIdx.x % Sh::TPE;
-  const int s = rem / SLOTS, slot = rem % SLOTS;
+  const int slot = rem >> 2, s = rem & 3;
   const int e = blockIdx.x * EPB + el;
   const bool active = el < EPB && e < E;
   const int le = active ? el : 0;
@@ -278,11 +299,12 @@ __global__ void __launch_bounds__(256) k_stage_tri(KParams P, const double* __re
   const bool fp = active && slot < NF;
   const long EN = (long)E * NPT;
 
-  // per-element geometry and the face this thread's flux point lies on
   const double* geo = P.tri_geo + (long)(active ? e : 0) * kTriGeo;
-  const double rx = geo[kGeoRx], ry = geo[kGeoRy], sx = geo[kGeoSx], sy = geo[kGeoSy];
+  const double rx = geo[kGeoRx], ry = geo[kGeoRy], sx = geo[kGeoSx], sy = geo[kGeoSy], det = geo[kGeoDet];
   const int f = fp ? slot / NFP : 0, kk = fp ? slot % NFP : 0;
   const double fnx = geo[kGeoN0 + 2 * f], fny = geo[kGeoN0 + 2 * f + 1], fsc = geo[kGeoSc0 + f];
+  // F . n from the contravariant fluxes: F = x_r Fr + x_s Gs, G = y_r Fr + y_s Gs
+  const double fa = det * (fnx * sy - fny * sx), fb = det * (fny * rx - fnx * ry);
   const int nb = fp ? P.tri_nbr[(long)e * 6 + f] : -1;
   const int g = fp ? P.tri_nbr[(long)e * 6 + 3 + f] : 0;
 
@@ -296,87 +318,73 @@ __global__ void __launch_bounds__(256) k_stage_tri(KParams P, const double* __re
   __syncthreads();
 
   for (int q = 0; q < NQ; ++q) {
-    // A: own nodal value at point j, neighbour trace at flux point fk
-    if (pt) {
-      double v = 0.0;
+    const int b = q & 1;
+    // A: nodal value of state s at point `slot`, the four states by quad exchange,
+    // physical flux of state s, stored in contravariant form
+    double v = 0.0, vr = 0.0;
 #pragma unroll
-      for (int k = 0; k < M; ++k) v += P.tab.Phi[k * NQ + q] * uc[k];
-      sU[le][s][slot] = v;
+    for (int k = 0; k < M; ++k) {
+      const double ph = P.tab.Phi[k * NQ + q];
+      v += ph * uc[k];
+      vr += ph * tn[k];
     }
-    if (fp && nb >= 0) {
-      double v = 0.0;
-#pragma unroll
-      for (int k = 0; k < M; ++k) v += P.tab.Phi[k * NQ + q] * tn[k];
-      sUR[le][s][slot] = v;
-    }
-    __syncthreads();
-    // B1: physical fluxes at the solution points, one state per thread
+    double U[4];
+    quad_gather(v, U);
     if (pt) {
-      const double r0 = sU[le][0][slot], m1 = sU[le][1][slot], m2 = sU[le][2][slot], en = sU[le][3][slot];
-      const double vx = m1 / r0, vy = m2 / r0;
-      const double p = (P.gamma - 1.0) * (en - 0.5 * (m1 * m1 + m2 * m2) / r0);
+      const double vx = U[1] / U[0], vy = U[2] / U[0];
+      const double p = (P.gamma - 1.0) * (U[3] - 0.5 * (U[1] * U[1] + U[2] * U[2]) / U[0]);
       double Fs, Gs;
       if (s == 0) {
-        Fs = m1;
-        Gs = m2;
+        Fs = U[1];
+        Gs = U[2];
       } else if (s == 1) {
-        Fs = m1 * vx + p;
-        Gs = m1 * vy;
+        Fs = U[1] * vx + p;
+        Gs = U[1] * vy;
       } else if (s == 2) {
-        Fs = m2 * vx;
-        Gs = m2 * vy + p;
+        Fs = U[2] * vx;
+        Gs = U[2] * vy + p;
       } else {
-        Fs = (en + p) * vx;
-        Gs = (en + p) * vy;
+        Fs = (U[3] + p) * vx;
+        Gs = (U[3] + p) * vy;
       }
-      sF[le][s][slot] = Fs;
-      sG[le][s][slot] = Gs;
+      sU[b][le][s][slot] = v;
+      sFr[b][le][s][slot] = rx * Fs + ry * Gs;
+      sGs[b][le][s][slot] = sx * Fs + sy * Gs;
     }
     __syncthreads();
-    // B2a: own trace and interpolated normal flux at flux point fk
-    double FDs = 0.0;
+    // B: own trace and interpolated normal flux at flux point `slot`; both traces
+    // of the four states by quad exchange; interactive flux; jump
+    double ul = 0.0, fr = 0.0, gs = 0.0;
     if (fp) {
-      double ul = 0.0, fx = 0.0, fy = 0.0;
 #pragma unroll
       for (int j = 0; j < NPT; ++j) {
         const double l = sLf[slot * NPT + j];
-        ul += l * sU[le][s][j];
-        fx += l * sF[le][s][j];
-        fy += l * sG[le][s][j];
+        ul += l * sU[b][le][s][j];
+        fr += l * sFr[b][le][s][j];
+        gs += l * sGs[b][le][s][j];
       }
-      sUL[le][s][slot] = ul;
-      FDs = fnx * fx + fny * fy;
     }
-    __syncthreads();
-    // B2b: interactive flux along the normal (each thread its own state), jump
+    double L[4], R[4];
+    quad_gather(ul, L);
+    quad_gather(vr, R);
     if (fp) {
-      double L[4], R[4], Fst[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) L[c] = sUL[le][c][slot];
-      if (nb >= 0) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) R[c] = sUR[le][c][slot];
-      } else {
-        ghost_n(P, -1 - nb, L, fnx, fny, R);
-      }
+      if (nb < 0) ghost_n(P, -1 - nb, L, fnx, fny, R);
+      double Fst[4];
       flux_n(P.flux, L, R, fnx, fny, P.gamma, Fst);
-      sJ[le][s][slot] = (Fst[s] - FDs) * fsc;
+      sJ[le][s][slot] = (Fst[s] - (fa * fr + fb * gs)) * fsc;
     }
     __syncthreads();
-    // C: nodal residual of state s at point j, projected onto the chaos
+    // C: nodal residual of state s at point `slot`, projected onto the chaos
     if (pt) {
-      double dr = 0.0, ds = 0.0, c = 0.0;
+      double d = 0.0, c = 0.0;
 #pragma unroll
-      for (int i = 0; i < NPT; ++i) {
-        const double Fi = sF[le][s][i], Gi = sG[le][s][i];
-        dr += sDr[slot * NPT + i] * (rx * Fi + ry * Gi);
-        ds += sDs[slot * NPT + i] * (sx * Fi + sy * Gi);
-      }
+      for (int i = 0; i < NPT; ++i)
+        d += sDr[slot * NPT + i] * sFr[b][le][s][i] + sDs[slot * NPT + i] * sGs[b][le][s][i];
 #pragma unroll
       for (int m = 0; m < NF; ++m) c += sLift[slot * NF + m] * sJ[le][s][m];
-      const double R = -(dr + ds + c);
+      const double Rq = -(d + c);
 #pragma unroll
-      for (int k = 0; k < M; ++k) acc[k] += P.tab.PW[k * NQ + q] * R;
+      for (int k = 0; k < M; ++k) acc[k] += P.tab.PW[k * NQ + q] * Rq;
     }
   }
   if (!pt) return;
@@ -404,6 +412,45 @@ __global__ void __launch_bounds__(256) k_cfl_tri_modal(KParams P, const double* 
       for (int s = 0; s < 4; ++s) {
         double v = 0.0;
         for (int k = 0; k < M; ++k) v += P.tab.Phi[k * Nq + q] * u[((long)s * M + k) * EN + t];
+        U[s] = v;
+      }
+      const double p = euler2_p(U, P.gamma);
+      double r = (sqrt(U[1] * U[1] + U[2] * U[2]) / U[0] + sqrt(P.gamma * p / U[0])) / din;
+      if (!(r == r)) r = __longlong_as_double(0x7ff0000000000000ll);
+      rate = fmax(rate, r);
+    }
+  }
+  sm[threadIdx.x] = rate;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(P.lam_bits, (unsigned long long)__double_as_longlong(sm[0]));
+}
+
+// the same for the (M, N_q) pairs of the fused stage: the thread's coefficients stay in registers
+template <int M, int NQ>
+__global__ void __launch_bounds__(256) k_cfl_tri_mq(KParams P, const double* __restrict__ u) {
+  __shared__ double sm[256];
+  const int np = P.nsp;
+  const long EN = (long)P.E * np;
+  const long t = blockIdx.x * 256l + threadIdx.x;
+  double rate = 0.0;
+  if (t < EN) {
+    const double din = P.tri_geo[(t / np) * kTriGeo + kGeoDin];
+    double c[4][M];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int k = 0; k < M; ++k) c[s][k] = u[((long)s * M + k) * EN + t];
+    for (int q = 0; q < NQ; ++q) {
+      double U[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < M; ++k) v += P.tab.Phi[k * NQ + q] * c[s][k];
         U[s] = v;
       }
       const double p = euler2_p(U, P.gamma);
@@ -471,6 +518,13 @@ hipError_t launch_stage_tri(const KParams& P, const double* in, const double* u,
 hipError_t launch_cfl_tri_modal(const KParams& P, const double* u, hipStream_t s) {
   if (P.eq != FRSG_EULER2D) return hipErrorInvalidValue;
   const long n = (long)P.E * P.nsp;
+#define FRSG_TRI_CFL(MM, QQ)                                                                    \
+  if (P.M == MM && P.Nq == QQ) {                                                                 \
+    hipLaunchKernelGGL((k_cfl_tri_mq<MM, QQ>), dim3(blocks(n)), dim3(256), 0, s, P, u);          \
+    return hipGetLastError();                                                                    \
+  }
+  FRSG_TRI_CFL(15, 25) FRSG_TRI_CFL(10, 16) FRSG_TRI_CFL(6, 9) FRSG_TRI_CFL(5, 5) FRSG_TRI_CFL(3, 4)
+#undef FRSG_TRI_CFL
   hipLaunchKernelGGL(k_cfl_tri_modal, dim3(blocks(n)), dim3(256), 0, s, P, u);
   return hipGetLastError();
 }
