@@ -46,6 +46,33 @@ __device__ __forceinline__ void flux_n(int kind, const double* L, const double* 
   }
 }
 
+// a[s] for a run-time s without indexing a private array
+__device__ __forceinline__ double pick4(const double* a, int s) {
+  return s == 0 ? a[0] : (s == 1 ? a[1] : (s == 2 ? a[2] : a[3]));
+}
+
+// component s of the interactive flux along the normal, with one reciprocal of the
+// density per side (the fused kernel's lanes each produce one conserved variable)
+__device__ __forceinline__ double flux_n_comp(int kind, const double* L, const double* R, double nx, double ny,
+                                              double gamma, int s) {
+  const double iL = 1.0 / L[0], iR = 1.0 / R[0];
+  const double uL = (L[1] * nx + L[2] * ny) * iL, uR = (R[1] * nx + R[2] * ny) * iR;
+  const double pL = (gamma - 1.0) * (L[3] - 0.5 * (L[1] * L[1] + L[2] * L[2]) * iL);
+  const double pR = (gamma - 1.0) * (R[3] - 0.5 * (R[1] * R[1] + R[2] * R[2]) * iR);
+  const double cL = sqrt(gamma * pL * iL), cR = sqrt(gamma * pR * iR);
+  const double ns = s == 1 ? nx : (s == 2 ? ny : 0.0);
+  const double Ls = pick4(L, s), Rs = pick4(R, s);
+  const double FL = (s == 3 ? Ls + pL : Ls) * uL + pL * ns;
+  const double FR = (s == 3 ? Rs + pR : Rs) * uR + pR * ns;
+  const double dU = Rs - Ls;
+  if (kind == FRSG_FLUX_HLL) {
+    const double SL = fmin(uL - cL, uR - cR), SR = fmax(uL + cL, uR + cR);
+    return (SL >= 0.0) ? FL : (SR <= 0.0) ? FR : (SR * FL - SL * FR + (SL * SR) * dU) / (SR - SL);
+  }
+  const double lam = fmax(fabs(uL) + cL, fabs(uR) + cR);
+  return 0.5 * (FL + FR) - 0.5 * lam * dU;
+}
+
 // ghost state outside a boundary face of kind bc[side] (reflection about the face)
 __device__ __forceinline__ void ghost_n(const KParams& P, int side, const double* in, double nx, double ny,
                                         double* out) {
@@ -331,8 +358,9 @@ __global__ void __launch_bounds__(256) k_stage_tri(KParams P, const double* __re
     double U[4];
     quad_gather(v, U);
     if (pt) {
-      const double vx = U[1] / U[0], vy = U[2] / U[0];
-      const double p = (P.gamma - 1.0) * (U[3] - 0.5 * (U[1] * U[1] + U[2] * U[2]) / U[0]);
+      const double ir = 1.0 / U[0];
+      const double vx = U[1] * ir, vy = U[2] * ir;
+      const double p = (P.gamma - 1.0) * (U[3] - 0.5 * (U[1] * vx + U[2] * vy));
       double Fs, Gs;
       if (s == 0) {
         Fs = U[1];
@@ -369,9 +397,7 @@ __global__ void __launch_bounds__(256) k_stage_tri(KParams P, const double* __re
     quad_gather(vr, R);
     if (fp) {
       if (nb < 0) ghost_n(P, -1 - nb, L, fnx, fny, R);
-      double Fst[4];
-      flux_n(P.flux, L, R, fnx, fny, P.gamma, Fst);
-      sJ[le][s][slot] = (Fst[s] - (fa * fr + fb * gs)) * fsc;
+      sJ[le][s][slot] = (flux_n_comp(P.flux, L, R, fnx, fny, P.gamma, s) - (fa * fr + fb * gs)) * fsc;
     }
     __syncthreads();
     // C: nodal residual of state s at point `slot`, projected onto the chaos
