@@ -119,7 +119,7 @@ def pass_times(sol, u, steps):
 STAGES = ("stage1", "stage2", "stage3")
 
 
-def roofline_for(passes, precision):
+def roofline_for(passes, precision, kern=None, name="stage kernel (stages 1-3)"):
     """Roofline of the dominant kernel from the library's per-pass event timings.
 
     On the fused path the three SSP-RK3 stages are launches of one kernel (the
@@ -130,8 +130,7 @@ def roofline_for(passes, precision):
         launches = sum(passes[k][0] for k in STAGES)
         tot_ms = sum(passes[k][1] for k in STAGES)
         alg = sum(passes[k][0] * passes[k][2] for k in STAGES) / launches
-        name = "stage kernel (stages 1-3)"
-        kern = KERNEL_NAME[precision]
+        kern = kern or KERNEL_NAME[precision]
     else:
         dom = max(passes, key=lambda k: passes[k][1])
         launches, tot_ms, alg = passes[dom]
@@ -154,14 +153,18 @@ def alu_roofline(roof, flop_per_dof, dof, precision):
             "flop_per_dof_per_launch": flop_per_dof}
 
 
-def other_workloads(torch, Solver, inputs, steps):
+# the triangle path's stage (trace pass + fused stage kernel) for the vortex workload
+TRI_KERNEL = "k_stage_tri<3, 15, 25>"
+
+
+def other_workloads(torch, Solver, inputs, steps, names=None):
     """DOF-updates/s of the other workloads (FP64, CFL steps in one call): the cache-resident 1D
     problems, with the Lasso filter, the HLL flux and the Bogacki-Shampine integrator, the
     shock-vortex problem with HLL, alone and with Bogacki-Shampine, and the vortex on 32768
     perturbed triangles (p = 3, 15 modes, 25 nodes)."""
     out = {}
-    for name in ("advection_sine", "burgers_sine", "sod_interface", "burgers_lasso", "sod_lasso", "sod_hll",
-                 "shock_vortex_hll", "sod_hll_bs3", "shock_vortex_hll_bs3", "tri_vortex"):
+    for name in names or ("advection_sine", "burgers_sine", "sod_interface", "burgers_lasso", "sod_lasso", "sod_hll",
+                          "shock_vortex_hll", "sod_hll_bs3", "shock_vortex_hll_bs3", "tri_vortex"):
         cfg = inputs.tri_vortex(128) if name == "tri_vortex" else inputs.CONFIGS[name]
         sol = Solver(cfg)
         u = sol.initial_state()
@@ -178,10 +181,14 @@ def other_workloads(torch, Solver, inputs, steps):
         ms = e0.elapsed_time(e1) / steps
         dof = int(sol.info["n_dof"])
         out[name] = {"dof": dof, "ms_per_step": ms, "dof_updates_per_s": dof / (ms / 1e3),
-                     "shape": "%s el, p=%d, %d modes, %d nodes, %d states" % (
-                         "%d triangles" % sol.E if cfg.get("element") == "tri" else
-                         "%dx%d" % (cfg["nx"], cfg["ny"]) if cfg["equation"] == "euler2d" else str(cfg["nx"]),
+                     "shape": "%s, p=%d, %d modes, %d nodes, %d states" % (
+                         "%d triangles" % sol.E if cfg.get("element") == "tri" else "%s el" % (
+                         "%dx%d" % (cfg["nx"], cfg["ny"]) if cfg["equation"] == "euler2d" else str(cfg["nx"])),
                          cfg["p"], sol.shape[1], sol.info["n_nodes"], sol.shape[0])}
+        if cfg.get("element") == "tri":
+            passes = pass_times(sol, u, 20)
+            out[name]["passes_ms_per_step"] = {k: v[1] / 20 for k, v in passes.items()}
+            out[name]["roofline"] = roofline_for(passes, "fp64", TRI_KERNEL, "trace pass + stage kernel (stages 1-3)")
         sol.close()
     return out
 
@@ -269,6 +276,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost run")
     ap.add_argument("--no-others", action="store_true", help="skip the 1D workloads")
     ap.add_argument("--no-convergence", action="store_true", help="skip the wave-propagation convergence study")
+    ap.add_argument("--profile-workload", default=None,
+                    help="run only this one of the other workloads (for profiling) and print its record")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the multi-GPU halo exchange is not built); "
@@ -281,6 +290,9 @@ def main():
     from paper_2112_05946_amd.binding import FrsgError, Solver
 
     torch.cuda.set_device(0)
+    if args.profile_workload:
+        print(json.dumps(other_workloads(torch, Solver, inputs, args.steps, [args.profile_workload])), flush=True)
+        return
     cfg = inputs.CONFIGS[args.config]
     sol = Solver(cfg, precision=args.precision)
     u = sol.initial_state()
