@@ -257,6 +257,9 @@ def nodal_at_face_points(prob, T, U):
     1D: the two faces r = -1, +1.  2D: for each of the 4 faces the (p+1) flux
     points on it, ordered x-lo (b), x-hi (b), y-lo (a), y-hi (a).
     """
+    if prob.element == "tri":
+        # the 3 (p+1) flux points, face-major
+        return np.einsum("fki,sqei->sqefk", T.Lf, U).reshape(U.shape[:3] + (-1,))
     if prob.dim == 1:
         return np.stack([np.einsum("j,sqej->sqe", T.lL, U), np.einsum("j,sqej->sqe", T.lR, U)], axis=-1)
     S, Nq, E, _ = U.shape

@@ -54,6 +54,8 @@ class NotRealizable(ArithmeticError):
 # ----------------------------------------------------------------------------
 
 def to_spatial_modal(prob, T, u):
+    if prob.element == "tri":
+        return np.einsum("ml,skel->skem", T.Vinv, u)
     if prob.dim == 1:
         return np.einsum("jl,skel->skej", T.Vinv, u)
     S, M, E, _ = u.shape
@@ -64,6 +66,8 @@ def to_spatial_modal(prob, T, u):
 
 
 def to_nodal(prob, T, ut):
+    if prob.element == "tri":
+        return np.einsum("jm,skem->skej", T.V, ut)
     if prob.dim == 1:
         return np.einsum("jl,skel->skej", T.V, ut)
     S, M, E, _ = ut.shape
@@ -74,7 +78,10 @@ def to_nodal(prob, T, ut):
 
 
 def spatial_degrees(prob, T):
-    """Per solution-point mode index: tuple of per-direction degrees."""
+    """Per solution-point mode index: tuple of per-direction degrees (on triangles
+    the total degree of the orthonormal mode, a one-element tuple)."""
+    if prob.element == "tri":
+        return [(int(d),) for d in T.deg]
     n = T.n
     if prob.dim == 1:
         return [(j,) for j in range(n)]
@@ -118,7 +125,8 @@ def filter_strength(prob, T, R, dt):
                 ex = sum((dj / prob.p) ** prob.s for dj in d)
                 lam[k, j] = np.exp(-prob.alpha * dt * (ex + ez))
     elif prob.filter == "l2":
-        Np = T.n
+        # N_p solution points per direction: the damping of the top degree p is 1/(1 + 1/eps1)
+        Np = prob.p + 1
         a1 = 1.0 / (prob.eps1 * Np * Np * (Np - 1) * (Np - 1))
         a2 = 1.0 / (prob.eps2 * Nc * Nc * (Nc + 1) * (Nc + 1)) if Nc > 0 else 0.0
         for k in range(R.M):
@@ -163,8 +171,6 @@ def sensor_filter(prob, T, R, u, dt):
     """Sensor-gated filter; returns (u_filtered, flags)."""
     if prob.filter == "none":
         return u.copy(), np.zeros(u.shape[2], dtype=bool)
-    if prob.element == "tri":
-        raise NotImplementedError("sensor and filter on triangles")
     flags = sensor_flags(prob, T, R, u)
     ut = to_spatial_modal(prob, T, u)
     if prob.filter == "lasso":
@@ -182,7 +188,10 @@ def sensor_filter(prob, T, R, u, dt):
 # ----------------------------------------------------------------------------
 
 def element_mean(prob, T, u):
-    """Mean over element x random space: sum_j (w_j/2) u[s, 0, e, j] (tensor in 2D)."""
+    """Mean over element x random space: sum_j (w_j/2) u[s, 0, e, j] (tensor in 2D; on
+    triangles the coefficient of the constant orthonormal mode)."""
+    if prob.element == "tri":
+        return np.einsum("sej,j->se", u[:, 0], T.mean_w)
     if prob.dim == 1:
         wts = T.w / 2.0
     else:
@@ -256,8 +265,6 @@ def limit(prob, T, R, u):
     flags = np.zeros(E, dtype=bool)
     if not prob.limiter:
         return u.copy(), flags
-    if prob.element == "tri":
-        raise NotImplementedError("positivity limiter on triangles")
     dim = prob.dim
     out = u.copy()
     ubar = element_mean(prob, T, u)  # [s, e]

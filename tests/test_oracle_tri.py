@@ -331,3 +331,114 @@ def test_density_wave_convergence_order(p):
     errs = [_density_wave_mean_error(p, n) for n in (6, 12)]
     order = math.log2(errs[0] / errs[1])
     assert abs(order - (p + 1)) < 0.4, (errs, order)
+
+
+# ----------------------------------------------------------------------------
+# discontinuity sensor, modal filters and positivity limiter on triangles
+# ----------------------------------------------------------------------------
+
+def _mono_poly(p, seed):
+    """A random polynomial of total degree <= p as (coefficients, exponents)."""
+    rng = np.random.default_rng(seed)
+    ex = tri.monomial_exponents(p)
+    return rng.normal(size=len(ex)), ex
+
+
+def test_tri_modal_coefficients_are_orthonormal_projections():
+    """Nodal -> modal on triangles equals (1/2) int_T u psi_m of the polynomial itself,
+    integrated by the collapsed rule (no Vandermonde inverse on this side)."""
+    from oracle.stabilize import to_spatial_modal
+    for p in (1, 2, 3, 4):
+        mesh = inputs.tri_mesh_rectangle(1, 1)
+        prob = _tri_problem(mesh, p=p)
+        T = tri.build_tri_tables(p)
+        c, ex = _mono_poly(p, p)
+        f = lambda r, s: sum(ci * r ** i * s ** j for ci, (i, j) in zip(c, ex))
+        u = np.zeros((4, 1, 2, T.n))
+        u[0, 0, 0] = f(T.r, T.s)
+        ut = to_spatial_modal(prob, T, u)[0, 0, 0]
+        rq, sq, wq = tri.duffy_rule(p + 3)
+        ref = 0.5 * (tri.basis_eval(p, rq, sq) * (wq * f(rq, sq))[:, None]).sum(axis=0)
+        assert np.max(np.abs(ut - ref)) < 1e-12
+
+
+@pytest.mark.parametrize("filt", ["exp", "l2"])
+def test_tri_filter_acts_mode_by_mode(filt):
+    """A state made of one orthonormal mode psi_m Phi_k (any state variable) comes back
+    times the filter factor of its total degree d and chaos degree |k|:
+    exp(-alpha dt ((d/p)^s + (|k|/N_c)^s)) or 1 / (1 + d^2 (d+1)^2 / (eps1 p^2 (p+1)^2)
+    + |k|^2 (|k|+1)^2 / (eps2 N_c^2 (N_c+1)^2)); the mean mode is untouched."""
+    from oracle.stabilize import sensor_filter
+    p, Nc = 3, 3
+    mesh = inputs.tri_mesh_rectangle(1, 1)
+    prob = _tri_problem(mesh, p=p, gpc_order=Nc, nq1d=5, filter=filt, sensor="always", alpha=36.0, s=3.0,
+                        eps1=0.6, eps2=0.8)
+    T = tri.build_tri_tables(p)
+    R = build_random_tables(Nc, 1, 5)
+    dt = 2e-3
+    _, _, deg = tri.orthonormal_basis(p)
+    for m in range(T.n):
+        for k in range(R.M):
+            u = np.zeros((4, R.M, 2, T.n))
+            u[2, k, 1] = T.V[:, m]          # psi_m at the solution points
+            out, flags = sensor_filter(prob, T, R, u, dt)
+            d = deg[m]
+            if filt == "exp":
+                lam = math.exp(-36.0 * dt * ((d / p) ** 3 + (k / Nc) ** 3))
+            else:
+                lam = 1.0 / (1.0 + d * d * (d + 1) ** 2 / (0.6 * p * p * (p + 1) ** 2)
+                             + k * k * (k + 1) ** 2 / (0.8 * Nc * Nc * (Nc + 1) ** 2))
+            assert np.max(np.abs(out - lam * u)) < 1e-13, (m, k)
+            if d == 0 and k == 0:
+                assert abs(lam - 1.0) < 1e-15
+
+
+def test_tri_sensor_flags_top_degree_content():
+    """S_e = energy of the modes of total degree p or chaos degree N_c (state 0) over the total."""
+    from oracle.stabilize import sensor_flags
+    p = 3
+    mesh = inputs.tri_mesh_rectangle(1, 1)
+    prob = _tri_problem(mesh, p=p, gpc_order=2, nq1d=3, filter="exp", sensor="detector", s0=-3.0, kappa=1.0)
+    T = tri.build_tri_tables(p)
+    R = build_random_tables(2, 1, 3)
+    _, _, deg = tri.orthonormal_basis(p)
+    low = [m for m in range(T.n) if deg[m] < p]
+    top = [m for m in range(T.n) if deg[m] == p]
+    u = np.zeros((4, R.M, 2, T.n))
+    u[0, 0, 0] = T.V[:, low] @ np.linspace(1.0, 0.2, len(low))   # smooth: no top-degree content
+    u[0, 1, 0] = 0.3 * T.V[:, low[1]]
+    u[0, 0, 1] = T.V[:, low] @ np.linspace(1.0, 0.2, len(low)) + 0.5 * T.V[:, top[0]]
+    flags = sensor_flags(prob, T, R, u)
+    assert not flags[0] and flags[1]
+
+
+def test_tri_limiter_restores_positivity_and_keeps_means():
+    from oracle.stabilize import element_mean, limit
+    mesh = inputs.tri_mesh_rectangle(5, 4, perturb=0.2, seed=8)
+    prob = _tri_problem(mesh, p=3, gpc_order=3, nq1d=4, limiter=True)
+    T = tri.build_tri_tables(3)
+    R = build_random_tables(3, 1, 4)
+    u = inputs.fuzz_euler(2, R.M, prob.E, T.n, seed=21, vacuum_frac=0.3)
+    out, flags = limit(prob, T, R, u)
+    assert flags.sum() >= 6
+    m0, m1 = element_mean(prob, T, u), element_mean(prob, T, out)
+    assert np.max(np.abs(m1 - m0)) < 1e-14
+    assert np.array_equal(out[:, :, ~flags], u[:, :, ~flags])
+    # density and pressure at solution and flux points, every node: independent
+    # evaluation through the polynomials (orthonormal basis at the points)
+    def pts(v):
+        U = np.einsum("kq,skej->sqej", R.Phi, v)
+        fr, fs = zip(*[tri.face_param(f, T.tq) for f in range(3)])
+        rr = np.concatenate([T.r] + list(fr))
+        ss = np.concatenate([T.s] + list(fs))
+        L = tri.basis_eval(3, rr, ss) @ T.Vinv
+        return np.einsum("pj,sqej->sqep", L, U)
+    P = pts(out)
+    rho = P[0]
+    pr = (GAMMA - 1) * (P[3] - 0.5 * (P[1] ** 2 + P[2] ** 2) / P[0])
+    pbar = (GAMMA - 1) * (m0[3] - 0.5 * (m0[1] ** 2 + m0[2] ** 2) / m0[0])
+    eps = np.minimum(1e-8, np.minimum(m0[0], pbar))
+    lo = np.minimum(rho.min(axis=(0, 2)), pr.min(axis=(0, 2)))
+    assert np.all(lo[flags] >= eps[flags] * (1 - 1e-6) - 1e-13)
+    # tight: each limited element touches eps at some point and node
+    assert np.all(np.abs(lo[flags] - eps[flags]) < 1e-9)
