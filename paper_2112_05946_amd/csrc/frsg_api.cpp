@@ -89,8 +89,8 @@ fr_sg_status validate(const fr_sg_problem& P, std::string& err) {
       err = "fr_degree must be in 1..4 on triangles";
       return FRSG_EUNSUPPORTED;
     }
-    if (P.filter != FRSG_FILTER_NONE || P.limiter || P.precision != FRSG_FP64) {
-      err = "filters, the limiter and FP32-mixed are not available on triangles";
+    if (P.precision != FRSG_FP64) {
+      err = "FP32-mixed is not available on triangles";
       return FRSG_EUNSUPPORTED;
     }
   } else {
@@ -279,6 +279,7 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
     delete c;
     return FRSG_EINVAL;
   }
+  if (c->is_tri) tri_filter_tables(P, c->tri, c->T);
   // the mesh arrays are the caller's and are read during this call only
   c->prob.tri_xy = nullptr;
   c->prob.tri_nbr = nullptr;
@@ -368,6 +369,8 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
     tb.insert(tb.end(), R.Lf.begin(), R.Lf.end());
     tb.insert(tb.end(), R.lift.begin(), R.lift.end());
     tb.insert(tb.end(), R.geo.begin(), R.geo.end());
+    tb.insert(tb.end(), R.V.begin(), R.V.end());
+    tb.insert(tb.end(), R.Vinv.begin(), R.Vinv.end());
     he = hipMalloc(&c->dtri, tb.size() * sizeof(double));
     if (he == hipSuccess) he = hipMemcpy(c->dtri, tb.data(), tb.size() * sizeof(double), hipMemcpyHostToDevice);
     if (he == hipSuccess) he = hipMalloc(&c->dtri_nbr, R.nbr.size() * sizeof(int));
@@ -504,7 +507,8 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
   }
   c->ws.bytes = total + blob.size() * sizeof(double);
   if (c->is_tri)
-    c->ws.bytes += (c->tri.Dr.size() + c->tri.Ds.size() + c->tri.Lf.size() + c->tri.lift.size() + c->tri.geo.size()) *
+    c->ws.bytes += (c->tri.Dr.size() + c->tri.Ds.size() + c->tri.Lf.size() + c->tri.lift.size() + c->tri.geo.size() +
+                    c->tri.V.size() + c->tri.Vinv.size()) *
                        sizeof(double) +
                    c->tri.nbr.size() * sizeof(int);
 
@@ -549,6 +553,8 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
     K.tri_Lf = K.tri_Ds + R.Ds.size();
     K.tri_lift = K.tri_Lf + R.Lf.size();
     K.tri_geo = K.tri_lift + R.lift.size();
+    K.tri_V = K.tri_geo + R.geo.size();
+    K.tri_Vinv = K.tri_V + R.V.size();
     K.tri_nbr = c->dtri_nbr;
   }
   K.dt = c->ws.scal;
@@ -704,7 +710,8 @@ static fr_sg_status step_generic(fr_sg_ctx* ctx, double* u, double dt, double* d
   FRSG_TRY_HIP(launch_set_scalars(K, cfl ? 0.0 : dt, s), ctx);
   const double sb = state_bytes(ctx);
   if (ctx->fused_tri) {
-    // triangles: one fused launch per stage (after its trace pass); no filter or limiter
+    // triangles: one fused launch per stage (after its trace pass), the limiter
+    // after each stage and the sensor-gated filter and limiter at the end
     if (cfl) {
       if ((st = timed(ctx, "cfl", sb, [&] { return launch_cfl_tri_modal(K, u, s); }))) return st;
       FRSG_TRY_HIP(launch_dt(K, ctx->dim, nullptr, s), ctx);
@@ -712,13 +719,19 @@ static fr_sg_status step_generic(fr_sg_ctx* ctx, double* u, double dt, double* d
     if ((st = timed(ctx, "stage1", 2 * sb,
                     [&] { return launch_stage_tri(K, u, u, u, W.w1, 0.0, 1.0, 0, W.Tm, s); })))
       return st;
+    if ((st = fr_sg_limit(ctx, W.w1, f0)) != FRSG_OK) return st;
     if ((st = timed(ctx, "stage2", 3 * sb,
                     [&] { return launch_stage_tri(K, W.w1, u, W.w1, W.w2, 0.75, 0.25, 0, W.Tm, s); })))
       return st;
+    if ((st = fr_sg_limit(ctx, W.w2, f1)) != FRSG_OK) return st;
     if ((st = timed(ctx, "stage3", 3 * sb,
                     [&] { return launch_stage_tri(K, W.w2, u, W.w2, u, 1.0 / 3.0, 2.0 / 3.0, 0, W.Tm, s); })))
       return st;
-    if (flags) FRSG_TRY_HIP(launch_fill_flags(flags, 4l * E, s), ctx);
+    if (ctx->prob.filter != FRSG_FILTER_NONE) {
+      if ((st = timed(ctx, "sensor_filter", 2 * sb, [&] { return launch_sensor_filter(K, u, f2, s); }))) return st;
+    } else if (f2)
+      FRSG_TRY_HIP(launch_fill_flags(f2, E, s), ctx);
+    if ((st = fr_sg_limit(ctx, u, f3)) != FRSG_OK) return st;
     if (dt_used) FRSG_TRY_HIP(launch_copy_dt(K, dt_used, s), ctx);
     return FRSG_OK;
   }

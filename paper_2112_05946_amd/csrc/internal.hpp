@@ -69,9 +69,12 @@ struct TriTables {
   std::vector<double> geo;         // [E][kTriGeo]
   std::vector<int> nbr;            // [E][6]: neighbour element (or -1 - side), then neighbour face
   std::vector<double> xy_pts;      // [E][np][2]: physical solution-point coordinates
+  std::vector<double> V, Vinv;     // [np][np]: V[j][m] = psi_m(r_j) and its inverse
 };
 // reference tables for degree p, mesh checks and geometry from the problem's arrays
 bool build_tri_tables(const fr_sg_problem& P, TriTables& T, std::string& err);
+// sensor shell, filter factors and element-mean weights of the host tables, by total degree
+void tri_filter_tables(const fr_sg_problem& P, const TriTables& R, HostTables& T);
 
 // ---------------------------------------------------------------------------
 // device-side view of the tables (one allocation, sub-arrays by offset)
@@ -114,6 +117,8 @@ struct KParams {
   const double* tri_Lf;    // [3 nfp][N_p]
   const double* tri_lift;  // [N_p][3 nfp]
   const double* tri_geo;   // [E][kTriGeo]
+  const double* tri_V;     // [N_p][N_p] orthonormal modes at the solution points, and inverse
+  const double* tri_Vinv;
   const int* tri_nbr;      // [E][6]
   unsigned* status;
   unsigned long long* lam_bits;  // CFL accumulator (bit pattern of a positive double)

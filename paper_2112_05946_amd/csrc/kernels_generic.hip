@@ -353,7 +353,16 @@ __device__ __forceinline__ void limiter_point(const KParams& P, const double* C,
     return;
   }
   const int f = pt - nsp;
-  if constexpr (DIM == 1) {
+  if constexpr (DIM == 3) {
+    // triangle flux point f: interpolation row of the face table
+    const double* l = P.tri_Lf + (long)f * nsp;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      double acc = 0.0;
+      for (int j = 0; j < nsp; ++j) acc += l[j] * at_sp(s, j);
+      U[s] = acc;
+    }
+  } else if constexpr (DIM == 1) {
     const double* l = (f == 0) ? P.tab.lL : P.tab.lR;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -410,7 +419,7 @@ __global__ void __launch_bounds__(kElemBlock) k_limiter(KParams P, double* __res
     return;
   }
   const double eps = fmin(1e-8, fmin(ub[0], pb));
-  const int nfp = DIM == 1 ? 2 : 4 * P.np1;
+  const int nfp = DIM == 1 ? 2 : (DIM == 2 ? 4 * P.np1 : 3 * P.nfp);
   const int items = (nsp + nfp) * Nq;
 
   // Decision from rigorous bounds first: at point pt the value at any node is
@@ -434,7 +443,10 @@ __global__ void __launch_bounds__(kElemBlock) k_limiter(KParams P, double* __res
           } else {
             const int f = pt - nsp;
             a = 0.0;
-            if constexpr (DIM == 1) {
+            if constexpr (DIM == 3) {
+              const double* l = P.tri_Lf + (long)f * nsp;
+              for (int j = 0; j < nsp; ++j) a += l[j] * ck[j];
+            } else if constexpr (DIM == 1) {
               const double* l = (f == 0) ? P.tab.lL : P.tab.lR;
               for (int j = 0; j < n; ++j) a += l[j] * ck[j];
             } else {
@@ -502,7 +514,10 @@ __global__ void __launch_bounds__(kElemBlock) k_limiter(KParams P, double* __res
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       double acc = 0.0;
-      if constexpr (DIM == 1) {
+      if constexpr (DIM == 3) {
+        const double* l = P.tri_Lf + (long)f * nsp;
+        for (int j = 0; j < nsp; ++j) acc += l[j] * sN[((long)s * nsp + j) * Nq + q];
+      } else if constexpr (DIM == 1) {
         const double* l = (f == 0) ? P.tab.lL : P.tab.lR;
         for (int j = 0; j < n; ++j) acc += l[j] * sN[((long)s * nsp + j) * Nq + q];
       } else {
@@ -569,7 +584,9 @@ __global__ void __launch_bounds__(kElemBlock) k_sensor_filter(KParams P, double*
     const int sk = it / nsp;
     const double* src = u + (long)sk * EN + (long)e * nsp;
     double acc = 0.0;
-    if constexpr (DIM == 1) {
+    if constexpr (DIM == 3) {
+      for (int l = 0; l < nsp; ++l) acc += P.tri_Vinv[m * nsp + l] * src[l];
+    } else if constexpr (DIM == 1) {
       for (int l = 0; l < n; ++l) acc += Vinv[m * n + l] * src[l];
     } else {
       const int ma = m % n, mb = m / n;
@@ -622,7 +639,9 @@ __global__ void __launch_bounds__(kElemBlock) k_sensor_filter(KParams P, double*
       return P.filter == FRSG_FILTER_EXP ? exp(-P.alpha * dt * f) : f;
     };
     double acc = 0.0;
-    if constexpr (DIM == 1) {
+    if constexpr (DIM == 3) {
+      for (int m = 0; m < nsp; ++m) acc += P.tri_V[j * nsp + m] * (src[m] * lam(m));
+    } else if constexpr (DIM == 1) {
       for (int m = 0; m < n; ++m) acc += V[j * n + m] * (src[m] * lam(m));
     } else {
       const int a = j % n, b = j / n;
@@ -738,6 +757,8 @@ hipError_t launch_limiter(const KParams& P, double* u, unsigned char* flags, hip
   const size_t shmem = staged == 2 ? bytes + nodal : (staged ? bytes : 0);
   if (P.eq == kEuler1)
     hipLaunchKernelGGL((k_limiter<kEuler1, 1>), dim3(P.E), dim3(kElemBlock), shmem, s, P, u, flags, staged);
+  else if (P.eq == kEuler2 && P.tri)
+    hipLaunchKernelGGL((k_limiter<kEuler2, 3>), dim3(P.E), dim3(kElemBlock), shmem, s, P, u, flags, staged);
   else if (P.eq == kEuler2)
     hipLaunchKernelGGL((k_limiter<kEuler2, 2>), dim3(P.E), dim3(kElemBlock), shmem, s, P, u, flags, staged);
   else
@@ -747,6 +768,11 @@ hipError_t launch_limiter(const KParams& P, double* u, unsigned char* flags, hip
 
 hipError_t launch_sensor_filter(const KParams& P, double* u, unsigned char* flags, hipStream_t s) {
   const size_t shmem = sizeof(double) * (size_t)P.S * P.M * P.nsp;
+  if (P.tri) {
+    if (P.eq != kEuler2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_sensor_filter<kEuler2, 3>), dim3(P.E), dim3(kElemBlock), shmem, s, P, u, flags);
+    return hipGetLastError();
+  }
   FRSG_DISPATCH_EQ(P.eq, {
     constexpr int DIM = EQ == kEuler2 ? 2 : 1;
     hipLaunchKernelGGL((k_sensor_filter<EQ, DIM>), dim3(P.E), dim3(kElemBlock), shmem, s, P, u, flags);

@@ -209,6 +209,8 @@ bool build_tri_tables(const fr_sg_problem& P, TriTables& T, std::string& err) {
     }
   // mode (0, 0) is first and equals 1: the element mean is its coefficient
   T.mean_w.assign(Vi.begin(), Vi.begin() + n);
+  T.V = V;
+  T.Vinv = Vi;
 
   // mesh: orientation, links, boundary kinds; per-element geometry
   const int E = P.n_tri;
@@ -271,6 +273,35 @@ bool build_tri_tables(const fr_sg_problem& P, TriTables& T, std::string& err) {
     }
   }
   return true;
+}
+
+// Sensor shell, filter factors and element-mean weights for triangles, in place of
+// the tensor-product ones: a mode of the orthonormal basis carries its total
+// degree d (i + j of psi_ij) where a quadrilateral mode carries one degree per
+// direction.  Exponential: exponent (d/p)^s + (|k|/N_c)^s; L2: 1 / (1 + d^2 (d+1)^2
+// / (eps1 p^2 (p+1)^2) + |k|^2 (|k|+1)^2 / (eps2 N_c^2 (N_c+1)^2)); shell: d = p or
+// |k| = N_c; element mean: the coefficient of psi_00 (= 1).
+void tri_filter_tables(const fr_sg_problem& P, const TriTables& R, HostTables& T) {
+  const int p = R.p, n = R.np, Nc = P.gpc_order;
+  std::vector<int> deg;
+  for (int i = 0; i <= p; ++i)
+    for (int j = 0; i + j <= p; ++j) deg.push_back(i + j);
+  T.filt.assign((size_t)T.M * n, 1.0);
+  T.shell.assign((size_t)T.M * n, 0.0);
+  const double a1 = 1.0 / (P.eps1 * (p + 1.0) * (p + 1.0) * p * p);
+  const double a2 = (Nc > 0) ? 1.0 / (P.eps2 * Nc * Nc * (Nc + 1.0) * (Nc + 1.0)) : 0.0;
+  for (int k = 0; k < T.M; ++k) {
+    const int kk = T.kdeg[k];
+    for (int m = 0; m < n; ++m) {
+      const int d = deg[m];
+      T.shell[k * n + m] = (d == p || kk == Nc) ? 1.0 : 0.0;
+      if (P.filter == FRSG_FILTER_EXP)
+        T.filt[k * n + m] = std::pow((double)d / p, P.s) + ((Nc > 0) ? std::pow((double)kk / Nc, P.s) : 0.0);
+      else if (P.filter == FRSG_FILTER_L2)
+        T.filt[k * n + m] = 1.0 / (1.0 + a1 * d * d * (d + 1.0) * (d + 1.0) + a2 * kk * kk * (kk + 1.0) * (kk + 1.0));
+    }
+  }
+  T.swts = R.mean_w;
 }
 
 }  // namespace frsg

@@ -233,6 +233,16 @@ def tri_vortex(n, p=3, perturb=0.1, seed=1):
         filter="none", limiter=False, cfl=0.3, t_end=0.1)
 
 
+def tri_shock_vortex(n, p=3, perturb=0.1, seed=2):
+    """The shock-vortex problem of Sec. 5.4 as set up on quadrilaterals (Mach 1.1 shock at
+    x = 0.5, vortex, left Dirichlet, right outflow, top and bottom reflect, L2 filter
+    switched by the detector, positivity limiter) on 2 (2n) n triangles of [0, 2] x [0, 1]
+    (a seeded perturbation of a split 2n x n grid), FR degree p."""
+    return dict(SHOCK_VORTEX, name="tri_shock_vortex", element="tri", nx=1, ny=1, p=p,
+                mesh=tri_mesh_rectangle(2 * n, n, 0.0, 2.0, 0.0, 1.0, periodic=(False, False), perturb=perturb,
+                                        seed=seed))
+
+
 def tri_density_wave(n, p=2, perturb=0.15, seed=7, gpc_order=3, nq1d=4):
     """Density wave rho = 1 + 0.2 sin(2 pi (x + y)) carried by the velocity
     (1 + 0.1 z, 0.5) at unit pressure, periodic unit square, 2 n^2 perturbed

@@ -119,12 +119,13 @@ def _tri_problem(**over):
 
 @pytest.mark.parametrize("over,status", [
     (dict(equation="burgers"), -2),
-    (dict(filter="exp"), -2),
-    (dict(limiter=True), -2),
+    (dict(filter="lasso"), -2),
     (dict(p=5), -2),
 ])
 def test_tri_unsupported_combinations(lib, over, status):
+    from paper_2112_05946_amd import binding
     P, _ = _tri_problem(**over)
+    assert P.precision == binding.PRECISION["fp64"]
     st, ctx, msg = _init(lib, P)
     assert st == status, msg
     assert not ctx.value and msg
@@ -156,3 +157,10 @@ def test_tri_invalid_meshes_rejected_before_launch(lib):
     P.n_tri = 0
     st, ctx, msg = _init(lib, P)
     assert st == -1
+
+
+def test_tri_fp32_mixed_unsupported(lib):
+    from paper_2112_05946_amd import binding, inputs
+    P = binding.problem_from_config(inputs.tri_density_wave(3), precision="fp32")
+    st, ctx, msg = _init(lib, P)
+    assert st == -2 and "FP32" in msg

@@ -166,3 +166,67 @@ def test_tri_vortex_full_size_sampled_and_properties():
     dtd, _ = sol.step(u)
     sol.sync()
     assert np.isfinite(to_np(u)).all() and to_np(dtd)[0] > 0
+
+
+# ----------------------------------------------------------------------------
+# sensor, filters and positivity limiter on triangles
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("label,cfg,seed", [
+    ("p3_m6q9", _cfg(4, 3, rdim=2), 31),
+    ("p2_m3q3", _cfg(5, 2, m=4), 32),
+])
+def test_tri_limiter_fuzz(label, cfg, seed):
+    announce("tri_limiter", label)
+    from oracle import stabilize as ost
+    cfg = dict(cfg, limiter=True)
+    prob = Problem.from_config(cfg)
+    T, R = build_tables(prob)
+    u = inputs.fuzz_euler(2, R.M, prob.E, T.n, seed=seed, vacuum_frac=0.3)
+    ref, rflags = ost.limit(prob, T, R, u)
+    sol = solver_for(cfg)
+    ud = to_dev(u)
+    import torch
+    flags = torch.zeros(prob.E, dtype=torch.uint8, device=ud.device)
+    sol.limit(ud, flags)
+    sol.sync()
+    g = to_np(flags).astype(bool)
+    assert rflags.sum() >= 5
+    assert rel_l2(to_np(ud), ref) < RTOL_FP64
+    mism = np.nonzero(g != rflags)[0]
+    if len(mism):
+        m, scale = ost.limiter_margin(prob, T, R, u)
+        assert np.all(np.abs(m[mism]) / scale[mism] <= 1e-12)
+
+
+TRI_STAB = [
+    ("fused_sv_p3_l2_detector", dict(inputs.tri_shock_vortex(4), gpc_order=2, nq1d=3)),
+    ("multipass_sv_p2_l2", dict(inputs.tri_shock_vortex(4, p=2), gpc_order=2, nq1d=3, rdim=1)),
+    ("fused_sv_p3_exp_always_hll", dict(inputs.tri_shock_vortex(3), gpc_order=2, nq1d=3, filter="exp",
+                                        sensor="always", alpha=36.0, s=8.0, flux="hll")),
+    ("fused_sv_p3_rk4", dict(inputs.tri_shock_vortex(3), gpc_order=2, nq1d=3, integrator="rk4")),
+]
+
+
+@pytest.mark.parametrize("label,cfg", TRI_STAB)
+def test_tri_steps_with_filter_and_limiter(label, cfg):
+    announce("tri_stab_steps", label)
+    from gpu_util import check_flags
+    prob = Problem.from_config(cfg)
+    T, R = build_tables(prob)
+    u = project_initial(prob, cfg["ic"], (T, R))
+    sol = solver_for(cfg)
+    ud = to_dev(u)
+    fired = 0
+    for i in range(4):
+        record = []
+        u, rdt, rflags = ostep.step(prob, u, None, (T, R), record=record)
+        dtd, flags = sol.step(ud)
+        sol.sync()
+        g = to_np(flags).reshape(4, prob.E)
+        assert abs(to_np(dtd)[0] / rdt - 1.0) < 1e-13, (i, to_np(dtd)[0], rdt)
+        if cfg.get("integrator", "ssprk3") == "ssprk3":
+            check_flags(prob, T, R, g, rflags, record)
+        fired += int(rflags[2].sum()) + int(rflags[3].sum()) + int(rflags[0].sum())
+        assert rel_l2(to_np(ud), u) < RTOL_FP64, (i, rel_l2(to_np(ud), u))
+    assert fired > 0
