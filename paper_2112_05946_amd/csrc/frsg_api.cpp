@@ -637,6 +637,8 @@ fr_sg_status fr_sg_limit(fr_sg_ctx* ctx, double* u, uint8_t* flags) {
     return timed(ctx, "limiter", 2 * state_bytes(ctx), [&] {
       return launch_fused_post(ctx->kp, ctx->dPhiT, ctx->dcmax, u, 0, 1, nullptr, flags, ctx->stream);
     });
+  if (ctx->prob.limiter && ctx->fused_tri)
+    return timed(ctx, "limiter", 2 * state_bytes(ctx), [&] { return launch_limit_tri(ctx->kp, u, flags, ctx->stream); });
   if (ctx->prob.limiter)
     return timed(ctx, "limiter", 2 * state_bytes(ctx), [&] { return launch_limiter(ctx->kp, u, flags, ctx->stream); });
   if (flags) FRSG_TRY_HIP(launch_fill_flags(flags, ctx->E, ctx->stream), ctx);

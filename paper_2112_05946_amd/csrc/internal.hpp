@@ -259,6 +259,8 @@ hipError_t launch_cfl_tri(const KParams& P, const double* Un, hipStream_t s);
 bool tri_fused_supported(const KParams& P);
 hipError_t launch_stage_tri(const KParams& P, const double* in, const double* u, const double* w, double* out,
                             double cu, double cw, int rhs_only, double* Tm, hipStream_t s);
+// positivity limiter on triangles with the fused lane layout (fused (p, M, N_q) set)
+hipError_t launch_limit_tri(const KParams& P, double* u, unsigned char* flags, hipStream_t s);
 // CFL maximum of a modal state on triangles into P.lam_bits
 hipError_t launch_cfl_tri_modal(const KParams& P, const double* u, hipStream_t s);
 // explicit Runge-Kutta stage combination: out = u + dt sum_j a[j] K[j] (flat state of n doubles)

@@ -494,6 +494,189 @@ __global__ void __launch_bounds__(256) k_cfl_tri_mq(KParams P, const double* __r
   if (threadIdx.x == 0) atomicMax(P.lam_bits, (unsigned long long)__double_as_longlong(sm[0]));
 }
 
+// Positivity limiter (Sec. 4.3) on triangles with the stage kernel's lane layout:
+// lane (slot, s) keeps the coefficients of variable s at solution point `slot` and,
+// as a flux-point lane, their interpolation to flux point `slot`.  The decision
+// first uses rigorous bounds per point (|Phi_k(z_q)| <= cmax_k, a relative margin
+// of 1e-10 for their rounding); only blocks holding an element whose bound fails
+// run the node-by-node minimum and the pressure roots, so the decision is the
+// node-by-node one.  The element mean is the coefficient of the constant mode.
+template <int PD, int M, int NQ>
+__global__ void __launch_bounds__(256) k_limit_tri(KParams P, double* __restrict__ u,
+                                                   unsigned char* __restrict__ flags) {
+  using Sh = TriShape<PD>;
+  constexpr int NPT = Sh::NPT, NF = Sh::NF, EPB = Sh::EPB;
+  __shared__ double sC[EPB][4][M][NPT];
+  __shared__ double sRed[EPB][4][2];   // per element: variable means; then rho_min, p_min
+  __shared__ int sNeed[EPB], sAny;
+  __shared__ double sMin[EPB][Sh::TPE];
+  const int E = P.E;
+  const int el = threadIdx.x / Sh::TPE;
+  const int rem = threadIdx.x % Sh::TPE;
+  const int slot = rem >> 2, s = rem & 3;
+  const int e = blockIdx.x * EPB + el;
+  const bool active = el < EPB && e < E;
+  const int le = active ? el : 0;
+  const bool pt = active && slot < NPT;
+  const bool fp = active && slot < NF;
+  const long EN = (long)E * NPT;
+  if (threadIdx.x < EPB) sNeed[threadIdx.x] = 0;
+  if (threadIdx.x == 0) sAny = 0;
+  double c[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    c[k] = pt ? u[((long)s * M + k) * EN + (long)e * NPT + slot] : 0.0;
+    if (pt) sC[le][s][k][slot] = c[k];
+  }
+  __syncthreads();
+  // element means of the four variables (every lane, from LDS)
+  double ub[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) acc += sC[le][v][0][j] * P.tab.swts[j];
+    ub[v] = acc;
+  }
+  const double pb = (P.gamma - 1.0) * (ub[3] - 0.5 * (ub[1] * ub[1] + ub[2] * ub[2]) / ub[0]);
+  const bool real = ub[0] > 0.0 && pb > 0.0 && isfinite(ub[0]) && isfinite(ub[1]) && isfinite(ub[2]) &&
+                    isfinite(ub[3]);
+  const double eps = fmin(1e-8, fmin(ub[0], pb));
+  // flux-point lanes: interpolate all modes to their flux point
+  double a[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    double acc = 0.0;
+    if (fp) {
+#pragma unroll
+      for (int j = 0; j < NPT; ++j) acc += P.tri_Lf[slot * NPT + j] * sC[le][s][k][j];
+    }
+    a[k] = acc;
+  }
+  // rigorous bounds at the solution point and the flux point of this lane
+  auto bound_ok = [&](const double* coef, bool on) {
+    double mn = coef[0], vr = 0.0;
+#pragma unroll
+    for (int k = 1; k < M; ++k) vr += fabs(coef[k]) * P.tab.cmax[k];
+    double MN[4], VR[4];
+    quad_gather(mn, MN);
+    quad_gather(vr, VR);
+    if (!on) return true;
+    const double rlo = MN[0] - VR[0];
+    const double tol_r = 1e-10 * (fabs(MN[0]) + VR[0]);
+    if (!(rlo > eps + tol_r)) return false;
+    double m2 = 0.0;
+#pragma unroll
+    for (int v = 1; v < 3; ++v) {
+      const double mx = fabs(MN[v]) + VR[v];
+      m2 += mx * mx;
+    }
+    const double ke = 0.5 * m2 / rlo;
+    const double elo = MN[3] - VR[3];
+    const double plo = (P.gamma - 1.0) * (elo - ke);
+    const double tol_p = 1e-10 * (P.gamma - 1.0) * (fabs(MN[3]) + VR[3] + ke);
+    return plo > eps + tol_p;
+  };
+  const bool ok_sp = bound_ok(c, pt && real);
+  const bool ok_fp = bound_ok(a, fp && real);
+  if (active && real && !(ok_sp && ok_fp)) {
+    sNeed[le] = 1;
+    sAny = 1;
+  }
+  if (active && !real && slot == 0 && s == 0) atomicOr(P.status, kStatusNotRealizable);
+  __syncthreads();
+  if (sAny) {
+    const bool need = active && real && sNeed[le];
+    // node-by-node minima of density and pressure over solution and flux points
+    double rmin = INFINITY, pmin = INFINITY;
+    for (int q = 0; q < NQ; ++q) {
+      double vs = 0.0, vf = 0.0;
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        const double ph = P.tab.Phi[k * NQ + q];
+        vs += ph * c[k];
+        vf += ph * a[k];
+      }
+      double Us[4], Uf[4];
+      quad_gather(vs, Us);
+      quad_gather(vf, Uf);
+      if (need && pt) {
+        rmin = fmin(rmin, Us[0]);
+        pmin = fmin(pmin, (P.gamma - 1.0) * (Us[3] - 0.5 * (Us[1] * Us[1] + Us[2] * Us[2]) / Us[0]));
+      }
+      if (need && fp) {
+        rmin = fmin(rmin, Uf[0]);
+        pmin = fmin(pmin, (P.gamma - 1.0) * (Uf[3] - 0.5 * (Uf[1] * Uf[1] + Uf[2] * Uf[2]) / Uf[0]));
+      }
+    }
+    if (active) sMin[le][rem] = rmin;
+    __syncthreads();
+    if (active && rem == 0) {
+      double r = INFINITY;
+      for (int i = 0; i < Sh::TPE; ++i) r = fmin(r, sMin[le][i]);
+      sRed[le][0][0] = r;
+    }
+    __syncthreads();
+    if (active) sMin[le][rem] = pmin;
+    __syncthreads();
+    if (active && rem == 0) {
+      double r = INFINITY;
+      for (int i = 0; i < Sh::TPE; ++i) r = fmin(r, sMin[le][i]);
+      sRed[le][0][1] = r;
+    }
+    __syncthreads();
+    const double Rmin = sRed[le][0][0], Pmin = sRed[le][0][1];
+    const bool act = need && fmin(Rmin, Pmin) < eps;
+    const double beta1 = (Rmin >= eps) ? 1.0 : (ub[0] - eps) / (ub[0] - Rmin);
+    // beta2: smallest root over the points whose pressure stays below eps after beta1
+    double bmin = 1.0;
+    for (int q = 0; q < NQ; ++q) {
+      double vs = 0.0, vf = 0.0;
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        const double ph = P.tab.Phi[k * NQ + q];
+        vs += ph * c[k];
+        vf += ph * a[k];
+      }
+      double Us[4], Uf[4];
+      quad_gather(vs, Us);
+      quad_gather(vf, Uf);
+      if (act && pt) {
+        Us[0] = beta1 * (Us[0] - ub[0]) + ub[0];
+        if ((P.gamma - 1.0) * (Us[3] - 0.5 * (Us[1] * Us[1] + Us[2] * Us[2]) / Us[0]) < eps)
+          bmin = fmin(bmin, pressure_root<kEuler2>(ub, Us, eps, P.gamma));
+      }
+      if (act && fp) {
+        Uf[0] = beta1 * (Uf[0] - ub[0]) + ub[0];
+        if ((P.gamma - 1.0) * (Uf[3] - 0.5 * (Uf[1] * Uf[1] + Uf[2] * Uf[2]) / Uf[0]) < eps)
+          bmin = fmin(bmin, pressure_root<kEuler2>(ub, Uf, eps, P.gamma));
+      }
+    }
+    if (active) sMin[le][rem] = bmin;
+    __syncthreads();
+    if (active && rem == 0) {
+      double r = 1.0;
+      for (int i = 0; i < Sh::TPE; ++i) r = fmin(r, sMin[le][i]);
+      sRed[le][1][0] = r;
+    }
+    __syncthreads();
+    const double beta2 = sRed[le][1][0];
+    if (act && pt) {
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        const double m0 = (k == 0) ? 1.0 : 0.0;
+        double v = c[k];
+        if (s == 0) v = beta1 * (v - ub[0] * m0) + ub[0] * m0;
+        v = beta2 * (v - pick4(ub, s) * m0) + pick4(ub, s) * m0;
+        u[((long)s * M + k) * EN + (long)e * NPT + slot] = v;
+      }
+    }
+    if (active && rem == 0 && flags) flags[e] = act ? 1 : 0;
+    return;
+  }
+  if (active && rem == 0 && flags) flags[e] = 0;
+}
+
 template <int PD, int M, int NQ>
 hipError_t go_stage_tri(const KParams& P, const double* in, const double* u, const double* w, double* out, double cu,
                         double cw, int rhs_only, const double* Tm, hipStream_t s) {
@@ -519,6 +702,20 @@ hipError_t dispatch_mq(const KParams& P, const double* in, const double* u, cons
 
 }  // namespace
 
+template <int PD>
+hipError_t dispatch_limit(const KParams& P, double* u, unsigned char* flags, hipStream_t s) {
+  using Sh = TriShape<PD>;
+  const unsigned grid = (unsigned)((P.E + Sh::EPB - 1) / Sh::EPB);
+#define FRSG_TRI_LIM(MM, QQ)                                                                        \
+  if (P.M == MM && P.Nq == QQ) {                                                                     \
+    hipLaunchKernelGGL((k_limit_tri<PD, MM, QQ>), dim3(grid), dim3(256), 0, s, P, u, flags);         \
+    return hipGetLastError();                                                                        \
+  }
+  FRSG_TRI_LIM(15, 25) FRSG_TRI_LIM(10, 16) FRSG_TRI_LIM(6, 9) FRSG_TRI_LIM(5, 5) FRSG_TRI_LIM(3, 4)
+#undef FRSG_TRI_LIM
+  return hipErrorInvalidValue;
+}
+
 bool tri_fused_supported(const KParams& P) {
   if (P.eq != FRSG_EULER2D || P.nfp < 2 || P.nfp > 5) return false;
   const int mq[5][2] = {{15, 25}, {10, 16}, {6, 9}, {5, 5}, {3, 4}};
@@ -537,6 +734,18 @@ hipError_t launch_stage_tri(const KParams& P, const double* in, const double* u,
     case 2: return dispatch_mq<2>(P, in, u, w, out, cu, cw, rhs_only, Tm, s);
     case 3: return dispatch_mq<3>(P, in, u, w, out, cu, cw, rhs_only, Tm, s);
     case 4: return dispatch_mq<4>(P, in, u, w, out, cu, cw, rhs_only, Tm, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// positivity limiter in place with the fused lane layout (the fused (p, M, N_q) set)
+hipError_t launch_limit_tri(const KParams& P, double* u, unsigned char* flags, hipStream_t s) {
+  if (!tri_fused_supported(P)) return hipErrorInvalidValue;
+  switch (P.nfp - 1) {
+    case 1: return dispatch_limit<1>(P, u, flags, s);
+    case 2: return dispatch_limit<2>(P, u, flags, s);
+    case 3: return dispatch_limit<3>(P, u, flags, s);
+    case 4: return dispatch_limit<4>(P, u, flags, s);
     default: return hipErrorInvalidValue;
   }
 }
