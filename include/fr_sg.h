@@ -30,9 +30,11 @@
  * time-step buffer.  The library owns the context, its operator tables and a
  * workspace allocated once by fr_sg_init (two stage states plus nodal
  * scratch, or, on the fused 2D path, two buffers of modal face traces on
- * tile boundaries that each stage launch writes for the next; fr_sg_query
- * reports its size) and freed by fr_sg_destroy.  No other call allocates
- * device memory.
+ * tile boundaries that each stage launch writes for the next, or, on the
+ * fused triangle path, one buffer of modal traces at the flux points; the
+ * tableau integrators add one right-hand-side buffer per stage; triangle
+ * meshes add their geometry and neighbour table; fr_sg_query reports its
+ * size) and freed by fr_sg_destroy.  No other call allocates device memory.
  *
  * Errors: invalid or unsupported problems are rejected by fr_sg_init before
  * any launch.  Non-finite or non-realizable states met on the device are
@@ -141,9 +143,14 @@ typedef int32_t fr_sg_status;
  *                         faces); links must be mutual.
  * Reflection mirrors the velocity about the face.  CFL step:
  * dt = cfl / ((p+1) max(lambda / d_e)) with lambda = |v| + c over the nodes
- * and points of element e and d_e its inscribed-circle diameter.  Not yet
- * available on triangles: filters, the limiter, FP32-mixed, the adjoint
- * (fr_sg_init returns FRSG_EUNSUPPORTED). */
+ * and points of element e and d_e its inscribed-circle diameter.  Shock
+ * capturing (Sec. 4) on triangles: a mode of the orthonormal triangle basis
+ * carries its total degree d; the detector's outer shell is d = p or
+ * |k| = N_c, the exponential filter exponent (d/p)^s + (|k|/N_c)^s, the L2
+ * penalty d^2 (d+1)^2 / (eps1 p^2 (p+1)^2) plus the chaos term; the limiter
+ * tests the solution and flux points at every node.  Not available on
+ * triangles: the Lasso filter, FP32-mixed, the adjoint (fr_sg_init returns
+ * FRSG_EUNSUPPORTED; fr_sg_adjoint_step too). */
 #define FRSG_ELEM_QUAD 0
 #define FRSG_ELEM_TRI 1
 
