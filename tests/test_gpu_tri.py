@@ -46,6 +46,20 @@ RHS_CASES = [
 ]
 
 
+def _single_triangle(p, gpc=2, nq=3, rdim=1):
+    """One triangle whose three faces are boundary faces (Dirichlet, outflow, reflect)."""
+    mesh = dict(xy=np.array([[[0.1, 0.0], [1.0, 0.2], [0.3, 0.9]]]), nbr=np.array([[-1, -2, -3]], dtype=np.int32),
+                nbr_face=np.full((1, 3), -1, dtype=np.int32))
+    cfg = _cfg(1, p, bounded=True, gpc=gpc, nq=nq, rdim=rdim)
+    return dict(cfg, mesh=mesh)
+
+
+RHS_CASES += [
+    ("single_triangle_multipass", _single_triangle(2)),
+    ("single_triangle_fused_p4", _single_triangle(4, gpc=2, nq=3, rdim=2)),
+]
+
+
 @pytest.mark.parametrize("label,cfg", RHS_CASES)
 def test_tri_rhs_fuzz(label, cfg):
     announce("tri_rhs", label)
