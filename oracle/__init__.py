@@ -17,13 +17,18 @@ stochastic Galerkin scheme for hyperbolic conservation laws" (arXiv
 * Sec. 4 (Eq. modal solution, Eq. vandermonde matrix): nodal/modal transform;
 * Sec. 4.1.1-4.1.2: exponential and L2 filters;
 * Sec. 4.2 (Eq. detector): modal-decay discontinuity sensor;
-* Sec. 4.3 (Eq. schemefullDiscr): positivity-preserving slope limiter.
+* Sec. 4.1.3: Lasso filter with automatic strengths;
+* Sec. 4.3 (Eq. schemefullDiscr): positivity-preserving slope limiter;
+* Sec. 3.3 and Tables 5-6: Lax-Friedrichs and HLL interactive fluxes;
+* Sec. 3.1 and 3.5 on triangles (``tri.py``): reference triangle, vector
+  correction fields, unstructured meshes.
 
-The paper integrates in time with RK4 / Tsitouras / Bogacki-Shampine; this
-oracle uses the three-stage strong-stability-preserving Runge-Kutta scheme of
-Shu and Osher, with the limiter after each stage and the sensor-gated filter
-at the end of the step (the paper's forward-Euler ordering "limit, update,
-filter", Eq. schemefullDiscr, applied stage-wise).
+Time integration: the three-stage strong-stability-preserving Runge-Kutta
+scheme of Shu and Osher, with the limiter after each stage and the
+sensor-gated filter at the end of the step (the paper's forward-Euler ordering
+"limit, update, filter", Eq. schemefullDiscr, applied stage-wise), or the
+paper's RK4, Tsitouras 5(4) and Bogacki-Shampine 3(2) tableaux at the same
+CFL step.
 
 Everything is float64 NumPy.  Functions that no independent pin checks carry
 the words "parity unpinned" in their docstring.
