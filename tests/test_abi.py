@@ -164,3 +164,14 @@ def test_tri_fp32_mixed_unsupported(lib):
     P = binding.problem_from_config(inputs.tri_density_wave(3), precision="fp32")
     st, ctx, msg = _init(lib, P)
     assert st == -2 and "FP32" in msg
+
+
+@pytest.mark.parametrize("over,status", [
+    (dict(gpc_order=128, nq1d=129), -2),          # 129 modes
+    (dict(rdim=2, gpc_order=10, nq1d=17), -2),    # 289 nodes
+])
+def test_chaos_limits(lib, over, status):
+    from paper_2112_05946_amd import binding, inputs
+    P = binding.problem_from_config(dict(inputs.BURGERS, **over))
+    st, ctx, msg = _init(lib, P)
+    assert st == status and "too many" in msg
