@@ -46,6 +46,16 @@ __device__ __forceinline__ void flux_n(int kind, const double* L, const double* 
   }
 }
 
+// 1/x: hardware estimate and two Newton steps (full double accuracy for the
+// positive densities it is applied to)
+__device__ __forceinline__ double rcp2(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 // a[s] for a run-time s without indexing a private array
 __device__ __forceinline__ double pick4(const double* a, int s) {
   return s == 0 ? a[0] : (s == 1 ? a[1] : (s == 2 ? a[2] : a[3]));
@@ -55,7 +65,7 @@ __device__ __forceinline__ double pick4(const double* a, int s) {
 // density per side (the fused kernel's lanes each produce one conserved variable)
 __device__ __forceinline__ double flux_n_comp(int kind, const double* L, const double* R, double nx, double ny,
                                               double gamma, int s) {
-  const double iL = 1.0 / L[0], iR = 1.0 / R[0];
+  const double iL = rcp2(L[0]), iR = rcp2(R[0]);
   const double uL = (L[1] * nx + L[2] * ny) * iL, uR = (R[1] * nx + R[2] * ny) * iR;
   const double pL = (gamma - 1.0) * (L[3] - 0.5 * (L[1] * L[1] + L[2] * L[2]) * iL);
   const double pR = (gamma - 1.0) * (R[3] - 0.5 * (R[1] * R[1] + R[2] * R[2]) * iR);
@@ -358,7 +368,7 @@ __global__ void __launch_bounds__(256) k_stage_tri(KParams P, const double* __re
     double U[4];
     quad_gather(v, U);
     if (pt) {
-      const double ir = 1.0 / U[0];
+      const double ir = rcp2(U[0]);
       const double vx = U[1] * ir, vy = U[2] * ir;
       const double p = (P.gamma - 1.0) * (U[3] - 0.5 * (U[1] * vx + U[2] * vy));
       double Fs, Gs;
