@@ -214,6 +214,32 @@ def convergence_study():
     return out
 
 
+def precision_at_horizon(torch, Solver, cfg, rel, std):
+    """FP32-mixed against FP64 at the workload's end time: both run the same number of CFL
+    steps from the same initial state, as many as FP64 needs to reach t_end; relative L2
+    distance of the modal state, of E[u] (mode 0) and of Std[u]."""
+    states, times = {}, {}
+    nsteps = None
+    for prec in ("fp64", "fp32"):
+        sol = Solver(cfg, precision=prec)
+        u = sol.initial_state()
+        dts = torch.empty(10, dtype=torch.float64, device=u.device)
+        t, n = 0.0, 0
+        while (nsteps is None and t < cfg["t_end"]) or (nsteps is not None and n < nsteps):
+            k = 10 if nsteps is None else min(10, nsteps - n)
+            sol.steps(u, k, dts)
+            t += float(dts[:k].sum())
+            n += k
+        sol.sync()
+        nsteps = n
+        states[prec], times[prec] = u, t
+        sol.close()
+    a, b = states["fp32"], states["fp64"]
+    return {"t_end": cfg["t_end"], "steps": nsteps, "t_fp64": times["fp64"], "t_fp32": times["fp32"],
+            "rel_l2_vs_fp64": rel(a, b), "rel_l2_mean_vs_fp64": rel(a[:, 0], b[:, 0]),
+            "rel_l2_std_vs_fp64": rel(std(a), std(b))}
+
+
 def adjoint_cost(torch, Solver, inputs):
     """Adjoint/forward cost on the 4096-element Burgers problem (p = 3, 9 modes, 16 nodes):
     500 steps at the CFL step of the initial state, held fixed."""
@@ -278,6 +304,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-mixed comparison run")
+    ap.add_argument("--no-horizon", action="store_true",
+                    help="skip the FP32-mixed against FP64 comparison at the workload's end time")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost run")
     ap.add_argument("--no-others", action="store_true", help="skip the 1D workloads")
     ap.add_argument("--no-convergence", action="store_true", help="skip the wave-propagation convergence study")
@@ -337,6 +365,8 @@ def main():
                  "roofline": roofline_for(p32, "fp32"),
                  "passes_ms_per_step": {k: v[1] / args.steps for k, v in p32.items()}}
         sol32.close()
+        if not args.no_horizon:
+            other["at_t_end"] = precision_at_horizon(torch, Solver, cfg, rel, std)
 
     adjoint = None if args.no_adjoint else adjoint_cost(torch, Solver, inputs)
     others = None if args.no_others else other_workloads(torch, Solver, inputs, 200)
