@@ -96,3 +96,18 @@ def test_random_modes_follow_the_exact_solution():
     _, u = oracle_wave_errors(3, 16)
     assert np.max(np.abs(u[0, 1] - 0.1 / math.sqrt(3.0) * u[0, 0])) < 1e-13
     assert np.max(np.abs(u[0, 2:])) < 1e-13
+
+
+def test_harness_step_rule_and_norms():
+    """The GPU harness's host helpers: the step count and size that land on t = 2 at
+    dt = 0.1 dx, and the dx-weighted norms of the expectation's error."""
+    from paper_2112_05946_amd.convergence import wave_norms, wave_steps
+    for nx in (4, 8, 16, 32, 64):
+        n, dt = wave_steps(nx)
+        assert n == 10 * nx and abs(dt - 0.2 / nx) < 1e-15
+    x = np.linspace(-0.9, 0.9, 12).reshape(4, 3)
+    e = 1e-3 * np.cos(x)
+    l1, l2, li = wave_norms(np.sin(np.pi * (x - 2.0)) + e, x, 2.0, 0.5)
+    assert abs(l1 - 0.5 * np.abs(e).sum()) < 1e-15
+    assert abs(l2 - 0.5 * math.sqrt(np.sum(e * e))) < 1e-15
+    assert abs(li - 0.5 * np.abs(e).max()) < 1e-15
