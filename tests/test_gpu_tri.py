@@ -244,3 +244,20 @@ def test_tri_steps_with_filter_and_limiter(label, cfg):
         fired += int(rflags[2].sum()) + int(rflags[3].sum()) + int(rflags[0].sum())
         assert rel_l2(to_np(ud), u) < RTOL_FP64, (i, rel_l2(to_np(ud), u))
     assert fired > 0
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_tri_rhs_seed_sweep(seed):
+    """Seeds 0-9 of the fuzz states on both triangle paths (fused: 6 modes, 9 nodes;
+    multi-pass: 3 modes, 3 nodes), fresh perturbed meshes per seed."""
+    announce("tri_seed", seed)
+    for cfg in (_cfg(4, 3, rdim=2, seed=seed), _cfg(3, 2, flux="hll", bounded=True, seed=seed, m=4)):
+        prob = Problem.from_config(cfg)
+        T, R = build_tables(prob)
+        u = inputs.fuzz_euler(2, R.M, prob.E, T.n, seed=100 + seed)
+        ref = otri.rhs_tri(prob, T, R, u)
+        sol = solver_for(cfg)
+        got = to_np(sol.rhs(to_dev(u)))
+        sol.sync()
+        assert rel_l2(got, ref) < RTOL_FP64, (seed, rel_l2(got, ref))
+        sol.close()
