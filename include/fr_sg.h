@@ -31,7 +31,7 @@
  * workspace allocated once by fr_sg_init (two stage states plus nodal
  * scratch, or, on the fused 2D path, two buffers of modal face traces on
  * tile boundaries that each stage launch writes for the next, or, on the
- * fused triangle path, one buffer of modal traces at the flux points; the
+ * fused triangle path, two buffers of modal traces at the flux points; the
  * tableau integrators add one right-hand-side buffer per stage; triangle
  * meshes add their geometry and neighbour table; fr_sg_query reports its
  * size) and freed by fr_sg_destroy.  No other call allocates device memory.

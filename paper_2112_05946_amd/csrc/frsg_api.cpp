@@ -462,7 +462,8 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
   const int nrk = tab_rk ? tab_rk->s : 0;
   size_t o_rk = align_up(o_tr1 + ntr * 8);
   size_t o_tm = align_up(o_rk + (size_t)nrk * align_up(state * 8));
-  size_t total = align_up(o_tm + ntm * 8);
+  size_t o_tm1 = align_up(o_tm + ntm * 8);
+  size_t total = align_up(o_tm1 + ntm * 8);
   char* ws = nullptr;
   he = hipMalloc(&ws, total);
   if (he != hipSuccess) {
@@ -500,7 +501,10 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
     c->ws.apart = (double*)(ws + o_apt);
   }
   for (int i = 0; i < nrk; ++i) c->ws.rk[i] = (double*)(ws + o_rk + (size_t)i * align_up(state * 8));
-  if (ntm) c->ws.Tm = (double*)(ws + o_tm);
+  if (ntm) {
+    c->ws.Tm[0] = (double*)(ws + o_tm);
+    c->ws.Tm[1] = (double*)(ws + o_tm1);
+  }
   if (ntr) {
     c->ws.tr[0] = (double*)(ws + o_tr0);
     c->ws.tr[1] = (double*)(ws + o_tr1);
@@ -638,7 +642,8 @@ fr_sg_status fr_sg_limit(fr_sg_ctx* ctx, double* u, uint8_t* flags) {
       return launch_fused_post(ctx->kp, ctx->dPhiT, ctx->dcmax, u, 0, 1, nullptr, flags, ctx->stream);
     });
   if (ctx->prob.limiter && ctx->fused_tri)
-    return timed(ctx, "limiter", 2 * state_bytes(ctx), [&] { return launch_limit_tri(ctx->kp, u, flags, ctx->stream); });
+    return timed(ctx, "limiter", 2 * state_bytes(ctx),
+                 [&] { return launch_limit_tri(ctx->kp, u, flags, nullptr, ctx->stream); });
   if (ctx->prob.limiter)
     return timed(ctx, "limiter", 2 * state_bytes(ctx), [&] { return launch_limiter(ctx->kp, u, flags, ctx->stream); });
   if (flags) FRSG_TRY_HIP(launch_fill_flags(flags, ctx->E, ctx->stream), ctx);
@@ -679,7 +684,7 @@ fr_sg_status fr_sg_rhs(fr_sg_ctx* ctx, const double* u, double* dudt) {
 static fr_sg_status rhs_into(fr_sg_ctx* ctx, const double* u, double* dudt) {
   if (ctx->fused_tri)
     return timed(ctx, "stage_rhs", 2 * state_bytes(ctx), [&] {
-      return launch_stage_tri(ctx->kp, u, u, u, dudt, 0.0, 1.0, 1, ctx->ws.Tm, ctx->stream);
+      return launch_stage_tri(ctx->kp, u, u, u, dudt, 0.0, 1.0, 1, ctx->ws.Tm[0], 0, nullptr, ctx->stream);
     });
   if (ctx->fused) {
     FusedStage S{u,          u,          dudt,         0.0,         1.0,           0,
@@ -697,7 +702,8 @@ static fr_sg_status rhs_into(fr_sg_ctx* ctx, const double* u, double* dudt) {
                [&] { return launch_project_stage(ctx->kp, ctx->ws.Un, u, u, dudt, 0.0, 1.0, 1, ctx->stream); });
 }
 
-static fr_sg_status step_generic(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, uint8_t* flags) {
+static fr_sg_status step_generic(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, uint8_t* flags,
+                                 bool chained = false) {
   const KParams& K = ctx->kp;
   Workspace& W = ctx->ws;
   hipStream_t s = ctx->stream;
@@ -712,28 +718,43 @@ static fr_sg_status step_generic(fr_sg_ctx* ctx, double* u, double dt, double* d
   FRSG_TRY_HIP(launch_set_scalars(K, cfl ? 0.0 : dt, s), ctx);
   const double sb = state_bytes(ctx);
   if (ctx->fused_tri) {
-    // triangles: one fused launch per stage (after its trace pass), the limiter
-    // after each stage and the sensor-gated filter and limiter at the end
+    // triangles: one fused launch per stage, the limiter after each stage and the
+    // sensor-gated filter and limiter at the end.  Each stage writes the modal traces
+    // of its output into the trace buffer its input's traces are not in, and the
+    // limiter and filter rewrite those of the elements they change, so only the first
+    // step of a call runs a trace pass over u (chained: u is the previous step's result)
     if (cfl) {
       if ((st = timed(ctx, "cfl", sb, [&] { return launch_cfl_tri_modal(K, u, s); }))) return st;
       FRSG_TRY_HIP(launch_dt(K, ctx->dim, nullptr, s), ctx);
     }
+    const int c0 = chained ? ctx->tm_cur : 0, c1 = c0 ^ 1;
+    double* T0 = W.Tm[c0];
+    double* T1 = W.Tm[c1];
+    auto lim = [&](double* x, uint8_t* f, double* tm) -> fr_sg_status {
+      if (ctx->prob.limiter)
+        return timed(ctx, "limiter", 2 * sb, [&] { return launch_limit_tri(K, x, f, tm, s); });
+      if (f) FRSG_TRY_HIP(launch_fill_flags(f, E, s), ctx);
+      return FRSG_OK;
+    };
     if ((st = timed(ctx, "stage1", 2 * sb,
-                    [&] { return launch_stage_tri(K, u, u, u, W.w1, 0.0, 1.0, 0, W.Tm, s); })))
+                    [&] { return launch_stage_tri(K, u, u, u, W.w1, 0.0, 1.0, 0, T0, chained ? 1 : 0, T1, s); })))
       return st;
-    if ((st = fr_sg_limit(ctx, W.w1, f0)) != FRSG_OK) return st;
+    if ((st = lim(W.w1, f0, T1)) != FRSG_OK) return st;
     if ((st = timed(ctx, "stage2", 3 * sb,
-                    [&] { return launch_stage_tri(K, W.w1, u, W.w1, W.w2, 0.75, 0.25, 0, W.Tm, s); })))
+                    [&] { return launch_stage_tri(K, W.w1, u, W.w1, W.w2, 0.75, 0.25, 0, T1, 1, T0, s); })))
       return st;
-    if ((st = fr_sg_limit(ctx, W.w2, f1)) != FRSG_OK) return st;
-    if ((st = timed(ctx, "stage3", 3 * sb,
-                    [&] { return launch_stage_tri(K, W.w2, u, W.w2, u, 1.0 / 3.0, 2.0 / 3.0, 0, W.Tm, s); })))
+    if ((st = lim(W.w2, f1, T0)) != FRSG_OK) return st;
+    if ((st = timed(ctx, "stage3", 3 * sb, [&] {
+           return launch_stage_tri(K, W.w2, u, W.w2, u, 1.0 / 3.0, 2.0 / 3.0, 0, T0, 1, T1, s);
+         })))
       return st;
     if (ctx->prob.filter != FRSG_FILTER_NONE) {
-      if ((st = timed(ctx, "sensor_filter", 2 * sb, [&] { return launch_sensor_filter(K, u, f2, s); }))) return st;
+      if ((st = timed(ctx, "sensor_filter", 2 * sb, [&] { return launch_sensor_filter(K, u, f2, s, T1); })))
+        return st;
     } else if (f2)
       FRSG_TRY_HIP(launch_fill_flags(f2, E, s), ctx);
-    if ((st = fr_sg_limit(ctx, u, f3)) != FRSG_OK) return st;
+    if ((st = lim(u, f3, T1)) != FRSG_OK) return st;
+    ctx->tm_cur = c1;
     if (dt_used) FRSG_TRY_HIP(launch_copy_dt(K, dt_used, s), ctx);
     return FRSG_OK;
   }
@@ -1011,7 +1032,7 @@ fr_sg_status fr_sg_steps(fr_sg_ctx* ctx, double* u, int32_t nsteps, double* dt_u
     else if (ctx->fused1d)
       st = step_fused1d(ctx, u, 0.0, dtu, f, i > 0);
     else
-      st = step_generic(ctx, u, 0.0, dtu, f);
+      st = step_generic(ctx, u, 0.0, dtu, f, i > 0);
     if (st != FRSG_OK) return st;
   }
   return FRSG_OK;

@@ -134,7 +134,8 @@ struct Workspace {
   double* Fn = nullptr;    // [S][Nq][E][nsp] nodal x-flux
   double* Gn = nullptr;    // [S][Nq][E][nsp] nodal y-flux (2D)
   double* Corr = nullptr;  // [S][Nq][E][nface] interface-flux minus interpolated flux
-  double* Tm = nullptr;    // fused triangles: modal traces [S][M][E][3 nfp] of the stage input
+  // fused triangles: modal traces [S][M][E][3 nfp] of a stage input, two buffers used in turn
+  double* Tm[2] = {nullptr, nullptr};
   double* scal = nullptr;  // scalars: dt, lam bits, status
   // adjoint (scalar 1D problems): stage adjoints, trace adjoints, partial sums
   double* avb = nullptr;   // adjoint of the unfiltered end-of-step state
@@ -194,6 +195,7 @@ struct fr_sg_ctx {
   int lam_cur = 0;              // which CFL accumulator holds the maximum of the current state
   const double* lam_for = nullptr;  // state whose maximum the previous step recorded (fr_sg_steps)
   int tr_cur = 0;               // fused 2D: which face-trace buffer holds the traces of the current state
+  int tm_cur = 0;               // fused triangles: which trace buffer holds the traces of the current state
   frsg::KParams kp;
   frsg::Workspace ws;
   std::string err;
@@ -245,7 +247,9 @@ hipError_t launch_project_stage(const KParams& P, const double* Rn, const double
                                 double* out, double cu, double cw, int rhs_only, hipStream_t s);
 hipError_t launch_project_ic(const KParams& P, const double* U0, double* u, hipStream_t s);
 hipError_t launch_limiter(const KParams& P, double* u, unsigned char* flags, hipStream_t s);
-hipError_t launch_sensor_filter(const KParams& P, double* u, unsigned char* flags, hipStream_t s);
+// tm (triangles, fused path): also rewrite the modal traces of the filtered elements there
+hipError_t launch_sensor_filter(const KParams& P, double* u, unsigned char* flags, hipStream_t s,
+                                double* tm = nullptr);
 hipError_t launch_fill_flags(unsigned char* flags, long n, hipStream_t s);
 // triangle passes (kernels_tri.hip): interactive-flux jumps [S][Nq][E][3 nfp],
 // nodal residual into Rn, CFL maximum of the nodal values into P.lam_bits
@@ -255,12 +259,15 @@ hipError_t launch_resid_tri(const KParams& P, const double* Fn, const double* Gn
                             hipStream_t s);
 hipError_t launch_cfl_tri(const KParams& P, const double* Un, hipStream_t s);
 // fused triangle stage (p = 1..4 and the (M, Nq) pairs of the fused 2D kernel): a trace pass
-// over `in` into Tm ([S][M][E][3 nfp]), then out = cu u + cw (w + dt R(in)), or R(in) with rhs_only
+// over `in` into Tm ([S][M][E][3 nfp]) unless traces_ready, then out = cu u + cw (w + dt R(in)),
+// or R(in) with rhs_only; with Tm_out the traces of `out` go there
 bool tri_fused_supported(const KParams& P);
 hipError_t launch_stage_tri(const KParams& P, const double* in, const double* u, const double* w, double* out,
-                            double cu, double cw, int rhs_only, double* Tm, hipStream_t s);
+                            double cu, double cw, int rhs_only, double* Tm, int traces_ready, double* Tm_out,
+                            hipStream_t s);
 // positivity limiter on triangles with the fused lane layout (fused (p, M, N_q) set)
-hipError_t launch_limit_tri(const KParams& P, double* u, unsigned char* flags, hipStream_t s);
+// Tm (may be null): rewrite the modal traces of the limited elements there
+hipError_t launch_limit_tri(const KParams& P, double* u, unsigned char* flags, double* Tm, hipStream_t s);
 // CFL maximum of a modal state on triangles into P.lam_bits
 hipError_t launch_cfl_tri_modal(const KParams& P, const double* u, hipStream_t s);
 // explicit Runge-Kutta stage combination: out = u + dt sum_j a[j] K[j] (flat state of n doubles)

@@ -311,12 +311,13 @@ __device__ __forceinline__ void quad_gather(double v, double* all) {
 template <int PD, int M, int NQ>
 __global__ void __launch_bounds__(256) k_stage_tri(KParams P, const double* __restrict__ in, const double* u,
                                                    const double* w, double* out, double cu, double cw, int rhs_only,
-                                                   const double* __restrict__ Tm) {
+                                                   const double* __restrict__ Tm, double* __restrict__ Tm_out) {
   using Sh = TriShape<PD>;
   constexpr int NPT = Sh::NPT, NFP = Sh::NFP, NF = Sh::NF, EPB = Sh::EPB;
   __shared__ double sU[2][EPB][4][NPT], sFr[2][EPB][4][NPT], sGs[2][EPB][4][NPT];
   __shared__ double sJ[EPB][4][NF];
   __shared__ double sDr[NPT * NPT], sDs[NPT * NPT], sLf[NF * NPT], sLift[NPT * NF];
+  __shared__ double sO[EPB][4][M][NPT];  // the output, for its traces (Tm_out)
   for (int i = threadIdx.x; i < NPT * NPT; i += 256) {
     sDr[i] = P.tri_Dr[i];
     sDs[i] = P.tri_Ds[i];
@@ -423,12 +424,27 @@ __global__ void __launch_bounds__(256) k_stage_tri(KParams P, const double* __re
       for (int k = 0; k < M; ++k) acc[k] += P.tab.PW[k * NQ + q] * Rq;
     }
   }
-  if (!pt) return;
   const double dt = rhs_only ? 0.0 : *P.dt;
+  if (pt) {
 #pragma unroll
-  for (int k = 0; k < M; ++k) {
-    const long idx = ((long)s * M + k) * EN + (long)e * NPT + slot;
-    out[idx] = rhs_only ? acc[k] : cu * u[idx] + cw * (w[idx] + dt * acc[k]);
+    for (int k = 0; k < M; ++k) {
+      const long idx = ((long)s * M + k) * EN + (long)e * NPT + slot;
+      const double o = rhs_only ? acc[k] : cu * u[idx] + cw * (w[idx] + dt * acc[k]);
+      out[idx] = o;
+      sO[le][s][k][slot] = o;
+    }
+  }
+  if (!Tm_out) return;
+  // modal traces of the output at the flux points, for the next stage's neighbours
+  __syncthreads();
+  if (fp) {
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      double t = 0.0;
+#pragma unroll
+      for (int j = 0; j < NPT; ++j) t += sLf[slot * NPT + j] * sO[le][s][k][j];
+      Tm_out[(((long)s * M + k) * E + e) * NF + slot] = t;
+    }
   }
 }
 
@@ -513,7 +529,7 @@ __global__ void __launch_bounds__(256) k_cfl_tri_mq(KParams P, const double* __r
 // node-by-node one.  The element mean is the coefficient of the constant mode.
 template <int PD, int M, int NQ>
 __global__ void __launch_bounds__(256) k_limit_tri(KParams P, double* __restrict__ u,
-                                                   unsigned char* __restrict__ flags) {
+                                                   unsigned char* __restrict__ flags, double* __restrict__ Tm) {
   using Sh = TriShape<PD>;
   constexpr int NPT = Sh::NPT, NF = Sh::NF, EPB = Sh::EPB;
   __shared__ double sC[EPB][4][M][NPT];
@@ -681,6 +697,18 @@ __global__ void __launch_bounds__(256) k_limit_tri(KParams P, double* __restrict
         u[((long)s * M + k) * EN + (long)e * NPT + slot] = v;
       }
     }
+    // the same affine map on the element's traces (the interpolation of a constant is
+    // the constant), when the caller keeps them
+    if (act && fp && Tm) {
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        const double m0 = (k == 0) ? 1.0 : 0.0;
+        double v = a[k];
+        if (s == 0) v = beta1 * (v - ub[0] * m0) + ub[0] * m0;
+        v = beta2 * (v - pick4(ub, s) * m0) + pick4(ub, s) * m0;
+        Tm[(((long)s * M + k) * E + e) * NF + slot] = v;
+      }
+    }
     if (active && rem == 0 && flags) flags[e] = act ? 1 : 0;
     return;
   }
@@ -689,22 +717,26 @@ __global__ void __launch_bounds__(256) k_limit_tri(KParams P, double* __restrict
 
 template <int PD, int M, int NQ>
 hipError_t go_stage_tri(const KParams& P, const double* in, const double* u, const double* w, double* out, double cu,
-                        double cw, int rhs_only, const double* Tm, hipStream_t s) {
+                        double cw, int rhs_only, double* Tm, int traces_ready, double* Tm_out, hipStream_t s) {
   using Sh = TriShape<PD>;
-  const long nt = 4l * M * P.E;
-  hipLaunchKernelGGL((k_trace_tri<PD>), dim3(blocks(nt)), dim3(256), 0, s, P, in, const_cast<double*>(Tm));
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (!traces_ready) {
+    const long nt = 4l * M * P.E;
+    hipLaunchKernelGGL((k_trace_tri<PD>), dim3(blocks(nt)), dim3(256), 0, s, P, in, Tm);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   const unsigned grid = (unsigned)((P.E + Sh::EPB - 1) / Sh::EPB);
-  hipLaunchKernelGGL((k_stage_tri<PD, M, NQ>), dim3(grid), dim3(256), 0, s, P, in, u, w, out, cu, cw, rhs_only, Tm);
+  hipLaunchKernelGGL((k_stage_tri<PD, M, NQ>), dim3(grid), dim3(256), 0, s, P, in, u, w, out, cu, cw, rhs_only,
+                     (const double*)Tm, Tm_out);
   return hipGetLastError();
 }
 
 template <int PD>
 hipError_t dispatch_mq(const KParams& P, const double* in, const double* u, const double* w, double* out, double cu,
-                       double cw, int rhs_only, const double* Tm, hipStream_t s) {
-#define FRSG_TRI_MQ(MM, QQ) \
-  if (P.M == MM && P.Nq == QQ) return go_stage_tri<PD, MM, QQ>(P, in, u, w, out, cu, cw, rhs_only, Tm, s);
+                       double cw, int rhs_only, double* Tm, int traces_ready, double* Tm_out, hipStream_t s) {
+#define FRSG_TRI_MQ(MM, QQ)                                                                                 \
+  if (P.M == MM && P.Nq == QQ)                                                                               \
+    return go_stage_tri<PD, MM, QQ>(P, in, u, w, out, cu, cw, rhs_only, Tm, traces_ready, Tm_out, s);
   FRSG_TRI_MQ(15, 25) FRSG_TRI_MQ(10, 16) FRSG_TRI_MQ(6, 9) FRSG_TRI_MQ(5, 5) FRSG_TRI_MQ(3, 4)
 #undef FRSG_TRI_MQ
   return hipErrorInvalidValue;
@@ -713,12 +745,12 @@ hipError_t dispatch_mq(const KParams& P, const double* in, const double* u, cons
 }  // namespace
 
 template <int PD>
-hipError_t dispatch_limit(const KParams& P, double* u, unsigned char* flags, hipStream_t s) {
+hipError_t dispatch_limit(const KParams& P, double* u, unsigned char* flags, double* Tm, hipStream_t s) {
   using Sh = TriShape<PD>;
   const unsigned grid = (unsigned)((P.E + Sh::EPB - 1) / Sh::EPB);
 #define FRSG_TRI_LIM(MM, QQ)                                                                        \
   if (P.M == MM && P.Nq == QQ) {                                                                     \
-    hipLaunchKernelGGL((k_limit_tri<PD, MM, QQ>), dim3(grid), dim3(256), 0, s, P, u, flags);         \
+    hipLaunchKernelGGL((k_limit_tri<PD, MM, QQ>), dim3(grid), dim3(256), 0, s, P, u, flags, Tm);     \
     return hipGetLastError();                                                                        \
   }
   FRSG_TRI_LIM(15, 25) FRSG_TRI_LIM(10, 16) FRSG_TRI_LIM(6, 9) FRSG_TRI_LIM(5, 5) FRSG_TRI_LIM(3, 4)
@@ -734,28 +766,30 @@ bool tri_fused_supported(const KParams& P) {
   return false;
 }
 
-// one stage: trace pass over `in` (into Tm), then out = cu u + cw (w + dt R(in)), or R(in)
-// with rhs_only
+// one stage: out = cu u + cw (w + dt R(in)), or R(in) with rhs_only, the neighbours' traces
+// of `in` from Tm (filled by a trace pass first unless traces_ready); with Tm_out the
+// traces of `out` are written there for the next stage
 hipError_t launch_stage_tri(const KParams& P, const double* in, const double* u, const double* w, double* out,
-                            double cu, double cw, int rhs_only, double* Tm, hipStream_t s) {
+                            double cu, double cw, int rhs_only, double* Tm, int traces_ready, double* Tm_out,
+                            hipStream_t s) {
   if (!tri_fused_supported(P)) return hipErrorInvalidValue;
   switch (P.nfp - 1) {
-    case 1: return dispatch_mq<1>(P, in, u, w, out, cu, cw, rhs_only, Tm, s);
-    case 2: return dispatch_mq<2>(P, in, u, w, out, cu, cw, rhs_only, Tm, s);
-    case 3: return dispatch_mq<3>(P, in, u, w, out, cu, cw, rhs_only, Tm, s);
-    case 4: return dispatch_mq<4>(P, in, u, w, out, cu, cw, rhs_only, Tm, s);
+    case 1: return dispatch_mq<1>(P, in, u, w, out, cu, cw, rhs_only, Tm, traces_ready, Tm_out, s);
+    case 2: return dispatch_mq<2>(P, in, u, w, out, cu, cw, rhs_only, Tm, traces_ready, Tm_out, s);
+    case 3: return dispatch_mq<3>(P, in, u, w, out, cu, cw, rhs_only, Tm, traces_ready, Tm_out, s);
+    case 4: return dispatch_mq<4>(P, in, u, w, out, cu, cw, rhs_only, Tm, traces_ready, Tm_out, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 // positivity limiter in place with the fused lane layout (the fused (p, M, N_q) set)
-hipError_t launch_limit_tri(const KParams& P, double* u, unsigned char* flags, hipStream_t s) {
+hipError_t launch_limit_tri(const KParams& P, double* u, unsigned char* flags, double* Tm, hipStream_t s) {
   if (!tri_fused_supported(P)) return hipErrorInvalidValue;
   switch (P.nfp - 1) {
-    case 1: return dispatch_limit<1>(P, u, flags, s);
-    case 2: return dispatch_limit<2>(P, u, flags, s);
-    case 3: return dispatch_limit<3>(P, u, flags, s);
-    case 4: return dispatch_limit<4>(P, u, flags, s);
+    case 1: return dispatch_limit<1>(P, u, flags, Tm, s);
+    case 2: return dispatch_limit<2>(P, u, flags, Tm, s);
+    case 3: return dispatch_limit<3>(P, u, flags, Tm, s);
+    case 4: return dispatch_limit<4>(P, u, flags, Tm, s);
     default: return hipErrorInvalidValue;
   }
 }

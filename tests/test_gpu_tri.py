@@ -244,6 +244,12 @@ def test_tri_steps_with_filter_and_limiter(label, cfg):
         fired += int(rflags[2].sum()) + int(rflags[3].sum()) + int(rflags[0].sum())
         assert rel_l2(to_np(ud), u) < RTOL_FP64, (i, rel_l2(to_np(ud), u))
     assert fired > 0
+    # the same four steps in one call (the face traces of each step's result carried
+    # to the next step, updated where the filter and limiter act)
+    u2 = to_dev(project_initial(prob, cfg["ic"], (T, R)))
+    sol.steps(u2, 4)
+    sol.sync()
+    assert rel_l2(to_np(u2), u) < RTOL_FP64, rel_l2(to_np(u2), u)
 
 
 @pytest.mark.parametrize("seed", range(10))
