@@ -748,12 +748,16 @@ static fr_sg_status step_generic(fr_sg_ctx* ctx, double* u, double dt, double* d
            return launch_stage_tri(K, W.w2, u, W.w2, u, 1.0 / 3.0, 2.0 / 3.0, 0, T0, 1, T1, s);
          })))
       return st;
-    if (ctx->prob.filter != FRSG_FILTER_NONE) {
-      if ((st = timed(ctx, "sensor_filter", 2 * sb, [&] { return launch_sensor_filter(K, u, f2, s, T1); })))
+    // end of step: sensor-gated filter and limiter in one element-wise pass
+    const bool filt = ctx->prob.filter != FRSG_FILTER_NONE;
+    if (!filt && f2) FRSG_TRY_HIP(launch_fill_flags(f2, E, s), ctx);
+    if (!ctx->prob.limiter && f3) FRSG_TRY_HIP(launch_fill_flags(f3, E, s), ctx);
+    if (filt || ctx->prob.limiter)
+      if ((st = timed(ctx, "filter_limiter", 2 * sb, [&] {
+             return launch_post_tri(K, u, filt ? 1 : 0, ctx->prob.limiter ? 1 : 0, filt ? f2 : nullptr,
+                                    ctx->prob.limiter ? f3 : nullptr, T1, s);
+           })))
         return st;
-    } else if (f2)
-      FRSG_TRY_HIP(launch_fill_flags(f2, E, s), ctx);
-    if ((st = lim(u, f3, T1)) != FRSG_OK) return st;
     ctx->tm_cur = c1;
     if (dt_used) FRSG_TRY_HIP(launch_copy_dt(K, dt_used, s), ctx);
     return FRSG_OK;

@@ -268,6 +268,9 @@ hipError_t launch_stage_tri(const KParams& P, const double* in, const double* u,
 // positivity limiter on triangles with the fused lane layout (fused (p, M, N_q) set)
 // Tm (may be null): rewrite the modal traces of the limited elements there
 hipError_t launch_limit_tri(const KParams& P, double* u, unsigned char* flags, double* Tm, hipStream_t s);
+// the sensor-gated filter and/or the limiter in one pass with the fused lane layout
+hipError_t launch_post_tri(const KParams& P, double* u, int do_filter, int do_limit, unsigned char* flag_filt,
+                           unsigned char* flag_lim, double* Tm, hipStream_t s);
 // CFL maximum of a modal state on triangles into P.lam_bits
 hipError_t launch_cfl_tri_modal(const KParams& P, const double* u, hipStream_t s);
 // explicit Runge-Kutta stage combination: out = u + dt sum_j a[j] K[j] (flat state of n doubles)

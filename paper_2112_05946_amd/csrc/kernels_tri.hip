@@ -529,11 +529,14 @@ __global__ void __launch_bounds__(256) k_cfl_tri_mq(KParams P, const double* __r
 // node-by-node one.  The element mean is the coefficient of the constant mode.
 template <int PD, int M, int NQ>
 __global__ void __launch_bounds__(256) k_limit_tri(KParams P, double* __restrict__ u,
-                                                   unsigned char* __restrict__ flags, double* __restrict__ Tm) {
+                                                   unsigned char* __restrict__ flags, double* __restrict__ Tm,
+                                                   int do_filter, int do_limit, unsigned char* __restrict__ fflags) {
   using Sh = TriShape<PD>;
   constexpr int NPT = Sh::NPT, NF = Sh::NF, EPB = Sh::EPB;
   __shared__ double sC[EPB][4][M][NPT];
-  __shared__ double sRed[EPB][4][2];   // per element: variable means; then rho_min, p_min
+  __shared__ double sLam[M * NPT];     // filter factors of the step (exponential: exp(-alpha dt f))
+  __shared__ int sFilt[EPB];
+  __shared__ double sRed[EPB][4][2];   // per element: rho_min, p_min, beta2; detector energy
   __shared__ int sNeed[EPB], sAny;
   __shared__ double sMin[EPB][Sh::TPE];
   const int E = P.E;
@@ -555,6 +558,72 @@ __global__ void __launch_bounds__(256) k_limit_tri(KParams P, double* __restrict
     if (pt) sC[le][s][k][slot] = c[k];
   }
   __syncthreads();
+  // sensor-gated modal filter first (Sec. 4.1, 4.2), in the triangle's orthonormal modes
+  bool filtered = false;
+  if (do_filter) {
+    const double dt = *P.dt;
+    for (int i = threadIdx.x; i < M * NPT; i += 256) {
+      const double f = P.tab.filt[i];
+      sLam[i] = P.filter == FRSG_FILTER_EXP ? exp(-P.alpha * dt * f) : f;
+    }
+    // detector: energy of the outer shell over the total, first variable (lanes s = 0
+    // hold modal index m = slot of every chaos mode)
+    double num = 0.0, den = 0.0;
+    if (pt && s == 0 && P.sensor == FRSG_SENSOR_DETECTOR) {
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        double um = 0.0;
+#pragma unroll
+        for (int l = 0; l < NPT; ++l) um += P.tri_Vinv[slot * NPT + l] * sC[le][0][k][l];
+        const double e2 = um * um;
+        num += e2 * P.tab.shell[k * NPT + slot];
+        den += e2;
+      }
+    }
+    if (active) sMin[le][rem] = num;
+    __syncthreads();
+    if (active && rem == 0) {
+      double a0 = 0.0;
+      for (int i = 0; i < Sh::TPE; ++i) a0 += sMin[le][i];
+      sRed[le][2][0] = a0;
+    }
+    __syncthreads();
+    if (active) sMin[le][rem] = den;
+    __syncthreads();
+    if (active && rem == 0) {
+      double a0 = 0.0;
+      for (int i = 0; i < Sh::TPE; ++i) a0 += sMin[le][i];
+      const double nm = sRed[le][2][0];
+      sFilt[le] = P.sensor != FRSG_SENSOR_DETECTOR ? 1 : ((a0 > 0.0 && nm / a0 > P.sensor_thr) ? 1 : 0);
+      if (fflags) fflags[e] = (unsigned char)sFilt[le];
+    }
+    __syncthreads();
+    filtered = active && sFilt[le];
+    // u_j <- sum_m V[j][m] lambda_km (V^-1 u)_m for every variable and chaos mode
+    if (filtered && pt) {
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m < NPT; ++m) {
+          double um = 0.0;
+#pragma unroll
+          for (int l = 0; l < NPT; ++l) um += P.tri_Vinv[m * NPT + l] * sC[le][s][k][l];
+          acc += P.tri_V[slot * NPT + m] * (um * sLam[k * NPT + m]);
+        }
+        c[k] = acc;
+      }
+    }
+    __syncthreads();
+    if (filtered && pt) {
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        sC[le][s][k][slot] = c[k];
+        u[((long)s * M + k) * EN + (long)e * NPT + slot] = c[k];
+      }
+    }
+    __syncthreads();
+  }
   // element means of the four variables (every lane, from LDS)
   double ub[4];
 #pragma unroll
@@ -605,12 +674,25 @@ __global__ void __launch_bounds__(256) k_limit_tri(KParams P, double* __restrict
   };
   const bool ok_sp = bound_ok(c, pt && real);
   const bool ok_fp = bound_ok(a, fp && real);
+  // filtered, not to be limited: the traces of the filtered element
+  if (!do_limit) {
+    if (filtered && fp && Tm) {
+#pragma unroll
+      for (int k = 0; k < M; ++k) Tm[(((long)s * M + k) * E + e) * NF + slot] = a[k];
+    }
+    return;
+  }
   if (active && real && !(ok_sp && ok_fp)) {
     sNeed[le] = 1;
     sAny = 1;
   }
   if (active && !real && slot == 0 && s == 0) atomicOr(P.status, kStatusNotRealizable);
   __syncthreads();
+  // filtered elements that the limiter leaves alone: their traces as filtered
+  if (filtered && fp && Tm && !sNeed[le]) {
+#pragma unroll
+    for (int k = 0; k < M; ++k) Tm[(((long)s * M + k) * E + e) * NF + slot] = a[k];
+  }
   if (sAny) {
     const bool need = active && real && sNeed[le];
     // node-by-node minima of density and pressure over solution and flux points
@@ -697,6 +779,10 @@ __global__ void __launch_bounds__(256) k_limit_tri(KParams P, double* __restrict
         u[((long)s * M + k) * EN + (long)e * NPT + slot] = v;
       }
     }
+    if (need && !act && filtered && fp && Tm) {
+#pragma unroll
+      for (int k = 0; k < M; ++k) Tm[(((long)s * M + k) * E + e) * NF + slot] = a[k];
+    }
     // the same affine map on the element's traces (the interpolation of a constant is
     // the constant), when the caller keeps them
     if (act && fp && Tm) {
@@ -745,12 +831,14 @@ hipError_t dispatch_mq(const KParams& P, const double* in, const double* u, cons
 }  // namespace
 
 template <int PD>
-hipError_t dispatch_limit(const KParams& P, double* u, unsigned char* flags, double* Tm, hipStream_t s) {
+hipError_t dispatch_limit(const KParams& P, double* u, unsigned char* flags, double* Tm, int do_filter, int do_limit,
+                          unsigned char* fflags, hipStream_t s) {
   using Sh = TriShape<PD>;
   const unsigned grid = (unsigned)((P.E + Sh::EPB - 1) / Sh::EPB);
 #define FRSG_TRI_LIM(MM, QQ)                                                                        \
   if (P.M == MM && P.Nq == QQ) {                                                                     \
-    hipLaunchKernelGGL((k_limit_tri<PD, MM, QQ>), dim3(grid), dim3(256), 0, s, P, u, flags, Tm);     \
+    hipLaunchKernelGGL((k_limit_tri<PD, MM, QQ>), dim3(grid), dim3(256), 0, s, P, u, flags, Tm, do_filter,  \
+                       do_limit, fflags);                                                               \
     return hipGetLastError();                                                                        \
   }
   FRSG_TRI_LIM(15, 25) FRSG_TRI_LIM(10, 16) FRSG_TRI_LIM(6, 9) FRSG_TRI_LIM(5, 5) FRSG_TRI_LIM(3, 4)
@@ -783,15 +871,20 @@ hipError_t launch_stage_tri(const KParams& P, const double* in, const double* u,
 }
 
 // positivity limiter in place with the fused lane layout (the fused (p, M, N_q) set)
-hipError_t launch_limit_tri(const KParams& P, double* u, unsigned char* flags, double* Tm, hipStream_t s) {
-  if (!tri_fused_supported(P)) return hipErrorInvalidValue;
+hipError_t launch_post_tri(const KParams& P, double* u, int do_filter, int do_limit, unsigned char* flag_filt,
+                           unsigned char* flag_lim, double* Tm, hipStream_t s) {
+  if (!tri_fused_supported(P) || P.filter == FRSG_FILTER_LASSO) return hipErrorInvalidValue;
   switch (P.nfp - 1) {
-    case 1: return dispatch_limit<1>(P, u, flags, Tm, s);
-    case 2: return dispatch_limit<2>(P, u, flags, Tm, s);
-    case 3: return dispatch_limit<3>(P, u, flags, Tm, s);
-    case 4: return dispatch_limit<4>(P, u, flags, Tm, s);
+    case 1: return dispatch_limit<1>(P, u, flag_lim, Tm, do_filter, do_limit, flag_filt, s);
+    case 2: return dispatch_limit<2>(P, u, flag_lim, Tm, do_filter, do_limit, flag_filt, s);
+    case 3: return dispatch_limit<3>(P, u, flag_lim, Tm, do_filter, do_limit, flag_filt, s);
+    case 4: return dispatch_limit<4>(P, u, flag_lim, Tm, do_filter, do_limit, flag_filt, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_limit_tri(const KParams& P, double* u, unsigned char* flags, double* Tm, hipStream_t s) {
+  return launch_post_tri(P, u, 0, 1, nullptr, flags, Tm, s);
 }
 
 hipError_t launch_cfl_tri_modal(const KParams& P, const double* u, hipStream_t s) {

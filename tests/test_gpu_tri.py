@@ -219,6 +219,7 @@ TRI_STAB = [
     ("fused_sv_p3_exp_always_hll", dict(inputs.tri_shock_vortex(3), gpc_order=2, nq1d=3, filter="exp",
                                         sensor="always", alpha=36.0, s=8.0, flux="hll")),
     ("fused_sv_p3_rk4", dict(inputs.tri_shock_vortex(3), gpc_order=2, nq1d=3, integrator="rk4")),
+    ("fused_sv_p3_filter_only", dict(inputs.tri_shock_vortex(3), gpc_order=2, nq1d=3, limiter=False)),
 ]
 
 
