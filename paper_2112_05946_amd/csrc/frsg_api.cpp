@@ -643,7 +643,7 @@ fr_sg_status fr_sg_limit(fr_sg_ctx* ctx, double* u, uint8_t* flags) {
     });
   if (ctx->prob.limiter && ctx->fused_tri)
     return timed(ctx, "limiter", 2 * state_bytes(ctx),
-                 [&] { return launch_limit_tri(ctx->kp, u, flags, nullptr, ctx->stream); });
+                 [&] { return launch_limit_tri(ctx->kp, u, flags, ctx->stream); });
   if (ctx->prob.limiter)
     return timed(ctx, "limiter", 2 * state_bytes(ctx), [&] { return launch_limiter(ctx->kp, u, flags, ctx->stream); });
   if (flags) FRSG_TRY_HIP(launch_fill_flags(flags, ctx->E, ctx->stream), ctx);
@@ -718,11 +718,11 @@ static fr_sg_status step_generic(fr_sg_ctx* ctx, double* u, double dt, double* d
   FRSG_TRY_HIP(launch_set_scalars(K, cfl ? 0.0 : dt, s), ctx);
   const double sb = state_bytes(ctx);
   if (ctx->fused_tri) {
-    // triangles: one fused launch per stage, the limiter after each stage and the
-    // sensor-gated filter and limiter at the end.  Each stage writes the modal traces
-    // of its output into the trace buffer its input's traces are not in, and the
-    // limiter and filter rewrite those of the elements they change, so only the first
-    // step of a call runs a trace pass over u (chained: u is the previous step's result)
+    // triangles: one fused launch per stage, which also runs the limiter on its output
+    // (stages 1 and 2) or the sensor-gated filter and then the limiter (stage 3).  Each
+    // stage writes the modal traces of its final output into the trace buffer its
+    // input's traces are not in, so only the first step of a call runs a trace pass over
+    // u (chained: u is the previous step's result)
     if (cfl) {
       if ((st = timed(ctx, "cfl", sb, [&] { return launch_cfl_tri_modal(K, u, s); }))) return st;
       FRSG_TRY_HIP(launch_dt(K, ctx->dim, nullptr, s), ctx);
@@ -730,34 +730,28 @@ static fr_sg_status step_generic(fr_sg_ctx* ctx, double* u, double dt, double* d
     const int c0 = chained ? ctx->tm_cur : 0, c1 = c0 ^ 1;
     double* T0 = W.Tm[c0];
     double* T1 = W.Tm[c1];
-    auto lim = [&](double* x, uint8_t* f, double* tm) -> fr_sg_status {
-      if (ctx->prob.limiter)
-        return timed(ctx, "limiter", 2 * sb, [&] { return launch_limit_tri(K, x, f, tm, s); });
-      if (f) FRSG_TRY_HIP(launch_fill_flags(f, E, s), ctx);
-      return FRSG_OK;
-    };
-    if ((st = timed(ctx, "stage1", 2 * sb,
-                    [&] { return launch_stage_tri(K, u, u, u, W.w1, 0.0, 1.0, 0, T0, chained ? 1 : 0, T1, s); })))
-      return st;
-    if ((st = lim(W.w1, f0, T1)) != FRSG_OK) return st;
-    if ((st = timed(ctx, "stage2", 3 * sb,
-                    [&] { return launch_stage_tri(K, W.w1, u, W.w1, W.w2, 0.75, 0.25, 0, T1, 1, T0, s); })))
-      return st;
-    if ((st = lim(W.w2, f1, T0)) != FRSG_OK) return st;
-    if ((st = timed(ctx, "stage3", 3 * sb, [&] {
-           return launch_stage_tri(K, W.w2, u, W.w2, u, 1.0 / 3.0, 2.0 / 3.0, 0, T0, 1, T1, s);
+    const bool lim = ctx->prob.limiter != 0, filt = ctx->prob.filter != FRSG_FILTER_NONE;
+    for (uint8_t* f : {f0, f1, f3})
+      if (!lim && f) FRSG_TRY_HIP(launch_fill_flags(f, E, s), ctx);
+    if (!filt && f2) FRSG_TRY_HIP(launch_fill_flags(f2, E, s), ctx);
+    TriPost p1, p2, p3;
+    p1.limit = p2.limit = p3.limit = lim ? 1 : 0;
+    p1.flag_lim = lim ? f0 : nullptr;
+    p2.flag_lim = lim ? f1 : nullptr;
+    p3.flag_lim = lim ? f3 : nullptr;
+    p3.filter = filt ? 1 : 0;
+    p3.flag_filt = filt ? f2 : nullptr;
+    if ((st = timed(ctx, "stage1", 2 * sb, [&] {
+           return launch_stage_tri(K, u, u, u, W.w1, 0.0, 1.0, 0, T0, chained ? 1 : 0, T1, s, p1);
          })))
       return st;
-    // end of step: sensor-gated filter and limiter in one element-wise pass
-    const bool filt = ctx->prob.filter != FRSG_FILTER_NONE;
-    if (!filt && f2) FRSG_TRY_HIP(launch_fill_flags(f2, E, s), ctx);
-    if (!ctx->prob.limiter && f3) FRSG_TRY_HIP(launch_fill_flags(f3, E, s), ctx);
-    if (filt || ctx->prob.limiter)
-      if ((st = timed(ctx, "filter_limiter", 2 * sb, [&] {
-             return launch_post_tri(K, u, filt ? 1 : 0, ctx->prob.limiter ? 1 : 0, filt ? f2 : nullptr,
-                                    ctx->prob.limiter ? f3 : nullptr, T1, s);
-           })))
-        return st;
+    if ((st = timed(ctx, "stage2", 3 * sb,
+                    [&] { return launch_stage_tri(K, W.w1, u, W.w1, W.w2, 0.75, 0.25, 0, T1, 1, T0, s, p2); })))
+      return st;
+    if ((st = timed(ctx, "stage3", 3 * sb, [&] {
+           return launch_stage_tri(K, W.w2, u, W.w2, u, 1.0 / 3.0, 2.0 / 3.0, 0, T0, 1, T1, s, p3);
+         })))
+      return st;
     ctx->tm_cur = c1;
     if (dt_used) FRSG_TRY_HIP(launch_copy_dt(K, dt_used, s), ctx);
     return FRSG_OK;

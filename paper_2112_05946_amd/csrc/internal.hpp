@@ -247,9 +247,7 @@ hipError_t launch_project_stage(const KParams& P, const double* Rn, const double
                                 double* out, double cu, double cw, int rhs_only, hipStream_t s);
 hipError_t launch_project_ic(const KParams& P, const double* U0, double* u, hipStream_t s);
 hipError_t launch_limiter(const KParams& P, double* u, unsigned char* flags, hipStream_t s);
-// tm (triangles, fused path): also rewrite the modal traces of the filtered elements there
-hipError_t launch_sensor_filter(const KParams& P, double* u, unsigned char* flags, hipStream_t s,
-                                double* tm = nullptr);
+hipError_t launch_sensor_filter(const KParams& P, double* u, unsigned char* flags, hipStream_t s);
 hipError_t launch_fill_flags(unsigned char* flags, long n, hipStream_t s);
 // triangle passes (kernels_tri.hip): interactive-flux jumps [S][Nq][E][3 nfp],
 // nodal residual into Rn, CFL maximum of the nodal values into P.lam_bits
@@ -258,19 +256,23 @@ hipError_t launch_faces_tri(const KParams& P, const double* Un, const double* Fn
 hipError_t launch_resid_tri(const KParams& P, const double* Fn, const double* Gn, const double* Jump, double* Rn,
                             hipStream_t s);
 hipError_t launch_cfl_tri(const KParams& P, const double* Un, hipStream_t s);
+// end-of-stage work of the fused triangle kernels: the sensor-gated filter (flags of the
+// filtered elements into flag_filt) and/or the limiter (flags of the limited ones into
+// flag_lim); the flag pointers may be null
+struct TriPost {
+  int filter = 0, limit = 0;
+  unsigned char *flag_filt = nullptr, *flag_lim = nullptr;
+};
 // fused triangle stage (p = 1..4 and the (M, Nq) pairs of the fused 2D kernel): a trace pass
 // over `in` into Tm ([S][M][E][3 nfp]) unless traces_ready, then out = cu u + cw (w + dt R(in)),
-// or R(in) with rhs_only; with Tm_out the traces of `out` go there
+// or R(in) with rhs_only; `post` on the output (not with rhs_only); with Tm_out the traces
+// of the final `out` go there
 bool tri_fused_supported(const KParams& P);
 hipError_t launch_stage_tri(const KParams& P, const double* in, const double* u, const double* w, double* out,
                             double cu, double cw, int rhs_only, double* Tm, int traces_ready, double* Tm_out,
-                            hipStream_t s);
+                            hipStream_t s, const TriPost& post = TriPost());
 // positivity limiter on triangles with the fused lane layout (fused (p, M, N_q) set)
-// Tm (may be null): rewrite the modal traces of the limited elements there
-hipError_t launch_limit_tri(const KParams& P, double* u, unsigned char* flags, double* Tm, hipStream_t s);
-// the sensor-gated filter and/or the limiter in one pass with the fused lane layout
-hipError_t launch_post_tri(const KParams& P, double* u, int do_filter, int do_limit, unsigned char* flag_filt,
-                           unsigned char* flag_lim, double* Tm, hipStream_t s);
+hipError_t launch_limit_tri(const KParams& P, double* u, unsigned char* flags, hipStream_t s);
 // CFL maximum of a modal state on triangles into P.lam_bits
 hipError_t launch_cfl_tri_modal(const KParams& P, const double* u, hipStream_t s);
 // explicit Runge-Kutta stage combination: out = u + dt sum_j a[j] K[j] (flat state of n doubles)

@@ -570,8 +570,7 @@ __global__ void __launch_bounds__(kElemBlock) k_limiter(KParams P, double* __res
 // ---------------------------------------------------------------------------
 template <int EQ, int DIM>
 __global__ void __launch_bounds__(kElemBlock) k_sensor_filter(KParams P, double* __restrict__ u,
-                                                              unsigned char* __restrict__ flags,
-                                                              double* __restrict__ tm) {
+                                                              unsigned char* __restrict__ flags) {
   constexpr int S = nstate<EQ>();
   extern __shared__ double ut[];  // [S][M][nsp] spatial modal coefficients
   __shared__ double sm[kElemBlock];
@@ -655,20 +654,6 @@ __global__ void __launch_bounds__(kElemBlock) k_sensor_filter(KParams P, double*
     u[(long)sk * EN + (long)e * nsp + j] = acc;
   }
   if (threadIdx.x == 0 && flags) flags[e] = 1;
-  if constexpr (DIM == 3) {
-    // fused triangle path: the filtered element's modal traces at its flux points
-    if (tm) {
-      __syncthreads();
-      const int nf = 3 * P.nfp;
-      for (int it = threadIdx.x; it < S * M * nf; it += kElemBlock) {
-        const int sk = it / nf, fk = it - sk * nf;
-        const double* src = u + (long)sk * EN + (long)e * nsp;
-        double t = 0.0;
-        for (int j = 0; j < nsp; ++j) t += P.tri_Lf[fk * nsp + j] * src[j];
-        tm[((long)sk * P.E + e) * nf + fk] = t;
-      }
-    }
-  }
 }
 
 }  // namespace
@@ -781,17 +766,16 @@ hipError_t launch_limiter(const KParams& P, double* u, unsigned char* flags, hip
   return hipGetLastError();
 }
 
-hipError_t launch_sensor_filter(const KParams& P, double* u, unsigned char* flags, hipStream_t s, double* tm) {
+hipError_t launch_sensor_filter(const KParams& P, double* u, unsigned char* flags, hipStream_t s) {
   const size_t shmem = sizeof(double) * (size_t)P.S * P.M * P.nsp;
   if (P.tri) {
     if (P.eq != kEuler2) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_sensor_filter<kEuler2, 3>), dim3(P.E), dim3(kElemBlock), shmem, s, P, u, flags, tm);
+    hipLaunchKernelGGL((k_sensor_filter<kEuler2, 3>), dim3(P.E), dim3(kElemBlock), shmem, s, P, u, flags);
     return hipGetLastError();
   }
   FRSG_DISPATCH_EQ(P.eq, {
     constexpr int DIM = EQ == kEuler2 ? 2 : 1;
-    hipLaunchKernelGGL((k_sensor_filter<EQ, DIM>), dim3(P.E), dim3(kElemBlock), shmem, s, P, u, flags,
-                       (double*)nullptr);
+    hipLaunchKernelGGL((k_sensor_filter<EQ, DIM>), dim3(P.E), dim3(kElemBlock), shmem, s, P, u, flags);
   });
   return hipGetLastError();
 }

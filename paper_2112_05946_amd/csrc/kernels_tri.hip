@@ -304,6 +304,258 @@ __device__ __forceinline__ void quad_gather(double v, double* all) {
   all[3] = quad_bcast<3>(v);
 }
 
+// End-of-stage work on triangles with the stage kernel's lane layout: the sensor-gated
+// modal filter (Sec. 4.1, 4.2) and the positivity limiter (Sec. 4.3).  Lane (slot, s)
+// keeps the coefficients c[] of variable s at solution point `slot`; sC holds those of
+// the block's elements.  The limiter decision first uses rigorous bounds per point
+// (|Phi_k(z_q)| <= cmax_k, a relative margin of 1e-10 for their rounding) at the
+// solution point and, as a flux-point lane, at flux point `slot`; only blocks holding an
+// element whose bound fails run the node-by-node minimum and the pressure roots, so the
+// decision is the node-by-node one.  The element mean is the coefficient of the
+// constant mode.  c[] and sC are updated in place; returns whether the lane's element
+// changed.  Every thread of the block calls it, with sC complete and visible.
+template <int PD, int M>
+struct TriPostShared {
+  using Sh = TriShape<PD>;
+  double lam[M * Sh::NPT];  // filter factors of the step (exponential: exp(-alpha dt f))
+  double red[Sh::EPB][4][2];
+  double mn[Sh::EPB][Sh::TPE];
+  int filt[Sh::EPB], need[Sh::EPB], any;
+};
+
+template <int PD, int M, int NQ>
+__device__ __forceinline__ bool post_tri(const KParams& P, double (&c)[M],
+                                         double (&sC)[TriShape<PD>::EPB][4][M][TriShape<PD>::NPT],
+                                         TriPostShared<PD, M>& sh, const int e, const int le, const int rem,
+                                         const bool active, const TriPost& post) {
+  using Sh = TriShape<PD>;
+  constexpr int NPT = Sh::NPT, NF = Sh::NF, TPE = Sh::TPE, EPB = Sh::EPB;
+  const int slot = rem >> 2, s = rem & 3;
+  const bool pt = active && slot < NPT;
+  const bool fp = active && slot < NF;
+  if ((int)threadIdx.x < EPB) sh.need[threadIdx.x] = 0;
+  if (threadIdx.x == 0) sh.any = 0;
+  bool filtered = false;
+  if (post.filter) {
+    const double dt = *P.dt;
+    for (int i = threadIdx.x; i < M * NPT; i += blockDim.x) {
+      const double f = P.tab.filt[i];
+      sh.lam[i] = P.filter == FRSG_FILTER_EXP ? exp(-P.alpha * dt * f) : f;
+    }
+    // spatial modal coefficient m = slot of variable s for every chaos mode: (V^-1 u)_m
+    double um[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      double acc = 0.0;
+      if (pt) {
+#pragma unroll
+        for (int l = 0; l < NPT; ++l) acc += P.tri_Vinv[slot * NPT + l] * sC[le][s][k][l];
+      }
+      um[k] = acc;
+    }
+    // detector: energy of the outer shell over the total, first variable
+    double num = 0.0, den = 0.0;
+    if (pt && s == 0 && P.sensor == FRSG_SENSOR_DETECTOR) {
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        const double e2 = um[k] * um[k];
+        num += e2 * P.tab.shell[k * NPT + slot];
+        den += e2;
+      }
+    }
+    if (active) sh.mn[le][rem] = num;
+    __syncthreads();
+    if (active && rem == 0) {
+      double a0 = 0.0;
+      for (int i = 0; i < TPE; ++i) a0 += sh.mn[le][i];
+      sh.red[le][2][0] = a0;
+    }
+    __syncthreads();
+    if (active) sh.mn[le][rem] = den;
+    __syncthreads();
+    if (active && rem == 0) {
+      double a0 = 0.0;
+      for (int i = 0; i < TPE; ++i) a0 += sh.mn[le][i];
+      const double nm = sh.red[le][2][0];
+      sh.filt[le] = P.sensor != FRSG_SENSOR_DETECTOR ? 1 : ((a0 > 0.0 && nm / a0 > P.sensor_thr) ? 1 : 0);
+      if (post.flag_filt) post.flag_filt[e] = (unsigned char)sh.filt[le];
+    }
+    __syncthreads();
+    filtered = active && sh.filt[le];
+    // u_j <- sum_m V[j][m] (lambda_km (V^-1 u)_m), the damped modes staged in sC (every
+    // lane has read sC before the barriers above)
+    if (filtered && pt) {
+#pragma unroll
+      for (int k = 0; k < M; ++k) sC[le][s][k][slot] = um[k] * sh.lam[k * NPT + slot];
+    }
+    __syncthreads();
+    if (filtered && pt) {
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m < NPT; ++m) acc += P.tri_V[slot * NPT + m] * sC[le][s][k][m];
+        c[k] = acc;
+      }
+    }
+    __syncthreads();
+    if (filtered && pt) {
+#pragma unroll
+      for (int k = 0; k < M; ++k) sC[le][s][k][slot] = c[k];
+    }
+  }
+  __syncthreads();
+  if (!post.limit) return filtered;
+  // element means of the four variables (every lane, from LDS)
+  double ub[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) acc += sC[le][v][0][j] * P.tab.swts[j];
+    ub[v] = acc;
+  }
+  const double pb = (P.gamma - 1.0) * (ub[3] - 0.5 * (ub[1] * ub[1] + ub[2] * ub[2]) / ub[0]);
+  const bool real = ub[0] > 0.0 && pb > 0.0 && isfinite(ub[0]) && isfinite(ub[1]) && isfinite(ub[2]) &&
+                    isfinite(ub[3]);
+  const double eps = fmin(1e-8, fmin(ub[0], pb));
+  // flux-point lanes: interpolate all modes to their flux point
+  double a[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    double acc = 0.0;
+    if (fp) {
+#pragma unroll
+      for (int j = 0; j < NPT; ++j) acc += P.tri_Lf[slot * NPT + j] * sC[le][s][k][j];
+    }
+    a[k] = acc;
+  }
+  // rigorous bounds at the solution point and the flux point of this lane
+  auto bound_ok = [&](const double* coef, bool on) {
+    double mn = coef[0], vr = 0.0;
+#pragma unroll
+    for (int k = 1; k < M; ++k) vr += fabs(coef[k]) * P.tab.cmax[k];
+    double MN[4], VR[4];
+    quad_gather(mn, MN);
+    quad_gather(vr, VR);
+    if (!on) return true;
+    const double rlo = MN[0] - VR[0];
+    const double tol_r = 1e-10 * (fabs(MN[0]) + VR[0]);
+    if (!(rlo > eps + tol_r)) return false;
+    double m2 = 0.0;
+#pragma unroll
+    for (int v = 1; v < 3; ++v) {
+      const double mx = fabs(MN[v]) + VR[v];
+      m2 += mx * mx;
+    }
+    const double ke = 0.5 * m2 / rlo;
+    const double elo = MN[3] - VR[3];
+    const double plo = (P.gamma - 1.0) * (elo - ke);
+    const double tol_p = 1e-10 * (P.gamma - 1.0) * (fabs(MN[3]) + VR[3] + ke);
+    return plo > eps + tol_p;
+  };
+  const bool ok_sp = bound_ok(c, pt && real);
+  const bool ok_fp = bound_ok(a, fp && real);
+  if (active && real && !(ok_sp && ok_fp)) {
+    sh.need[le] = 1;
+    sh.any = 1;
+  }
+  if (active && !real && slot == 0 && s == 0) atomicOr(P.status, kStatusNotRealizable);
+  __syncthreads();
+  bool act = false;
+  if (sh.any) {
+    const bool need = active && real && sh.need[le];
+    // node-by-node minima of density and pressure over solution and flux points
+    double rmin = INFINITY, pmin = INFINITY;
+    for (int q = 0; q < NQ; ++q) {
+      double vs = 0.0, vf = 0.0;
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        const double ph = P.tab.Phi[k * NQ + q];
+        vs += ph * c[k];
+        vf += ph * a[k];
+      }
+      double Us[4], Uf[4];
+      quad_gather(vs, Us);
+      quad_gather(vf, Uf);
+      if (need && pt) {
+        rmin = fmin(rmin, Us[0]);
+        pmin = fmin(pmin, (P.gamma - 1.0) * (Us[3] - 0.5 * (Us[1] * Us[1] + Us[2] * Us[2]) / Us[0]));
+      }
+      if (need && fp) {
+        rmin = fmin(rmin, Uf[0]);
+        pmin = fmin(pmin, (P.gamma - 1.0) * (Uf[3] - 0.5 * (Uf[1] * Uf[1] + Uf[2] * Uf[2]) / Uf[0]));
+      }
+    }
+    if (active) sh.mn[le][rem] = rmin;
+    __syncthreads();
+    if (active && rem == 0) {
+      double r = INFINITY;
+      for (int i = 0; i < TPE; ++i) r = fmin(r, sh.mn[le][i]);
+      sh.red[le][0][0] = r;
+    }
+    __syncthreads();
+    if (active) sh.mn[le][rem] = pmin;
+    __syncthreads();
+    if (active && rem == 0) {
+      double r = INFINITY;
+      for (int i = 0; i < TPE; ++i) r = fmin(r, sh.mn[le][i]);
+      sh.red[le][0][1] = r;
+    }
+    __syncthreads();
+    const double Rmin = sh.red[le][0][0], Pmin = sh.red[le][0][1];
+    act = need && fmin(Rmin, Pmin) < eps;
+    const double beta1 = (Rmin >= eps) ? 1.0 : (ub[0] - eps) / (ub[0] - Rmin);
+    // beta2: smallest root over the points whose pressure stays below eps after beta1
+    double bmin = 1.0;
+    for (int q = 0; q < NQ; ++q) {
+      double vs = 0.0, vf = 0.0;
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        const double ph = P.tab.Phi[k * NQ + q];
+        vs += ph * c[k];
+        vf += ph * a[k];
+      }
+      double Us[4], Uf[4];
+      quad_gather(vs, Us);
+      quad_gather(vf, Uf);
+      if (act && pt) {
+        Us[0] = beta1 * (Us[0] - ub[0]) + ub[0];
+        if ((P.gamma - 1.0) * (Us[3] - 0.5 * (Us[1] * Us[1] + Us[2] * Us[2]) / Us[0]) < eps)
+          bmin = fmin(bmin, pressure_root<kEuler2>(ub, Us, eps, P.gamma));
+      }
+      if (act && fp) {
+        Uf[0] = beta1 * (Uf[0] - ub[0]) + ub[0];
+        if ((P.gamma - 1.0) * (Uf[3] - 0.5 * (Uf[1] * Uf[1] + Uf[2] * Uf[2]) / Uf[0]) < eps)
+          bmin = fmin(bmin, pressure_root<kEuler2>(ub, Uf, eps, P.gamma));
+      }
+    }
+    if (active) sh.mn[le][rem] = bmin;
+    __syncthreads();
+    if (active && rem == 0) {
+      double r = 1.0;
+      for (int i = 0; i < TPE; ++i) r = fmin(r, sh.mn[le][i]);
+      sh.red[le][1][0] = r;
+    }
+    __syncthreads();
+    const double beta2 = sh.red[le][1][0];
+    // no lane reads sC past the last barrier: rewrite it in place
+    if (act && pt) {
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        const double m0 = (k == 0) ? 1.0 : 0.0;
+        double v = c[k];
+        if (s == 0) v = beta1 * (v - ub[0] * m0) + ub[0] * m0;
+        v = beta2 * (v - pick4(ub, s) * m0) + pick4(ub, s) * m0;
+        c[k] = v;
+        sC[le][s][k][slot] = v;
+      }
+    }
+  }
+  if (active && rem == 0 && post.flag_lim) post.flag_lim[e] = act ? 1 : 0;
+  return filtered || act;
+}
+
 // Lane layout: lane = 4 slot + s within an element's 4 x SLOTS lanes, so the four
 // conserved variables of one point sit in one group of four lanes and trade values
 // by DPP instead of LDS.  Per node two barriers: after the nodal values and
@@ -311,13 +563,15 @@ __device__ __forceinline__ void quad_gather(double v, double* all) {
 template <int PD, int M, int NQ>
 __global__ void __launch_bounds__(256) k_stage_tri(KParams P, const double* __restrict__ in, const double* u,
                                                    const double* w, double* out, double cu, double cw, int rhs_only,
-                                                   const double* __restrict__ Tm, double* __restrict__ Tm_out) {
+                                                   const double* __restrict__ Tm, double* __restrict__ Tm_out,
+                                                   TriPost post) {
   using Sh = TriShape<PD>;
   constexpr int NPT = Sh::NPT, NFP = Sh::NFP, NF = Sh::NF, EPB = Sh::EPB;
   __shared__ double sU[2][EPB][4][NPT], sFr[2][EPB][4][NPT], sGs[2][EPB][4][NPT];
   __shared__ double sJ[EPB][4][NF];
   __shared__ double sDr[NPT * NPT], sDs[NPT * NPT], sLf[NF * NPT], sLift[NPT * NF];
-  __shared__ double sO[EPB][4][M][NPT];  // the output, for its traces (Tm_out)
+  __shared__ double sO[EPB][4][M][NPT];  // the output, for the filter, the limiter and its traces
+  __shared__ TriPostShared<PD, M> sh;
   for (int i = threadIdx.x; i < NPT * NPT; i += 256) {
     sDr[i] = P.tri_Dr[i];
     sDs[i] = P.tri_Ds[i];
@@ -430,9 +684,18 @@ __global__ void __launch_bounds__(256) k_stage_tri(KParams P, const double* __re
     for (int k = 0; k < M; ++k) {
       const long idx = ((long)s * M + k) * EN + (long)e * NPT + slot;
       const double o = rhs_only ? acc[k] : cu * u[idx] + cw * (w[idx] + dt * acc[k]);
-      out[idx] = o;
+      acc[k] = o;
       sO[le][s][k][slot] = o;
     }
+  }
+  // the limiter after the stage, or the end-of-step filter and limiter, on the output
+  if (post.filter || post.limit) {
+    __syncthreads();
+    post_tri<PD, M, NQ>(P, acc, sO, sh, e, le, rem, active, post);
+  }
+  if (pt) {
+#pragma unroll
+    for (int k = 0; k < M; ++k) out[((long)s * M + k) * EN + (long)e * NPT + slot] = acc[k];
   }
   if (!Tm_out) return;
   // modal traces of the output at the flux points, for the next stage's neighbours
@@ -520,25 +783,13 @@ __global__ void __launch_bounds__(256) k_cfl_tri_mq(KParams P, const double* __r
   if (threadIdx.x == 0) atomicMax(P.lam_bits, (unsigned long long)__double_as_longlong(sm[0]));
 }
 
-// Positivity limiter (Sec. 4.3) on triangles with the stage kernel's lane layout:
-// lane (slot, s) keeps the coefficients of variable s at solution point `slot` and,
-// as a flux-point lane, their interpolation to flux point `slot`.  The decision
-// first uses rigorous bounds per point (|Phi_k(z_q)| <= cmax_k, a relative margin
-// of 1e-10 for their rounding); only blocks holding an element whose bound fails
-// run the node-by-node minimum and the pressure roots, so the decision is the
-// node-by-node one.  The element mean is the coefficient of the constant mode.
+// the limiter in place on a state, as a pass of its own
 template <int PD, int M, int NQ>
-__global__ void __launch_bounds__(256) k_limit_tri(KParams P, double* __restrict__ u,
-                                                   unsigned char* __restrict__ flags, double* __restrict__ Tm,
-                                                   int do_filter, int do_limit, unsigned char* __restrict__ fflags) {
+__global__ void __launch_bounds__(256) k_limit_tri(KParams P, double* __restrict__ u, TriPost post) {
   using Sh = TriShape<PD>;
-  constexpr int NPT = Sh::NPT, NF = Sh::NF, EPB = Sh::EPB;
+  constexpr int NPT = Sh::NPT, EPB = Sh::EPB;
   __shared__ double sC[EPB][4][M][NPT];
-  __shared__ double sLam[M * NPT];     // filter factors of the step (exponential: exp(-alpha dt f))
-  __shared__ int sFilt[EPB];
-  __shared__ double sRed[EPB][4][2];   // per element: rho_min, p_min, beta2; detector energy
-  __shared__ int sNeed[EPB], sAny;
-  __shared__ double sMin[EPB][Sh::TPE];
+  __shared__ TriPostShared<PD, M> sh;
   const int E = P.E;
   const int el = threadIdx.x / Sh::TPE;
   const int rem = threadIdx.x % Sh::TPE;
@@ -547,10 +798,7 @@ __global__ void __launch_bounds__(256) k_limit_tri(KParams P, double* __restrict
   const bool active = el < EPB && e < E;
   const int le = active ? el : 0;
   const bool pt = active && slot < NPT;
-  const bool fp = active && slot < NF;
   const long EN = (long)E * NPT;
-  if (threadIdx.x < EPB) sNeed[threadIdx.x] = 0;
-  if (threadIdx.x == 0) sAny = 0;
   double c[M];
 #pragma unroll
   for (int k = 0; k < M; ++k) {
@@ -558,252 +806,17 @@ __global__ void __launch_bounds__(256) k_limit_tri(KParams P, double* __restrict
     if (pt) sC[le][s][k][slot] = c[k];
   }
   __syncthreads();
-  // sensor-gated modal filter first (Sec. 4.1, 4.2), in the triangle's orthonormal modes
-  bool filtered = false;
-  if (do_filter) {
-    const double dt = *P.dt;
-    for (int i = threadIdx.x; i < M * NPT; i += 256) {
-      const double f = P.tab.filt[i];
-      sLam[i] = P.filter == FRSG_FILTER_EXP ? exp(-P.alpha * dt * f) : f;
-    }
-    // detector: energy of the outer shell over the total, first variable (lanes s = 0
-    // hold modal index m = slot of every chaos mode)
-    double num = 0.0, den = 0.0;
-    if (pt && s == 0 && P.sensor == FRSG_SENSOR_DETECTOR) {
+  const bool changed = post_tri<PD, M, NQ>(P, c, sC, sh, e, le, rem, active, post);
+  if (changed && pt) {
 #pragma unroll
-      for (int k = 0; k < M; ++k) {
-        double um = 0.0;
-#pragma unroll
-        for (int l = 0; l < NPT; ++l) um += P.tri_Vinv[slot * NPT + l] * sC[le][0][k][l];
-        const double e2 = um * um;
-        num += e2 * P.tab.shell[k * NPT + slot];
-        den += e2;
-      }
-    }
-    if (active) sMin[le][rem] = num;
-    __syncthreads();
-    if (active && rem == 0) {
-      double a0 = 0.0;
-      for (int i = 0; i < Sh::TPE; ++i) a0 += sMin[le][i];
-      sRed[le][2][0] = a0;
-    }
-    __syncthreads();
-    if (active) sMin[le][rem] = den;
-    __syncthreads();
-    if (active && rem == 0) {
-      double a0 = 0.0;
-      for (int i = 0; i < Sh::TPE; ++i) a0 += sMin[le][i];
-      const double nm = sRed[le][2][0];
-      sFilt[le] = P.sensor != FRSG_SENSOR_DETECTOR ? 1 : ((a0 > 0.0 && nm / a0 > P.sensor_thr) ? 1 : 0);
-      if (fflags) fflags[e] = (unsigned char)sFilt[le];
-    }
-    __syncthreads();
-    filtered = active && sFilt[le];
-    // u_j <- sum_m V[j][m] lambda_km (V^-1 u)_m for every variable and chaos mode
-    if (filtered && pt) {
-#pragma unroll
-      for (int k = 0; k < M; ++k) {
-        double acc = 0.0;
-#pragma unroll
-        for (int m = 0; m < NPT; ++m) {
-          double um = 0.0;
-#pragma unroll
-          for (int l = 0; l < NPT; ++l) um += P.tri_Vinv[m * NPT + l] * sC[le][s][k][l];
-          acc += P.tri_V[slot * NPT + m] * (um * sLam[k * NPT + m]);
-        }
-        c[k] = acc;
-      }
-    }
-    __syncthreads();
-    if (filtered && pt) {
-#pragma unroll
-      for (int k = 0; k < M; ++k) {
-        sC[le][s][k][slot] = c[k];
-        u[((long)s * M + k) * EN + (long)e * NPT + slot] = c[k];
-      }
-    }
-    __syncthreads();
+    for (int k = 0; k < M; ++k) u[((long)s * M + k) * EN + (long)e * NPT + slot] = c[k];
   }
-  // element means of the four variables (every lane, from LDS)
-  double ub[4];
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    double acc = 0.0;
-#pragma unroll
-    for (int j = 0; j < NPT; ++j) acc += sC[le][v][0][j] * P.tab.swts[j];
-    ub[v] = acc;
-  }
-  const double pb = (P.gamma - 1.0) * (ub[3] - 0.5 * (ub[1] * ub[1] + ub[2] * ub[2]) / ub[0]);
-  const bool real = ub[0] > 0.0 && pb > 0.0 && isfinite(ub[0]) && isfinite(ub[1]) && isfinite(ub[2]) &&
-                    isfinite(ub[3]);
-  const double eps = fmin(1e-8, fmin(ub[0], pb));
-  // flux-point lanes: interpolate all modes to their flux point
-  double a[M];
-#pragma unroll
-  for (int k = 0; k < M; ++k) {
-    double acc = 0.0;
-    if (fp) {
-#pragma unroll
-      for (int j = 0; j < NPT; ++j) acc += P.tri_Lf[slot * NPT + j] * sC[le][s][k][j];
-    }
-    a[k] = acc;
-  }
-  // rigorous bounds at the solution point and the flux point of this lane
-  auto bound_ok = [&](const double* coef, bool on) {
-    double mn = coef[0], vr = 0.0;
-#pragma unroll
-    for (int k = 1; k < M; ++k) vr += fabs(coef[k]) * P.tab.cmax[k];
-    double MN[4], VR[4];
-    quad_gather(mn, MN);
-    quad_gather(vr, VR);
-    if (!on) return true;
-    const double rlo = MN[0] - VR[0];
-    const double tol_r = 1e-10 * (fabs(MN[0]) + VR[0]);
-    if (!(rlo > eps + tol_r)) return false;
-    double m2 = 0.0;
-#pragma unroll
-    for (int v = 1; v < 3; ++v) {
-      const double mx = fabs(MN[v]) + VR[v];
-      m2 += mx * mx;
-    }
-    const double ke = 0.5 * m2 / rlo;
-    const double elo = MN[3] - VR[3];
-    const double plo = (P.gamma - 1.0) * (elo - ke);
-    const double tol_p = 1e-10 * (P.gamma - 1.0) * (fabs(MN[3]) + VR[3] + ke);
-    return plo > eps + tol_p;
-  };
-  const bool ok_sp = bound_ok(c, pt && real);
-  const bool ok_fp = bound_ok(a, fp && real);
-  // filtered, not to be limited: the traces of the filtered element
-  if (!do_limit) {
-    if (filtered && fp && Tm) {
-#pragma unroll
-      for (int k = 0; k < M; ++k) Tm[(((long)s * M + k) * E + e) * NF + slot] = a[k];
-    }
-    return;
-  }
-  if (active && real && !(ok_sp && ok_fp)) {
-    sNeed[le] = 1;
-    sAny = 1;
-  }
-  if (active && !real && slot == 0 && s == 0) atomicOr(P.status, kStatusNotRealizable);
-  __syncthreads();
-  // filtered elements that the limiter leaves alone: their traces as filtered
-  if (filtered && fp && Tm && !sNeed[le]) {
-#pragma unroll
-    for (int k = 0; k < M; ++k) Tm[(((long)s * M + k) * E + e) * NF + slot] = a[k];
-  }
-  if (sAny) {
-    const bool need = active && real && sNeed[le];
-    // node-by-node minima of density and pressure over solution and flux points
-    double rmin = INFINITY, pmin = INFINITY;
-    for (int q = 0; q < NQ; ++q) {
-      double vs = 0.0, vf = 0.0;
-#pragma unroll
-      for (int k = 0; k < M; ++k) {
-        const double ph = P.tab.Phi[k * NQ + q];
-        vs += ph * c[k];
-        vf += ph * a[k];
-      }
-      double Us[4], Uf[4];
-      quad_gather(vs, Us);
-      quad_gather(vf, Uf);
-      if (need && pt) {
-        rmin = fmin(rmin, Us[0]);
-        pmin = fmin(pmin, (P.gamma - 1.0) * (Us[3] - 0.5 * (Us[1] * Us[1] + Us[2] * Us[2]) / Us[0]));
-      }
-      if (need && fp) {
-        rmin = fmin(rmin, Uf[0]);
-        pmin = fmin(pmin, (P.gamma - 1.0) * (Uf[3] - 0.5 * (Uf[1] * Uf[1] + Uf[2] * Uf[2]) / Uf[0]));
-      }
-    }
-    if (active) sMin[le][rem] = rmin;
-    __syncthreads();
-    if (active && rem == 0) {
-      double r = INFINITY;
-      for (int i = 0; i < Sh::TPE; ++i) r = fmin(r, sMin[le][i]);
-      sRed[le][0][0] = r;
-    }
-    __syncthreads();
-    if (active) sMin[le][rem] = pmin;
-    __syncthreads();
-    if (active && rem == 0) {
-      double r = INFINITY;
-      for (int i = 0; i < Sh::TPE; ++i) r = fmin(r, sMin[le][i]);
-      sRed[le][0][1] = r;
-    }
-    __syncthreads();
-    const double Rmin = sRed[le][0][0], Pmin = sRed[le][0][1];
-    const bool act = need && fmin(Rmin, Pmin) < eps;
-    const double beta1 = (Rmin >= eps) ? 1.0 : (ub[0] - eps) / (ub[0] - Rmin);
-    // beta2: smallest root over the points whose pressure stays below eps after beta1
-    double bmin = 1.0;
-    for (int q = 0; q < NQ; ++q) {
-      double vs = 0.0, vf = 0.0;
-#pragma unroll
-      for (int k = 0; k < M; ++k) {
-        const double ph = P.tab.Phi[k * NQ + q];
-        vs += ph * c[k];
-        vf += ph * a[k];
-      }
-      double Us[4], Uf[4];
-      quad_gather(vs, Us);
-      quad_gather(vf, Uf);
-      if (act && pt) {
-        Us[0] = beta1 * (Us[0] - ub[0]) + ub[0];
-        if ((P.gamma - 1.0) * (Us[3] - 0.5 * (Us[1] * Us[1] + Us[2] * Us[2]) / Us[0]) < eps)
-          bmin = fmin(bmin, pressure_root<kEuler2>(ub, Us, eps, P.gamma));
-      }
-      if (act && fp) {
-        Uf[0] = beta1 * (Uf[0] - ub[0]) + ub[0];
-        if ((P.gamma - 1.0) * (Uf[3] - 0.5 * (Uf[1] * Uf[1] + Uf[2] * Uf[2]) / Uf[0]) < eps)
-          bmin = fmin(bmin, pressure_root<kEuler2>(ub, Uf, eps, P.gamma));
-      }
-    }
-    if (active) sMin[le][rem] = bmin;
-    __syncthreads();
-    if (active && rem == 0) {
-      double r = 1.0;
-      for (int i = 0; i < Sh::TPE; ++i) r = fmin(r, sMin[le][i]);
-      sRed[le][1][0] = r;
-    }
-    __syncthreads();
-    const double beta2 = sRed[le][1][0];
-    if (act && pt) {
-#pragma unroll
-      for (int k = 0; k < M; ++k) {
-        const double m0 = (k == 0) ? 1.0 : 0.0;
-        double v = c[k];
-        if (s == 0) v = beta1 * (v - ub[0] * m0) + ub[0] * m0;
-        v = beta2 * (v - pick4(ub, s) * m0) + pick4(ub, s) * m0;
-        u[((long)s * M + k) * EN + (long)e * NPT + slot] = v;
-      }
-    }
-    if (need && !act && filtered && fp && Tm) {
-#pragma unroll
-      for (int k = 0; k < M; ++k) Tm[(((long)s * M + k) * E + e) * NF + slot] = a[k];
-    }
-    // the same affine map on the element's traces (the interpolation of a constant is
-    // the constant), when the caller keeps them
-    if (act && fp && Tm) {
-#pragma unroll
-      for (int k = 0; k < M; ++k) {
-        const double m0 = (k == 0) ? 1.0 : 0.0;
-        double v = a[k];
-        if (s == 0) v = beta1 * (v - ub[0] * m0) + ub[0] * m0;
-        v = beta2 * (v - pick4(ub, s) * m0) + pick4(ub, s) * m0;
-        Tm[(((long)s * M + k) * E + e) * NF + slot] = v;
-      }
-    }
-    if (active && rem == 0 && flags) flags[e] = act ? 1 : 0;
-    return;
-  }
-  if (active && rem == 0 && flags) flags[e] = 0;
 }
 
 template <int PD, int M, int NQ>
 hipError_t go_stage_tri(const KParams& P, const double* in, const double* u, const double* w, double* out, double cu,
-                        double cw, int rhs_only, double* Tm, int traces_ready, double* Tm_out, hipStream_t s) {
+                        double cw, int rhs_only, double* Tm, int traces_ready, double* Tm_out, const TriPost& post,
+                        hipStream_t s) {
   using Sh = TriShape<PD>;
   if (!traces_ready) {
     const long nt = 4l * M * P.E;
@@ -813,16 +826,17 @@ hipError_t go_stage_tri(const KParams& P, const double* in, const double* u, con
   }
   const unsigned grid = (unsigned)((P.E + Sh::EPB - 1) / Sh::EPB);
   hipLaunchKernelGGL((k_stage_tri<PD, M, NQ>), dim3(grid), dim3(256), 0, s, P, in, u, w, out, cu, cw, rhs_only,
-                     (const double*)Tm, Tm_out);
+                     (const double*)Tm, Tm_out, post);
   return hipGetLastError();
 }
 
 template <int PD>
 hipError_t dispatch_mq(const KParams& P, const double* in, const double* u, const double* w, double* out, double cu,
-                       double cw, int rhs_only, double* Tm, int traces_ready, double* Tm_out, hipStream_t s) {
+                       double cw, int rhs_only, double* Tm, int traces_ready, double* Tm_out, const TriPost& post,
+                       hipStream_t s) {
 #define FRSG_TRI_MQ(MM, QQ)                                                                                 \
   if (P.M == MM && P.Nq == QQ)                                                                               \
-    return go_stage_tri<PD, MM, QQ>(P, in, u, w, out, cu, cw, rhs_only, Tm, traces_ready, Tm_out, s);
+    return go_stage_tri<PD, MM, QQ>(P, in, u, w, out, cu, cw, rhs_only, Tm, traces_ready, Tm_out, post, s);
   FRSG_TRI_MQ(15, 25) FRSG_TRI_MQ(10, 16) FRSG_TRI_MQ(6, 9) FRSG_TRI_MQ(5, 5) FRSG_TRI_MQ(3, 4)
 #undef FRSG_TRI_MQ
   return hipErrorInvalidValue;
@@ -831,14 +845,12 @@ hipError_t dispatch_mq(const KParams& P, const double* in, const double* u, cons
 }  // namespace
 
 template <int PD>
-hipError_t dispatch_limit(const KParams& P, double* u, unsigned char* flags, double* Tm, int do_filter, int do_limit,
-                          unsigned char* fflags, hipStream_t s) {
+hipError_t dispatch_limit(const KParams& P, double* u, const TriPost& post, hipStream_t s) {
   using Sh = TriShape<PD>;
   const unsigned grid = (unsigned)((P.E + Sh::EPB - 1) / Sh::EPB);
 #define FRSG_TRI_LIM(MM, QQ)                                                                        \
   if (P.M == MM && P.Nq == QQ) {                                                                     \
-    hipLaunchKernelGGL((k_limit_tri<PD, MM, QQ>), dim3(grid), dim3(256), 0, s, P, u, flags, Tm, do_filter,  \
-                       do_limit, fflags);                                                               \
+    hipLaunchKernelGGL((k_limit_tri<PD, MM, QQ>), dim3(grid), dim3(256), 0, s, P, u, post);              \
     return hipGetLastError();                                                                        \
   }
   FRSG_TRI_LIM(15, 25) FRSG_TRI_LIM(10, 16) FRSG_TRI_LIM(6, 9) FRSG_TRI_LIM(5, 5) FRSG_TRI_LIM(3, 4)
@@ -859,32 +871,31 @@ bool tri_fused_supported(const KParams& P) {
 // traces of `out` are written there for the next stage
 hipError_t launch_stage_tri(const KParams& P, const double* in, const double* u, const double* w, double* out,
                             double cu, double cw, int rhs_only, double* Tm, int traces_ready, double* Tm_out,
-                            hipStream_t s) {
-  if (!tri_fused_supported(P)) return hipErrorInvalidValue;
+                            hipStream_t s, const TriPost& post) {
+  if (!tri_fused_supported(P) || (post.filter && P.filter == FRSG_FILTER_LASSO) || (rhs_only && (post.filter || post.limit)))
+    return hipErrorInvalidValue;
   switch (P.nfp - 1) {
-    case 1: return dispatch_mq<1>(P, in, u, w, out, cu, cw, rhs_only, Tm, traces_ready, Tm_out, s);
-    case 2: return dispatch_mq<2>(P, in, u, w, out, cu, cw, rhs_only, Tm, traces_ready, Tm_out, s);
-    case 3: return dispatch_mq<3>(P, in, u, w, out, cu, cw, rhs_only, Tm, traces_ready, Tm_out, s);
-    case 4: return dispatch_mq<4>(P, in, u, w, out, cu, cw, rhs_only, Tm, traces_ready, Tm_out, s);
+    case 1: return dispatch_mq<1>(P, in, u, w, out, cu, cw, rhs_only, Tm, traces_ready, Tm_out, post, s);
+    case 2: return dispatch_mq<2>(P, in, u, w, out, cu, cw, rhs_only, Tm, traces_ready, Tm_out, post, s);
+    case 3: return dispatch_mq<3>(P, in, u, w, out, cu, cw, rhs_only, Tm, traces_ready, Tm_out, post, s);
+    case 4: return dispatch_mq<4>(P, in, u, w, out, cu, cw, rhs_only, Tm, traces_ready, Tm_out, post, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 // positivity limiter in place with the fused lane layout (the fused (p, M, N_q) set)
-hipError_t launch_post_tri(const KParams& P, double* u, int do_filter, int do_limit, unsigned char* flag_filt,
-                           unsigned char* flag_lim, double* Tm, hipStream_t s) {
-  if (!tri_fused_supported(P) || P.filter == FRSG_FILTER_LASSO) return hipErrorInvalidValue;
+hipError_t launch_limit_tri(const KParams& P, double* u, unsigned char* flags, hipStream_t s) {
+  if (!tri_fused_supported(P)) return hipErrorInvalidValue;
+  TriPost post;
+  post.limit = 1;
+  post.flag_lim = flags;
   switch (P.nfp - 1) {
-    case 1: return dispatch_limit<1>(P, u, flag_lim, Tm, do_filter, do_limit, flag_filt, s);
-    case 2: return dispatch_limit<2>(P, u, flag_lim, Tm, do_filter, do_limit, flag_filt, s);
-    case 3: return dispatch_limit<3>(P, u, flag_lim, Tm, do_filter, do_limit, flag_filt, s);
-    case 4: return dispatch_limit<4>(P, u, flag_lim, Tm, do_filter, do_limit, flag_filt, s);
+    case 1: return dispatch_limit<1>(P, u, post, s);
+    case 2: return dispatch_limit<2>(P, u, post, s);
+    case 3: return dispatch_limit<3>(P, u, post, s);
+    case 4: return dispatch_limit<4>(P, u, post, s);
     default: return hipErrorInvalidValue;
   }
-}
-
-hipError_t launch_limit_tri(const KParams& P, double* u, unsigned char* flags, double* Tm, hipStream_t s) {
-  return launch_post_tri(P, u, 0, 1, nullptr, flags, Tm, s);
 }
 
 hipError_t launch_cfl_tri_modal(const KParams& P, const double* u, hipStream_t s) {
