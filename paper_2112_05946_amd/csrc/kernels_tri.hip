@@ -679,6 +679,7 @@ __global__ void __launch_bounds__(256) k_stage_tri(KParams P, const double* __re
     }
   }
   const double dt = rhs_only ? 0.0 : *P.dt;
+  const bool do_post = post.filter || post.limit;
   if (pt) {
 #pragma unroll
     for (int k = 0; k < M; ++k) {
@@ -686,16 +687,17 @@ __global__ void __launch_bounds__(256) k_stage_tri(KParams P, const double* __re
       const double o = rhs_only ? acc[k] : cu * u[idx] + cw * (w[idx] + dt * acc[k]);
       acc[k] = o;
       sO[le][s][k][slot] = o;
+      if (!do_post) out[idx] = o;
     }
   }
   // the limiter after the stage, or the end-of-step filter and limiter, on the output
-  if (post.filter || post.limit) {
+  if (do_post) {
     __syncthreads();
     post_tri<PD, M, NQ>(P, acc, sO, sh, e, le, rem, active, post);
-  }
-  if (pt) {
+    if (pt) {
 #pragma unroll
-    for (int k = 0; k < M; ++k) out[((long)s * M + k) * EN + (long)e * NPT + slot] = acc[k];
+      for (int k = 0; k < M; ++k) out[((long)s * M + k) * EN + (long)e * NPT + slot] = acc[k];
+    }
   }
   if (!Tm_out) return;
   // modal traces of the output at the flux points, for the next stage's neighbours
