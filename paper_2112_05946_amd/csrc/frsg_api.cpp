@@ -967,7 +967,18 @@ static fr_sg_status step_rk(fr_sg_ctx* ctx, double* u, double dt, double* dt_use
   uint8_t* f2 = flags ? flags + 2 * E : nullptr;
   uint8_t* f3 = flags ? flags + 3 * E : nullptr;
   const bool filt = ctx->prob.filter != FRSG_FILTER_NONE;
-  if (ctx->fused) {
+  if (ctx->fused_tri) {
+    // filter and limiter in one element-wise pass
+    if (!filt && f2) FRSG_TRY_HIP(launch_fill_flags(f2, E, s), ctx);
+    if (!ctx->prob.limiter && f3) FRSG_TRY_HIP(launch_fill_flags(f3, E, s), ctx);
+    TriPost p;
+    p.filter = filt ? 1 : 0;
+    p.limit = ctx->prob.limiter ? 1 : 0;
+    p.flag_filt = filt ? f2 : nullptr;
+    p.flag_lim = ctx->prob.limiter ? f3 : nullptr;
+    if (p.filter || p.limit)
+      if ((st = timed(ctx, "filter_limiter", 2 * sb, [&] { return launch_post_tri(K, u, p, s); }))) return st;
+  } else if (ctx->fused) {
     // filter and limiter in one element-wise pass
     if (!filt && f2) FRSG_TRY_HIP(launch_fill_flags(f2, E, s), ctx);
     if (!ctx->prob.limiter && f3) FRSG_TRY_HIP(launch_fill_flags(f3, E, s), ctx);

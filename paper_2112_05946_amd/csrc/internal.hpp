@@ -273,6 +273,8 @@ hipError_t launch_stage_tri(const KParams& P, const double* in, const double* u,
                             hipStream_t s, const TriPost& post = TriPost());
 // positivity limiter on triangles with the fused lane layout (fused (p, M, N_q) set)
 hipError_t launch_limit_tri(const KParams& P, double* u, unsigned char* flags, hipStream_t s);
+// the sensor-gated filter and/or the limiter of `post` as a pass of its own (same set)
+hipError_t launch_post_tri(const KParams& P, double* u, const TriPost& post, hipStream_t s);
 // CFL maximum of a modal state on triangles into P.lam_bits
 hipError_t launch_cfl_tri_modal(const KParams& P, const double* u, hipStream_t s);
 // explicit Runge-Kutta stage combination: out = u + dt sum_j a[j] K[j] (flat state of n doubles)

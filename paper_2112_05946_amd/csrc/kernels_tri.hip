@@ -785,7 +785,7 @@ __global__ void __launch_bounds__(256) k_cfl_tri_mq(KParams P, const double* __r
   if (threadIdx.x == 0) atomicMax(P.lam_bits, (unsigned long long)__double_as_longlong(sm[0]));
 }
 
-// the limiter in place on a state, as a pass of its own
+// the filter and/or limiter in place on a state, as a pass of its own
 template <int PD, int M, int NQ>
 __global__ void __launch_bounds__(256) k_limit_tri(KParams P, double* __restrict__ u, TriPost post) {
   using Sh = TriShape<PD>;
@@ -885,12 +885,10 @@ hipError_t launch_stage_tri(const KParams& P, const double* in, const double* u,
   }
 }
 
-// positivity limiter in place with the fused lane layout (the fused (p, M, N_q) set)
-hipError_t launch_limit_tri(const KParams& P, double* u, unsigned char* flags, hipStream_t s) {
-  if (!tri_fused_supported(P)) return hipErrorInvalidValue;
-  TriPost post;
-  post.limit = 1;
-  post.flag_lim = flags;
+// the sensor-gated filter and/or the limiter in place with the fused lane layout (the
+// fused (p, M, N_q) set)
+hipError_t launch_post_tri(const KParams& P, double* u, const TriPost& post, hipStream_t s) {
+  if (!tri_fused_supported(P) || (post.filter && P.filter == FRSG_FILTER_LASSO)) return hipErrorInvalidValue;
   switch (P.nfp - 1) {
     case 1: return dispatch_limit<1>(P, u, post, s);
     case 2: return dispatch_limit<2>(P, u, post, s);
@@ -898,6 +896,13 @@ hipError_t launch_limit_tri(const KParams& P, double* u, unsigned char* flags, h
     case 4: return dispatch_limit<4>(P, u, post, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_limit_tri(const KParams& P, double* u, unsigned char* flags, hipStream_t s) {
+  TriPost post;
+  post.limit = 1;
+  post.flag_lim = flags;
+  return launch_post_tri(P, u, post, s);
 }
 
 hipError_t launch_cfl_tri_modal(const KParams& P, const double* u, hipStream_t s) {
