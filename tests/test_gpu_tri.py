@@ -9,6 +9,7 @@ import pytest
 
 from gpu_util import RTOL_FP64, announce, rel_l2, solver_for, to_dev, to_np
 from oracle import stepper as ostep
+from oracle import stabilize as ost
 from oracle import tri as otri
 from oracle.initial import project_initial
 from oracle.problem import Problem
@@ -180,6 +181,37 @@ def test_tri_vortex_full_size_sampled_and_properties():
     dtd, _ = sol.step(u)
     sol.sync()
     assert np.isfinite(to_np(u)).all() and to_np(dtd)[0] > 0
+
+
+def test_tri_shock_vortex_full_size_properties():
+    """The triangle shock-vortex workload at its benchmark size (16,384 triangles, p = 3,
+    15 modes, 25 nodes), stepped as the benchmark steps it (one multi-step call, the
+    limiter, detector and filter in the stage kernels), then one more step: the state
+    stays finite; the limiter's guarantee holds on every element (density and pressure
+    at every solution and flux point and random node at least eps, up to the rounding of
+    the state); the detector switches the filter on in the last step (the limiter need
+    not act: this flow stays well inside the admissible set at this resolution); the last
+    step's CFL dt equals the oracle's for the state it started from."""
+    cfg = inputs.tri_shock_vortex(64)
+    announce("tri_shock_vortex_full", cfg["mesh"]["xy"].shape[0])
+    prob = Problem.from_config(cfg)
+    T, R = build_tables(prob)
+    sol = solver_for(cfg)
+    u = sol.initial_state()
+    sol.steps(u, 9)
+    sol.sync()
+    u0 = to_np(u)
+    dtd, flags = sol.step(u)
+    sol.sync()
+    u1 = to_np(u)
+    g = to_np(flags).reshape(4, prob.E)
+    assert np.isfinite(u0).all() and np.isfinite(u1).all()
+    for st in (u0, u1):
+        m, scale = ost.limiter_margin(prob, T, R, st)
+        assert np.all(m >= -1e-13 * scale), (m.min(), np.argmin(m))
+    assert g[2].sum() > 0, g.sum(axis=1)
+    rdt = ostep.cfl_dt(prob, T, R, u0)
+    assert abs(to_np(dtd)[0] / rdt - 1.0) < 1e-13, (to_np(dtd)[0], rdt)
 
 
 # ----------------------------------------------------------------------------
