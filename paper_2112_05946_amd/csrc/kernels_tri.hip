@@ -304,16 +304,7 @@ __device__ __forceinline__ void quad_gather(double v, double* all) {
   all[3] = quad_bcast<3>(v);
 }
 
-// End-of-stage work on triangles with the stage kernel's lane layout: the sensor-gated
-// modal filter (Sec. 4.1, 4.2) and the positivity limiter (Sec. 4.3).  Lane (slot, s)
-// keeps the coefficients c[] of variable s at solution point `slot`; sC holds those of
-// the block's elements.  The limiter decision first uses rigorous bounds per point
-// (|Phi_k(z_q)| <= cmax_k, a relative margin of 1e-10 for their rounding) at the
-// solution point and, as a flux-point lane, at flux point `slot`; only blocks holding an
-// element whose bound fails run the node-by-node minimum and the pressure roots, so the
-// decision is the node-by-node one.  The element mean is the coefficient of the
-// constant mode.  c[] and sC are updated in place; returns whether the lane's element
-// changed.  Every thread of the block calls it, with sC complete and visible.
+// LDS of the end-of-stage work below, per block
 template <int PD, int M>
 struct TriPostShared {
   using Sh = TriShape<PD>;
@@ -323,6 +314,17 @@ struct TriPostShared {
   int filt[Sh::EPB], need[Sh::EPB], any;
 };
 
+// End-of-stage work on triangles with the stage kernel's lane layout: the sensor-gated
+// modal filter (Sec. 4.1, 4.2), then the positivity limiter (Sec. 4.3).  Lane (slot, s)
+// keeps the coefficients c[] of variable s at solution point `slot`; sC holds those of
+// the block's elements.  The limiter decision first uses rigorous bounds per point
+// (|Phi_k(z_q)| <= cmax_k, a relative margin of 1e-10 for their rounding) at the
+// solution point and, as a flux-point lane, at flux point `slot`; only blocks holding an
+// element whose bound fails run the node-by-node minimum and the pressure roots, so the
+// decision is the node-by-node one.  The element mean is the constant chaos mode
+// averaged with the triangle's quadrature weights.  c[] and sC are updated in place;
+// returns whether the lane's element changed.  Every thread of the block calls it, with
+// sC complete and visible.
 template <int PD, int M, int NQ>
 __device__ __forceinline__ bool post_tri(const KParams& P, double (&c)[M],
                                          double (&sC)[TriShape<PD>::EPB][4][M][TriShape<PD>::NPT],
