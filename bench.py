@@ -40,7 +40,7 @@ KERNEL_NAME = {"fp64": "k_stage2d<15, 25, double, 0>", "fp32": "k_stage2d<15, 25
 
 def traffic_for(kernel, alg_bytes):
     """HBM bytes per launch of `kernel` measured with rocprofv3 counters (FETCH_SIZE, WRITE_SIZE,
-    scaled by a copy kernel's readings), if they were taken on this build's kernel source."""
+    scaled by a copy kernel's readings), if they were taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -321,7 +321,7 @@ def main():
                     help="run only this one of the other workloads (for profiling) and print its record")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the multi-GPU halo exchange is not built); "
+        print("bench.py: the library runs on one GPU only (the multi-GPU halo exchange is not built); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
