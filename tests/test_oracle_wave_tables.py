@@ -98,8 +98,8 @@ def test_random_modes_follow_the_exact_solution():
     assert np.max(np.abs(u[0, 2:])) < 1e-13
 
 
-def test_harness_step_rule_and_norms():
-    """The GPU harness's host helpers: the step count and size that land on t = 2 at
+def test_convergence_step_rule_and_norms():
+    """The convergence study's host helpers: the step count and size that land on t = 2 at
     dt = 0.1 dx, and the dx-weighted norms of the expectation's error."""
     from paper_2112_05946_amd.convergence import wave_norms, wave_steps
     for nx in (4, 8, 16, 32, 64):
