@@ -30,8 +30,11 @@ sensor-gated filter at the end of the step (the paper's forward-Euler ordering
 paper's RK4, Tsitouras 5(4) and Bogacki-Shampine 3(2) tableaux at the same
 CFL step.
 
-Everything is float64 NumPy.  Functions that no independent pin checks carry
-the words "parity unpinned" in their docstring.
+Everything is float64 NumPy.  Every function is pinned by tests that do not
+restate it (closed forms, library routines, an independent discontinuous
+Galerkin weak form, published stability limits, the paper's printed tables);
+a function without such a pin would say "parity unpinned" in its docstring,
+and none does.
 """
 
 from .tables import Tables1D, RandomTables, build_tables  # noqa: F401

@@ -107,6 +107,32 @@ def vortex_ic(x, y, z1, z2, gamma=GAMMA):
     return _cons2d(rho, up[1] + amp * st, -amp * ct, rho * T, gamma)
 
 
+# isentropic vortex carried by a uniform flow through the periodic rectangle
+# [0, 2] x [0, 1] (the vortex form of Sec. 5.4 with a wider, faster-decaying
+# core, so the rectangle is periodic to ~1e-6): core radius 0.13, mu = 1,
+# strength 0.3, free stream rho = p = 1, velocity (1 + 0.001 z1, 0.5).  The
+# exact solution at time t is the initial field translated by the free-stream
+# velocity of each random node.
+VC_RC = 0.13
+VC_MU = 1.0
+VC_ZETA = 0.3
+VC_U = (1.0, 0.5)
+VC_DELTA = 0.001
+
+
+def vortex_convection_exact(x, y, z1, t, gamma=GAMMA):
+    """Conservative state of the convected vortex at time t (points x, y; random z1)."""
+    ui = VC_U[0] + VC_DELTA * z1
+    vi = VC_U[1] + 0.0 * z1
+    dx = (x - (1.0 + ui * t) + 1.0) % 2.0 - 1.0
+    dy = (y - (0.5 + vi * t) + 0.5) % 1.0 - 0.5
+    eta2 = (dx * dx + dy * dy) / (VC_RC * VC_RC)
+    amp = VC_ZETA * np.exp(VC_MU * (1.0 - eta2)) / VC_RC
+    T = 1.0 - (gamma - 1.0) * VC_ZETA ** 2 / (4.0 * VC_MU * gamma) * np.exp(2.0 * VC_MU * (1.0 - eta2))
+    rho = T ** (1.0 / (gamma - 1.0))
+    return _cons2d(rho, ui + amp * dy, vi - amp * dx, rho * T, gamma)
+
+
 def initial_condition(name, x, y, z, gamma=GAMMA):
     """Conservative initial data at points x, y (same shape) and random z[..., rdim]."""
     z1 = z[..., 0]
@@ -125,6 +151,8 @@ def initial_condition(name, x, y, z, gamma=GAMMA):
         # rho = 1 + 0.2 sin(2 pi (x + y)), velocity (1 + 0.1 z1, 0.5), p = 1
         rho = 1.0 + 0.2 * np.sin(2.0 * np.pi * (x + y))
         return _cons2d(rho, 1.0 + 0.1 * z1, 0.5 + 0.0 * x, 1.0 + 0.0 * x, gamma)
+    if name == "vortex_convection":
+        return vortex_convection_exact(x, y, z1, 0.0, gamma)
     if name == "tri_vortex":
         z2 = z[..., 1] if z.shape[-1] > 1 else np.zeros_like(z1)
         return vortex_ic(x, y, z1, z2, gamma)
@@ -255,6 +283,13 @@ def tri_density_wave(n, p=2, perturb=0.15, seed=7, gpc_order=3, nq1d=4):
 
 CONFIGS = {c["name"]: c for c in (ADVECTION, WAVE, BURGERS, SOD, SHOCK_VORTEX, BURGERS_ADJOINT, BURGERS_LASSO, SOD_LASSO,
                                   SOD_HLL, SHOCK_VORTEX_HLL, SOD_HLL_BS3, SHOCK_VORTEX_HLL_BS3)}
+
+
+def vortex_convection(n, p, gpc_order=1, nq1d=2, cfl=0.15):
+    """The convected vortex on n x n cells of 2 x 1 aspect ratio (dx = 2 dy), no filter or limiter."""
+    return dict(name="vortex_convection", equation="euler2d", ic="vortex_convection", nx=n, ny=n, p=p,
+                xlo=0.0, xhi=2.0, ylo=0.0, yhi=1.0, rdim=1, gpc_order=gpc_order, nq1d=nq1d, cfl=cfl,
+                bc=["periodic"] * 4, filter="none", limiter=False)
 
 
 def small(cfg, nx, ny=None, **kw):

@@ -3,7 +3,7 @@
 import numpy as np
 import pytest
 
-from indep import dg_weak_rhs_1d
+from indep import chaos, dg_weak_rhs_1d, dg_weak_rhs_2d_euler
 from oracle.fr import rhs
 from oracle.problem import Problem
 from oracle.tables import build_tables
@@ -95,11 +95,12 @@ def test_2d_y_independent_equals_1d(bcy):
 
 
 def test_2d_transpose_symmetry():
-    """Swapping x<->y (and the momenta) maps the RHS onto its transpose."""
+    """Swapping x<->y (and the momenta) maps the RHS onto its transpose; the cells are
+    0.2 x 0.3, so a Jacobian taken from the wrong direction breaks the symmetry."""
     n, nx, ny = 4, 5, 3
     kw = dict(equation="euler2d", p=n - 1, gpc_order=2, nq1d=3, rdim=2)
-    pa = _prob(nx=nx, ny=ny, xhi=1.0, yhi=0.6, bc=["periodic", "periodic", "reflect", "reflect"], **kw)
-    pb = _prob(nx=ny, ny=nx, xhi=0.6, yhi=1.0, bc=["reflect", "reflect", "periodic", "periodic"], **kw)
+    pa = _prob(nx=nx, ny=ny, xhi=1.0, yhi=0.9, bc=["periodic", "periodic", "reflect", "reflect"], **kw)
+    pb = _prob(nx=ny, ny=nx, xhi=0.9, yhi=1.0, bc=["reflect", "reflect", "periodic", "periodic"], **kw)
     T, R = build_tables(pa)
     ua = inputs.fuzz_euler(2, R.M, pa.E, n * n, seed=11)
 
@@ -111,6 +112,59 @@ def test_2d_transpose_symmetry():
     da = rhs(pa, T, R, ua)
     db = rhs(pb, T, R, tr(ua, ny, nx))
     assert np.max(np.abs(db - tr(da, ny, nx))) < 1e-11 * np.max(np.abs(da))
+
+
+def _to2d_xconst(u1, nx, n):
+    """Embed a 1D Euler state along y as an x-independent 2D state (mx = 0, my = m)."""
+    S, M, E, _ = u1.shape
+    u2 = np.zeros((4, M, E, nx, n, n))
+    for s_src, s_dst in ((0, 0), (1, 2), (2, 3)):
+        u2[s_dst] = u1[s_src][:, :, None, :, None]
+    return u2.reshape(4, M, E * nx, n * n)
+
+
+@pytest.mark.parametrize("bcx", ["periodic", "reflect"])
+def test_2d_x_independent_equals_1d_along_y(bcx):
+    """An x-independent 2D Euler problem on 0.35 x 0.15 cells is the 1D problem along y
+    with the momenta swapped (Sec. 3.5 tensor extension, y part)."""
+    p, order, nq = 3, 3, 4
+    p1 = _prob(equation="euler1d", p=p, gpc_order=order, nq1d=nq, nx=6, xlo=0.0, xhi=0.9)
+    p2 = _prob(equation="euler2d", p=p, gpc_order=order, nq1d=nq, nx=4, ny=6, xhi=1.4, yhi=0.9,
+               rdim=1, bc=[bcx, bcx, "periodic", "periodic"])
+    T1, R1 = build_tables(p1)
+    T2, R2 = build_tables(p2)
+    u1 = inputs.fuzz_euler(1, R1.M, p1.E, p + 1, seed=8)
+    d1 = rhs(p1, T1, R1, u1)
+    d2 = rhs(p2, T2, R2, _to2d_xconst(u1, 4, p + 1))
+    ref = _to2d_xconst(d1, 4, p + 1)
+    assert np.max(np.abs(d2 - ref)) < 1e-11 * np.max(np.abs(ref))
+
+
+_BC2 = [["periodic"] * 4, ["dirichlet", "outflow", "reflect", "reflect"],
+        ["reflect", "dirichlet", "outflow", "dirichlet"]]
+_ST2 = [[1.0, 0.3, -0.1, 2.6], [0.9, 0.1, 0.05, 2.2], [1.1, -0.2, 0.1, 2.5], [0.95, 0.0, 0.2, 2.4]]
+
+
+@pytest.mark.parametrize("bc", _BC2)
+@pytest.mark.parametrize("p,rdim,order,nq", [(1, 1, 3, 5), (2, 2, 2, 3), (3, 1, 3, 5), (3, 2, 2, 4)])
+def test_2d_fr_radau_equals_dg_weak_form_rectangles(bc, p, rdim, order, nq):
+    """2D FR with Radau corrections == tensor nodal DG weak form (Huynh; Sec. 3.5) on
+    0.2 x 0.5 cells, genuinely 2D fuzz data, every boundary kind."""
+    prob = _prob(equation="euler2d", nx=5, ny=4, p=p, gpc_order=order, nq1d=nq, rdim=rdim,
+                 xlo=0.0, xhi=1.0, ylo=0.0, yhi=2.0, bc=bc, bc_state=_ST2)
+    T, R = build_tables(prob)
+    u = inputs.fuzz_euler(2, R.M, prob.E, (p + 1) ** 2, seed=4 + p)
+    got = rhs(prob, T, R, u)
+    # the chaos basis on the tensor rule from numpy's Legendre routines
+    z, wq, Phi1 = chaos(order, nq)
+    if rdim == 1:
+        Phi, w = Phi1, wq
+    else:
+        degs = [(a, t - a) for t in range(order + 1) for a in range(t, -1, -1)]
+        Phi = np.array([np.kron(Phi1[b], Phi1[a]) for a, b in degs])   # node q = a + nq b
+        w = np.kron(wq, wq)
+    ref = dg_weak_rhs_2d_euler(u, p, len(w), Phi, w, 5, 4, prob.dx, prob.dy, bc, _ST2)
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
 
 
 def test_linear_advection_modes_decouple():
