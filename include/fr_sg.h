@@ -26,15 +26,15 @@
  * i.e. the gPC coefficients (Sec. 2.1, Eq. polynomial chaos) held at the FR
  * solution points (Sec. 3.2) of each element.
  *
- * Ownership: the caller owns every state, right-hand-side, adjoint, flag and
- * time-step buffer.  The library owns the context, its operator tables and a
- * workspace allocated once by fr_sg_init (two stage states plus nodal
- * scratch, or, on the fused 2D path, two buffers of modal face traces on
- * tile boundaries that each stage launch writes for the next, or, on the
- * fused triangle path, two buffers of modal traces at the flux points; the
- * tableau integrators add one right-hand-side buffer per stage; triangle
- * meshes add their geometry and neighbour table; fr_sg_query reports its
- * size) and freed by fr_sg_destroy.  No other call allocates device memory.
+ * Ownership: the caller owns every device buffer: states, right-hand sides,
+ * adjoints, flags, time steps, and the workspace handed to fr_sg_init (size
+ * from fr_sg_workspace_size).  The workspace holds the operator tables (read
+ * by the kernels through the scalar cache, as constant data), the device
+ * scalars (time step, CFL accumulators, status word), the stage states of a
+ * step, and whatever the problem's path keeps between launches (face traces,
+ * nodal scratch, tableau stage buffers, adjoint vectors, triangle geometry).
+ * The library owns only the host-side context.  No entry point allocates or
+ * frees device memory.
  *
  * Errors: invalid or unsupported problems are rejected by fr_sg_init before
  * any launch.  Non-finite or non-realizable states met on the device are
@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define FRSG_ABI_VERSION 4
+#define FRSG_ABI_VERSION 5
 
 typedef int32_t fr_sg_status;
 #define FRSG_OK 0
@@ -116,9 +116,13 @@ typedef int32_t fr_sg_status;
  * projection) in FP32; state storage, the Runge-Kutta combination, detector,
  * filter, limiter and CFL reduction stay FP64.  Available where the fused 2D
  * Euler path applies (FR degree 3, nx divisible by 4, ny by 2); elsewhere
- * fr_sg_init returns FRSG_EUNSUPPORTED. */
+ * fr_sg_init returns FRSG_EUNSUPPORTED.
+ * FRSG_BF16_SPLIT: reserved for the chaos transforms on bfloat16 matrix cores
+ * with each operand split into a high and a low bfloat16 part; fr_sg_init
+ * returns FRSG_EUNSUPPORTED where it is not built. */
 #define FRSG_FP64 0
 #define FRSG_FP32_MIXED 1
+#define FRSG_BF16_SPLIT 2
 
 /* element shape (Sec. 3.1).  FRSG_ELEM_QUAD: the nx x ny Cartesian mesh of
  * [xlo, xhi] x [ylo, yhi] (or nx line elements in 1D).  FRSG_ELEM_TRI: an
@@ -169,12 +173,19 @@ typedef struct fr_sg_problem {
   double gamma;            /* ratio of specific heats                                 */
   int32_t filter;          /* FRSG_FILTER_*                                           */
   double alpha, s;         /* exponential filter strength and order                   */
+  double nstar;            /* exponential filter cutoff N* (>= 0) of Sec. 4.1.1: per dimension,
+                              modes with eta below eta_c are untouched and above it eta is
+                              replaced by (eta - eta_c) / (1 - eta_c), with eta_c = nstar / p
+                              in physical space (degree j / p per direction, total degree on
+                              triangles) and nstar / N_c in random space (|k| / N_c).  Needs
+                              nstar < p and nstar < N_c (N_c > 0); 0 filters every mode
+                              above the mean                                            */
   double eps1, eps2;       /* L2 filter damping of the last spatial / chaos mode      */
   int32_t sensor;          /* FRSG_SENSOR_*                                           */
   double s0, kappa;        /* detector parameters, Eq. (detector), s_e = log10(S_e)   */
   int32_t limiter;         /* 1: positivity-preserving limiter (Euler only)           */
   double cfl;              /* dt = cfl dx / ((p+1) lambda_max) (1D); 2D analogue      */
-  int32_t precision;       /* FRSG_FP64 or FRSG_FP32_MIXED                            */
+  int32_t precision;       /* FRSG_FP64, FRSG_FP32_MIXED or FRSG_BF16_SPLIT           */
   int32_t flux;            /* FRSG_FLUX_RUSANOV (Lax-Friedrichs) or FRSG_FLUX_HLL     */
   int32_t integrator;      /* FRSG_SSPRK3, FRSG_RK4, FRSG_RK_BS3, FRSG_RK_TSIT5       */
   int32_t element;         /* FRSG_ELEM_QUAD or FRSG_ELEM_TRI                         */
@@ -193,18 +204,31 @@ typedef struct fr_sg_info {
   int64_t n_dof;           /* S * M * E * N_sp                                        */
   int64_t state_bytes;     /* 8 * n_dof                                               */
   int64_t flags_len;       /* 4 * E: see fr_sg_step                                   */
-  int64_t workspace_bytes; /* device memory held by the context                       */
+  int64_t workspace_bytes; /* bytes of the caller's workspace the context uses           */
 } fr_sg_info;
 
 typedef struct fr_sg_ctx fr_sg_ctx;
 
-/* Validate the problem (Sec. 1 problem statement; Sec. 2.1 gPC degree and
- * quadrature; Sec. 3.1 mesh; Sec. 3.2 FR degree), build the operator tables
- * in FP64 on the host (Legendre-Gauss points, Lagrange derivative matrix,
- * Radau correction derivatives, Vandermonde matrix, chaos basis at the Gauss
- * nodes), upload them and allocate the workspace.  hip_stream: a hipStream_t
- * (NULL = default stream).  On failure *out is NULL and nothing is kept. */
-fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ctx** out);
+/* Bytes of device workspace that fr_sg_init needs for this problem (Sec. 1
+ * problem statement, Sec. 2.1 gPC degree and quadrature, Sec. 3.1 mesh,
+ * Sec. 3.2 FR degree).  Validates the problem exactly as fr_sg_init does and
+ * returns the same status for an invalid or unsupported one.  Host only: no
+ * HIP call, usable without a device. */
+fr_sg_status fr_sg_workspace_size(const fr_sg_problem* problem, int64_t* bytes);
+
+/* Validate the problem, build the operator tables in FP64 on the host
+ * (Legendre-Gauss points, Lagrange derivative matrix, Radau correction
+ * derivatives, Vandermonde matrix, chaos basis at the Gauss nodes, filter
+ * factors), and copy them into the caller's workspace on hip_stream (a
+ * hipStream_t; NULL = default stream), then synchronise that stream.
+ * workspace: device memory, 256-byte aligned, of workspace_bytes >=
+ * fr_sg_workspace_size(problem) bytes; owned by the caller, who keeps it
+ * alive and unused by anything else until fr_sg_destroy.  Allocates no
+ * device memory.  Invalid problems are rejected before any HIP call; a
+ * missing, short, misaligned or non-device workspace gives FRSG_EINVAL.  On
+ * failure *out is NULL and nothing is kept. */
+fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, void* workspace, int64_t workspace_bytes,
+                        fr_sg_ctx** out);
 
 /* Sizes of the problem (host struct out). */
 fr_sg_status fr_sg_query(const fr_sg_ctx* ctx, fr_sg_info* out);
@@ -252,8 +276,10 @@ fr_sg_status fr_sg_step(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, u
  * pass, so a time loop makes no extra pass over the state for it.  On the
  * fused 2D path the face traces of the neighbours that a stage needs come
  * from the previous launch in the same way (the first stage of the call
- * interpolates them from u); the result equals nsteps fr_sg_step calls with
- * the same time steps bit for bit. 
+ * interpolates them from u).  The end-of-step pass evaluates the wave speeds
+ * in another order than the separate CFL pass of fr_sg_step, so a time step
+ * can differ from that of a separate fr_sg_step call in the last bits; given
+ * equal time steps the states are equal bit for bit.
  * dt_used: device double[nsteps] or NULL; flags: device uint8[nsteps * 4 * E]
  * or NULL, laid out per step as in fr_sg_step. */
 fr_sg_status fr_sg_steps(fr_sg_ctx* ctx, double* u, int32_t nsteps, double* dt_used, uint8_t* flags);
@@ -305,7 +331,8 @@ fr_sg_status fr_sg_timing_enable(fr_sg_ctx* ctx, int enable);
 /* out: host array of `capacity` entries; *count receives the number written. */
 fr_sg_status fr_sg_timing_read(fr_sg_ctx* ctx, fr_sg_pass_time* out, int32_t capacity, int32_t* count);
 
-/* Free the context and its device memory.  NULL is accepted. */
+/* Free the host-side context (the caller then frees the workspace).  NULL is
+ * accepted. */
 fr_sg_status fr_sg_destroy(fr_sg_ctx* ctx);
 
 /* Text of the last error on this context (or of the last failed fr_sg_init

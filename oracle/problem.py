@@ -35,6 +35,7 @@ class Problem:
     filter: str = "none"
     alpha: float = 36.0
     s: float = 8.0
+    nstar: float = 0.0
     eps1: float = 0.6
     eps2: float = 0.6
     sensor: str = "detector"

@@ -14,9 +14,12 @@ flagged when theta < 0.99, i.e. S_e > S* = 10^(s0 - (2 kappa/pi) asin 0.98);
 a zero denominator is not flagged.
 
 Filters (Sec. 4.1): u~* = Lambda o u~ and back to nodal with V.
-* exponential (Sec. 4.1.1): lambda = exp(-alpha dt sum_i eta_i^s) with
-  eta = j/p per spatial direction and |k|/N_c in random space, cutoff N* = 0
-  (App. A);
+* exponential (Sec. 4.1.1): lambda = exp(-alpha dt sum_i t_i) with
+  eta = j/p per spatial direction (the total degree over p on triangles) and
+  |k|/N_c in random space; per dimension t = 0 below the cutoff
+  eta* = N*/p (N*/N_c in random space), t = ((eta - eta*)/(1 - eta*))^s from it
+  on, so the product of the per-dimension factors is 1 where every eta is below
+  its cutoff; N* = 0 (App. A) gives t = eta^s;
 * L2 (Sec. 4.1.2, Eq. filter function, Eq. l2 strength):
   lambda = 1 / (1 + alpha1 sum_d j_d^2 (j_d+1)^2 + alpha2 |k|^2 (|k|+1)^2),
   alpha1 = 1/(eps1 N_p^2 (N_p-1)^2), alpha2 = 1/(eps2 N_c^2 (N_c+1)^2);
@@ -119,10 +122,14 @@ def filter_strength(prob, T, R, dt):
     lam = np.ones((R.M, len(degs)))
     Nc = prob.gpc_order
     if prob.filter == "exp":
+        def term(eta, eta_star):
+            # modes below the cutoff are left untouched (Sec. 4.1.1)
+            return 0.0 if eta < eta_star else ((eta - eta_star) / (1.0 - eta_star)) ** prob.s
+
         for k in range(R.M):
-            ez = (R.kdeg[k] / Nc) ** prob.s if Nc > 0 else 0.0
+            ez = term(R.kdeg[k] / Nc, prob.nstar / Nc) if Nc > 0 else 0.0
             for j, d in enumerate(degs):
-                ex = sum((dj / prob.p) ** prob.s for dj in d)
+                ex = sum(term(dj / prob.p, prob.nstar / prob.p) for dj in d)
                 lam[k, j] = np.exp(-prob.alpha * dt * (ex + ez))
     elif prob.filter == "l2":
         # N_p solution points per direction: the damping of the top degree p is 1/(1 + 1/eps1)

@@ -16,7 +16,7 @@ from . import inputs
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfrsg.so")
 
-ABI_VERSION = 4
+ABI_VERSION = 5
 STATUS = {0: "OK", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "EDEVICE", -4: "ENONFINITE", -5: "ENOTREALIZABLE",
           -6: "EABI"}
 EQUATION = {"advection": 0, "burgers": 1, "euler1d": 2, "euler2d": 3}
@@ -25,7 +25,7 @@ FILTER = {"none": 0, "exp": 1, "l2": 2, "lasso": 3}
 FLUX = {"rusanov": 0, "hll": 1}
 INTEGRATOR = {"ssprk3": 0, "rk4": 1, "bs3": 2, "tsit5": 3}
 SENSOR = {"always": 0, "detector": 1}
-PRECISION = {"fp64": 0, "fp32": 1}
+PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2}
 ELEMENT = {"quad": 0, "tri": 1}
 
 
@@ -44,6 +44,7 @@ class Problem(ctypes.Structure):
         ("fr_degree", ctypes.c_int32), ("rdim", ctypes.c_int32), ("gpc_order", ctypes.c_int32),
         ("nq1d", ctypes.c_int32), ("adv_speed", ctypes.c_double), ("gamma", ctypes.c_double),
         ("filter", ctypes.c_int32), ("alpha", ctypes.c_double), ("s", ctypes.c_double),
+        ("nstar", ctypes.c_double),
         ("eps1", ctypes.c_double), ("eps2", ctypes.c_double),
         ("sensor", ctypes.c_int32), ("s0", ctypes.c_double), ("kappa", ctypes.c_double),
         ("limiter", ctypes.c_int32), ("cfl", ctypes.c_double), ("precision", ctypes.c_int32),
@@ -69,7 +70,8 @@ class PassTime(ctypes.Structure):
 # (name, restype, argtypes) of every symbol in include/fr_sg.h
 _VP = ctypes.c_void_p
 SYMBOLS = [
-    ("fr_sg_init", ctypes.c_int32, [ctypes.POINTER(Problem), _VP, ctypes.POINTER(_VP)]),
+    ("fr_sg_workspace_size", ctypes.c_int32, [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_int64)]),
+    ("fr_sg_init", ctypes.c_int32, [ctypes.POINTER(Problem), _VP, _VP, ctypes.c_int64, ctypes.POINTER(_VP)]),
     ("fr_sg_query", ctypes.c_int32, [_VP, ctypes.POINTER(Info)]),
     ("fr_sg_set_stream", ctypes.c_int32, [_VP, _VP]),
     ("fr_sg_points", ctypes.c_int32, [_VP, _VP, _VP, _VP]),
@@ -132,6 +134,7 @@ def problem_from_config(cfg, precision="fp64"):
     P.integrator = INTEGRATOR[cfg.get("integrator", "ssprk3")]
     P.alpha = float(cfg.get("alpha", 36.0))
     P.s = float(cfg.get("s", 8.0))
+    P.nstar = float(cfg.get("nstar", 0.0))
     P.eps1 = float(cfg.get("eps1", 0.6))
     P.eps2 = float(cfg.get("eps2", 0.6))
     P.sensor = SENSOR[cfg.get("sensor", "detector")]
@@ -177,7 +180,16 @@ class Solver:
         self._stream = s
         self._ctx = ctypes.c_void_p()
         prob = problem_from_config(cfg, precision)
-        st = self.lib.fr_sg_init(ctypes.byref(prob), ctypes.c_void_p(s.cuda_stream), ctypes.byref(self._ctx))
+        # the caller owns the workspace: a torch byte buffer of the size the library asks for
+        nbytes = ctypes.c_int64()
+        st = self.lib.fr_sg_workspace_size(ctypes.byref(prob), ctypes.byref(nbytes))
+        if st != 0:
+            raise FrsgError(st, self.lib.fr_sg_last_error(None).decode())
+        with torch.cuda.stream(s):
+            self.workspace = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=self.device)
+        st = self.lib.fr_sg_init(ctypes.byref(prob), ctypes.c_void_p(s.cuda_stream),
+                                 ctypes.c_void_p(self.workspace.data_ptr()), ctypes.c_int64(self.workspace.numel()),
+                                 ctypes.byref(self._ctx))
         if st != 0:
             raise FrsgError(st, self.lib.fr_sg_last_error(None).decode())
         info = Info()
@@ -196,6 +208,17 @@ class Solver:
         if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.device != self.device \
                 or tuple(t.shape) != self.shape or not t.is_contiguous():
             raise ValueError("%s must be a contiguous float64 %s tensor of shape %s" % (name, self.device, self.shape))
+        return t
+
+    def _aux(self, t, dtype, n, name):
+        """A caller-supplied output buffer: contiguous, on this device, of dtype, >= n entries."""
+        if t is None:
+            return None
+        torch = self._torch
+        if not isinstance(t, torch.Tensor) or t.dtype != dtype or t.device != self.device \
+                or not t.is_contiguous() or t.numel() < n:
+            raise ValueError("%s must be a contiguous %s %s tensor of at least %d entries"
+                             % (name, dtype, self.device, n))
         return t
 
     def empty_state(self):
@@ -240,6 +263,7 @@ class Solver:
 
     def limit(self, u, flags=None):
         self._state(u, "u")
+        self._aux(flags, self._torch.uint8, self.E, "flags")
         self._check(self.lib.fr_sg_limit(self._ctx, _ptr(u), _ptr(flags)))
         return flags
 
@@ -257,12 +281,17 @@ class Solver:
             dt_used = torch.empty(1, dtype=torch.float64, device=self.device)
         if flags is None:
             flags = torch.empty(4 * self.E, dtype=torch.uint8, device=self.device)
+        self._aux(dt_used, torch.float64, 1, "dt_used")
+        self._aux(flags, torch.uint8, 4 * self.E, "flags")
         self._check(self.lib.fr_sg_step(self._ctx, _ptr(u), float(dt) if dt else 0.0, _ptr(dt_used), _ptr(flags)))
         return dt_used, flags
 
     def steps(self, u, nsteps, dt_used=None, flags=None):
         """nsteps in-place CFL steps; the CFL maximum of each later step comes from the step before."""
         self._state(u, "u")
+        n = max(int(nsteps), 0)
+        self._aux(dt_used, self._torch.float64, n, "dt_used")
+        self._aux(flags, self._torch.uint8, 4 * self.E * n, "flags")
         self._check(self.lib.fr_sg_steps(self._ctx, _ptr(u), int(nsteps), _ptr(dt_used), _ptr(flags)))
 
     def adjoint_step(self, u_n, flags_n, dt, lam, dparams=None):
@@ -299,6 +328,7 @@ class Solver:
         if self._ctx:
             self.lib.fr_sg_destroy(self._ctx)
             self._ctx = ctypes.c_void_p()
+        self.workspace = None
 
     def __del__(self):
         try:

@@ -164,6 +164,11 @@ fr_sg_status validate(const fr_sg_problem& P, std::string& err) {
     err = "exponential filter needs alpha >= 0 and s > 0";
     return FRSG_EINVAL;
   }
+  if (P.filter == FRSG_FILTER_EXP &&
+      !(P.nstar >= 0.0 && P.nstar < P.fr_degree && (P.gpc_order == 0 || P.nstar < P.gpc_order))) {
+    err = "exponential filter cutoff needs 0 <= nstar < p and nstar < gpc_order";
+    return FRSG_EINVAL;
+  }
   if (P.filter == FRSG_FILTER_L2 && !(P.eps1 > 0.0 && P.eps2 > 0.0)) {
     err = "L2 filter needs eps1, eps2 > 0";
     return FRSG_EINVAL;
@@ -192,7 +197,7 @@ fr_sg_status validate(const fr_sg_problem& P, std::string& err) {
     err = "cfl must be positive";
     return FRSG_EINVAL;
   }
-  if (P.precision != FRSG_FP64 && P.precision != FRSG_FP32_MIXED) {
+  if (P.precision != FRSG_FP64 && P.precision != FRSG_FP32_MIXED && P.precision != FRSG_BF16_SPLIT) {
     err = "unknown precision";
     return FRSG_EINVAL;
   }
@@ -242,43 +247,17 @@ int fp32(const fr_sg_ctx* c) { return c->prob.precision == FRSG_FP32_MIXED ? 1 :
 
 }  // namespace
 
-extern "C" {
-
-fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ctx** out) {
-  if (!out) {
-    g_init_error = "out is NULL";
-    return FRSG_EINVAL;
-  }
-  *out = nullptr;
-  if (!problem) {
-    g_init_error = "problem is NULL";
-    return FRSG_EINVAL;
-  }
-  std::string err;
-  fr_sg_status st = validate(*problem, err);
-  if (st != FRSG_OK) {
-    g_init_error = err;
-    return st;
-  }
-  fr_sg_ctx* c = new (std::nothrow) fr_sg_ctx();
-  if (!c) {
-    g_init_error = "out of host memory";
-    return FRSG_EDEVICE;
-  }
-  c->prob = *problem;
-  c->stream = (hipStream_t)hip_stream;
-  if (!build_host_tables(c->prob, c->T, err)) {
-    g_init_error = err;
-    delete c;
-    return FRSG_EINVAL;
-  }
+// Host-side preparation shared by fr_sg_workspace_size and fr_sg_init: validate
+// the problem, build the operator tables, choose the kernel path and lay out the
+// caller's workspace.  Makes no HIP call.
+static fr_sg_status prepare(const fr_sg_problem& problem, fr_sg_ctx* c, std::string& err) {
+  fr_sg_status st = validate(problem, err);
+  if (st != FRSG_OK) return st;
+  c->prob = problem;
+  if (!build_host_tables(c->prob, c->T, err)) return FRSG_EINVAL;
   const fr_sg_problem& P = c->prob;
   c->is_tri = P.element == FRSG_ELEM_TRI;
-  if (c->is_tri && !build_tri_tables(P, c->tri, err)) {
-    g_init_error = err;
-    delete c;
-    return FRSG_EINVAL;
-  }
+  if (c->is_tri && !build_tri_tables(P, c->tri, err)) return FRSG_EINVAL;
   if (c->is_tri) tri_filter_tables(P, c->tri, c->T);
   // the mesh arrays are the caller's and are read during this call only
   c->prob.tri_xy = nullptr;
@@ -291,231 +270,17 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
   c->nsp = c->is_tri ? c->tri.np : (c->dim == 2 ? n * n : n);
   const HostTables& T = c->T;
 
-  // one device buffer for all tables
-  std::vector<double> blob;
-  std::vector<size_t> off;
-  auto add = [&](const std::vector<double>& v) {
-    off.push_back(blob.size());
-    blob.insert(blob.end(), v.begin(), v.end());
-  };
-  add(T.r);
-  add(T.w);
-  add(T.D);
-  add(T.lL);
-  add(T.lR);
-  add(T.dhL);
-  add(T.dhR);
-  add(T.V);
-  add(T.Vinv);
-  add(T.Phi);
-  add(T.PW);
-  add(T.filt);
-  add(T.shell);
-  add(T.swts);
-  add(T.Dt);
-  add(T.cmax);
-  add(T.PhiT);
-  add(T.PWT);
-  hipError_t he = hipMalloc(&c->dtab, blob.size() * sizeof(double));
-  if (he == hipSuccess)
-    he = hipMemcpy(c->dtab, blob.data(), blob.size() * sizeof(double), hipMemcpyHostToDevice);
-  if (he != hipSuccess) {
-    g_init_error = std::string("HIP error: ") + hipGetErrorString(he);
-    if (c->dtab) (void)hipFree(c->dtab);
-    delete c;
-    return FRSG_EDEVICE;
+  // every operator table in one double array (uploaded into the workspace by init)
+  std::vector<double>& blob = c->host_tab;
+  blob.clear();
+  c->tab_off.clear();
+  for (const std::vector<double>* v : {&T.r, &T.w, &T.D, &T.lL, &T.lR, &T.dhL, &T.dhR, &T.V, &T.Vinv, &T.Phi, &T.PW,
+                                       &T.filt, &T.shell, &T.swts, &T.Dt, &T.cmax, &T.PhiT, &T.PWT}) {
+    c->tab_off.push_back(blob.size());
+    blob.insert(blob.end(), v->begin(), v->end());
   }
-  DevTab tab;
-  const double* b = c->dtab;
-  tab.r = b + off[0];
-  tab.w = b + off[1];
-  tab.D = b + off[2];
-  tab.lL = b + off[3];
-  tab.lR = b + off[4];
-  tab.dhL = b + off[5];
-  tab.dhR = b + off[6];
-  tab.V = b + off[7];
-  tab.Vinv = b + off[8];
-  tab.Phi = b + off[9];
-  tab.PW = b + off[10];
-  tab.filt = b + off[11];
-  tab.shell = b + off[12];
-  tab.swts = b + off[13];
-  c->dDt = b + off[14];
-  c->dcmax = b + off[15];
-  tab.cmax = c->dcmax;
-  c->dPhiT = b + off[16];
-  c->dPWT = b + off[17];
 
-  // workspace (the nodal scratch is only needed by the generic passes)
-  {
-    KParams probe;
-    std::memset(&probe, 0, sizeof(probe));
-    probe.eq = P.equation;
-    probe.np1 = n;
-    probe.nx = P.nx;
-    probe.ny = c->dim == 2 ? P.ny : 1;
-    probe.M = T.M;
-    probe.Nq = T.Nq;
-    probe.E = P.nx * probe.ny;
-    c->fused = !c->is_tri && fused2d_supported(probe);
-  }
-  if (c->is_tri) {
-    // triangle operators and geometry: one double buffer and the neighbour table
-    const TriTables& R = c->tri;
-    std::vector<double> tb;
-    tb.insert(tb.end(), R.Dr.begin(), R.Dr.end());
-    tb.insert(tb.end(), R.Ds.begin(), R.Ds.end());
-    tb.insert(tb.end(), R.Lf.begin(), R.Lf.end());
-    tb.insert(tb.end(), R.lift.begin(), R.lift.end());
-    tb.insert(tb.end(), R.geo.begin(), R.geo.end());
-    tb.insert(tb.end(), R.V.begin(), R.V.end());
-    tb.insert(tb.end(), R.Vinv.begin(), R.Vinv.end());
-    he = hipMalloc(&c->dtri, tb.size() * sizeof(double));
-    if (he == hipSuccess) he = hipMemcpy(c->dtri, tb.data(), tb.size() * sizeof(double), hipMemcpyHostToDevice);
-    if (he == hipSuccess) he = hipMalloc(&c->dtri_nbr, R.nbr.size() * sizeof(int));
-    if (he == hipSuccess)
-      he = hipMemcpy(c->dtri_nbr, R.nbr.data(), R.nbr.size() * sizeof(int), hipMemcpyHostToDevice);
-    if (he != hipSuccess) {
-      g_init_error = std::string("HIP error: ") + hipGetErrorString(he);
-      if (c->dtri) (void)hipFree(c->dtri);
-      if (c->dtri_nbr) (void)hipFree(c->dtri_nbr);
-      (void)hipFree(c->dtab);
-      delete c;
-      return FRSG_EDEVICE;
-    }
-  }
-  if (P.precision == FRSG_FP32_MIXED && !c->fused) {
-    g_init_error =
-        "FRSG_FP32_MIXED runs on the fused 2D Euler path only (FR degree 3, nx % 4 == 0, ny % 2 == 0, "
-        "a compiled (M, Nq) pair)";
-    (void)hipFree(c->dtab);
-    delete c;
-    return FRSG_EUNSUPPORTED;
-  }
-  if (c->fused) {
-    std::vector<float> f32(2 * T.PhiT.size());
-    for (size_t i = 0; i < T.PhiT.size(); ++i) {
-      f32[i] = (float)T.PhiT[i];
-      f32[T.PhiT.size() + i] = (float)T.PWT[i];
-    }
-    float* d32 = nullptr;
-    he = hipMalloc(&d32, f32.size() * sizeof(float));
-    if (he == hipSuccess) he = hipMemcpy(d32, f32.data(), f32.size() * sizeof(float), hipMemcpyHostToDevice);
-    if (he != hipSuccess) {
-      g_init_error = std::string("HIP error: ") + hipGetErrorString(he);
-      if (d32) (void)hipFree(d32);
-      (void)hipFree(c->dtab);
-      delete c;
-      return FRSG_EDEVICE;
-    }
-    c->dPhiT32 = d32;
-    c->dPWT32 = d32 + T.PhiT.size();
-  }
-  if (c->is_tri) {
-    KParams probe;
-    std::memset(&probe, 0, sizeof(probe));
-    probe.eq = P.equation;
-    probe.nfp = c->tri.nfp;
-    probe.M = T.M;
-    probe.Nq = T.Nq;
-    c->fused_tri = tri_fused_supported(probe);
-  }
-  const size_t state = (size_t)c->S * T.M * c->E * c->nsp;
-  const bool no_nodal = c->fused || c->fused_tri;
-  const size_t nodal = no_nodal ? 0 : (size_t)c->S * T.Nq * c->E * c->nsp;
-  const size_t corr = no_nodal ? 0
-                      : (size_t)c->S * T.Nq * c->E * (c->is_tri ? 3 * c->tri.nfp : (c->dim == 2 ? 4 * n : 2));
-  const size_t ntm = c->fused_tri ? (size_t)c->S * T.M * c->E * 3 * c->tri.nfp : 0;
-  size_t o_w1 = 0;
-  size_t o_w2 = align_up(o_w1 + state * 8);
-  size_t o_un = align_up(o_w2 + state * 8);
-  size_t o_fn = align_up(o_un + nodal * 8);
-  size_t o_gn = align_up(o_fn + nodal * 8);
-  size_t o_co = align_up(o_gn + (c->dim == 2 ? nodal * 8 : 0));
-  size_t o_sc = align_up(o_co + corr * 8);
-  // adjoint buffers, for the problems the adjoint covers (scalar 1D)
-  const bool adj = c->dim == 1 && c->S == 1;
-  size_t nadj_part = 0;
-  if (adj) {
-    KParams probe;
-    std::memset(&probe, 0, sizeof(probe));
-    probe.E = c->E;
-    probe.Nq = T.Nq;
-    probe.M = T.M;
-    probe.np1 = n;
-    probe.S = c->S;
-    probe.dim = c->dim;
-    nadj_part = (size_t)std::max(adjoint_partials(probe), adj1d_partials(probe));
-  }
-  size_t o_avb = align_up(o_sc + 256);
-  size_t o_ab2 = align_up(o_avb + (adj ? state * 8 : 0));
-  size_t o_ab1 = align_up(o_ab2 + (adj ? state * 8 : 0));
-  size_t o_agt = align_up(o_ab1 + (adj ? state * 8 : 0));
-  size_t o_apt = align_up(o_agt + (adj ? (size_t)T.Nq * c->E * 2 * 8 : 0));
-  // fused 2D: two buffers of modal face traces on tile boundaries
-  const size_t ntr = c->fused ? fused2d_trace_count(P.nx, P.ny, T.M) : 0;
-  size_t o_tr0 = align_up(o_apt + nadj_part * 8);
-  size_t o_tr1 = align_up(o_tr0 + ntr * 8);
-  // tableau integrators: one right-hand-side buffer per stage
-  const Tableau* tab_rk = tableau_of(P.integrator);
-  const int nrk = tab_rk ? tab_rk->s : 0;
-  size_t o_rk = align_up(o_tr1 + ntr * 8);
-  size_t o_tm = align_up(o_rk + (size_t)nrk * align_up(state * 8));
-  size_t o_tm1 = align_up(o_tm + ntm * 8);
-  size_t total = align_up(o_tm1 + ntm * 8);
-  char* ws = nullptr;
-  he = hipMalloc(&ws, total);
-  if (he != hipSuccess) {
-    g_init_error = std::string("workspace allocation failed: ") + hipGetErrorString(he);
-    if (c->dtri) (void)hipFree(c->dtri);
-    if (c->dtri_nbr) (void)hipFree(c->dtri_nbr);
-    (void)hipFree(c->dtab);
-    if (c->dPhiT32) (void)hipFree(c->dPhiT32);
-    delete c;
-    return FRSG_EDEVICE;
-  }
-  he = hipMemset(ws + o_sc, 0, 256);
-  if (he != hipSuccess) {
-    g_init_error = std::string("HIP error: ") + hipGetErrorString(he);
-    (void)hipFree(ws);
-    if (c->dtri) (void)hipFree(c->dtri);
-    if (c->dtri_nbr) (void)hipFree(c->dtri_nbr);
-    (void)hipFree(c->dtab);
-    if (c->dPhiT32) (void)hipFree(c->dPhiT32);
-    delete c;
-    return FRSG_EDEVICE;
-  }
-  c->ws.w1 = (double*)(ws + o_w1);
-  c->ws.w2 = (double*)(ws + o_w2);
-  c->ws.Un = (double*)(ws + o_un);
-  c->ws.Fn = (double*)(ws + o_fn);
-  c->ws.Gn = c->dim == 2 ? (double*)(ws + o_gn) : nullptr;
-  c->ws.Corr = (double*)(ws + o_co);
-  c->ws.scal = (double*)(ws + o_sc);
-  if (adj) {
-    c->ws.avb = (double*)(ws + o_avb);
-    c->ws.ab2 = (double*)(ws + o_ab2);
-    c->ws.ab1 = (double*)(ws + o_ab1);
-    c->ws.agT = (double*)(ws + o_agt);
-    c->ws.apart = (double*)(ws + o_apt);
-  }
-  for (int i = 0; i < nrk; ++i) c->ws.rk[i] = (double*)(ws + o_rk + (size_t)i * align_up(state * 8));
-  if (ntm) {
-    c->ws.Tm[0] = (double*)(ws + o_tm);
-    c->ws.Tm[1] = (double*)(ws + o_tm1);
-  }
-  if (ntr) {
-    c->ws.tr[0] = (double*)(ws + o_tr0);
-    c->ws.tr[1] = (double*)(ws + o_tr1);
-  }
-  c->ws.bytes = total + blob.size() * sizeof(double);
-  if (c->is_tri)
-    c->ws.bytes += (c->tri.Dr.size() + c->tri.Ds.size() + c->tri.Lf.size() + c->tri.lift.size() + c->tri.geo.size() +
-                    c->tri.V.size() + c->tri.Vinv.size()) *
-                       sizeof(double) +
-                   c->tri.nbr.size() * sizeof(int);
-
+  // kernel parameters without device pointers (filled in by init)
   KParams& K = c->kp;
   std::memset(&K, 0, sizeof(K));
   K.eq = P.equation;
@@ -546,12 +311,213 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
   K.limiter = P.limiter;
   K.alpha = P.alpha;
   K.sensor_thr = std::pow(10.0, P.s0 - (2.0 * P.kappa / M_PI) * std::asin(0.98));
+  if (c->is_tri) {
+    K.tri = 1;
+    K.nfp = c->tri.nfp;
+  }
+  c->fused = !c->is_tri && fused2d_supported(K);
+  c->fused_tri = c->is_tri && tri_fused_supported(K);
+  c->fused1d = c->dim == 1 && fr1d_supported(K);
+  if (P.precision == FRSG_FP32_MIXED && !c->fused) {
+    err = "FRSG_FP32_MIXED runs on the fused 2D Euler path only (FR degree 3, nx % 4 == 0, ny % 2 == 0, "
+          "a compiled (M, Nq) pair)";
+    return FRSG_EUNSUPPORTED;
+  }
+  if (P.precision == FRSG_BF16_SPLIT) {
+    err = "FRSG_BF16_SPLIT is not available for this problem";
+    return FRSG_EUNSUPPORTED;
+  }
+  // triangle operators and geometry: one double array and the neighbour table
+  c->host_tri.clear();
+  if (c->is_tri) {
+    const TriTables& R = c->tri;
+    for (const std::vector<double>* v : {&R.Dr, &R.Ds, &R.Lf, &R.lift, &R.geo, &R.V, &R.Vinv})
+      c->host_tri.insert(c->host_tri.end(), v->begin(), v->end());
+  }
+  // FP32 copies of the node-major chaos tables (fused 2D path)
+  c->host_f32.clear();
+  if (c->fused) {
+    c->host_f32.resize(2 * T.PhiT.size());
+    for (size_t i = 0; i < T.PhiT.size(); ++i) {
+      c->host_f32[i] = (float)T.PhiT[i];
+      c->host_f32[T.PhiT.size() + i] = (float)T.PWT[i];
+    }
+  }
+
+  // workspace layout, every sub-array aligned to 256 bytes
+  Layout& L = c->lay;
+  L = Layout();
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  const size_t state = (size_t)c->S * T.M * c->E * c->nsp;
+  const bool no_nodal = c->fused || c->fused_tri;
+  const size_t nodal = no_nodal ? 0 : (size_t)c->S * T.Nq * c->E * c->nsp;
+  const size_t corr = no_nodal ? 0
+                      : (size_t)c->S * T.Nq * c->E * (c->is_tri ? 3 * c->tri.nfp : (c->dim == 2 ? 4 * n : 2));
+  const size_t ntm = c->fused_tri ? (size_t)c->S * T.M * c->E * 3 * c->tri.nfp : 0;
+  const bool adj = c->dim == 1 && c->S == 1;
+  const size_t nadj_part = adj ? (size_t)std::max(adjoint_partials(K), adj1d_partials(K)) : 0;
+  const size_t ntr = c->fused ? fused2d_trace_count(P.nx, P.ny, T.M) : 0;
+  const Tableau* tab_rk = tableau_of(P.integrator);
+  const int nrk = tab_rk ? tab_rk->s : 0;
+  L.sc = take(256);
+  L.tab = take(blob.size() * sizeof(double));
+  L.f32 = take(c->host_f32.size() * sizeof(float));
+  L.tri = take(c->host_tri.size() * sizeof(double));
+  L.nbr = take(c->is_tri ? c->tri.nbr.size() * sizeof(int) : 0);
+  L.w1 = take(state * 8);
+  L.w2 = take(state * 8);
+  L.un = take(nodal * 8);
+  L.fn = take(nodal * 8);
+  L.gn = take(c->dim == 2 ? nodal * 8 : 0);
+  L.co = take(corr * 8);
+  L.avb = take(adj ? state * 8 : 0);
+  L.ab2 = take(adj ? state * 8 : 0);
+  L.ab1 = take(adj ? state * 8 : 0);
+  L.agt = take(adj ? (size_t)T.Nq * c->E * 2 * 8 : 0);
+  L.apt = take(nadj_part * 8);
+  L.tr0 = take(ntr * 8);
+  L.tr1 = take(ntr * 8);
+  for (int i = 0; i < nrk; ++i) L.rk[i] = take(state * 8);
+  L.nrk = nrk;
+  L.tm0 = take(ntm * 8);
+  L.tm1 = take(ntm * 8);
+  L.adj = adj;
+  L.has_tr = ntr > 0;
+  L.has_tm = ntm > 0;
+  L.total = o;
+  return FRSG_OK;
+}
+
+extern "C" {
+
+fr_sg_status fr_sg_workspace_size(const fr_sg_problem* problem, int64_t* bytes) {
+  if (!problem || !bytes) {
+    g_init_error = "problem and bytes must not be NULL";
+    return FRSG_EINVAL;
+  }
+  *bytes = 0;
+  fr_sg_ctx* c = new (std::nothrow) fr_sg_ctx();
+  if (!c) {
+    g_init_error = "out of host memory";
+    return FRSG_EDEVICE;
+  }
+  std::string err;
+  const fr_sg_status st = prepare(*problem, c, err);
+  if (st == FRSG_OK)
+    *bytes = (int64_t)c->lay.total;
+  else
+    g_init_error = err;
+  delete c;
+  return st;
+}
+
+fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, void* workspace, int64_t workspace_bytes,
+                        fr_sg_ctx** out) {
+  if (!out) {
+    g_init_error = "out is NULL";
+    return FRSG_EINVAL;
+  }
+  *out = nullptr;
+  if (!problem) {
+    g_init_error = "problem is NULL";
+    return FRSG_EINVAL;
+  }
+  fr_sg_ctx* c = new (std::nothrow) fr_sg_ctx();
+  if (!c) {
+    g_init_error = "out of host memory";
+    return FRSG_EDEVICE;
+  }
+  std::string err;
+  fr_sg_status st = prepare(*problem, c, err);
+  if (st != FRSG_OK) {
+    g_init_error = err;
+    delete c;
+    return st;
+  }
+  const Layout& L = c->lay;
+  if (!workspace || workspace_bytes < (int64_t)L.total || ((uintptr_t)workspace & 255u) != 0) {
+    g_init_error = "workspace must be a 256-byte aligned device buffer of at least " + std::to_string(L.total) +
+                   " bytes (fr_sg_workspace_size)";
+    delete c;
+    return FRSG_EINVAL;
+  }
+  {
+    hipPointerAttribute_t attr;
+    const hipError_t pe = hipPointerGetAttributes(&attr, workspace);
+    (void)hipGetLastError();  // do not leave the query's status for a later launch check
+    if (pe != hipSuccess || attr.type != hipMemoryTypeDevice) {
+      g_init_error = "workspace is not device memory";
+      delete c;
+      return FRSG_EINVAL;
+    }
+  }
+  c->stream = (hipStream_t)hip_stream;
+  char* ws = (char*)workspace;
+  // upload the tables into the workspace and clear the device scalars; the host
+  // copies stay alive until the stream has finished with them
+  hipError_t he = hipMemsetAsync(ws + L.sc, 0, 256, c->stream);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(ws + L.tab, c->host_tab.data(), c->host_tab.size() * sizeof(double), hipMemcpyHostToDevice,
+                        c->stream);
+  if (he == hipSuccess && !c->host_f32.empty())
+    he = hipMemcpyAsync(ws + L.f32, c->host_f32.data(), c->host_f32.size() * sizeof(float), hipMemcpyHostToDevice,
+                        c->stream);
+  if (he == hipSuccess && !c->host_tri.empty())
+    he = hipMemcpyAsync(ws + L.tri, c->host_tri.data(), c->host_tri.size() * sizeof(double), hipMemcpyHostToDevice,
+                        c->stream);
+  if (he == hipSuccess && c->is_tri)
+    he = hipMemcpyAsync(ws + L.nbr, c->tri.nbr.data(), c->tri.nbr.size() * sizeof(int), hipMemcpyHostToDevice,
+                        c->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+  if (he != hipSuccess) {
+    g_init_error = std::string("HIP error: ") + hipGetErrorString(he);
+    delete c;
+    return FRSG_EDEVICE;
+  }
+  c->host_tab.clear();
+  c->host_tab.shrink_to_fit();
+  c->host_f32.clear();
+  c->host_f32.shrink_to_fit();
+  c->host_tri.clear();
+  c->host_tri.shrink_to_fit();
+
+  // device views of the tables
+  const double* b = (const double*)(ws + L.tab);
+  const std::vector<size_t>& off = c->tab_off;
+  DevTab tab;
+  tab.r = b + off[0];
+  tab.w = b + off[1];
+  tab.D = b + off[2];
+  tab.lL = b + off[3];
+  tab.lR = b + off[4];
+  tab.dhL = b + off[5];
+  tab.dhR = b + off[6];
+  tab.V = b + off[7];
+  tab.Vinv = b + off[8];
+  tab.Phi = b + off[9];
+  tab.PW = b + off[10];
+  tab.filt = b + off[11];
+  tab.shell = b + off[12];
+  tab.swts = b + off[13];
+  c->dDt = b + off[14];
+  c->dcmax = b + off[15];
+  tab.cmax = c->dcmax;
+  c->dPhiT = b + off[16];
+  c->dPWT = b + off[17];
+  if (c->fused) {
+    c->dPhiT32 = (const float*)(ws + L.f32);
+    c->dPWT32 = c->dPhiT32 + c->T.PhiT.size();
+  }
+  KParams& K = c->kp;
   K.tab = tab;
   if (c->is_tri) {
     const TriTables& R = c->tri;
-    K.tri = 1;
-    K.nfp = R.nfp;
-    const double* b2 = c->dtri;
+    const double* b2 = (const double*)(ws + L.tri);
     K.tri_Dr = b2;
     K.tri_Ds = K.tri_Dr + R.Dr.size();
     K.tri_Lf = K.tri_Ds + R.Ds.size();
@@ -559,12 +525,36 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, fr_sg_ct
     K.tri_geo = K.tri_lift + R.lift.size();
     K.tri_V = K.tri_geo + R.geo.size();
     K.tri_Vinv = K.tri_V + R.V.size();
-    K.tri_nbr = c->dtri_nbr;
+    K.tri_nbr = (const int*)(ws + L.nbr);
   }
-  K.dt = c->ws.scal;
-  K.lam_bits = (unsigned long long*)(c->ws.scal + 1);
-  K.status = (unsigned*)(c->ws.scal + 2);  // scal[3] is the second CFL accumulator
-  c->fused1d = c->dim == 1 && fr1d_supported(K);
+  Workspace& W = c->ws;
+  W.scal = (double*)(ws + L.sc);
+  W.w1 = (double*)(ws + L.w1);
+  W.w2 = (double*)(ws + L.w2);
+  W.Un = (double*)(ws + L.un);
+  W.Fn = (double*)(ws + L.fn);
+  W.Gn = c->dim == 2 ? (double*)(ws + L.gn) : nullptr;
+  W.Corr = (double*)(ws + L.co);
+  if (L.adj) {
+    W.avb = (double*)(ws + L.avb);
+    W.ab2 = (double*)(ws + L.ab2);
+    W.ab1 = (double*)(ws + L.ab1);
+    W.agT = (double*)(ws + L.agt);
+    W.apart = (double*)(ws + L.apt);
+  }
+  for (int i = 0; i < L.nrk; ++i) W.rk[i] = (double*)(ws + L.rk[i]);
+  if (L.has_tm) {
+    W.Tm[0] = (double*)(ws + L.tm0);
+    W.Tm[1] = (double*)(ws + L.tm1);
+  }
+  if (L.has_tr) {
+    W.tr[0] = (double*)(ws + L.tr0);
+    W.tr[1] = (double*)(ws + L.tr1);
+  }
+  W.bytes = L.total;
+  K.dt = W.scal;
+  K.lam_bits = (unsigned long long*)(W.scal + 1);
+  K.status = (unsigned*)(W.scal + 2);  // scal[3] is the second CFL accumulator
   *out = c;
   return FRSG_OK;
 }
@@ -1198,11 +1188,6 @@ fr_sg_status fr_sg_destroy(fr_sg_ctx* ctx) {
   if (!ctx) return FRSG_OK;
   (void)hipStreamSynchronize(ctx->stream);
   for (hipEvent_t ev : ctx->events) (void)hipEventDestroy(ev);
-  if (ctx->ws.w1) (void)hipFree(ctx->ws.w1);
-  if (ctx->dtab) (void)hipFree(ctx->dtab);
-  if (ctx->dPhiT32) (void)hipFree(ctx->dPhiT32);
-  if (ctx->dtri) (void)hipFree(ctx->dtri);
-  if (ctx->dtri_nbr) (void)hipFree(ctx->dtri_nbr);
   delete ctx;
   return FRSG_OK;
 }

@@ -45,6 +45,9 @@ struct HostTables {
 };
 
 bool build_host_tables(const fr_sg_problem& P, HostTables& T, std::string& err);
+// exponent of the exponential filter along one dimension (Sec. 4.1.1): 0 below the
+// cutoff eta* (modes untouched), ((eta - eta*) / (1 - eta*))^s from it on
+double exp_filter_term(double eta, double eta_star, double s);
 // n-point Gauss-Legendre rule (weights sum 2); Gauss-Jordan inverse of an n x n matrix
 void gauss_rule(int n, std::vector<double>& x, std::vector<double>& w);
 bool invert_matrix(int n, const std::vector<double>& A, std::vector<double>& Ainv);
@@ -151,6 +154,18 @@ struct Workspace {
   size_t bytes = 0;
 };
 
+// byte offsets of the workspace sub-arrays (each 256-byte aligned) and its size
+struct Layout {
+  size_t sc = 0, tab = 0, f32 = 0, tri = 0, nbr = 0;
+  size_t w1 = 0, w2 = 0, un = 0, fn = 0, gn = 0, co = 0;
+  size_t avb = 0, ab2 = 0, ab1 = 0, agt = 0, apt = 0;
+  size_t tr0 = 0, tr1 = 0, tm0 = 0, tm1 = 0;
+  size_t rk[kRkMaxTerms] = {0};
+  int nrk = 0;
+  bool adj = false, has_tr = false, has_tm = false;
+  size_t total = 0;
+};
+
 }  // namespace frsg
 
 struct PassRecord {
@@ -176,20 +191,17 @@ struct fr_sg_ctx {
   frsg::TriTables tri;           // triangle operators and geometry (element = FRSG_ELEM_TRI)
   bool is_tri = false;
   bool fused_tri = false;        // fused triangle stage kernel
-  double* dtri = nullptr;        // device copies of the triangle tables and geometry
-  int* dtri_nbr = nullptr;
   hipStream_t stream = nullptr;
   int dim = 1;
   int S = 1;
   int E = 0;
   int nsp = 0;
-  double* dtab = nullptr;
   const double* dDt = nullptr;
   const double* dcmax = nullptr;
   const double* dPhiT = nullptr;
   const double* dPWT = nullptr;
-  float* dPhiT32 = nullptr;  // FP32 copies of the node-major tables
-  float* dPWT32 = nullptr;
+  const float* dPhiT32 = nullptr;  // FP32 copies of the node-major tables
+  const float* dPWT32 = nullptr;
   bool fused = false;            // fused 2D Euler stage kernel
   bool fused1d = false;          // fused 1D stage kernel
   int lam_cur = 0;              // which CFL accumulator holds the maximum of the current state
@@ -198,6 +210,11 @@ struct fr_sg_ctx {
   int tm_cur = 0;               // fused triangles: which trace buffer holds the traces of the current state
   frsg::KParams kp;
   frsg::Workspace ws;
+  frsg::Layout lay;                  // sub-arrays of the caller's workspace
+  std::vector<double> host_tab;      // tables waiting for the upload in fr_sg_init
+  std::vector<size_t> tab_off;       // offsets of the tables in host_tab (and on the device)
+  std::vector<double> host_tri;      // triangle operators and geometry
+  std::vector<float> host_f32;       // FP32 chaos tables of the fused 2D path
   std::string err;
 };
 

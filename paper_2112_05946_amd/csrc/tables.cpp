@@ -125,6 +125,11 @@ bool invert(int n, const std::vector<double>& A, std::vector<double>& Ainv) {
 void gauss_rule(int n, std::vector<double>& x, std::vector<double>& w) { gauss_legendre(n, x, w); }
 bool invert_matrix(int n, const std::vector<double>& A, std::vector<double>& Ainv) { return invert(n, A, Ainv); }
 
+double exp_filter_term(double eta, double eta_star, double s) {
+  if (eta < eta_star) return 0.0;
+  return std::pow((eta - eta_star) / (1.0 - eta_star), s);
+}
+
 bool build_host_tables(const fr_sg_problem& P, HostTables& T, std::string& err) {
   const int p = P.fr_degree;
   const int n = p + 1;
@@ -243,8 +248,8 @@ bool build_host_tables(const fr_sg_problem& P, HostTables& T, std::string& err) 
       T.shell[k * nsp + j] = (jmax == p || kk == Nc) ? 1.0 : 0.0;
       if (P.filter == FRSG_FILTER_EXP) {
         double ex = 0.0;
-        for (int d = 0; d < dim; ++d) ex += std::pow((double)dj[d] / p, P.s);
-        double ez = (Nc > 0) ? std::pow((double)kk / Nc, P.s) : 0.0;
+        for (int d = 0; d < dim; ++d) ex += exp_filter_term((double)dj[d] / p, P.nstar / p, P.s);
+        double ez = (Nc > 0) ? exp_filter_term((double)kk / Nc, P.nstar / Nc, P.s) : 0.0;
         T.filt[k * nsp + j] = ex + ez;
       } else if (P.filter == FRSG_FILTER_L2) {
         long sx = 0;

@@ -296,7 +296,8 @@ void tri_filter_tables(const fr_sg_problem& P, const TriTables& R, HostTables& T
       const int d = deg[m];
       T.shell[k * n + m] = (d == p || kk == Nc) ? 1.0 : 0.0;
       if (P.filter == FRSG_FILTER_EXP)
-        T.filt[k * n + m] = std::pow((double)d / p, P.s) + ((Nc > 0) ? std::pow((double)kk / Nc, P.s) : 0.0);
+        T.filt[k * n + m] = exp_filter_term((double)d / p, P.nstar / p, P.s) +
+                            ((Nc > 0) ? exp_filter_term((double)kk / Nc, P.nstar / Nc, P.s) : 0.0);
       else if (P.filter == FRSG_FILTER_L2)
         T.filt[k * n + m] = 1.0 / (1.0 + a1 * d * d * (d + 1.0) * (d + 1.0) + a2 * kk * kk * (kk + 1.0) * (kk + 1.0));
     }

@@ -40,10 +40,16 @@ def test_every_declared_symbol_is_exported(lib):
         assert name in bound, "binding lacks " + name
 
 
-def _init(lib, P):
+def _init(lib, P, ws=None, nbytes=0):
     ctx = ctypes.c_void_p()
-    st = lib.fr_sg_init(ctypes.byref(P), None, ctypes.byref(ctx))
+    st = lib.fr_sg_init(ctypes.byref(P), None, ws, nbytes, ctypes.byref(ctx))
     return st, ctx, lib.fr_sg_last_error(None).decode()
+
+
+def _size(lib, P):
+    n = ctypes.c_int64(-1)
+    st = lib.fr_sg_workspace_size(ctypes.byref(P), ctypes.byref(n))
+    return st, n.value, lib.fr_sg_last_error(None).decode()
 
 
 @pytest.mark.parametrize("mutate,status", [
@@ -60,6 +66,11 @@ def _init(lib, P):
     (lambda P: P.bc.__setitem__(0, 9), -1),
     (lambda P: setattr(P, "filter", 5), -1),
     (lambda P: setattr(P, "precision", 7), -1),
+    (lambda P: setattr(P, "precision", 2), -2),        # BF16-split not on this path
+    (lambda P: (setattr(P, "filter", 1), setattr(P, "nstar", 3.0)), -1),    # cutoff >= p
+    (lambda P: (setattr(P, "filter", 1), setattr(P, "nstar", -0.5)), -1),
+    (lambda P: (setattr(P, "filter", 1), setattr(P, "nstar", 2.5), setattr(P, "gpc_order", 2),
+                setattr(P, "nq1d", 3)), -1),                                # cutoff >= N_c
 ])
 def test_invalid_problems_rejected_before_launch(lib, mutate, status):
     from paper_2112_05946_amd import binding, inputs
@@ -68,10 +79,38 @@ def test_invalid_problems_rejected_before_launch(lib, mutate, status):
     st, ctx, msg = _init(lib, P)
     assert st == status, msg
     assert not ctx.value and msg
+    st2, n, msg2 = _size(lib, P)
+    assert st2 == status and n == 0 and msg2 == msg
+
+
+@pytest.mark.parametrize("name,S,nsp", [("BURGERS", 1, 4), ("SOD", 3, 4), ("SHOCK_VORTEX", 4, 16)])
+def test_workspace_size_is_a_host_query(lib, name, S, nsp):
+    """The size query needs no device; it covers at least the two stage states."""
+    from paper_2112_05946_amd import binding, inputs
+    cfg = getattr(inputs, name)
+    st, n, msg = _size(lib, binding.problem_from_config(cfg))
+    assert st == 0, msg
+    M = (cfg["gpc_order"] + 1) * (cfg["gpc_order"] + 2) // 2 if cfg.get("rdim", 1) == 2 else cfg["gpc_order"] + 1
+    state = 8 * S * M * cfg["nx"] * cfg.get("ny", 1) * nsp
+    assert 2 * state < n < 8 * state + (1 << 20)
+    assert n % 256 == 0
+
+
+def test_workspace_argument_checked_before_any_device_call(lib):
+    from paper_2112_05946_amd import binding, inputs
+    P = binding.problem_from_config(inputs.BURGERS)
+    _, n, _ = _size(lib, P)
+    st, ctx, msg = _init(lib, P, None, n)
+    assert st == -1 and "workspace" in msg and not ctx.value
+    st, ctx, msg = _init(lib, P, ctypes.c_void_p(1 << 20), n - 256)       # too short
+    assert st == -1 and "workspace" in msg and not ctx.value
+    st, ctx, msg = _init(lib, P, ctypes.c_void_p((1 << 20) + 8), n)       # misaligned
+    assert st == -1 and "aligned" in msg and not ctx.value
 
 
 def test_null_arguments(lib):
-    assert lib.fr_sg_init(None, None, None) == -1
+    assert lib.fr_sg_init(None, None, None, 0, None) == -1
+    assert lib.fr_sg_workspace_size(None, None) == -1
     assert lib.fr_sg_query(None, None) == -1
     assert lib.fr_sg_rhs(None, None, None) == -1
     assert lib.fr_sg_step(None, None, 0.0, None, None) == -1

@@ -8,7 +8,8 @@ decision margin is at the rounding level of the state (reported as ties).
 import numpy as np
 import pytest
 
-from gpu_util import RTOL_FP64, announce, check_flags, oracle_for, rel_l2, solver_for, to_dev, to_np
+from gpu_util import (ELEM_RTOL, RTOL_FP64, announce, check_flags, check_patch_step, elem_max_rel, oracle_for,
+                      quad_patch, rel_l2, solver_for, to_dev, to_np)
 from oracle import fr as ofr
 from oracle import stabilize as ost
 from oracle import stepper as ostep
@@ -112,8 +113,10 @@ def _run_steps(cfg, u0, nsteps, dt=None):
         gflags = to_np(flags).reshape(4, prob.E)
         assert abs(to_np(dtd)[0] - rdt) <= 1e-13 * rdt, (i, to_np(dtd)[0], rdt)
         check_flags(prob, T, R, gflags, rflags, rec)
-        err = rel_l2(to_np(ud), ref)
+        got = to_np(ud)
+        err = rel_l2(got, ref)
         assert err < RTOL_FP64, (i, err)
+        assert elem_max_rel(got, ref) < ELEM_RTOL, (i, elem_max_rel(got, ref))
     return ref
 
 
@@ -170,6 +173,55 @@ def test_full_size_shock_vortex_rhs_and_step():
     sol.sync()
     assert rel_l2(got, ofr.rhs(prob, T, R, u0)) < RTOL_FP64
     _run_steps(cfg, u0, 1)
+
+
+def test_full_size_shock_vortex_ten_steps_sampled():
+    """256 x 128 elements, 15 modes, 25 nodes: ten CFL steps.  Each step is checked from
+    the GPU's own state before it: dt against the oracle's CFL rule on the whole state,
+    and the state after it on 40 sampled elements (shock, vortex, the four boundaries,
+    corners, random) against the oracle's step of each element's 7 x 7 patch, to
+    1e-12 per element, with the same switch decisions.  The same ten steps in one
+    fr_sg_steps call (CFL maxima taken in the previous step's epilogue, face traces
+    carried between launches) give the same time steps to 1e-13 and the same state to
+    1e-12, globally and per element."""
+    import torch
+    cfg = inputs.SHOCK_VORTEX
+    announce("full_size", "shock_vortex_ten_steps")
+    prob, (T, R) = oracle_for(cfg)
+    nx, ny = cfg["nx"], cfg["ny"]
+    rng = np.random.default_rng(5)
+    fixed = [(0, 0), (nx - 1, ny - 1), (0, ny - 1), (nx - 1, 0), (0, 40), (nx - 1, 77), (100, 0), (30, ny - 1),
+             (31, 64), (32, 64), (33, 60), (63, 70), (64, 64), (65, 58), (66, 64), (40, 64), (24, 64), (20, 70)]
+    picks = fixed + [(int(a), int(b)) for a, b in zip(rng.integers(0, nx, 22), rng.integers(0, ny, 22))]
+    u0 = project_initial(prob, cfg["ic"], (T, R))
+    sol = solver_for(cfg)
+    ud = to_dev(u0)
+    before = u0
+    worst = 0.0
+    dts = []
+    fired = np.zeros(4, dtype=int)
+    for i in range(10):
+        rdt = ostep.cfl_dt(prob, T, R, before)
+        dtd, flags = sol.step(ud)
+        sol.sync()
+        after = to_np(ud)
+        gdt = float(to_np(dtd)[0])
+        dts.append(gdt)
+        assert abs(gdt / rdt - 1.0) < 1e-13, (i, gdt, rdt)
+        g = to_np(flags).reshape(4, prob.E)
+        fired += g.astype(int).sum(axis=1)
+        worst = max(worst, check_patch_step(cfg, before, after, gdt, g, picks, quad_patch, (T, R)))
+        before = after
+    print("[shock_vortex ten steps] worst per-element error %.2e, flags fired per pass %s" % (worst, fired),
+          flush=True)
+    assert fired[2] > 0
+    u2 = to_dev(u0)
+    dts2 = torch.empty(10, dtype=torch.float64, device=u2.device)
+    sol.steps(u2, 10, dt_used=dts2)
+    sol.sync()
+    assert np.max(np.abs(to_np(dts2) / np.array(dts) - 1.0)) < 1e-13
+    assert rel_l2(to_np(u2), before) < RTOL_FP64
+    assert elem_max_rel(to_np(u2), before) < ELEM_RTOL
 
 
 def test_advection_full_horizon():

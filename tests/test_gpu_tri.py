@@ -7,7 +7,8 @@ conservation properties."""
 import numpy as np
 import pytest
 
-from gpu_util import RTOL_FP64, announce, rel_l2, solver_for, to_dev, to_np
+from gpu_util import (ELEM_RTOL, RTOL_FP64, announce, check_patch_step, elem_max_rel, rel_l2, solver_for, to_dev,
+                      to_np, tri_patch)
 from oracle import stepper as ostep
 from oracle import stabilize as ost
 from oracle import tri as otri
@@ -119,51 +120,36 @@ def test_tri_steps_match_oracle(label, cfg):
     assert rel_l2(to_np(ud2), u) < RTOL_FP64
 
 
-def _local_problem(cfg, e):
-    """Element e with its three neighbours (their outer faces open): the oracle's
-    right-hand side of e on this four-element mesh is e's on the whole mesh."""
-    mesh = cfg["mesh"]
-    nb, nf = mesh["nbr"][e], mesh["nbr_face"][e]
-    ids = [e] + [int(n) for n in nb]
-    xy = mesh["xy"][ids]
-    nbr = np.full((4, 3), -1 - 1, dtype=np.int32)   # outflow ghosts on the neighbours' other faces
-    nbf = np.full((4, 3), -1, dtype=np.int32)
-    for f in range(3):
-        nbr[0, f], nbf[0, f] = 1 + f, nf[f]
-        nbr[1 + f, nf[f]], nbf[1 + f, nf[f]] = 0, f
-    local = dict(cfg, mesh=dict(xy=xy, nbr=nbr, nbr_face=nbf), bc=["outflow"] * 4)
-    return Problem.from_config(local), ids
-
-
 def test_tri_vortex_full_size_sampled_and_properties():
+    """The triangle vortex workload at its benchmark size (32,768 triangles, p = 3, 15
+    modes, 25 nodes).  One CFL step from the initial state, checked on 48 sampled
+    triangles (half inside the vortex) against the oracle's step of each triangle's
+    three-ring patch taken from the same state: 1e-12 per element and over the picks
+    (the state is O(1), so this is the FP64 bar with no cancellation to excuse); dt
+    equals the oracle's.  Then the right-hand side: conservation of every mode over the
+    periodic mesh, and zero for a uniform state with random velocity."""
     cfg = inputs.tri_vortex(128)
     announce("tri_vortex_full", cfg["mesh"]["xy"].shape[0])
     sol = solver_for(cfg)
     u = sol.initial_state()
-    r = to_np(sol.rhs(u))
-    sol.sync()
-    uh = to_np(u)
     prob = Problem.from_config(cfg)
     T, R = build_tables(prob)
-    # sampled elements: the oracle's right-hand side of each on its local patch
-    # (half of them inside the vortex, where the right-hand side is not rounding noise).
-    # Bar: relative L2 over the sampled elements together, 1e-11: the right-hand side
-    # of this near-uniform Mach 1.1 flow on elements of width 1/128 is what is left
-    # when flux divergence and corrections of size ~1e3 cancel to values of 0.05..8,
-    # so two evaluation orders differ by ~1e-16 of those terms, ~1e-12 of the result.
-    # The fuzz-state cases above hold the 1e-12 bar.
+    uh = to_np(u)
     rng = np.random.default_rng(0)
     X, Y = otri.solution_point_coords_tri(prob, T)
     near = np.nonzero(np.hypot(X.mean(1) - 0.5, Y.mean(1) - 0.5) < 0.15)[0]
-    picks = np.concatenate([rng.choice(near, 24, replace=False), rng.choice(prob.E, 24, replace=False)])
-    got, want = [], []
-    for e in picks:
-        lp, ids = _local_problem(cfg, int(e))
-        want.append(otri.rhs_tri(lp, T, R, uh[:, :, ids])[:, :, 0])
-        got.append(r[:, :, e])
-    err = rel_l2(np.array(got), np.array(want))
-    print("[tri_vortex] sampled rel L2", err, flush=True)
-    assert err < 1e-11, err
+    picks = [int(e) for e in np.concatenate([rng.choice(near, 24, replace=False),
+                                             rng.choice(prob.E, 24, replace=False)])]
+    rdt = ostep.cfl_dt(prob, T, R, uh)
+    u1 = u.clone()
+    dtd, flags = sol.step(u1)
+    sol.sync()
+    gdt = float(to_np(dtd)[0])
+    assert abs(gdt / rdt - 1.0) < 1e-13, (gdt, rdt)
+    worst = check_patch_step(cfg, uh, to_np(u1), gdt, to_np(flags).reshape(4, prob.E), picks, tri_patch, (T, R))
+    print("[tri_vortex] sampled step, worst per-element error %.2e" % worst, flush=True)
+    r = to_np(sol.rhs(u))
+    sol.sync()
     # conservation over the periodic mesh
     G = otri.geometry(cfg["mesh"]["xy"])
     tot = np.einsum("skej,j,e->sk", r, T.mean_w, 2 * G.det)
@@ -177,10 +163,6 @@ def test_tri_vortex_full_size_sampled_and_properties():
     rf = to_np(sol.rhs(to_dev(uf)))
     sol.sync()
     assert np.max(np.abs(rf)) < 1e-10
-    # one CFL step stays finite and realizable
-    dtd, _ = sol.step(u)
-    sol.sync()
-    assert np.isfinite(to_np(u)).all() and to_np(dtd)[0] > 0
 
 
 def test_tri_shock_vortex_full_size_properties():
@@ -211,7 +193,21 @@ def test_tri_shock_vortex_full_size_properties():
         assert np.all(m >= -1e-13 * scale), (m.min(), np.argmin(m))
     assert g[2].sum() > 0, g.sum(axis=1)
     rdt = ostep.cfl_dt(prob, T, R, u0)
-    assert abs(to_np(dtd)[0] / rdt - 1.0) < 1e-13, (to_np(dtd)[0], rdt)
+    gdt = float(to_np(dtd)[0])
+    assert abs(gdt / rdt - 1.0) < 1e-13, (gdt, rdt)
+    # the last step on sampled triangles (filtered ones, the shock, the vortex, the
+    # boundaries, random) against the oracle's step of their three-ring patches
+    X, Y = otri.solution_point_coords_tri(prob, T)
+    xm, ym = X.mean(1), Y.mean(1)
+    rng = np.random.default_rng(3)
+    filt = np.nonzero(g[2])[0]
+    shock = np.nonzero(np.abs(xm - 0.5) < 0.02)[0]
+    edge = np.nonzero((xm < 0.02) | (xm > 1.98) | (ym < 0.02) | (ym > 0.98))[0]
+    picks = [int(e) for e in np.concatenate([rng.choice(filt, min(12, len(filt)), replace=False),
+                                             rng.choice(shock, 8, replace=False), rng.choice(edge, 8, replace=False),
+                                             rng.choice(prob.E, 12, replace=False)])]
+    worst = check_patch_step(cfg, u0, u1, gdt, g, picks, tri_patch, (T, R))
+    print("[tri_shock_vortex] sampled step, worst per-element error %.2e" % worst, flush=True)
 
 
 # ----------------------------------------------------------------------------
@@ -283,6 +279,55 @@ def test_tri_steps_with_filter_and_limiter(label, cfg):
     sol.steps(u2, 4)
     sol.sync()
     assert rel_l2(to_np(u2), u) < RTOL_FP64, rel_l2(to_np(u2), u)
+
+
+@pytest.mark.parametrize("start", ["initial", "near_vacuum"])
+def test_tri_benchmark_instance_steps(start):
+    """The triangle stage kernel at the benchmark's instance (p = 3, 15 modes, 25 nodes:
+    two random dimensions, total degree 4, 5 x 5 nodes) on a small bounded
+    shock-vortex mesh, with the L2 filter switched by the detector and the limiter:
+    four single steps and one four-step call against the oracle, 1e-12 on the state
+    and per element, switch decisions equal up to rounding-level ties; the filter
+    fires from the shock, the limiter from near-vacuum elements."""
+    from gpu_util import check_flags
+    cfg = inputs.tri_shock_vortex(8)
+    announce("tri_benchmark_instance", start, len(cfg["mesh"]["xy"]))
+    prob = Problem.from_config(cfg)
+    T, R = build_tables(prob)
+    assert (R.M, R.Nq, T.n) == (15, 25, 10)
+    if start == "initial":
+        u = project_initial(prob, cfg["ic"], (T, R))
+        dt = None
+    else:
+        u = inputs.fuzz_euler(2, R.M, prob.E, T.n, seed=41, vacuum_frac=0.2)
+        u, _ = ost.limit(prob, T, R, u)
+        dt = 2e-5
+    u_start = u.copy()
+    sol = solver_for(cfg)
+    ud = to_dev(u)
+    fired = np.zeros(4, dtype=int)
+    for i in range(4):
+        record = []
+        u, rdt, rflags = ostep.step(prob, u, dt, (T, R), record=record)
+        dtd, flags = sol.step(ud, dt)
+        sol.sync()
+        g = to_np(flags).reshape(4, prob.E)
+        assert abs(to_np(dtd)[0] / rdt - 1.0) < 1e-13, (i, to_np(dtd)[0], rdt)
+        check_flags(prob, T, R, g, rflags, record)
+        fired += rflags.astype(int).sum(axis=1)
+        got = to_np(ud)
+        assert rel_l2(got, u) < RTOL_FP64, (i, rel_l2(got, u))
+        assert elem_max_rel(got, u) < ELEM_RTOL, (i, elem_max_rel(got, u))
+    print("[tri_benchmark_instance] %s: flags fired per pass %s" % (start, fired), flush=True)
+    assert fired[2] > 0
+    if start == "near_vacuum":
+        assert fired[0] + fired[1] + fired[3] > 0
+    if dt is None:
+        u2 = to_dev(u_start)
+        sol.steps(u2, 4)
+        sol.sync()
+        assert rel_l2(to_np(u2), u) < RTOL_FP64, rel_l2(to_np(u2), u)
+        assert elem_max_rel(to_np(u2), u) < ELEM_RTOL
 
 
 @pytest.mark.parametrize("seed", range(10))

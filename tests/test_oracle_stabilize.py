@@ -42,6 +42,37 @@ def test_exponential_filter_strengths():
     assert abs(lam[R.M - 1, prob.p] - math.exp(-72.0 * dt)) < 1e-15
 
 
+def test_exponential_filter_cutoff():
+    """Sec. 4.1.1 with N* = 2 (p = 3, N_c = 4): eta* = 2/3 in x, 1/2 in z.  Modes below
+    both cutoffs are untouched, the factor is continuous (= 1) at the cutoff, the top
+    modes are still damped by exp(-alpha dt), and eta = 3/4 in z gives
+    ((3/4 - 1/2) / (1/2))^8 = 1/256 in the exponent (values worked by hand)."""
+    prob = _p(filter="exp", alpha=36.0, s=8.0, nstar=2.0)
+    T, R = build_tables(prob)
+    dt = 0.01
+    lam = filter_strength(prob, T, R, dt)
+    for k in (0, 1):
+        for j in (0, 1, 2):
+            assert lam[k, j] == 1.0
+    assert lam[2, 0] == 1.0                                              # eta_z = 1/2 = eta*
+    assert abs(lam[0, 3] - math.exp(-36.0 * dt)) < 1e-15
+    assert abs(lam[4, 0] - math.exp(-36.0 * dt)) < 1e-15
+    assert abs(lam[4, 3] - math.exp(-72.0 * dt)) < 1e-15
+    assert abs(lam[3, 0] - math.exp(-36.0 * dt / 256.0)) < 1e-15
+    assert abs(lam[3, 3] - math.exp(-36.0 * dt * (1.0 + 1.0 / 256.0))) < 1e-15
+    assert np.all(np.diff(lam, axis=0) <= 0) and np.all(np.diff(lam, axis=1) <= 0)
+    # 2D tensor modes (p = 3, N* = 1): eta* = 1/3 in each direction, per-direction terms add
+    p2 = Problem.from_config(dict(equation="euler2d", nx=2, ny=2, p=3, gpc_order=2, nq1d=3, rdim=2,
+                                  filter="exp", alpha=36.0, s=2.0, nstar=1.0))
+    T2, R2 = build_tables(p2)
+    lam2 = filter_strength(p2, T2, R2, dt)
+    for j in range(16):
+        a, b = j % 4, j // 4
+        tx = sum(0.0 if d / 3 < 1 / 3 else ((d / 3 - 1 / 3) / (2 / 3)) ** 2 for d in (a, b))
+        assert abs(lam2[0, j] - math.exp(-36.0 * dt * tx)) < 1e-15
+    assert lam2[0, 1 + 4] == 1.0 and lam2[1, 0] == 1.0 and lam2[2, 0] == 1.0       # (1,1) x and |k| = 1
+
+
 def test_filter_nodal_form_equals_modal_form():
     """F* = V Lambda o V^-1 on nodal values (Sec. 4.1.1) equals filtering the modal coefficients."""
     prob = _p(sensor="always")
