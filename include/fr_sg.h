@@ -230,6 +230,22 @@ fr_sg_status fr_sg_workspace_size(const fr_sg_problem* problem, int64_t* bytes);
 fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, void* workspace, int64_t workspace_bytes,
                         fr_sg_ctx** out);
 
+/* fr_sg_init for callers that cannot allocate device memory (code under HIP
+ * graph capture of the later calls, tight serving loops, harnesses that forbid
+ * hipMalloc): the workspace is a fixed 64 MiB array inside the library's device
+ * image, one per GPU, held from the library's first use on that GPU until the
+ * process ends; the caller passes no workspace.  Problems whose
+ * fr_sg_workspace_size exceeds 64 MiB are rejected with FRSG_EUNSUPPORTED and a
+ * message naming both sizes.  Every context made by this call on one GPU shares
+ * that GPU's array: a later fr_sg_init_static on the same GPU overwrites the
+ * tables and scalars of the earlier contexts (destroy them first), and calls on
+ * such contexts that overlap in time race.  The array keeps the last call's
+ * contents; this call clears the device scalars (time step, CFL accumulators,
+ * status word) and uploads the tables, and every other part of the workspace is
+ * written before it is read.  Otherwise as fr_sg_init (synchronises the
+ * stream; allocates and frees no device memory). */
+fr_sg_status fr_sg_init_static(const fr_sg_problem* problem, void* hip_stream, fr_sg_ctx** out);
+
 /* Sizes of the problem (host struct out). */
 fr_sg_status fr_sg_query(const fr_sg_ctx* ctx, fr_sg_info* out);
 

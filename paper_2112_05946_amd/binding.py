@@ -72,6 +72,7 @@ _VP = ctypes.c_void_p
 SYMBOLS = [
     ("fr_sg_workspace_size", ctypes.c_int32, [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_int64)]),
     ("fr_sg_init", ctypes.c_int32, [ctypes.POINTER(Problem), _VP, _VP, ctypes.c_int64, ctypes.POINTER(_VP)]),
+    ("fr_sg_init_static", ctypes.c_int32, [ctypes.POINTER(Problem), _VP, ctypes.POINTER(_VP)]),
     ("fr_sg_query", ctypes.c_int32, [_VP, ctypes.POINTER(Info)]),
     ("fr_sg_set_stream", ctypes.c_int32, [_VP, _VP]),
     ("fr_sg_points", ctypes.c_int32, [_VP, _VP, _VP, _VP]),
@@ -167,7 +168,7 @@ def _ptr(t):
 class Solver:
     """One FR-SG problem on the current HIP device and stream."""
 
-    def __init__(self, cfg, precision="fp64", stream=None):
+    def __init__(self, cfg, precision="fp64", stream=None, static_workspace=False):
         import torch
 
         self._torch = torch
@@ -180,6 +181,15 @@ class Solver:
         self._stream = s
         self._ctx = ctypes.c_void_p()
         prob = problem_from_config(cfg, precision)
+        if static_workspace:
+            # the library's fixed per-GPU array (fr_sg_init_static): nothing is allocated
+            self.workspace = None
+            st = self.lib.fr_sg_init_static(ctypes.byref(prob), ctypes.c_void_p(s.cuda_stream),
+                                            ctypes.byref(self._ctx))
+            if st != 0:
+                raise FrsgError(st, self.lib.fr_sg_last_error(None).decode())
+            self._finish_init()
+            return
         # the caller owns the workspace: a torch byte buffer of the size the library asks for
         nbytes = ctypes.c_int64()
         st = self.lib.fr_sg_workspace_size(ctypes.byref(prob), ctypes.byref(nbytes))
@@ -192,6 +202,9 @@ class Solver:
                                  ctypes.byref(self._ctx))
         if st != 0:
             raise FrsgError(st, self.lib.fr_sg_last_error(None).decode())
+        self._finish_init()
+
+    def _finish_init(self):
         info = Info()
         self._check(self.lib.fr_sg_query(self._ctx, ctypes.byref(info)))
         self.info = {f: getattr(info, f) for f, _ in Info._fields_}

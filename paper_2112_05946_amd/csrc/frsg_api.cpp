@@ -418,6 +418,16 @@ fr_sg_status fr_sg_workspace_size(const fr_sg_problem* problem, int64_t* bytes) 
 
 fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, void* workspace, int64_t workspace_bytes,
                         fr_sg_ctx** out) {
+  return frsg::init_with_workspace(problem, hip_stream, workspace, workspace_bytes, out, true);
+}
+
+}  // extern "C"
+
+void frsg::set_init_error(const std::string& msg) { g_init_error = msg; }
+
+// fr_sg_init on a given workspace (the caller's, or the library's static array)
+fr_sg_status frsg::init_with_workspace(const fr_sg_problem* problem, void* hip_stream, void* workspace,
+                                       int64_t workspace_bytes, fr_sg_ctx** out, bool check_device) {
   if (!out) {
     g_init_error = "out is NULL";
     return FRSG_EINVAL;
@@ -446,7 +456,7 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, void* wo
     delete c;
     return FRSG_EINVAL;
   }
-  {
+  if (check_device) {
     hipPointerAttribute_t attr;
     const hipError_t pe = hipPointerGetAttributes(&attr, workspace);
     (void)hipGetLastError();  // do not leave the query's status for a later launch check
@@ -558,6 +568,8 @@ fr_sg_status fr_sg_init(const fr_sg_problem* problem, void* hip_stream, void* wo
   *out = c;
   return FRSG_OK;
 }
+
+extern "C" {
 
 fr_sg_status fr_sg_query(const fr_sg_ctx* ctx, fr_sg_info* out) {
   if (!ctx || !out) return FRSG_EINVAL;

@@ -219,6 +219,13 @@ struct fr_sg_ctx {
 };
 
 namespace frsg {
+// fr_sg_init's work on a given device workspace (frsg_api.cpp), and the text that
+// fr_sg_last_error(NULL) reports after a failed init
+// (check_device: confirm that the caller's pointer is device memory)
+fr_sg_status init_with_workspace(const fr_sg_problem* problem, void* hip_stream, void* workspace,
+                                 int64_t workspace_bytes, fr_sg_ctx** out, bool check_device);
+void set_init_error(const std::string& msg);
+
 // one fused stage of the 2D Euler path (kernels_euler2d.hip)
 struct FusedStage {
   const double* in;
