@@ -274,8 +274,9 @@ static fr_sg_status prepare(const fr_sg_problem& problem, fr_sg_ctx* c, std::str
   std::vector<double>& blob = c->host_tab;
   blob.clear();
   c->tab_off.clear();
+  if (c->dim == 2 && !c->is_tri) build_quad_fragments(c->T);
   for (const std::vector<double>* v : {&T.r, &T.w, &T.D, &T.lL, &T.lR, &T.dhL, &T.dhR, &T.V, &T.Vinv, &T.Phi, &T.PW,
-                                       &T.filt, &T.shell, &T.swts, &T.Dt, &T.cmax, &T.PhiT, &T.PWT}) {
+                                       &T.filt, &T.shell, &T.swts, &T.Dt, &T.cmax, &T.PhiT, &T.PWT, &T.qfrag}) {
     c->tab_off.push_back(blob.size());
     blob.insert(blob.end(), v->begin(), v->end());
   }
@@ -316,6 +317,10 @@ static fr_sg_status prepare(const fr_sg_problem& problem, fr_sg_ctx* c, std::str
     K.nfp = c->tri.nfp;
   }
   c->fused = !c->is_tri && fused2d_supported(K);
+  // the matrix-core kernel takes the BF16-split steps of the 2D quadrilateral path (and the
+  // FP64 ones where the VALU kernel does not apply)
+  c->quad = !c->is_tri && quad_mfma_supported(K) &&
+            (P.precision == FRSG_BF16_SPLIT || (P.precision == FRSG_FP64 && !c->fused));
   c->fused_tri = c->is_tri && tri_fused_supported(K);
   c->fused1d = c->dim == 1 && fr1d_supported(K);
   if (P.precision == FRSG_FP32_MIXED && !c->fused) {
@@ -323,8 +328,9 @@ static fr_sg_status prepare(const fr_sg_problem& problem, fr_sg_ctx* c, std::str
           "a compiled (M, Nq) pair)";
     return FRSG_EUNSUPPORTED;
   }
-  if (P.precision == FRSG_BF16_SPLIT) {
-    err = "FRSG_BF16_SPLIT is not available for this problem";
+  if (P.precision == FRSG_BF16_SPLIT && !c->quad) {
+    err = "FRSG_BF16_SPLIT runs on the matrix-core 2D Euler path only (FR degree 3, nx and ny even, "
+          "a compiled (M, Nq) pair)";
     return FRSG_EUNSUPPORTED;
   }
   // triangle operators and geometry: one double array and the neighbour table
@@ -354,14 +360,14 @@ static fr_sg_status prepare(const fr_sg_problem& problem, fr_sg_ctx* c, std::str
     return at;
   };
   const size_t state = (size_t)c->S * T.M * c->E * c->nsp;
-  const bool no_nodal = c->fused || c->fused_tri;
+  const bool no_nodal = c->fused || c->quad || c->fused_tri;
   const size_t nodal = no_nodal ? 0 : (size_t)c->S * T.Nq * c->E * c->nsp;
   const size_t corr = no_nodal ? 0
                       : (size_t)c->S * T.Nq * c->E * (c->is_tri ? 3 * c->tri.nfp : (c->dim == 2 ? 4 * n : 2));
   const size_t ntm = c->fused_tri ? (size_t)c->S * T.M * c->E * 3 * c->tri.nfp : 0;
   const bool adj = c->dim == 1 && c->S == 1;
   const size_t nadj_part = adj ? (size_t)std::max(adjoint_partials(K), adj1d_partials(K)) : 0;
-  const size_t ntr = c->fused ? fused2d_trace_count(P.nx, P.ny, T.M) : 0;
+  const size_t ntr = c->quad ? quad_trace_count(P.nx, P.ny, T.M) : c->fused ? fused2d_trace_count(P.nx, P.ny, T.M) : 0;
   const Tableau* tab_rk = tableau_of(P.integrator);
   const int nrk = tab_rk ? tab_rk->s : 0;
   L.sc = take(256);
@@ -519,6 +525,7 @@ fr_sg_status frsg::init_with_workspace(const fr_sg_problem* problem, void* hip_s
   tab.cmax = c->dcmax;
   c->dPhiT = b + off[16];
   c->dPWT = b + off[17];
+  c->dfrag = b + off[18];
   if (c->fused) {
     c->dPhiT32 = (const float*)(ws + L.f32);
     c->dPWT32 = c->dPhiT32 + c->T.PhiT.size();
@@ -688,6 +695,13 @@ static fr_sg_status rhs_into(fr_sg_ctx* ctx, const double* u, double* dudt) {
     return timed(ctx, "stage_rhs", 2 * state_bytes(ctx), [&] {
       return launch_stage_tri(ctx->kp, u, u, u, dudt, 0.0, 1.0, 1, ctx->ws.Tm[0], 0, nullptr, ctx->stream);
     });
+  if (ctx->quad) {
+    fr_sg_status st = timed(ctx, "traces", 0.0, [&] { return launch_quad_traces(ctx->kp, u, ctx->ws.tr[0], ctx->stream); });
+    if (st != FRSG_OK) return st;
+    QuadStage S{u, u, dudt, 0.0, 1.0, 0, nullptr, nullptr, nullptr, ctx->dDt, ctx->dcmax, ctx->dfrag,
+                ctx->prob.precision == FRSG_BF16_SPLIT ? 1 : 0, ctx->ws.tr[0], nullptr};
+    return timed(ctx, "stage_rhs", 2 * state_bytes(ctx), [&] { return launch_quad_stage(ctx->kp, S, ctx->stream); });
+  }
   if (ctx->fused) {
     FusedStage S{u,          u,          dudt,         0.0,         1.0,           0,
                  nullptr,    nullptr,    nullptr,      ctx->dDt,    ctx->dcmax,    ctx->dPhiT,
@@ -890,6 +904,50 @@ static fr_sg_status step_fused(fr_sg_ctx* ctx, double* u, double dt, double* dt_
   return FRSG_OK;
 }
 
+// matrix-core 2D Euler step (FP64 or BF16-split): one kernel per stage.  Every
+// stage reads the modal face traces of its input from the trace buffer the
+// previous launch wrote; the first stage of a call gets them from a trace pass
+// over u unless the previous step of the same call wrote them (chained).
+static fr_sg_status step_quad(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, uint8_t* flags, bool chained) {
+  const KParams& K = ctx->kp;
+  Workspace& W = ctx->ws;
+  hipStream_t s = ctx->stream;
+  const int E = ctx->E;
+  const double sb = state_bytes(ctx);
+  unsigned long long* lam[2] = {(unsigned long long*)(W.scal + 1), (unsigned long long*)(W.scal + 3)};
+  const int cur = ctx->lam_cur;
+  fr_sg_status st;
+  if (dt > 0.0) {
+    FRSG_TRY_HIP(launch_set_dt(K, dt, nullptr, lam[cur ^ 1], s), ctx);
+  } else {
+    if (!chained)
+      if ((st = timed(ctx, "cfl", sb, [&] { return launch_fused_cfl(K, u, lam[cur], s); }))) return st;
+    FRSG_TRY_HIP(launch_dt_from(K, lam[cur], lam[cur ^ 1], nullptr, s), ctx);
+  }
+  const int tc = ctx->tr_cur;
+  if (!chained)
+    if ((st = timed(ctx, "traces", 0.0, [&] { return launch_quad_traces(K, u, W.tr[tc], s); }))) return st;
+  uint8_t* f0 = flags ? flags : nullptr;
+  uint8_t* f1 = flags ? flags + E : nullptr;
+  uint8_t* f2 = flags ? flags + 2 * E : nullptr;
+  uint8_t* f3 = flags ? flags + 3 * E : nullptr;
+  const int bf = ctx->prob.precision == FRSG_BF16_SPLIT ? 1 : 0;
+  QuadStage s1{u, u, W.w1, 0.0, 1.0, 1, f0, nullptr, nullptr, ctx->dDt, ctx->dcmax, ctx->dfrag, bf, W.tr[tc],
+               W.tr[tc ^ 1]};
+  if ((st = timed(ctx, "stage1", 2 * sb, [&] { return launch_quad_stage(K, s1, s); }))) return st;
+  QuadStage s2{W.w1, u, W.w2, 0.75, 0.25, 2, f1, nullptr, nullptr, ctx->dDt, ctx->dcmax, ctx->dfrag, bf,
+               W.tr[tc ^ 1], W.tr[tc]};
+  if ((st = timed(ctx, "stage2", 3 * sb, [&] { return launch_quad_stage(K, s2, s); }))) return st;
+  QuadStage s3{W.w2, u, u, 1.0 / 3.0, 2.0 / 3.0, 3, f3, f2, lam[cur ^ 1], ctx->dDt, ctx->dcmax, ctx->dfrag, bf,
+               W.tr[tc], W.tr[tc ^ 1]};
+  if ((st = timed(ctx, "stage3", 3 * sb, [&] { return launch_quad_stage(K, s3, s); }))) return st;
+  ctx->tr_cur = tc ^ 1;
+  ctx->lam_cur = cur ^ 1;
+  ctx->lam_for = u;
+  if (dt_used) FRSG_TRY_HIP(launch_copy_dt(K, dt_used, s), ctx);
+  return FRSG_OK;
+}
+
 // One step of a tableau integrator (RK4, Bogacki-Shampine 3(2), Tsitouras 5(4)):
 //   K_1 = R(u), Y_i = Lim(u + dt sum_{j<i} a_ij K_j), K_i = R(Y_i),
 //   u <- Lim(Filter(u + dt sum_i b_i K_i)),
@@ -908,11 +966,11 @@ static fr_sg_status step_rk(fr_sg_ctx* ctx, double* u, double dt, double* dt_use
   fr_sg_status st;
   // dt on the device: fixed, or from the CFL maximum of u
   if (dt > 0.0) {
-    if (ctx->fused || ctx->fused1d)
+    if (ctx->fused || ctx->quad || ctx->fused1d)
       FRSG_TRY_HIP(launch_set_dt(K, dt, nullptr, nullptr, s), ctx);
     else
       FRSG_TRY_HIP(launch_set_scalars(K, dt, s), ctx);
-  } else if (ctx->fused) {
+  } else if (ctx->fused || ctx->quad) {
     if ((st = timed(ctx, "cfl", sb, [&] { return launch_fused_cfl(K, u, lam, s); }))) return st;
     FRSG_TRY_HIP(launch_dt_from(K, lam, nullptr, nullptr, s), ctx);
   } else if (ctx->fused1d) {
@@ -1020,6 +1078,7 @@ fr_sg_status fr_sg_step(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, u
   fr_sg_status st = check_step_args(ctx, u, dt);
   if (st != FRSG_OK) return st;
   if (ctx->prob.integrator != FRSG_SSPRK3) return step_rk(ctx, u, dt, dt_used, flags);
+  if (ctx->quad) return step_quad(ctx, u, dt, dt_used, flags, false);
   if (ctx->fused) return step_fused(ctx, u, dt, dt_used, flags, false);
   if (ctx->fused1d) return step_fused1d(ctx, u, dt, dt_used, flags, false);
   return step_generic(ctx, u, dt, dt_used, flags);
@@ -1038,6 +1097,8 @@ fr_sg_status fr_sg_steps(fr_sg_ctx* ctx, double* u, int32_t nsteps, double* dt_u
     uint8_t* f = flags ? flags + i * fl : nullptr;
     if (ctx->prob.integrator != FRSG_SSPRK3)
       st = step_rk(ctx, u, 0.0, dtu, f);
+    else if (ctx->quad)
+      st = step_quad(ctx, u, 0.0, dtu, f, i > 0);
     else if (ctx->fused)
       st = step_fused(ctx, u, 0.0, dtu, f, i > 0);
     else if (ctx->fused1d)

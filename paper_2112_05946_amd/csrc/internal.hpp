@@ -42,7 +42,34 @@ struct HostTables {
   std::vector<double> Dt;                // D - h_L' l(-1)^T - h_R' l(+1)^T (np1 x np1)
   std::vector<double> cmax;              // [M]: max_q |Phi_k(z_q)|
   std::vector<double> PhiT, PWT;         // [Nq * M] node-major copies of Phi, PW
+  std::vector<double> qfrag;             // matrix-core operand tables (quadrilateral 2D path)
 };
+
+// offsets (in doubles) of the matrix-core operand tables of the quadrilateral
+// 2D stage kernel (tables_quad.cpp), for nb = ceil(N_q / 16) node blocks:
+//   aexp_f [nb][4][64]  chaos basis, FP64 instruction, mode 4 t + lane/16
+//   aexp_b [nb][4][64]  chaos basis, FP64 instruction, mode 4 lane/16 + t
+//   aprj   [nb][4][64]  weighted basis for the FP64 projection
+//   bexp   [nb][2][64]  chaos basis as bfloat16 high / low parts (4 per lane)
+//   bprj   [nb][2][64]  weighted basis as bfloat16 high / low parts
+//   wslot  [nb][16]     quadrature weight of the node in register r, lane group g
+struct QuadFragLayout {
+  int nb = 0;
+  int aexp_f = 0, aexp_b = 0, aprj = 0, bexp = 0, bprj = 0, wslot = 0, total = 0;
+};
+__host__ __device__ inline QuadFragLayout quad_frag_layout(int Nq) {
+  QuadFragLayout L;
+  L.nb = (Nq + 15) / 16;
+  L.aexp_f = 0;
+  L.aexp_b = L.aexp_f + L.nb * 4 * 64;
+  L.aprj = L.aexp_b + L.nb * 4 * 64;
+  L.bexp = L.aprj + L.nb * 4 * 64;
+  L.bprj = L.bexp + L.nb * 2 * 64;
+  L.wslot = L.bprj + L.nb * 2 * 64;
+  L.total = L.wslot + L.nb * 16;
+  return L;
+}
+void build_quad_fragments(HostTables& T);
 
 bool build_host_tables(const fr_sg_problem& P, HostTables& T, std::string& err);
 // exponent of the exponential filter along one dimension (Sec. 4.1.1): 0 below the
@@ -202,7 +229,9 @@ struct fr_sg_ctx {
   const double* dPWT = nullptr;
   const float* dPhiT32 = nullptr;  // FP32 copies of the node-major tables
   const float* dPWT32 = nullptr;
-  bool fused = false;            // fused 2D Euler stage kernel
+  bool fused = false;            // fused 2D Euler stage kernel (FP32-mixed, and the element-wise passes)
+  bool quad = false;             // matrix-core 2D Euler stage kernel (FP64, BF16-split)
+  const double* dfrag = nullptr; // its operand tables
   bool fused1d = false;          // fused 1D stage kernel
   int lam_cur = 0;              // which CFL accumulator holds the maximum of the current state
   const double* lam_for = nullptr;  // state whose maximum the previous step recorded (fr_sg_steps)
@@ -247,6 +276,30 @@ struct FusedStage {
   double* tr_out = nullptr;       // where to write those of `out` (may be null)
 };
 bool fused2d_supported(const KParams& P);
+
+// one stage of the matrix-core 2D Euler path on quadrilaterals (kernels_quad_mfma.hip)
+struct QuadStage {
+  const double* in;
+  const double* u;
+  double* out;
+  double cu, cw;
+  int stage;  // 0: rhs; 1, 2: limited stage output; 3: end of step
+  unsigned char* flag_lim;
+  unsigned char* flag_filt;
+  unsigned long long* lam_next;
+  const double* Dt;
+  const double* cmax;
+  const double* frag;   // operand tables (QuadFragLayout)
+  int bf16;             // 1: bfloat16-split transforms (FRSG_BF16_SPLIT)
+  const double* tr_in;  // modal face traces of `in` on tile boundaries (required)
+  double* tr_out;       // where to write those of `out` (may be null)
+};
+bool quad_mfma_supported(const KParams& P);
+// doubles of one modal face-trace buffer of the matrix-core path
+size_t quad_trace_count(int nx, int ny, int M);
+hipError_t launch_quad_stage(const KParams& P, const QuadStage& S, hipStream_t s);
+// modal face traces of a state on every tile boundary face
+hipError_t launch_quad_traces(const KParams& P, const double* u, double* tr, hipStream_t s);
 // doubles of one modal face-trace buffer of the fused 2D kernel
 size_t fused2d_trace_count(int nx, int ny, int M);
 hipError_t launch_fused_stage(const KParams& P, const FusedStage& S, hipStream_t s);
