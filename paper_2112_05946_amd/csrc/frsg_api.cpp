@@ -323,11 +323,12 @@ static fr_sg_status prepare(const fr_sg_problem& problem, fr_sg_ctx* c, std::str
             (P.precision == FRSG_BF16_SPLIT || (P.precision == FRSG_FP64 && !c->fused));
   c->fused_tri = c->is_tri && tri_fused_supported(K);
   c->fused1d = c->dim == 1 && fr1d_supported(K);
-  if (P.precision == FRSG_FP32_MIXED && !c->fused) {
-    err = "FRSG_FP32_MIXED runs on the fused 2D Euler path only (FR degree 3, nx % 4 == 0, ny % 2 == 0, "
-          "a compiled (M, Nq) pair)";
+  if (P.precision == FRSG_FP32_MIXED && !c->fused && !c->fused1d) {
+    err = "FRSG_FP32_MIXED runs on the fused 1D path (FR degree <= 7, Nq <= 85, one block's LDS within "
+          "64 KiB) and the fused 2D Euler path (FR degree 3, nx % 4 == 0, ny % 2 == 0, a compiled (M, Nq) pair)";
     return FRSG_EUNSUPPORTED;
   }
+  K.fp32 = P.precision == FRSG_FP32_MIXED ? 1 : 0;
   if (P.precision == FRSG_BF16_SPLIT && !c->quad) {
     err = "FRSG_BF16_SPLIT runs on the matrix-core 2D Euler path only (FR degree 3, nx and ny even, "
           "a compiled (M, Nq) pair)";
@@ -1136,6 +1137,11 @@ fr_sg_status fr_sg_adjoint_step(fr_sg_ctx* ctx, const double* u_n, const uint8_t
   if (ctx->prob.filter != FRSG_FILTER_NONE && !flags_n) {
     ctx->err = "flags_n is needed: the filter decisions of the forward step";
     return FRSG_EINVAL;
+  }
+  if (ctx->kp.fp32 && !adj1d_fused_supported(ctx->kp)) {
+    ctx->err = "the FP32-mixed adjoint runs on the fused adjoint kernel (FR degree <= 7, Nq <= 85, one block's "
+               "LDS within 48 KiB)";
+    return FRSG_EUNSUPPORTED;
   }
   const KParams& K = ctx->kp;
   Workspace& W = ctx->ws;

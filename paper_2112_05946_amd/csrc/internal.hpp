@@ -139,6 +139,7 @@ struct KParams {
   int filter, sensor, limiter;
   int flux;  // FRSG_FLUX_*
   double alpha, sensor_thr;
+  int fp32;  // 1: FP32-mixed node loops (1D stage and adjoint kernels)
   DevTab tab;
   // triangles (element = FRSG_ELEM_TRI; tri = 0 on quadrilateral meshes)
   int tri, nfp;

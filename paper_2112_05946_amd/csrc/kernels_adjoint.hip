@@ -41,46 +41,49 @@ constexpr int kMaxNp = 8;  // FR degree <= 7
 
 inline unsigned grid_for(long n, int block = kBlock) { return (unsigned)((n + block - 1) / block); }
 
-__device__ __forceinline__ double sgn(double x) { return (double)((x > 0.0) - (x < 0.0)); }
+template <typename T>
+__device__ __forceinline__ T sgn(T x) { return (T)((x > T(0)) - (x < T(0))); }
 
 // f'(U) of the scalar flux
-template <int EQ>
-__device__ __forceinline__ double dflux(double U, double adv) {
+template <int EQ, typename T>
+__device__ __forceinline__ T dflux(T U, T adv) {
   if constexpr (EQ == kAdvection) return adv;
   else return U;
 }
 
 // transpose of F = (f(L) + f(R))/2 - lam (R - L)/2 applied to g; also d/da of g F
-template <int EQ>
-__device__ __forceinline__ void rusanov_adj(double L, double R, double g, double adv, double& gL, double& gR,
-                                            double& da) {
+template <int EQ, typename T>
+__device__ __forceinline__ void rusanov_adj(T L, T R, T g, T adv, T& gL, T& gR, T& da) {
+  const T h = T(0.5);
   if constexpr (EQ == kAdvection) {
-    const double aa = fabs(adv);
-    gL = 0.5 * adv * g + 0.5 * aa * g;
-    gR = 0.5 * adv * g - 0.5 * aa * g;
-    da = g * (0.5 * (L + R) - 0.5 * sgn(adv) * (R - L));
+    const T aa = fabs(adv);
+    gL = h * adv * g + h * aa * g;
+    gR = h * adv * g - h * aa * g;
+    da = g * (h * (L + R) - h * sgn(adv) * (R - L));
   } else {
-    const double sL = fabs(L), sR = fabs(R);
-    const double lam = fmax(sL, sR);
-    const double dlam = -0.5 * (R - L) * g;
-    gL = 0.5 * L * g + 0.5 * lam * g;
-    gR = 0.5 * R * g - 0.5 * lam * g;
+    const T sL = fabs(L), sR = fabs(R);
+    const T lam = fmax(sL, sR);
+    const T dlam = -h * (R - L) * g;
+    gL = h * L * g + h * lam * g;
+    gR = h * R * g - h * lam * g;
     if (sL >= sR)
       gL += sgn(L) * dlam;
     else
       gR += sgn(R) * dlam;
-    da = 0.0;
+    da = T(0);
   }
 }
 
 // transpose of the ghost trace of a boundary side (outflow: copy, Dirichlet: constant)
-__device__ __forceinline__ double ghost_adj(const KParams& P, int side, double g) {
-  return P.bc[side] == FRSG_BC_OUTFLOW ? g : 0.0;
+template <typename T>
+__device__ __forceinline__ T ghost_adj(const KParams& P, int side, T g) {
+  return P.bc[side] == FRSG_BC_OUTFLOW ? g : T(0);
 }
 
 // ghost value of a boundary side for a scalar interior trace
-__device__ __forceinline__ double ghost_val(const KParams& P, int side, double t) {
-  return P.bc[side] == FRSG_BC_DIRICHLET ? P.bc_state[side][0] : t;
+template <typename T>
+__device__ __forceinline__ T ghost_val(const KParams& P, int side, T t) {
+  return P.bc[side] == FRSG_BC_DIRICHLET ? (T)P.bc_state[side][0] : t;
 }
 
 // ---------------------------------------------------------------------------
@@ -251,6 +254,9 @@ __global__ void __launch_bounds__(kBlock) k_filter_adj(KParams P, const double* 
 // steps as k_adj_node / k_adj_face / k_adj_project, with the state and adjoint
 // coefficients of the block and one neighbour on each side staged in LDS)
 //   out = c0 x0 + c1 x1 + c2 x2 + cg (dR/dw)^T g
+// FP32-mixed (R = float): the node and face steps and the projection of the
+// modes k >= 1 in FP32 on the FP64 inputs and tables rounded to FP32; mode 0 is
+// projected in FP64, and the combination is FP64.
 // ---------------------------------------------------------------------------
 constexpr int kBlockA = 256;
 
@@ -266,7 +272,7 @@ struct AdjStageArgs {
   int EB;
 };
 
-template <int EQ, int N>
+template <int EQ, int N, typename R>
 __global__ void __launch_bounds__(kBlockA) k_adj_stage1d(KParams P, AdjStageArgs A) {
   constexpr int n = N;
   extern __shared__ double smem[];
@@ -300,38 +306,40 @@ __global__ void __launch_bounds__(kBlockA) k_adj_stage1d(KParams P, AdjStageArgs
   const int ls = tid / Nq, q = tid - ls * Nq;
   const bool active = ls < nloc + 2;
   const bool owned = active && ls >= 1 && ls <= nloc;
-  double U[n], GU[n];
-  double pa = 0.0;
-  double tm = 0.0, tp = 0.0;
+  const R adv = (R)P.adv;
+  R U[n], GU[n];
+  R pa = R(0);
+  R tm = R(0), tp = R(0);
   if (active) {
     const double* W = sW + ls * nc;
     const double* Gc = sGc + ls * nc;
-    double d[n];
+    const R Jx = (R)P.Jx;
+    R d[n];
 #pragma unroll
     for (int j = 0; j < n; ++j) {
-      double u = 0.0, gr = 0.0;
+      R u = R(0), gr = R(0);
       for (int k = 0; k < M; ++k) {
-        u += W[k * n + j] * P.tab.Phi[k * Nq + q];
-        gr += P.tab.PW[k * Nq + q] * Gc[k * n + j];
+        u += (R)W[k * n + j] * (R)P.tab.Phi[k * Nq + q];
+        gr += (R)P.tab.PW[k * Nq + q] * (R)Gc[k * n + j];
       }
       U[j] = u;
-      d[j] = -gr / P.Jx;
+      d[j] = -gr / Jx;
     }
-    double GL = 0.0, GR = 0.0;
+    R GL = R(0), GR = R(0);
 #pragma unroll
     for (int j = 0; j < n; ++j) {
-      GL += P.tab.dhL[j] * d[j];
-      GR += P.tab.dhR[j] * d[j];
-      tm += P.tab.lL[j] * U[j];
-      tp += P.tab.lR[j] * U[j];
+      GL += (R)P.tab.dhL[j] * d[j];
+      GR += (R)P.tab.dhR[j] * d[j];
+      tm += (R)P.tab.lL[j] * U[j];
+      tp += (R)P.tab.lR[j] * U[j];
     }
 #pragma unroll
     for (int l = 0; l < n; ++l) {
-      double gF = 0.0;
+      R gF = R(0);
 #pragma unroll
-      for (int j = 0; j < n; ++j) gF += P.tab.D[j * n + l] * d[j];
-      gF = gF - P.tab.lL[l] * GL - P.tab.lR[l] * GR;
-      GU[l] = dflux<EQ>(U[l], P.adv) * gF;
+      for (int j = 0; j < n; ++j) gF += (R)P.tab.D[j * n + l] * d[j];
+      gF = gF - (R)P.tab.lL[l] * GL - (R)P.tab.lR[l] * GR;
+      GU[l] = dflux<EQ>(U[l], adv) * gF;
       if constexpr (EQ == kAdvection)
         if (owned) pa += gF * U[l];
     }
@@ -351,31 +359,31 @@ __global__ void __launch_bounds__(kBlockA) k_adj_stage1d(KParams P, AdjStageArgs
     const double* Sl = sS + ((long)(ls - 1) * Nq + q) * 2;
     const double* Sc = sS + ((long)ls * Nq + q) * 2;
     const double* Sr = sS + ((long)(ls + 1) * Nq + q) * 2;
-    double gTm, gTp;
+    R gTm, gTp;
     {  // left face
       const bool interior = e > 0 || periodic;
-      const double UL = interior ? Tl[1] : ghost_val(P, 0, tm);
-      const double gF = Sc[0] + (interior ? Sl[1] : 0.0);
-      double gL, gR, da;
-      rusanov_adj<EQ>(UL, tm, gF, P.adv, gL, gR, da);
-      gTm = gR + (interior ? 0.0 : ghost_adj(P, 0, gL));
+      const R UL = interior ? (R)Tl[1] : ghost_val(P, 0, tm);
+      const R gF = (R)Sc[0] + (interior ? (R)Sl[1] : R(0));
+      R gL, gR, da;
+      rusanov_adj<EQ>(UL, tm, gF, adv, gL, gR, da);
+      gTm = gR + (interior ? R(0) : ghost_adj(P, 0, gL));
       pa += da;
     }
     {  // right face
       const bool interior = e < E - 1 || periodic;
-      const double UR = interior ? Tr[0] : ghost_val(P, 1, tp);
-      const double gF = Sc[1] + (interior ? Sr[0] : 0.0);
-      double gL, gR, da;
-      rusanov_adj<EQ>(tp, UR, gF, P.adv, gL, gR, da);
-      gTp = gL + (interior ? 0.0 : ghost_adj(P, 1, gR));
+      const R UR = interior ? (R)Tr[0] : ghost_val(P, 1, tp);
+      const R gF = (R)Sc[1] + (interior ? (R)Sr[0] : R(0));
+      R gL, gR, da;
+      rusanov_adj<EQ>(tp, UR, gF, adv, gL, gR, da);
+      gTp = gL + (interior ? R(0) : ghost_adj(P, 1, gR));
       if (!interior) pa += da;
     }
 #pragma unroll
     for (int j = 0; j < n; ++j)
-      sU[((long)(ls - 1) * n + j) * Nq + q] = GU[j] + P.tab.lL[j] * gTm + P.tab.lR[j] * gTp;
+      sU[((long)(ls - 1) * n + j) * Nq + q] = (double)(GU[j] + (R)P.tab.lL[j] * gTm + (R)P.tab.lR[j] * gTp);
   }
   if (A.part) {
-    const double sum = block_reduce_sum(pa, sm);
+    const double sum = block_reduce_sum((double)pa, sm);
     if (tid == 0) A.part[blockIdx.x] = sum;
   } else {
     __syncthreads();
@@ -387,7 +395,13 @@ __global__ void __launch_bounds__(kBlockA) k_adj_stage1d(KParams P, AdjStageArgs
     const int le = rem / n, j = rem - le * n;
     const double* Gq = sU + ((long)le * n + j) * Nq;
     double acc = 0.0;
-    for (int qq = 0; qq < Nq; ++qq) acc += P.tab.Phi[k * Nq + qq] * Gq[qq];
+    if (std::is_same<R, double>::value || k == 0) {
+      for (int qq = 0; qq < Nq; ++qq) acc += P.tab.Phi[k * Nq + qq] * Gq[qq];
+    } else {
+      R a = R(0);
+      for (int qq = 0; qq < Nq; ++qq) a += (R)P.tab.Phi[k * Nq + qq] * (R)Gq[qq];
+      acc = (double)a;
+    }
     const long idx = (long)k * EN + (long)(e0 + le) * n + j;
     double v = A.cg * acc;
     if (A.x0) v += A.c0 * A.x0[idx];
@@ -443,12 +457,22 @@ hipError_t launch_adj_stage1d(const KParams& P, const double* w, const double* g
   const unsigned grid = (unsigned)((P.E + EB - 1) / EB);
   auto go = [&](auto eq_tag) -> hipError_t {
     constexpr int EQ = decltype(eq_tag)::value;
-    switch (P.np1) {
+    if (P.fp32) {
+      switch (P.np1) {
 #define FRSG_N(NN) \
-  case NN: hipLaunchKernelGGL((k_adj_stage1d<EQ, NN>), dim3(grid), dim3(kBlockA), shmem, s, P, A); break;
-      FRSG_N(2) FRSG_N(3) FRSG_N(4) FRSG_N(5) FRSG_N(6) FRSG_N(7) FRSG_N(8)
+  case NN: hipLaunchKernelGGL((k_adj_stage1d<EQ, NN, float>), dim3(grid), dim3(kBlockA), shmem, s, P, A); break;
+        FRSG_N(2) FRSG_N(3) FRSG_N(4) FRSG_N(5) FRSG_N(6) FRSG_N(7) FRSG_N(8)
 #undef FRSG_N
-      default: return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+      }
+    } else {
+      switch (P.np1) {
+#define FRSG_N(NN) \
+  case NN: hipLaunchKernelGGL((k_adj_stage1d<EQ, NN, double>), dim3(grid), dim3(kBlockA), shmem, s, P, A); break;
+        FRSG_N(2) FRSG_N(3) FRSG_N(4) FRSG_N(5) FRSG_N(6) FRSG_N(7) FRSG_N(8)
+#undef FRSG_N
+        default: return hipErrorInvalidValue;
+      }
     }
     return hipGetLastError();
   };

@@ -39,6 +39,14 @@
 // threshold evaluate density and pressure node by node, so both routes give the
 // same decision as the node-by-node test.
 //
+// FP32-mixed precision (R = float): the node loop (expansion, fluxes, traces,
+// interface fluxes, residual, projection of the modes k >= 1) runs in FP32 on
+// the coefficients and tables rounded to FP32; the mean mode k = 0 is projected
+// in FP64, and the stage combination, detector, filter, limiter, face traces for
+// the neighbours and the CFL maximum are FP64.  Inside a tile both sides of a
+// face read the same FP32 trace; across tiles the neighbour's side comes from
+// its FP64 modal trace, so the two traces agree to FP32 rounding there.
+//
 // Exchanges inside an element: the 16 threads of an (element, h) form one
 // 16-lane DPP row, quad_perm rotations move along x (a) and row_ror:4k along y
 // (b); the two rows of an element trade values with v_permlane16_swap.
@@ -584,6 +592,8 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ PhiTd,
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int k = 0; k < M; ++k) acc[i][k] = R(0);
+  // the mean mode k = 0 of the FP32 loop is projected in FP64 (weights w_q = PW[0][q])
+  double acc0[2] = {0.0, 0.0};
 
   // own pair at (j, q): gPC expansion at the node
   auto expand = [&](int q, R* u2) {
@@ -706,14 +716,25 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ PhiTd,
                (ydot(dy, G[s]) + fyl[s] * dhLb + fyr[s] * dhRb) * iJy;
       swap_rows(r[0], r[2]);
       swap_rows(r[1], r[3]);
+      constexpr int K0 = kFP64 ? 0 : 1;
+      if constexpr (!kFP64) {
+        const double w0 = P.tab.PW[q0];
+        acc0[0] += w0 * (double)r[0];
+        acc0[1] += w0 * (double)r[1];
+      }
 #pragma unroll
-      for (int k = 0; k < M; ++k) {
+      for (int k = K0; k < M; ++k) {
         acc[0][k] += PWT[q0 * M + k] * r[0];
         acc[1][k] += PWT[q0 * M + k] * r[1];
       }
       if (q1 != q0) {
+        if constexpr (!kFP64) {
+          const double w1 = P.tab.PW[q1];
+          acc0[0] += w1 * (double)r[2];
+          acc0[1] += w1 * (double)r[3];
+        }
 #pragma unroll
-        for (int k = 0; k < M; ++k) {
+        for (int k = K0; k < M; ++k) {
           acc[0][k] += PWT[q1 * M + k] * r[2];
           acc[1][k] += PWT[q1 * M + k] * r[3];
         }
@@ -722,12 +743,14 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ PhiTd,
   }
 
   // ----------------------------------------------------------------- epilogue
+  // projected residual of mode k of variable 2h + i, in FP64
+  auto res = [&](int i, int k) { return (!kFP64 && k == 0) ? acc0[i] : (double)acc[i][k]; };
   const auto rout = state_rsrc(out, sbytes);
   if (A.stage == 0) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int k = 0; k < M; ++k) bstore((double)acc[i][k], rout, voff, soff(i, k));
+      for (int k = 0; k < M; ++k) bstore(res(i, k), rout, voff, soff(i, k));
     return;
   }
   double o[2][M];
@@ -741,7 +764,7 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ PhiTd,
         const double uu = bload(ru, voff, soff(i, k));  // 0 from an empty range when cu = 0
         // the FP64 input: kept in registers by the FP64 loop, re-read otherwise
         const double mi = kFP64 ? (double)m[i][k] : bload(rin2, voff, soff(i, k));
-        o[i][k] = A.cu * uu + A.cw * (mi + dt * (double)acc[i][k]);
+        o[i][k] = A.cu * uu + A.cw * (mi + dt * res(i, k));
       }
   }
 

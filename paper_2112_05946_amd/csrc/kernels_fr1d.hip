@@ -18,6 +18,13 @@
 //   4. thread (element, variable, mode, point) projects, sum_q PW[k,q] R_q[j],
 //      and writes cu u + cw (w + dt R) (or R alone for a right-hand side).
 // Element counts that are not a multiple of EB leave the last workgroup partly idle.
+//
+// FP32-mixed precision (R = float): steps 2 and 3 and the projection of the
+// modes k >= 1 run in FP32 on the FP64 coefficients and tables rounded to FP32;
+// the mean mode k = 0 is projected in FP64 (of the FP32 nodal residual), and the
+// stage combination, the filter, the limiter and the CFL maximum stay in FP64.
+// Both sides of a face read the same trace from LDS, so the interface flux is
+// single-valued.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -55,7 +62,7 @@ struct Stage1DArgs {
   double* dt_used;
 };
 
-template <int EQ, int N>
+template <int EQ, int N, typename R>
 __global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
   constexpr int S = nstate<EQ>();
   constexpr int n = N;
@@ -87,37 +94,38 @@ __global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
   // 2. expansion at node q, flux, traces
   const int ls = tid / Nq, q = tid - ls * Nq;
   const bool active = ls < nloc + 2;
-  double F[S][N];
+  const R adv = (R)P.adv, gam = (R)P.gamma;
+  R F[S][N];
   if (active) {
-    double U[S][N];
+    R U[S][N];
     const double* C = sC + ls * ncoef;
 #pragma unroll
     for (int j = 0; j < n; ++j) {
 #pragma unroll
       for (int s = 0; s < S; ++s) {
-        double acc = 0.0;
-        for (int k = 0; k < M; ++k) acc += C[(s * M + k) * n + j] * P.tab.Phi[k * Nq + q];
+        R acc = R(0);
+        for (int k = 0; k < M; ++k) acc += (R)C[(s * M + k) * n + j] * (R)P.tab.Phi[k * Nq + q];
         U[s][j] = acc;
       }
     }
-    double tm[S], tp[S];
+    R tm[S], tp[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      double a = 0.0, b = 0.0;
+      R a = R(0), b = R(0);
 #pragma unroll
       for (int j = 0; j < n; ++j) {
-        a += P.tab.lL[j] * U[s][j];
-        b += P.tab.lR[j] * U[s][j];
+        a += (R)P.tab.lL[j] * U[s][j];
+        b += (R)P.tab.lR[j] * U[s][j];
       }
       tm[s] = a;
       tp[s] = b;
     }
 #pragma unroll
     for (int j = 0; j < n; ++j) {
-      double Uj[S], Fj[S];
+      R Uj[S], Fj[S];
 #pragma unroll
       for (int s = 0; s < S; ++s) Uj[s] = U[s][j];
-      flux<EQ, 0>(Uj, Fj, P.adv, P.gamma);
+      flux<EQ, 0>(Uj, Fj, adv, gam);
 #pragma unroll
       for (int s = 0; s < S; ++s) F[s][j] = Fj[s];
     }
@@ -136,40 +144,48 @@ __global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
     const double* Tl = sTr + ((long)(ls - 1) * Nq + q) * 2 * S;  // left neighbour
     const double* Tc = sTr + ((long)ls * Nq + q) * 2 * S;
     const double* Tr = sTr + ((long)(ls + 1) * Nq + q) * 2 * S;  // right neighbour
-    double UL[S], UR[S], FL[S], FR[S];
+    // traces in the arithmetic of the node loop (exact: LDS holds the values it wrote)
+    R TL[S], TC[S], TCp[S], TR[S], UL[S], UR[S], FL[S], FR[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      TL[s] = (R)Tl[S + s];
+      TC[s] = (R)Tc[s];
+      TCp[s] = (R)Tc[S + s];
+      TR[s] = (R)Tr[s];
+    }
     // left face: left state = neighbour's r = +1 trace, or the ghost of our r = -1 trace
     if (e == 0 && !periodic) {
-      ghost<EQ>(P, 0, Tc, UL);
+      ghost<EQ>(P, 0, TC, UL);
     } else {
 #pragma unroll
-      for (int s = 0; s < S; ++s) UL[s] = Tl[S + s];
+      for (int s = 0; s < S; ++s) UL[s] = TL[s];
     }
-    interface_flux<EQ, 0>(P.flux, UL, Tc, FL, P.adv, P.gamma);
+    interface_flux<EQ, 0>(P.flux, UL, TC, FL, adv, gam);
     // right face: right state = neighbour's r = -1 trace, or the ghost of our r = +1 trace
     if (e == E - 1 && !periodic) {
-      ghost<EQ>(P, 1, Tc + S, UR);
+      ghost<EQ>(P, 1, TCp, UR);
     } else {
 #pragma unroll
-      for (int s = 0; s < S; ++s) UR[s] = Tr[s];
+      for (int s = 0; s < S; ++s) UR[s] = TR[s];
     }
-    interface_flux<EQ, 0>(P.flux, Tc + S, UR, FR, P.adv, P.gamma);
-    const double iJ = 1.0 / P.Jx;
+    interface_flux<EQ, 0>(P.flux, TCp, UR, FR, adv, gam);
+    const R iJ = (R)(1.0 / P.Jx);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       // f^D at the faces enters through Dt; the interface fluxes through h'
-      double fdl = 0.0, fdr = 0.0;
+      R fdl = R(0), fdr = R(0);
 #pragma unroll
       for (int l = 0; l < n; ++l) {
-        fdl += P.tab.lL[l] * F[s][l];
-        fdr += P.tab.lR[l] * F[s][l];
+        fdl += (R)P.tab.lL[l] * F[s][l];
+        fdr += (R)P.tab.lR[l] * F[s][l];
       }
 #pragma unroll
       for (int j = 0; j < n; ++j) {
-        double acc = 0.0;
+        R acc = R(0);
 #pragma unroll
-        for (int l = 0; l < n; ++l) acc += P.tab.D[j * n + l] * F[s][l];
-        acc = acc + (FL[s] - fdl) * P.tab.dhL[j] + (FR[s] - fdr) * P.tab.dhR[j];
-        sR[(((long)(ls - 1) * S + s) * n + j) * Nq + q] = -acc * iJ;
+        for (int l = 0; l < n; ++l) acc += (R)P.tab.D[j * n + l] * F[s][l];
+        acc = acc + (FL[s] - fdl) * (R)P.tab.dhL[j] + (FR[s] - fdr) * (R)P.tab.dhR[j];
+        sR[(((long)(ls - 1) * S + s) * n + j) * Nq + q] = (double)(-acc * iJ);
       }
     }
   }
@@ -202,7 +218,13 @@ __global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
     const int s = sk / M, k = sk - s * M;
     const double* Rq = sR + (((long)le * S + s) * n + j) * Nq;
     double acc = 0.0;
-    for (int qq = 0; qq < Nq; ++qq) acc += P.tab.PW[k * Nq + qq] * Rq[qq];
+    if (std::is_same<R, double>::value || k == 0) {
+      for (int qq = 0; qq < Nq; ++qq) acc += P.tab.PW[k * Nq + qq] * Rq[qq];
+    } else {
+      R a = R(0);
+      for (int qq = 0; qq < Nq; ++qq) a += (R)P.tab.PW[k * Nq + qq] * (R)Rq[qq];
+      acc = (double)a;
+    }
     const long idx = (long)sk * EN + (long)(e0 + le) * n + j;
     const double v = A.rhs_only ? acc : A.cu * A.u[idx] + A.cw * (A.w[idx] + dt * acc);
     if (epi)
@@ -541,12 +563,22 @@ hipError_t launch_stage1d(const KParams& P, const double* in, const double* u, c
   const unsigned grid = (unsigned)((P.E + EB - 1) / EB);
   auto go = [&](auto eq_tag) -> hipError_t {
     constexpr int EQ = decltype(eq_tag)::value;
-    switch (P.np1) {
+    if (P.fp32) {
+      switch (P.np1) {
 #define FRSG_N(NN) \
-  case NN: hipLaunchKernelGGL((k_stage1d<EQ, NN>), dim3(grid), dim3(kBlock1), shmem, s, P, A); break;
-      FRSG_N(2) FRSG_N(3) FRSG_N(4) FRSG_N(5) FRSG_N(6) FRSG_N(7) FRSG_N(8)
+  case NN: hipLaunchKernelGGL((k_stage1d<EQ, NN, float>), dim3(grid), dim3(kBlock1), shmem, s, P, A); break;
+        FRSG_N(2) FRSG_N(3) FRSG_N(4) FRSG_N(5) FRSG_N(6) FRSG_N(7) FRSG_N(8)
 #undef FRSG_N
-      default: return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+      }
+    } else {
+      switch (P.np1) {
+#define FRSG_N(NN) \
+  case NN: hipLaunchKernelGGL((k_stage1d<EQ, NN, double>), dim3(grid), dim3(kBlock1), shmem, s, P, A); break;
+        FRSG_N(2) FRSG_N(3) FRSG_N(4) FRSG_N(5) FRSG_N(6) FRSG_N(7) FRSG_N(8)
+#undef FRSG_N
+        default: return hipErrorInvalidValue;
+      }
     }
     return hipGetLastError();
   };

@@ -125,10 +125,3 @@ def test_fp32_full_size_step():
     print("[fp32] full-size step rel L2 error %.3e" % err, flush=True)
     assert abs(to_np(dtd)[0] - rdt) <= FP32_DT_TOL * rdt
     assert err < FP32_STEP_TOL
-
-
-def test_fp32_rejected_off_the_fused_path():
-    from paper_2112_05946_amd.binding import FrsgError
-    with pytest.raises(FrsgError) as ei:
-        solver_for(inputs.small(inputs.BURGERS, 16), "fp32")
-    assert ei.value.status == -2
