@@ -35,7 +35,10 @@ FP32_VECTOR_TFLOPS = 157.3
 SV_FLOP_PER_DOF_LAUNCH = 199.0
 # symbol of the stage kernel for the shock-vortex sizes (15 modes, 25 nodes), per precision
 # the stage kernel's instances for the headline workload (Lax-Friedrichs flux)
-KERNEL_NAME = {"fp64": "k_stage2d<15, 25, double, 0>", "fp32": "k_stage2d<15, 25, float, 0>"}
+KERNEL_NAME = {"fp64": "k_stage2d<15, 25, double, 0>", "fp32": "k_stage2d<15, 25, float, 0>",
+               "bf16": "k_quad_stage<15, 25, 1, 0>"}
+# arithmetic the path computes in, per precision
+DTYPE = {"fp64": "f64", "fp32": "f32 node loop, f64 state", "bf16": "bf16 hi+lo transforms (f32 accumulation), f64 state"}
 
 
 def traffic_for(kernel, alg_bytes):
@@ -55,28 +58,101 @@ def traffic_for(kernel, alg_bytes):
         return None
 
 
-def cpu_baseline(cfg_full):
-    """Oracle timed on the host: one SSP-RK3 step of the same problem on a quarter-size mesh."""
-    import numpy as np  # noqa: F401
+CPU_SAMPLE_MESH = (128, 64)  # quarter of the shock-vortex mesh: one oracle step is a few seconds of one core
+
+
+def cpu_sample_child(nx, ny):
+    """Child process: one oracle SSP-RK3 step of the shock-vortex problem on an nx x ny
+    mesh; prints {"dof", "wall", "cpu"} as JSON.  Touches no GPU."""
     from oracle.initial import project_initial
     from oracle.problem import Problem
     from oracle.stepper import step
     from oracle.tables import build_tables
     from paper_2112_05946_amd import inputs
 
-    cfg = inputs.small(cfg_full, cfg_full["nx"] // 2, cfg_full.get("ny", 1) // 2 if cfg_full.get("ny") else None)
+    cfg = inputs.small(inputs.SHOCK_VORTEX, nx, ny)
     prob = Problem.from_config(cfg)
     T, R = build_tables(prob)
     u = project_initial(prob, cfg["ic"], (T, R))
     t0, c0 = time.perf_counter(), time.process_time()
     step(prob, u, None, (T, R))
     el, cpu = time.perf_counter() - t0, time.process_time() - c0
-    dof = prob.S * R.M * prob.E * prob.nsp
-    # threads actually used: process CPU time over wall time (NumPy's own threading)
-    cores = max(1, int(round(cpu / el)))
-    return {"value": dof / el, "unit": "DOF-updates/s", "cores": cores, "kind": "oracle",
-            "sample": "1 SSP-RK3 step of the same problem on a %dx%d mesh (%d DOF), %.1f s wall, %.1f s CPU" %
-                      (prob.nx, prob.ny, dof, el, cpu)}
+    print(json.dumps({"dof": prob.S * R.M * prob.E * prob.nsp, "wall": el, "cpu": cpu}), flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline():
+    """The oracle timed on the host, before anything touches the GPU: one SSP-RK3 step of the
+    shock-vortex problem on a 128 x 64 mesh in one process pinned to one thread, then the same
+    sample in P concurrent single-threaded processes (P = the cores this process may run on, at
+    most 16), whose aggregate DOF-updates/s is the all-cores figure."""
+    import subprocess
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
+        env[k] = "1"
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-sample-child", "%dx%d" % CPU_SAMPLE_MESH]
+
+    def run(nproc):
+        t0 = time.perf_counter()
+        procs = [subprocess.Popen(cmd, env=env, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+                 for _ in range(nproc)]
+        res = []
+        for pr in procs:
+            out, err = pr.communicate()
+            if pr.returncode != 0:
+                raise RuntimeError("oracle sample failed: " + err[-400:])
+            res.append(json.loads(out.strip().splitlines()[-1]))
+        return res, time.perf_counter() - t0
+
+    one, _ = run(1)
+    r1 = one[0]
+    try:
+        ncores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncores = os.cpu_count() or 1
+    P = max(1, min(16, ncores))
+    many, wall = run(P)
+    dof_all = sum(r["dof"] for r in many)
+    sample = "1 oracle SSP-RK3 step of the shock-vortex problem on a %dx%d mesh (%d DOF) per process" % (
+        CPU_SAMPLE_MESH + (r1["dof"],))
+    return {"value": dof_all / wall, "unit": "DOF-updates/s", "cores": P, "kind": "oracle",
+            "sample": sample + ", %d single-threaded processes at once, %.1f s wall, %.1f s CPU" % (
+                P, wall, sum(r["cpu"] for r in many)),
+            "cpu_model": cpu_model(), "host_cores_visible": ncores,
+            "single_core": {"value": r1["dof"] / r1["wall"], "unit": "DOF-updates/s", "cores": 1,
+                            "sample": sample + ", one process, %.1f s wall, %.1f s CPU" % (r1["wall"], r1["cpu"])}}
+
+
+def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
+    """Bandwidth of the library's streaming copy kernel (fr_sg_copy) on 1 GiB: 2 nbytes of HBM
+    traffic per copy, timed with events on the stream it is enqueued on."""
+    from paper_2112_05946_amd.binding import device_copy
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        device_copy(a, b)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        device_copy(a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ok = bool(torch.equal(a, b))
+    del a, b
+    gbs = 2 * nbytes / (ms / 1e3) / 1e9
+    return {"kernel": "k_copy (fr_sg_copy)", "bytes_per_copy": 2 * nbytes, "ms_per_copy": ms, "achieved": gbs,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "result_checked": ok}
 
 
 def timed_steps(torch, sol, u, steps, warmup):
@@ -214,21 +290,36 @@ def convergence_study():
     return out
 
 
-def precision_at_horizon(torch, Solver, cfg, rel, std):
-    """FP32-mixed against FP64 at the workload's end time: both run the same number of CFL
-    steps from the same initial state, as many as FP64 needs to reach t_end; relative L2
-    distance of the modal state, of E[u] (mode 0) and of Std[u].  For scale, the same
-    distances for FP64 started from the initial state perturbed by 1e-7 relative noise
-    (seeded): how far FP32-level perturbations carry on this problem in FP64."""
+def _rel(torch):
+    return lambda a, b: float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
+def _std(torch):
+    # Std[u] of the orthonormal chaos expansion: the root sum of squares of the modes k >= 1
+    return lambda x: torch.sqrt(torch.sum(x[:, 1:] ** 2, dim=1))
+
+
+def precision_at_horizon(torch, Solver, cfg, precs):
+    """Each reduced precision against FP64 at the workload's end time: every run takes the
+    same number of CFL steps from the same initial state, as many as FP64 needs to reach
+    t_end; relative L2 distance of the modal state, of E[u] (mode 0) and of Std[u].  For
+    scale, the same distances for FP64 started from the initial state perturbed by 1e-7
+    relative noise (seeded; then limited where the problem has the limiter): how far FP32-level
+    perturbations carry on this problem."""
+    rel, std = _rel(torch), _std(torch)
     states, times = {}, {}
     nsteps = None
-    for prec in ("fp64", "fp32", "fp64_perturbed"):
-        sol = Solver(cfg, precision="fp32" if prec == "fp32" else "fp64")
+    for prec in ("fp64",) + tuple(precs) + ("fp64_perturbed",):
+        sol = Solver(cfg, precision="fp64" if prec == "fp64_perturbed" else prec)
         u = sol.initial_state()
         if prec == "fp64_perturbed":
             gen = torch.Generator(device=u.device)
             gen.manual_seed(0)
             u.mul_(1.0 + 1e-7 * torch.randn(u.shape, generator=gen, device=u.device, dtype=u.dtype))
+            if cfg.get("limiter"):
+                # the projected data leaves some nodal pressures near zero (Gibbs points of the
+                # interface); the noise can push them below, so the start is limited first
+                sol.limit(u)
         dts = torch.empty(10, dtype=torch.float64, device=u.device)
         t, n = 0.0, 0
         while (nsteps is None and t < cfg["t_end"]) or (nsteps is not None and n < nsteps):
@@ -240,25 +331,74 @@ def precision_at_horizon(torch, Solver, cfg, rel, std):
         nsteps = n
         states[prec], times[prec] = u, t
         sol.close()
-    a, b, c = states["fp32"], states["fp64"], states["fp64_perturbed"]
-    return {"t_end": cfg["t_end"], "steps": nsteps, "t_fp64": times["fp64"], "t_fp32": times["fp32"],
-            "rel_l2_vs_fp64": rel(a, b), "rel_l2_mean_vs_fp64": rel(a[:, 0], b[:, 0]),
-            "rel_l2_std_vs_fp64": rel(std(a), std(b)),
-            "fp64_from_1e-7_perturbed_start": {"rel_l2": rel(c, b), "rel_l2_mean": rel(c[:, 0], b[:, 0]),
-                                               "rel_l2_std": rel(std(c), std(b))}}
+    b = states["fp64"]
+    out = {"t_end": cfg["t_end"], "steps": nsteps, "t_fp64": times["fp64"]}
+    for prec in tuple(precs) + ("fp64_perturbed",):
+        a = states[prec]
+        out[prec] = {"t": times[prec], "rel_l2_vs_fp64": rel(a, b), "rel_l2_mean_vs_fp64": rel(a[:, 0], b[:, 0]),
+                     "rel_l2_std_vs_fp64": rel(std(a), std(b))}
+    return out
+
+
+def reduced_precisions(torch, Solver, FrsgError, cfg, ms64, ref_state, steps, warmup, horizon=True,
+                       kernel_names=None):
+    """FP32-mixed and BF16-split on one workload: throughput, speed-up over FP64, the distance
+    of the state from FP64's after the same W + K steps, the dominant kernel's roofline, and
+    the distances at the end time.  A precision the workload's path does not provide is
+    reported as skipped with the library's reason."""
+    rel, std = _rel(torch), _std(torch)
+    out, ran = {}, []
+    for prec in ("fp32", "bf16"):
+        try:
+            sol = Solver(cfg, precision=prec)
+        except FrsgError as e:
+            out[prec] = {"skipped": str(e)}
+            continue
+        u = sol.initial_state()
+        ms, _ = timed_steps(torch, sol, u, steps, warmup)
+        passes = pass_times(sol, u.clone(), steps)
+        n_dof = int(sol.info["n_dof"])
+        rec = {"value": n_dof / (ms / 1e3), "ms_per_step": ms, "speedup_vs_fp64": ms64 / ms,
+               "rel_l2_vs_fp64": rel(u, ref_state), "rel_l2_mean_vs_fp64": rel(u[:, 0], ref_state[:, 0]),
+               "rel_l2_std_vs_fp64": rel(std(u), std(ref_state)), "steps_compared": warmup + steps,
+               "passes_ms_per_step": {k: v[1] / steps for k, v in passes.items()}}
+        if kernel_names and prec in kernel_names:
+            rec["roofline"] = roofline_for(passes, prec, kernel_names[prec])
+        else:
+            rec["roofline"] = roofline_for(passes, prec, "-")
+        out[prec] = rec
+        ran.append(prec)
+        sol.close()
+    if horizon and ran:
+        out["at_t_end"] = precision_at_horizon(torch, Solver, cfg, ran)
+    return out
+
+
+def precision_1d(torch, Solver, FrsgError, inputs, steps=200, warmup=10):
+    """The 1D workloads (Burgers, Sod) in FP64, FP32-mixed and BF16-split: ms per step and the
+    distances from FP64 at the end time.  They are cache resident, so their step time is
+    launch-bound and the reduced precisions are there for their accuracy, not their speed."""
+    out = {}
+    for name in ("burgers_sine", "sod_interface"):
+        cfg = inputs.CONFIGS[name]
+        sol = Solver(cfg)
+        u = sol.initial_state()
+        ms, _ = timed_steps(torch, sol, u, steps, warmup)
+        ref = u.clone()
+        sol.close()
+        rec = {"fp64_ms_per_step": ms, "dof": int(sol.info["n_dof"])}
+        rec.update(reduced_precisions(torch, Solver, FrsgError, cfg, ms, ref, steps, warmup))
+        out[name] = rec
+    return out
 
 
 def adjoint_cost(torch, Solver, inputs):
     """Adjoint/forward cost on the 4096-element Burgers problem (p = 3, 9 modes, 16 nodes):
-    500 steps at the CFL step of the initial state, held fixed."""
+    500 steps at the CFL step of the initial state, held fixed, in FP64 and FP32-mixed; the
+    FP32-mixed gradient's distance from the FP64 one."""
     from paper_2112_05946_amd.adjoint import AdjointSolve, mean_square
     cfg = inputs.BURGERS_ADJOINT
     n, k = int(cfg["n_steps"]), int(cfg["checkpoint_every"])
-    sol = Solver(cfg)
-    u0 = sol.initial_state()
-    u = u0.clone()
-    dtd, flags = sol.step(u)
-    dt = float(dtd.item())
     ev = lambda: torch.cuda.Event(enable_timing=True)
 
     def timed(fn):
@@ -270,37 +410,53 @@ def adjoint_cost(torch, Solver, inputs):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1)
 
-    dts = torch.empty(1, dtype=torch.float64, device=u.device)
-    fl = torch.empty(4 * sol.E, dtype=torch.uint8, device=u.device)
+    res, grads = {}, {}
+    for prec in ("fp64", "fp32"):
+        sol = Solver(cfg, precision=prec)
+        u0 = sol.initial_state()
+        u = u0.clone()
+        dtd, flags = sol.step(u)
+        dt = float(dtd.item())
+        dts = torch.empty(1, dtype=torch.float64, device=u.device)
+        fl = torch.empty(4 * sol.E, dtype=torch.uint8, device=u.device)
 
-    def fwd():
-        for _ in range(n):
-            sol.step(u, dt, dts, fl)
-    fwd()  # warm-up
-    u.copy_(u0)
-    t_fwd = timed(fwd) / n
-    lam = torch.randn_like(u0)
+        def fwd():
+            for _ in range(n):
+                sol.step(u, dt, dts, fl)
+        fwd()  # warm-up
+        u.copy_(u0)
+        t_fwd = timed(fwd) / n
+        lam = torch.randn_like(u0)
 
-    def adj():
-        for _ in range(n):
-            sol.adjoint_step(u0, flags, dt, lam)
-    adj()
-    t_adj = timed(adj) / n
-    params = torch.tensor([0.0, float(cfg["gamma"]) if "gamma" in cfg else 1.4], dtype=torch.float64)
+        def adj():
+            for _ in range(n):
+                sol.adjoint_step(u0, flags, dt, lam)
+        adj()
+        t_adj = timed(adj) / n
+        params = torch.tensor([0.0, 1.4], dtype=torch.float64)
+        box = {}
 
-    def grad():
-        x = u0.clone().requires_grad_(True)
-        J = mean_square(AdjointSolve.apply(x, params, sol, n, dt, k), sol)
-        J.backward()
-    grad()
-    t_grad = timed(grad) / n
-    sol.close()
-    dof = int(sol.info["n_dof"])
-    return {"workload": "burgers_adjoint %d elements, p=%d, %d modes, %d nodes, %d DOF, %d steps, checkpoint every %d"
-                        % (cfg["nx"], cfg["p"], sol.shape[1], sol.info["n_nodes"], dof, n, k),
-            "forward_ms_per_step": t_fwd, "adjoint_step_ms": t_adj, "adjoint_over_forward": t_adj / t_fwd,
-            "gradient_ms_per_step": t_grad, "gradient_over_forward": t_grad / t_fwd,
-            "note": "gradient = forward with checkpoints + backward (segment recompute + adjoint steps), per step"}
+        def grad():
+            x = u0.clone().requires_grad_(True)
+            J = mean_square(AdjointSolve.apply(x, params, sol, n, dt, k), sol)
+            J.backward()
+            box["g"] = x.grad
+        grad()
+        t_grad = timed(grad) / n
+        grads[prec] = box["g"]
+        dof = int(sol.info["n_dof"])
+        res[prec] = {"forward_ms_per_step": t_fwd, "adjoint_step_ms": t_adj, "adjoint_over_forward": t_adj / t_fwd,
+                     "gradient_ms_per_step": t_grad, "gradient_over_forward": t_grad / t_fwd}
+        shape = (sol.shape[1], sol.info["n_nodes"])
+        sol.close()
+    res["fp32"]["gradient_rel_l2_vs_fp64"] = _rel(torch)(grads["fp32"], grads["fp64"])
+    res["fp32"]["speedup_vs_fp64_gradient"] = res["fp64"]["gradient_ms_per_step"] / res["fp32"]["gradient_ms_per_step"]
+    out = {"workload": "burgers_adjoint %d elements, p=%d, %d modes, %d nodes, %d DOF, %d steps, checkpoint every %d"
+                       % (cfg["nx"], cfg["p"], shape[0], shape[1], dof, n, k),
+           "note": "gradient = forward with checkpoints + backward (segment recompute + adjoint steps), per step"}
+    out.update(res["fp64"])
+    out["fp32_mixed"] = res["fp32"]
+    return out
 
 
 def main():
@@ -309,21 +465,33 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", default="shock_vortex")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-mixed comparison run")
+    ap.add_argument("--no-precisions", action="store_true",
+                    help="skip the FP32-mixed and BF16-split runs (c4 and the 1D workloads)")
     ap.add_argument("--no-horizon", action="store_true",
-                    help="skip the FP32-mixed against FP64 comparison at the workload's end time")
+                    help="skip the reduced-precision against FP64 comparison at the workload's end time")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost run")
-    ap.add_argument("--no-others", action="store_true", help="skip the 1D workloads")
+    ap.add_argument("--no-others", action="store_true", help="skip the other workloads")
     ap.add_argument("--no-convergence", action="store_true", help="skip the wave-propagation convergence study")
+    ap.add_argument("--no-copy", action="store_true", help="skip the copy-kernel bandwidth reference")
     ap.add_argument("--profile-workload", default=None,
                     help="run only this one of the other workloads (for profiling) and print its record")
+    ap.add_argument("--cpu-sample-child", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_sample_child:
+        nx, ny = (int(v) for v in args.cpu_sample_child.split("x"))
+        cpu_sample_child(nx, ny)
+        return
     if args.gpus != 1:
         print("bench.py: the library runs on one GPU only (the multi-GPU halo exchange is not built); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    # the oracle's host timing runs in child processes before anything touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline and not args.profile_workload:
+        cpu = cpu_baseline()
 
     import torch
 
@@ -346,36 +514,15 @@ def main():
     passes = pass_times(sol, u, args.steps)
     roofline = roofline_for(passes, args.precision)
     roof_alu = alu_roofline(roofline, SV_FLOP_PER_DOF_LAUNCH, int(sol.info["n_dof"]), args.precision) \
-        if args.config == "shock_vortex" else None
+        if args.config == "shock_vortex" and args.precision != "bf16" else None
     sol.close()
 
-    # the other precision on the same workload: throughput and the L2 distance of
-    # its state from this run's after the same W + K steps
-    other = None
-    if args.precision == "fp64" and not args.no_fp32:
-        try:
-            sol32 = Solver(cfg, precision="fp32")
-        except FrsgError as e:  # FP32-mixed exists on the fused 2D Euler path only
-            sol32 = None
-            other = {"precision": "fp32_mixed", "skipped": str(e)}
-    if other is None and args.precision == "fp64" and not args.no_fp32:
-        u32 = sol32.initial_state()
-        ms32, _ = timed_steps(torch, sol32, u32, args.steps, args.warmup)
-        p32 = pass_times(sol32, u32.clone(), args.steps)
-        rel = lambda a, b: float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
-        err = rel(u32, snapshot)
-        # moments of the gPC expansion (orthonormal chaos): E[u] = mode 0, Std[u]^2 = sum of the others squared
-        std = lambda x: torch.sqrt(torch.sum(x[:, 1:] ** 2, dim=1))
-        other = {"precision": "fp32_mixed", "value": n_dof / (ms32 / 1e3), "ms_per_step": ms32,
-                 "speedup_vs_fp64": ms / ms32, "rel_l2_vs_fp64": err,
-                 "rel_l2_mean_vs_fp64": rel(u32[:, 0], snapshot[:, 0]),
-                 "rel_l2_std_vs_fp64": rel(std(u32), std(snapshot)), "steps_compared": args.warmup + args.steps,
-                 "roofline": roofline_for(p32, "fp32"),
-                 "passes_ms_per_step": {k: v[1] / args.steps for k, v in p32.items()}}
-        sol32.close()
-        if not args.no_horizon:
-            other["at_t_end"] = precision_at_horizon(torch, Solver, cfg, rel, std)
-
+    copy = None if args.no_copy else copy_bandwidth(torch)
+    reduced = None
+    if args.precision == "fp64" and not args.no_precisions:
+        reduced = reduced_precisions(torch, Solver, FrsgError, cfg, ms, snapshot, args.steps, args.warmup,
+                                     horizon=not args.no_horizon, kernel_names=KERNEL_NAME)
+    prec1d = None if args.no_precisions else precision_1d(torch, Solver, FrsgError, inputs)
     adjoint = None if args.no_adjoint else adjoint_cost(torch, Solver, inputs)
     others = None if args.no_others else other_workloads(torch, Solver, inputs, 200)
     convergence = None if args.no_convergence else convergence_study()
@@ -383,7 +530,7 @@ def main():
     out = {
         "metric": METRIC, "value": value, "unit": "DOF-updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32 node loop, f64 state", "data": "synthetic",
+        "vs_baseline": None, "dtype": DTYPE[args.precision], "data": "synthetic",
         "config": {"workload": "%s %dx%d elements, p=%d, %d gPC modes (rdim %d), %d random nodes, %d states, "
                                "%d DOF" % (args.config, cfg["nx"], cfg.get("ny", 1), cfg["p"], sol.shape[1],
                                            cfg.get("rdim", 1), sol.info["n_nodes"], sol.shape[0], n_dof),
@@ -391,14 +538,14 @@ def main():
         "roofline": roofline,
         "roofline_alu": roof_alu,
         "passes_ms_per_step": {k: v[1] / args.steps for k, v in passes.items()},
-        "fp32_mixed": other,
+        "copy_bandwidth": copy,
+        "reduced_precision": reduced,
+        "precision_1d": prec1d,
         "adjoint": adjoint,
         "other_workloads": others,
         "wave_propagation_convergence": convergence,
-        "cpu_baseline": None,
+        "cpu_baseline": cpu,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out), flush=True)
 
 

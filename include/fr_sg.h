@@ -351,9 +351,21 @@ fr_sg_status fr_sg_timing_read(fr_sg_ctx* ctx, fr_sg_pass_time* out, int32_t cap
  * accepted. */
 fr_sg_status fr_sg_destroy(fr_sg_ctx* ctx);
 
-/* Text of the last error on this context (or of the last failed fr_sg_init
- * when ctx is NULL).  Valid until the next call on the same context. */
+/* Text of the last error on this context (or of the last failed fr_sg_init,
+ * fr_sg_workspace_size or fr_sg_copy when ctx is NULL).  Valid until the next
+ * call on the same context. */
 const char* fr_sg_last_error(const fr_sg_ctx* ctx);
+
+/* Measurement utility, not part of the method: dst[i] = src[i] for i < n with
+ * the library's streaming copy kernel (16-byte vector loads and stores, a grid
+ * of 8 workgroups per compute unit striding over the array), enqueued on
+ * hip_stream (NULL: the default stream).  It is the bandwidth reference beside
+ * the HBM peak and the kernel of known traffic (8 n bytes read, 8 n bytes
+ * written) that calibrates the HBM byte counters of the stage kernels.
+ * src, dst: device arrays of n doubles, 16-byte aligned, not overlapping.
+ * Returns FRSG_EINVAL for a bad argument (before any device call) and
+ * FRSG_EDEVICE for a launch error; asynchronous otherwise. */
+fr_sg_status fr_sg_copy(const double* src, double* dst, int64_t n, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -88,6 +88,7 @@ SYMBOLS = [
                                            ctypes.POINTER(ctypes.c_int32)]),
     ("fr_sg_destroy", ctypes.c_int32, [_VP]),
     ("fr_sg_last_error", ctypes.c_char_p, [_VP]),
+    ("fr_sg_copy", ctypes.c_int32, [_VP, _VP, ctypes.c_int64, _VP]),
 ]
 
 _lib = None
@@ -163,6 +164,21 @@ def problem_from_config(cfg, precision="fp64"):
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def device_copy(src, dst, stream=None):
+    """dst <- src with the library's streaming copy kernel (fr_sg_copy): contiguous
+    float64 CUDA tensors of equal size, enqueued on `stream` (default: torch's current
+    stream).  A measurement utility: the bandwidth reference of the benchmark."""
+    import torch
+    if not (src.is_cuda and dst.is_cuda and src.dtype == torch.float64 and dst.dtype == torch.float64
+            and src.is_contiguous() and dst.is_contiguous() and src.numel() == dst.numel()):
+        raise ValueError("device_copy needs contiguous float64 CUDA tensors of equal size")
+    lib = load_library()
+    s = stream if stream is not None else torch.cuda.current_stream(src.device)
+    st = lib.fr_sg_copy(_ptr(src), _ptr(dst), src.numel(), ctypes.c_void_p(s.cuda_stream))
+    if st != 0:
+        raise FrsgError(st, lib.fr_sg_last_error(None).decode())
 
 
 class Solver:

@@ -1,9 +1,15 @@
-"""Plain device copy of a known size, used to calibrate the HBM byte counters
-(FETCH_SIZE / WRITE_SIZE) against which the stage kernels' traffic is scaled."""
+"""Device copy of a known size with the library's streaming copy kernel
+(fr_sg_copy): the run whose FETCH_SIZE / WRITE_SIZE readings calibrate the HBM
+byte counters against which the stage kernels' traffic is scaled."""
 
+import os
 import sys
 
-import torch
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+import torch  # noqa: E402
+
+from paper_2112_05946_amd.binding import device_copy  # noqa: E402
 
 NBYTES = 1 << 30  # 1 GiB read + 1 GiB written per copy
 
@@ -13,9 +19,10 @@ def main():
     a = torch.ones(NBYTES // 8, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
     for _ in range(3):
-        b.copy_(a)
+        device_copy(a, b)
     torch.cuda.synchronize()
-    print("copied %d bytes x 3" % NBYTES, flush=True)
+    assert torch.equal(a, b)
+    print("copied %d bytes x 3 with k_copy" % NBYTES, flush=True)
     return 0
 
 

@@ -59,6 +59,16 @@ __device__ __forceinline__ void flux(const R* U, R* F, R adv, R gamma) {
   }
 }
 
+// sound speed from gamma p / rho.  In FP32 node loops a pressure that the FP64
+// limiter kept at or above its small positive floor can round to a tiny
+// negative value (the rounding of the energy exceeds the floor); it counts as
+// zero there.  FP64 takes the square root as it is.
+template <typename R>
+__device__ __forceinline__ R sound_speed(R g_p_over_rho) {
+  if constexpr (sizeof(R) == sizeof(float)) return sqrtf(fmaxf(g_p_over_rho, 0.0f));
+  else return sqrt(g_p_over_rho);
+}
+
 // spectral radius of the flux Jacobian along DIR
 template <int EQ, int DIR, typename R>
 __device__ __forceinline__ R speed(const R* U, R adv, R gamma) {
@@ -68,7 +78,7 @@ __device__ __forceinline__ R speed(const R* U, R adv, R gamma) {
     return fabs(U[0]);
   } else {
     R p = pressure<EQ>(U, gamma);
-    R c = sqrt(gamma * p / U[0]);
+    R c = sound_speed(gamma * p / U[0]);
     return fabs(U[1 + DIR] / U[0]) + c;
   }
 }
@@ -93,8 +103,8 @@ __device__ __forceinline__ void hll(const R* L, const R* Rt, R* Fs, R gamma) {
   flux<EQ, DIR>(L, fL, R(0), gamma);
   flux<EQ, DIR>(Rt, fR, R(0), gamma);
   const R uL = L[1 + DIR] / L[0], uR = Rt[1 + DIR] / Rt[0];
-  const R cL = sqrt(gamma * pressure<EQ>(L, gamma) / L[0]);
-  const R cR = sqrt(gamma * pressure<EQ>(Rt, gamma) / Rt[0]);
+  const R cL = sound_speed(gamma * pressure<EQ>(L, gamma) / L[0]);
+  const R cR = sound_speed(gamma * pressure<EQ>(Rt, gamma) / Rt[0]);
   const R SL = fmin(uL - cL, uR - cR), SR = fmax(uL + cL, uR + cR);
 #pragma unroll
   for (int s = 0; s < S; ++s)

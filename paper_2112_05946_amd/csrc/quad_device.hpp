@@ -45,7 +45,9 @@ __device__ __forceinline__ float recip(float x) {
   return fmaf(r, fmaf(-x, r, 1.0f), r);
 }
 __device__ __forceinline__ double sqrt_t(double x) { return sqrt(x); }
-__device__ __forceinline__ float sqrt_t(float x) { return sqrtf(x); }
+// FP32: a pressure the FP64 limiter kept at its small positive floor can round
+// below zero in FP32 arithmetic; under a square root it counts as zero
+__device__ __forceinline__ float sqrt_t(float x) { return sqrtf(fmaxf(x, 0.0f)); }
 
 // value at point ((a + k) & 3, b)
 template <int K, typename T>

@@ -214,3 +214,14 @@ def test_chaos_limits(lib, over, status):
     P = binding.problem_from_config(dict(inputs.BURGERS, **over))
     st, ctx, msg = _init(lib, P)
     assert st == status and "too many" in msg
+
+
+def test_copy_arguments_checked_before_any_device_call(lib):
+    vp = ctypes.c_void_p
+    assert lib.fr_sg_copy(None, None, 0, None) == 0                              # nothing to copy
+    assert lib.fr_sg_copy(None, None, -1, None) == -1
+    assert lib.fr_sg_copy(None, vp(1 << 24), 5, None) == -1
+    assert lib.fr_sg_copy(vp((1 << 20) + 8), vp(1 << 24), 4, None) == -1         # misaligned
+    assert "aligned" in lib.fr_sg_last_error(None).decode()
+    assert lib.fr_sg_copy(vp(1 << 20), vp((1 << 20) + 16), 4, None) == -1        # overlapping
+    assert "overlap" in lib.fr_sg_last_error(None).decode()

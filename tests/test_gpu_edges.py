@@ -71,3 +71,18 @@ def test_all_zero_state_with_detector():
     dtd, flags = sol.step(u, 1e-3)
     sol.sync()
     assert not np.any(to_np(u)) and not to_np(flags).any()
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 1000003])
+def test_device_copy_kernel(n):
+    """The streaming copy kernel (the bandwidth reference of the benchmark) copies
+    every element, odd tails included, and nothing beyond."""
+    import torch
+    from paper_2112_05946_amd.binding import device_copy
+    announce("device_copy", n)
+    src = torch.randn(n, dtype=torch.float64, device="cuda")
+    dst = torch.full((n + 2,), 7.0, dtype=torch.float64, device="cuda")
+    device_copy(src, dst[:n])
+    torch.cuda.synchronize()
+    assert torch.equal(dst[:n], src)
+    assert torch.all(dst[n:] == 7.0)
