@@ -247,7 +247,7 @@ def other_workloads(torch, Solver, inputs, steps, names=None):
                inputs.tri_shock_vortex(64) if name == "tri_shock_vortex" else inputs.CONFIGS[name])
         sol = Solver(cfg)
         u = sol.initial_state()
-        dts = torch.empty(steps, dtype=torch.float64, device=u.device)
+        dts = torch.empty(max(steps, 10), dtype=torch.float64, device=u.device)
         sol.steps(u, 10, dts)
         sol.sync()
         torch.cuda.synchronize()

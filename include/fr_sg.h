@@ -357,8 +357,8 @@ fr_sg_status fr_sg_destroy(fr_sg_ctx* ctx);
 const char* fr_sg_last_error(const fr_sg_ctx* ctx);
 
 /* Measurement utility, not part of the method: dst[i] = src[i] for i < n with
- * the library's streaming copy kernel (16-byte vector loads and stores, a grid
- * of 8 workgroups per compute unit striding over the array), enqueued on
+ * the library's streaming copy kernel (16-byte vector loads and stores, one
+ * workgroup per contiguous 32 KiB block), enqueued on
  * hip_stream (NULL: the default stream).  It is the bandwidth reference beside
  * the HBM peak and the kernel of known traffic (8 n bytes read, 8 n bytes
  * written) that calibrates the HBM byte counters of the stage kernels.

@@ -316,6 +316,8 @@ static fr_sg_status prepare(const fr_sg_problem& problem, fr_sg_ctx* c, std::str
     K.tri = 1;
     K.nfp = c->tri.nfp;
   }
+  K.fp32 = P.precision == FRSG_FP32_MIXED ? 1 : 0;
+  K.bf16 = (P.precision == FRSG_BF16_SPLIT && c->dim == 1) ? 1 : 0;
   c->fused = !c->is_tri && fused2d_supported(K);
   // the matrix-core kernel takes the BF16-split steps of the 2D quadrilateral path (and the
   // FP64 ones where the VALU kernel does not apply)
@@ -328,10 +330,10 @@ static fr_sg_status prepare(const fr_sg_problem& problem, fr_sg_ctx* c, std::str
           "64 KiB) and the fused 2D Euler path (FR degree 3, nx % 4 == 0, ny % 2 == 0, a compiled (M, Nq) pair)";
     return FRSG_EUNSUPPORTED;
   }
-  K.fp32 = P.precision == FRSG_FP32_MIXED ? 1 : 0;
-  if (P.precision == FRSG_BF16_SPLIT && !c->quad) {
-    err = "FRSG_BF16_SPLIT runs on the matrix-core 2D Euler path only (FR degree 3, nx and ny even, "
-          "a compiled (M, Nq) pair)";
+  if (P.precision == FRSG_BF16_SPLIT && !c->quad && !(c->dim == 1 && c->fused1d)) {
+    err = "FRSG_BF16_SPLIT runs on the matrix-core paths: the 1D stage kernel (at most 16 gPC modes, FR degree "
+          "<= 7, Nq <= 85, one block's LDS within 64 KiB) and the 2D Euler quadrilateral kernel (FR degree 3, "
+          "nx and ny even, a compiled (M, Nq) pair)";
     return FRSG_EUNSUPPORTED;
   }
   // triangle operators and geometry: one double array and the neighbour table
@@ -1137,6 +1139,10 @@ fr_sg_status fr_sg_adjoint_step(fr_sg_ctx* ctx, const double* u_n, const uint8_t
   if (ctx->prob.filter != FRSG_FILTER_NONE && !flags_n) {
     ctx->err = "flags_n is needed: the filter decisions of the forward step";
     return FRSG_EINVAL;
+  }
+  if (ctx->prob.precision == FRSG_BF16_SPLIT) {
+    ctx->err = "the adjoint runs in FP64 and FP32-mixed precision";
+    return FRSG_EUNSUPPORTED;
   }
   if (ctx->kp.fp32 && !adj1d_fused_supported(ctx->kp)) {
     ctx->err = "the FP32-mixed adjoint runs on the fused adjoint kernel (FR degree <= 7, Nq <= 85, one block's "

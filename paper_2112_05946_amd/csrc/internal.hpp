@@ -140,6 +140,7 @@ struct KParams {
   int flux;  // FRSG_FLUX_*
   double alpha, sensor_thr;
   int fp32;  // 1: FP32-mixed node loops (1D stage and adjoint kernels)
+  int bf16;  // 1: BF16-split matrix-core transforms (1D stage kernel)
   DevTab tab;
   // triangles (element = FRSG_ELEM_TRI; tri = 0 on quadrilateral meshes)
   int tri, nfp;

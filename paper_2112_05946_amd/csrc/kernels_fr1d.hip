@@ -25,12 +25,22 @@
 // stage combination, the filter, the limiter and the CFL maximum stay in FP64.
 // Both sides of a face read the same trace from LDS, so the interface flux is
 // single-valued.
+//
+// BF16-split precision (XF = 1, R = float): the two random-space transforms are
+// dense contractions and run on the matrix cores.  The chaos expansion of step 2
+// is one product per 16 rows (element, variable, solution point) and 16 nodes,
+// [rows x modes] x [modes x nodes], and the projection of step 4 one product per
+// 16 rows, [rows x nodes] x [nodes x modes] accumulated over the blocks of 16
+// nodes; both with each operand split into bfloat16 high and low parts and FP32
+// accumulation.  The fluxes and residual are FP32 as above; the mean mode is
+// projected in FP64, and the epilogue is FP64.  M <= 16 (one block of modes).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
 
 #include "device_common.hpp"
 #include "internal.hpp"
+#include "mfma_bf16.hpp"
 
 namespace frsg {
 namespace {
@@ -62,7 +72,10 @@ struct Stage1DArgs {
   double* dt_used;
 };
 
-template <int EQ, int N, typename R>
+// padded sizes of the matrix-core operands: rows of 16, nodes in blocks of 16
+__host__ __device__ inline int pad16(int x) { return (x + 15) & ~15; }
+
+template <int EQ, int N, typename R, int XF>
 __global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
   constexpr int S = nstate<EQ>();
   constexpr int n = N;
@@ -75,8 +88,14 @@ __global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
   double* sC = smem;                           // [EB + 2][S][M][n]
   double* sTr = sC + (EB + 2) * ncoef;         // [EB + 2][Nq][2][S] traces at r = -1, +1
   double* sR = sTr + (EB + 2) * Nq * 2 * S;    // [EB][S][n][Nq] nodal residual
+  // matrix-core transforms: projected mean mode (FP64), nodal values, projected modes
+  const int NQP = pad16(Nq);
+  double* sP0 = sR + (long)EB * S * n * Nq;             // [EB S n]
+  float* sU = reinterpret_cast<float*>(sP0 + EB * S * n);  // [pad16((EB + 2) S n)][NQP]
+  float* sPk = sU + (long)pad16((EB + 2) * S * n) * NQP;  // [pad16(EB S n)][16]
   const bool periodic = P.bc[0] == FRSG_BC_PERIODIC;
   const int tid = threadIdx.x;
+  const int wave = tid >> 6, li = tid & 15, lc = (tid >> 4) & 3;
 
   // 1. stage coefficients: local slot ls = 0 .. nloc + 1 holds element e0 - 1 + ls
   // (variable, mode) outer, so consecutive threads read consecutive addresses
@@ -91,6 +110,34 @@ __global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
   }
   __syncthreads();
 
+  // 1b. matrix cores: nodal values of every (element slot, variable, point) row at
+  // every node, 16 rows x 16 nodes per product (whole waves, rows and nodes past
+  // the end padded with zeros)
+  if constexpr (XF) {
+    const int xrows = (nloc + 2) * S * n;
+    const int RT = (xrows + 15) >> 4, NT = NQP >> 4;
+    for (int t = wave; t < RT * NT; t += kBlock1 / 64) {
+      const int rt = t / NT, nt = t - rt * NT;
+      const int r = 16 * rt + li, qq = 16 * nt + li;
+      const int lsr = r / (S * n), rr = r - lsr * S * n, sr = rr / n, jr = rr - sr * n;
+      float a[4], b[4];
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        const int k = 4 * lc + it;
+        a[it] = (r < xrows && k < M) ? (float)sC[lsr * ncoef + (sr * M + k) * n + jr] : 0.0f;
+        b[it] = (k < M && qq < Nq) ? (float)P.tab.Phi[k * Nq + qq] : 0.0f;
+      }
+      v4s ah, al, bh, bl;
+      split4(a, ah, al);
+      split4(b, bh, bl);
+      const v4f z = {0.0f, 0.0f, 0.0f, 0.0f};
+      const v4f d = mfma_split(ah, al, bh, bl, z);
+#pragma unroll
+      for (int reg = 0; reg < 4; ++reg) sU[(long)(16 * rt + 4 * lc + reg) * NQP + qq] = d[reg];
+    }
+    __syncthreads();
+  }
+
   // 2. expansion at node q, flux, traces
   const int ls = tid / Nq, q = tid - ls * Nq;
   const bool active = ls < nloc + 2;
@@ -103,9 +150,13 @@ __global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
     for (int j = 0; j < n; ++j) {
 #pragma unroll
       for (int s = 0; s < S; ++s) {
-        R acc = R(0);
-        for (int k = 0; k < M; ++k) acc += (R)C[(s * M + k) * n + j] * (R)P.tab.Phi[k * Nq + q];
-        U[s][j] = acc;
+        if constexpr (XF) {
+          U[s][j] = (R)sU[(long)((ls * S + s) * n + j) * NQP + q];
+        } else {
+          R acc = R(0);
+          for (int k = 0; k < M; ++k) acc += (R)C[(s * M + k) * n + j] * (R)P.tab.Phi[k * Nq + q];
+          U[s][j] = acc;
+        }
       }
     }
     R tm[S], tp[S];
@@ -209,6 +260,38 @@ __global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
       if (A.lam_reset) *A.lam_reset = 0ull;
     }
   }
+  // matrix cores: projection of the nodal residual rows (owned element, variable,
+  // point) onto the modes, 16 rows x 16 modes per product accumulated over the node
+  // blocks; the mean mode in FP64 by one thread per row
+  if constexpr (XF) {
+    const int prows = nloc * S * n;
+    const int RT = (prows + 15) >> 4, KS = NQP >> 4;
+    for (int rt = wave; rt < RT; rt += kBlock1 / 64) {
+      const int r = 16 * rt + li;
+      v4f d = {0.0f, 0.0f, 0.0f, 0.0f};
+      for (int ks = 0; ks < KS; ++ks) {
+        float a[4], b[4];
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+          const int qq = 16 * ks + 4 * lc + it;
+          a[it] = (r < prows && qq < Nq) ? (float)sR[(long)r * Nq + qq] : 0.0f;
+          b[it] = (li < M && qq < Nq) ? (float)P.tab.PW[li * Nq + qq] : 0.0f;
+        }
+        v4s ah, al, bh, bl;
+        split4(a, ah, al);
+        split4(b, bh, bl);
+        d = mfma_split(ah, al, bh, bl, d);
+      }
+#pragma unroll
+      for (int reg = 0; reg < 4; ++reg) sPk[(long)(16 * rt + 4 * lc + reg) * 16 + li] = d[reg];
+    }
+    for (int r = tid; r < prows; r += kBlock1) {
+      double a0 = 0.0;
+      for (int qq = 0; qq < Nq; ++qq) a0 += P.tab.PW[qq] * sR[(long)r * Nq + qq];
+      sP0[r] = a0;
+    }
+    __syncthreads();
+  }
   const bool epi = A.limit || A.end_of_step;
   double* sO = sC;  // [EB][S][M][n] output coefficients
   const int ospan = nloc * n;
@@ -218,7 +301,10 @@ __global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
     const int s = sk / M, k = sk - s * M;
     const double* Rq = sR + (((long)le * S + s) * n + j) * Nq;
     double acc = 0.0;
-    if (std::is_same<R, double>::value || k == 0) {
+    if constexpr (XF) {
+      const int r = (le * S + s) * n + j;
+      acc = (k == 0) ? sP0[r] : (double)sPk[(long)r * 16 + k];
+    } else if (std::is_same<R, double>::value || k == 0) {
       for (int qq = 0; qq < Nq; ++qq) acc += P.tab.PW[k * Nq + qq] * Rq[qq];
     } else {
       R a = R(0);
@@ -534,6 +620,12 @@ static void fr1d_shape(const KParams& P, int& EB, size_t& shmem) {
   }
   const size_t ncoef = (size_t)P.S * P.M * P.np1;
   shmem = sizeof(double) * ((EB + 2) * ncoef + (size_t)(EB + 2) * P.Nq * 2 * P.S + (size_t)EB * P.S * P.np1 * P.Nq);
+  if (P.bf16) {  // matrix-core operands: one block of 16 modes
+    const int rows = P.S * P.np1;
+    shmem += sizeof(double) * (size_t)EB * rows +
+             sizeof(float) * ((size_t)pad16((EB + 2) * rows) * pad16(P.Nq) + (size_t)pad16(EB * rows) * 16);
+    if (P.M > 16) shmem = ~(size_t)0;
+  }
   if (shmem > 64 * 1024) {
     EB = 0;
     shmem = 0;
@@ -563,10 +655,18 @@ hipError_t launch_stage1d(const KParams& P, const double* in, const double* u, c
   const unsigned grid = (unsigned)((P.E + EB - 1) / EB);
   auto go = [&](auto eq_tag) -> hipError_t {
     constexpr int EQ = decltype(eq_tag)::value;
-    if (P.fp32) {
+    if (P.bf16) {
       switch (P.np1) {
 #define FRSG_N(NN) \
-  case NN: hipLaunchKernelGGL((k_stage1d<EQ, NN, float>), dim3(grid), dim3(kBlock1), shmem, s, P, A); break;
+  case NN: hipLaunchKernelGGL((k_stage1d<EQ, NN, float, 1>), dim3(grid), dim3(kBlock1), shmem, s, P, A); break;
+        FRSG_N(2) FRSG_N(3) FRSG_N(4) FRSG_N(5) FRSG_N(6) FRSG_N(7) FRSG_N(8)
+#undef FRSG_N
+        default: return hipErrorInvalidValue;
+      }
+    } else if (P.fp32) {
+      switch (P.np1) {
+#define FRSG_N(NN) \
+  case NN: hipLaunchKernelGGL((k_stage1d<EQ, NN, float, 0>), dim3(grid), dim3(kBlock1), shmem, s, P, A); break;
         FRSG_N(2) FRSG_N(3) FRSG_N(4) FRSG_N(5) FRSG_N(6) FRSG_N(7) FRSG_N(8)
 #undef FRSG_N
         default: return hipErrorInvalidValue;
@@ -574,7 +674,7 @@ hipError_t launch_stage1d(const KParams& P, const double* in, const double* u, c
     } else {
       switch (P.np1) {
 #define FRSG_N(NN) \
-  case NN: hipLaunchKernelGGL((k_stage1d<EQ, NN, double>), dim3(grid), dim3(kBlock1), shmem, s, P, A); break;
+  case NN: hipLaunchKernelGGL((k_stage1d<EQ, NN, double, 0>), dim3(grid), dim3(kBlock1), shmem, s, P, A); break;
         FRSG_N(2) FRSG_N(3) FRSG_N(4) FRSG_N(5) FRSG_N(6) FRSG_N(7) FRSG_N(8)
 #undef FRSG_N
         default: return hipErrorInvalidValue;

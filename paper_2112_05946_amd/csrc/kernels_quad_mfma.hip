@@ -40,6 +40,7 @@
 
 #include "device_common.hpp"
 #include "internal.hpp"
+#include "mfma_bf16.hpp"
 #include "quad_device.hpp"
 
 namespace frsg {
@@ -48,8 +49,6 @@ namespace {
 using namespace quad;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef short v4s __attribute__((ext_vector_type(4)));
 
 enum { kQF64 = 0, kQBF16 = 1 };
 
@@ -71,24 +70,6 @@ __host__ __device__ constexpr int qslots(int NQ, int nb) {
 
 __device__ __forceinline__ v4d mfma64(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ v4f mfma_bf(v4s a, v4s b, v4f c) {
-  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
-}
-
-// bfloat16 split x = hi + lo (round to nearest even, about 16 significant bits)
-__device__ __forceinline__ unsigned short bf16_rne(float x) {
-  unsigned u = __float_as_uint(x);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-__device__ __forceinline__ void split4(const float* x, v4s& hi, v4s& lo) {
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const unsigned short h = bf16_rne(x[i]);
-    hi[i] = (short)h;
-    lo[i] = (short)bf16_rne(x[i] - __uint_as_float((unsigned)h << 16));
-  }
 }
 __device__ __forceinline__ v4s as_v4s(double d) { return __builtin_bit_cast(v4s, d); }
 
@@ -181,10 +162,8 @@ __device__ __forceinline__ v4d expand64(const double* fA_nb, const double (&b)[4
 }
 // bfloat16-split expansion: the small cross terms first, the main product last
 __device__ __forceinline__ v4f expand_bf(v4s ah, v4s al, v4s bh, v4s bl) {
-  v4f d = {0.0f, 0.0f, 0.0f, 0.0f};
-  d = mfma_bf(al, bh, d);
-  d = mfma_bf(ah, bl, d);
-  return mfma_bf(ah, bh, d);
+  const v4f d = {0.0f, 0.0f, 0.0f, 0.0f};
+  return mfma_split(ah, al, bh, bl, d);
 }
 
 // ---------------------------------------------------------------------------

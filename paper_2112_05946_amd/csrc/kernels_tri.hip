@@ -268,13 +268,19 @@ struct TriShape {
   static constexpr int EPB = 256 / TPE;           // elements per block
 };
 
-// modal traces of every element at its flux points: Tm[s][k][e][fk] = sum_j Lf[fk][j] u[s][k][e][j]
+// modal traces of every element at its flux points, flux point by flux point:
+//   Tm[e][fk][s][k] = sum_j Lf[fk][j] u[s][k][e][j],
+// so that the 4 M values of one flux point, and the NFP points of one face, are
+// contiguous: a neighbour's face is one 32 NFP M-byte run (whole cache lines).
 template <int PD>
 __global__ void __launch_bounds__(256) k_trace_tri(KParams P, const double* __restrict__ u, double* __restrict__ Tm) {
   using Sh = TriShape<PD>;
-  const long n = 4l * P.M * P.E;
-  const long t = blockIdx.x * 256l + threadIdx.x;
+  const int M = P.M;
+  const long E = P.E;
+  const long n = 4l * M * E;
+  const long t = blockIdx.x * 256l + threadIdx.x;  // (s M + k) E + e
   if (t >= n) return;
+  const long e = t % E, sk = t / E;
   double v[Sh::NPT];
 #pragma unroll
   for (int j = 0; j < Sh::NPT; ++j) v[j] = u[t * Sh::NPT + j];
@@ -283,7 +289,7 @@ __global__ void __launch_bounds__(256) k_trace_tri(KParams P, const double* __re
     double acc = 0.0;
 #pragma unroll
     for (int j = 0; j < Sh::NPT; ++j) acc += P.tri_Lf[fk * Sh::NPT + j] * v[j];
-    Tm[t * Sh::NF + fk] = acc;
+    Tm[(e * Sh::NF + fk) * 4 * M + sk] = acc;
   }
 }
 
@@ -606,7 +612,7 @@ __global__ void __launch_bounds__(256) k_stage_tri(KParams P, const double* __re
 #pragma unroll
   for (int k = 0; k < M; ++k) {
     uc[k] = pt ? in[((long)s * M + k) * EN + (long)e * NPT + slot] : 0.0;
-    tn[k] = (fp && nb >= 0) ? Tm[(((long)s * M + k) * E + nb) * NF + g * NFP + (NFP - 1 - kk)] : 0.0;
+    tn[k] = (fp && nb >= 0) ? Tm[(((long)nb * NF + g * NFP + (NFP - 1 - kk)) * 4 + s) * M + k] : 0.0;
     acc[k] = 0.0;
   }
   __syncthreads();
@@ -682,11 +688,15 @@ __global__ void __launch_bounds__(256) k_stage_tri(KParams P, const double* __re
   }
   const double dt = rhs_only ? 0.0 : *P.dt;
   const bool do_post = post.filter || post.limit;
+  // the stages combine with w == in (uc holds it already) and read u only where cu != 0
+  const bool w_in = (w == in), need_u = (cu != 0.0);
   if (pt) {
 #pragma unroll
     for (int k = 0; k < M; ++k) {
       const long idx = ((long)s * M + k) * EN + (long)e * NPT + slot;
-      const double o = rhs_only ? acc[k] : cu * u[idx] + cw * (w[idx] + dt * acc[k]);
+      const double wv = w_in ? uc[k] : w[idx];
+      const double uv = need_u ? u[idx] : 0.0;
+      const double o = rhs_only ? acc[k] : cu * uv + cw * (wv + dt * acc[k]);
       acc[k] = o;
       sO[le][s][k][slot] = o;
       if (!do_post) out[idx] = o;
@@ -710,7 +720,7 @@ __global__ void __launch_bounds__(256) k_stage_tri(KParams P, const double* __re
       double t = 0.0;
 #pragma unroll
       for (int j = 0; j < NPT; ++j) t += sLf[slot * NPT + j] * sO[le][s][k][j];
-      Tm_out[(((long)s * M + k) * E + e) * NF + slot] = t;
+      Tm_out[(((long)e * NF + slot) * 4 + s) * M + k] = t;
     }
   }
 }

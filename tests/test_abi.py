@@ -66,7 +66,7 @@ def _size(lib, P):
     (lambda P: P.bc.__setitem__(0, 9), -1),
     (lambda P: setattr(P, "filter", 5), -1),
     (lambda P: setattr(P, "precision", 7), -1),
-    (lambda P: setattr(P, "precision", 2), -2),        # BF16-split not on this path
+    (lambda P: (setattr(P, "precision", 2), setattr(P, "gpc_order", 20), setattr(P, "nq1d", 21)), -2),  # 21 modes
     (lambda P: (setattr(P, "filter", 1), setattr(P, "nstar", 3.0)), -1),    # cutoff >= p
     (lambda P: (setattr(P, "filter", 1), setattr(P, "nstar", -0.5)), -1),
     (lambda P: (setattr(P, "filter", 1), setattr(P, "nstar", 2.5), setattr(P, "gpc_order", 2),
