@@ -112,14 +112,22 @@ typedef int32_t fr_sg_status;
 
 /* arithmetic of the right-hand side.  FRSG_FP64: everything in FP64.
  * FRSG_FP32_MIXED: the per-node work of the right-hand side (chaos expansion at
- * the node, fluxes, traces, interface fluxes, nodal residual and its Galerkin
- * projection) in FP32; state storage, the Runge-Kutta combination, detector,
- * filter, limiter and CFL reduction stay FP64.  Available where the fused 2D
- * Euler path applies (FR degree 3, nx divisible by 4, ny by 2); elsewhere
- * fr_sg_init returns FRSG_EUNSUPPORTED.
- * FRSG_BF16_SPLIT: reserved for the chaos transforms on bfloat16 matrix cores
- * with each operand split into a high and a low bfloat16 part; fr_sg_init
- * returns FRSG_EUNSUPPORTED where it is not built. */
+ * the node, fluxes, traces, interface fluxes, nodal residual and the Galerkin
+ * projection of the modes k >= 1) in FP32 on the FP64 coefficients and tables
+ * rounded to FP32; the projection of the mean mode k = 0, state storage, the
+ * Runge-Kutta combination, detector, filter, limiter and CFL reduction stay
+ * FP64.  Available on the fused 1D path (FR degree <= 7, Nq <= 85), the fused
+ * 2D Euler path (FR degree 3, nx divisible by 4, ny by 2, a compiled (M, Nq)
+ * pair) and for fr_sg_adjoint_step on the fused adjoint kernel.
+ * FRSG_BF16_SPLIT: the chaos expansion and the Galerkin projection on the
+ * bfloat16 matrix cores, each operand split into a high and a low bfloat16 part
+ * (x = hi + lo to 2^-16 relative) and the products hi*hi + hi*lo + lo*hi
+ * accumulated in FP32; fluxes and residual in FP32; the mean-mode projection
+ * and everything after the right-hand side as in FRSG_FP32_MIXED.  Available on
+ * the 1D stage kernel (at most 16 gPC modes) and the matrix-core 2D Euler
+ * kernel (FR degree 3, nx and ny even, a compiled (M, Nq) pair); not for
+ * fr_sg_adjoint_step.
+ * Elsewhere fr_sg_init returns FRSG_EUNSUPPORTED for the reduced precisions. */
 #define FRSG_FP64 0
 #define FRSG_FP32_MIXED 1
 #define FRSG_BF16_SPLIT 2
@@ -308,8 +316,11 @@ fr_sg_status fr_sg_steps(fr_sg_ctx* ctx, double* u, int32_t nsteps, double* dt_u
  * where u_{n+1} = fr_sg_step(u_n, dt) produced the filter flags flags_n.  The
  * stage states are recomputed from u_n with the forward passes.  The
  * Lax-Friedrichs dissipation speed is differentiated through the side that
- * attains the maximum.  Covers the scalar 1D equations (advection, Burgers);
- * other problems return FRSG_EUNSUPPORTED.
+ * attains the maximum.  Covers the scalar 1D equations (advection, Burgers) in
+ * FP64 and FP32-mixed (the transposed right-hand side's node and face work in
+ * FP32, its mean mode and the stage chain in FP64, the stage states recomputed
+ * by the FP32-mixed forward kernel); other problems and BF16-split return
+ * FRSG_EUNSUPPORTED.
  * u_n: device state at the start of the step (not modified).
  * flags_n: device uint8[4*E] of that step as written by fr_sg_step (row 2,
  *   the filter decisions, is used); may be NULL when the problem has no filter.
