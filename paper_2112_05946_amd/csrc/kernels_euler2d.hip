@@ -453,7 +453,9 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ PhiTd,
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int k = 0; k < M; ++k) m[i][k] = (R)bload(rin, voff, soff(i, k));
+      for (int k = 0; k < M; ++k)
+        // the FP32 loop reads its input again in the epilogue: keep it cacheable there
+        m[i][k] = (R)(kFP64 ? bload_stream(rin, voff, soff(i, k)) : bload(rin, voff, soff(i, k)));
   }
 
   // traces of the elements around the tile at every node: one thread per
@@ -761,9 +763,9 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ PhiTd,
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int k = 0; k < M; ++k) {
-        const double uu = bload(ru, voff, soff(i, k));  // 0 from an empty range when cu = 0
+        const double uu = bload_stream(ru, voff, soff(i, k));  // 0 from an empty range when cu = 0
         // the FP64 input: kept in registers by the FP64 loop, re-read otherwise
-        const double mi = kFP64 ? (double)m[i][k] : bload(rin2, voff, soff(i, k));
+        const double mi = kFP64 ? (double)m[i][k] : bload_stream(rin2, voff, soff(i, k));
         o[i][k] = A.cu * uu + A.cw * (mi + dt * res(i, k));
       }
   }
@@ -916,7 +918,7 @@ k_post2d(KParams P, const double* __restrict__ PhiTd, const double* __restrict__
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int k = 0; k < M; ++k) o[i][k] = bload(ru, voff, soff(i, k));
+    for (int k = 0; k < M; ++k) o[i][k] = bload_stream(ru, voff, soff(i, k));
   if (do_filter) {
     const int ff = sensor_filter_pair<M>(P, o, h, a, b, j, sLam);
     if (tid % 32 == 0 && flag_filt) flag_filt[e] = (unsigned char)ff;

