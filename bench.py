@@ -386,7 +386,8 @@ def precision_1d(torch, Solver, FrsgError, inputs, steps=200, warmup=10):
         ms, _ = timed_steps(torch, sol, u, steps, warmup)
         ref = u.clone()
         sol.close()
-        rec = {"fp64_ms_per_step": ms, "dof": int(sol.info["n_dof"])}
+        rec = {"fp64_ms_per_step": ms, "dof": int(sol.info["n_dof"]),
+               "fp64_dof_updates_per_s": int(sol.info["n_dof"]) / (ms / 1e3)}
         rec.update(reduced_precisions(torch, Solver, FrsgError, cfg, ms, ref, steps, warmup))
         out[name] = rec
     return out
@@ -518,6 +519,9 @@ def main():
     sol.close()
 
     copy = None if args.no_copy else copy_bandwidth(torch)
+    if copy:  # the same launches against the copy kernel's measured bandwidth
+        roofline["copy_GBs"] = copy["achieved"]
+        roofline["frac_of_copy"] = roofline["achieved"] / copy["achieved"]
     reduced = None
     if args.precision == "fp64" and not args.no_precisions:
         reduced = reduced_precisions(torch, Solver, FrsgError, cfg, ms, snapshot, args.steps, args.warmup,

@@ -90,7 +90,7 @@ fr_sg_status validate(const fr_sg_problem& P, std::string& err) {
       return FRSG_EUNSUPPORTED;
     }
     if (P.precision != FRSG_FP64) {
-      err = "FP32-mixed is not available on triangles";
+      err = "triangles run in FP64 only (no FP32-mixed or BF16-split)";
       return FRSG_EUNSUPPORTED;
     }
   } else {
