@@ -654,15 +654,20 @@ __global__ void __launch_bounds__(256) k_stage_tri(KParams P, const double* __re
     }
     __syncthreads();
     // B: own trace and interpolated normal flux at flux point `slot`; both traces
-    // of the four states by quad exchange; interactive flux; jump
-    double ul = 0.0, fr = 0.0, gs = 0.0;
+    // of the four states by quad exchange; interactive flux; jump.  The flux
+    // divergence at solution point `slot` reads the same contravariant fluxes, so
+    // it is formed here too (one LDS read of each flux value per node)
+    double ul = 0.0, fr = 0.0, gs = 0.0, d = 0.0;
     if (fp) {
+      const int drow = (slot < NPT ? slot : NPT - 1) * NPT;  // flux-only lanes: any row, d unused
 #pragma unroll
       for (int j = 0; j < NPT; ++j) {
         const double l = sLf[slot * NPT + j];
+        const double Frj = sFr[b][le][s][j], Gsj = sGs[b][le][s][j];
         ul += l * sU[b][le][s][j];
-        fr += l * sFr[b][le][s][j];
-        gs += l * sGs[b][le][s][j];
+        fr += l * Frj;
+        gs += l * Gsj;
+        d += sDr[drow + j] * Frj + sDs[drow + j] * Gsj;
       }
     }
     double L[4], R[4];
@@ -675,10 +680,7 @@ __global__ void __launch_bounds__(256) k_stage_tri(KParams P, const double* __re
     __syncthreads();
     // C: nodal residual of state s at point `slot`, projected onto the chaos
     if (pt) {
-      double d = 0.0, c = 0.0;
-#pragma unroll
-      for (int i = 0; i < NPT; ++i)
-        d += sDr[slot * NPT + i] * sFr[b][le][s][i] + sDs[slot * NPT + i] * sGs[b][le][s][i];
+      double c = 0.0;
 #pragma unroll
       for (int m = 0; m < NF; ++m) c += sLift[slot * NF + m] * sJ[le][s][m];
       const double Rq = -(d + c);
