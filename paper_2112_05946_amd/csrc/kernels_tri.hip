@@ -64,14 +64,14 @@ __device__ __forceinline__ double pick4(const double* a, int s) {
 // component s of the interactive flux along the normal, with one reciprocal of the
 // density per side (the fused kernel's lanes each produce one conserved variable)
 __device__ __forceinline__ double flux_n_comp(int kind, const double* L, const double* R, double nx, double ny,
-                                              double gamma, int s) {
+                                              double gamma, int s, double Ls, double Rs) {
   const double iL = rcp2(L[0]), iR = rcp2(R[0]);
   const double uL = (L[1] * nx + L[2] * ny) * iL, uR = (R[1] * nx + R[2] * ny) * iR;
   const double pL = (gamma - 1.0) * (L[3] - 0.5 * (L[1] * L[1] + L[2] * L[2]) * iL);
   const double pR = (gamma - 1.0) * (R[3] - 0.5 * (R[1] * R[1] + R[2] * R[2]) * iR);
   const double cL = sqrt(gamma * pL * iL), cR = sqrt(gamma * pR * iR);
   const double ns = s == 1 ? nx : (s == 2 ? ny : 0.0);
-  const double Ls = pick4(L, s), Rs = pick4(R, s);
+  // Ls = L[s] and Rs = R[s] are the lane's own values
   const double FL = (s == 3 ? Ls + pL : Ls) * uL + pL * ns;
   const double FR = (s == 3 ? Rs + pR : Rs) * uR + pR * ns;
   const double dU = Rs - Ls;
@@ -634,20 +634,13 @@ __global__ void __launch_bounds__(256) k_stage_tri(KParams P, const double* __re
       const double ir = rcp2(U[0]);
       const double vx = U[1] * ir, vy = U[2] * ir;
       const double p = (P.gamma - 1.0) * (U[3] - 0.5 * (U[1] * vx + U[2] * vy));
-      double Fs, Gs;
-      if (s == 0) {
-        Fs = U[1];
-        Gs = U[2];
-      } else if (s == 1) {
-        Fs = U[1] * vx + p;
-        Gs = U[1] * vy;
-      } else if (s == 2) {
-        Fs = U[2] * vx;
-        Gs = U[2] * vy + p;
-      } else {
-        Fs = (U[3] + p) * vx;
-        Gs = (U[3] + p) * vy;
-      }
+      // component s of F and G as A v + B without branching on s (the four variables
+      // of a point sit in neighbouring lanes): s = 0: F = m_x, G = m_y; s = 1: A = m_x,
+      // B = (p, 0); s = 2: A = m_y, B = (0, p); s = 3: A = E + p, B = 0
+      const double A = (s == 0) ? 0.0 : ((s == 3) ? v + p : v);
+      const double Bx = (s == 0) ? U[1] : ((s == 1) ? p : 0.0);
+      const double By = (s == 0) ? U[2] : ((s == 2) ? p : 0.0);
+      const double Fs = A * vx + Bx, Gs = A * vy + By;
       sU[b][le][s][slot] = v;
       sFr[b][le][s][slot] = rx * Fs + ry * Gs;
       sGs[b][le][s][slot] = sx * Fs + sy * Gs;
@@ -674,8 +667,12 @@ __global__ void __launch_bounds__(256) k_stage_tri(KParams P, const double* __re
     quad_gather(ul, L);
     quad_gather(vr, R);
     if (fp) {
-      if (nb < 0) ghost_n(P, -1 - nb, L, fnx, fny, R);
-      sJ[le][s][slot] = (flux_n_comp(P.flux, L, R, fnx, fny, P.gamma, s) - (fa * fr + fb * gs)) * fsc;
+      double Rs = vr;
+      if (nb < 0) {  // domain boundary: the ghost state
+        ghost_n(P, -1 - nb, L, fnx, fny, R);
+        Rs = pick4(R, s);
+      }
+      sJ[le][s][slot] = (flux_n_comp(P.flux, L, R, fnx, fny, P.gamma, s, ul, Rs) - (fa * fr + fb * gs)) * fsc;
     }
     __syncthreads();
     // C: nodal residual of state s at point `slot`, projected onto the chaos
