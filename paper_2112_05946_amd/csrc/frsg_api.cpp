@@ -528,6 +528,8 @@ fr_sg_status frsg::init_with_workspace(const fr_sg_problem* problem, void* hip_s
   tab.cmax = c->dcmax;
   c->dPhiT = b + off[16];
   c->dPWT = b + off[17];
+  tab.PhiT = c->dPhiT;
+  tab.PWT = c->dPWT;
   c->dfrag = b + off[18];
   if (c->fused) {
     c->dPhiT32 = (const float*)(ws + L.f32);

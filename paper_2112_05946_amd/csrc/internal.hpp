@@ -125,6 +125,8 @@ struct DevTab {
   const double* shell;
   const double* swts;
   const double* cmax;  // [M] max over the random nodes of |Phi_k|
+  const double* PhiT;  // [Nq][M] node-major copies of Phi and PW (one node's modes contiguous)
+  const double* PWT;
 };
 
 // Everything a kernel needs about the problem, passed by value.

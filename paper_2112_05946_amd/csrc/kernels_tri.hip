@@ -624,7 +624,7 @@ __global__ void __launch_bounds__(256) k_stage_tri(KParams P, const double* __re
     double v = 0.0, vr = 0.0;
 #pragma unroll
     for (int k = 0; k < M; ++k) {
-      const double ph = P.tab.Phi[k * NQ + q];
+      const double ph = P.tab.PhiT[q * M + k];  // node-major: wide scalar loads
       v += ph * uc[k];
       vr += ph * tn[k];
     }
@@ -682,7 +682,7 @@ __global__ void __launch_bounds__(256) k_stage_tri(KParams P, const double* __re
       for (int m = 0; m < NF; ++m) c += sLift[slot * NF + m] * sJ[le][s][m];
       const double Rq = -(d + c);
 #pragma unroll
-      for (int k = 0; k < M; ++k) acc[k] += P.tab.PW[k * NQ + q] * Rq;
+      for (int k = 0; k < M; ++k) acc[k] += P.tab.PWT[q * M + k] * Rq;
     }
   }
   const double dt = rhs_only ? 0.0 : *P.dt;
