@@ -479,7 +479,7 @@ __device__ __forceinline__ bool post_tri(const KParams& P, double (&c)[M],
       double vs = 0.0, vf = 0.0;
 #pragma unroll
       for (int k = 0; k < M; ++k) {
-        const double ph = P.tab.Phi[k * NQ + q];
+        const double ph = P.tab.PhiT[q * M + k];
         vs += ph * c[k];
         vf += ph * a[k];
       }
@@ -520,7 +520,7 @@ __device__ __forceinline__ bool post_tri(const KParams& P, double (&c)[M],
       double vs = 0.0, vf = 0.0;
 #pragma unroll
       for (int k = 0; k < M; ++k) {
-        const double ph = P.tab.Phi[k * NQ + q];
+        const double ph = P.tab.PhiT[q * M + k];
         vs += ph * c[k];
         vf += ph * a[k];
       }
@@ -778,7 +778,7 @@ __global__ void __launch_bounds__(256) k_cfl_tri_mq(KParams P, const double* __r
       for (int s = 0; s < 4; ++s) {
         double v = 0.0;
 #pragma unroll
-        for (int k = 0; k < M; ++k) v += P.tab.Phi[k * NQ + q] * c[s][k];
+        for (int k = 0; k < M; ++k) v += P.tab.PhiT[q * M + k] * c[s][k];
         U[s] = v;
       }
       const double p = euler2_p(U, P.gamma);
