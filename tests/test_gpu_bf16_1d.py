@@ -32,7 +32,9 @@ BF16_TIE = 1e-3
 BURGERS = inputs.small(inputs.BURGERS, 64)
 BURGERS_RAGGED = inputs.small(inputs.BURGERS, 37)
 SOD = inputs.small(inputs.SOD, 96)            # 11 modes, 24 nodes: two blocks of 16 nodes
+SOD_HLL = inputs.small(inputs.SOD_HLL, 50)
 ADVECTION = inputs.small(inputs.ADVECTION, 20)  # p = 2, 5 modes, 8 nodes
+BURGERS_LASSO = inputs.small(inputs.BURGERS_LASSO, 40)
 
 
 def _state(cfg, prob, T, R, seed):
@@ -57,7 +59,7 @@ def _flags_close(prob, T, R, gflags, rflags, record):
 
 
 @pytest.mark.parametrize("label,cfg", [("burgers", BURGERS), ("burgers_ragged", BURGERS_RAGGED), ("sod", SOD),
-                                       ("advection", ADVECTION)])
+                                       ("sod_hll", SOD_HLL), ("advection", ADVECTION)])
 @pytest.mark.parametrize("seed", [0, 1])
 def test_bf16_1d_rhs_error(label, cfg, seed):
     announce("bf16_1d_rhs", label, seed)
@@ -75,7 +77,8 @@ def test_bf16_1d_rhs_error(label, cfg, seed):
     assert err < BF16_RHS_TOL
 
 
-@pytest.mark.parametrize("label,cfg", [("burgers", BURGERS), ("sod", SOD)])
+@pytest.mark.parametrize("label,cfg", [("burgers", BURGERS), ("sod", SOD), ("sod_hll", SOD_HLL),
+                                       ("burgers_lasso", BURGERS_LASSO)])
 def test_bf16_1d_steps_error(label, cfg):
     """Four CFL steps against the oracle's FP64 steps, with the detector, the filter
     and (Sod) the limiter in the FP64 epilogue."""

@@ -98,7 +98,8 @@ def test_fp32_1d_rhs_error(label, cfg, seed):
     assert err < FP32_RHS_TOL
 
 
-@pytest.mark.parametrize("label,cfg", [("burgers", BURGERS), ("sod", SOD), ("sod_hll", SOD_HLL)])
+@pytest.mark.parametrize("label,cfg", [("burgers", BURGERS), ("sod", SOD), ("sod_hll", SOD_HLL),
+                                       ("sod_lasso", inputs.small(inputs.SOD_LASSO, 40))])
 def test_fp32_1d_steps_error(label, cfg):
     """Four CFL steps of the fused 1D kernel in FP32-mixed against the oracle's FP64
     steps, with the detector, the filter and (Sod) the limiter in the epilogue."""
