@@ -57,6 +57,76 @@ def build(verbose=False):
     return LIB
 
 
+# Host code checked by AddressSanitizer and UndefinedBehaviorSanitizer: the host
+# sources (problem validation, operator tables, meshes, workspace layout) are
+# compiled with both, the device sources are the objects of the normal build
+# (the flags reach the host pass only), and the result is a separate library
+# that a process loads after preloading the sanitizer runtime.
+SAN_LIB = os.path.join(BUILD, "libfrsg_san.so")
+SAN_LINK = "-Xarch_host -fsanitize=address -Xarch_host -fsanitize=undefined".split()
+SAN_FLAGS = "-O1 -g -fno-omit-frame-pointer -Xarch_host -fno-sanitize-recover=undefined".split() + SAN_LINK
+
+
+def sanitizer_runtime():
+    """Path of the clang AddressSanitizer runtime that hipcc's host compiler links against."""
+    r = subprocess.run([HIPCC, "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = (r.stdout or "").strip()
+    if r.returncode == 0 and os.path.isabs(path) and os.path.exists(path):
+        return path
+    root = "/opt/rocm/llvm/lib/clang"
+    for ver in sorted(os.listdir(root)) if os.path.isdir(root) else []:
+        cand = os.path.join(root, ver, "lib", "linux", "libclang_rt.asan-x86_64.so")
+        if os.path.exists(cand):
+            return cand
+    return None
+
+
+def _fresh(obj, src):
+    """True when obj is newer than src and every header the sources include."""
+    if not os.path.exists(obj):
+        return False
+    t = os.path.getmtime(obj)
+    deps = [src] + [os.path.join(d, f) for d in (CSRC, INCLUDE) for f in os.listdir(d) if f.endswith((".h", ".hpp"))]
+    return all(os.path.getmtime(d) < t for d in deps)
+
+
+def build_sanitized(verbose=False, reuse_device_objects=False):
+    """Build libfrsg_san.so: sanitized host sources linked with the normal device objects
+    (reused from the normal build when they are newer than their sources and headers)."""
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = sources()
+    dev = [s for s in srcs if s.endswith(".hip")]
+    host = [s for s in srcs if s.endswith(".cpp")]
+
+    def compile_host(src):
+        obj = os.path.join(BUILD, os.path.basename(src) + ".san.o")
+        cmd = [HIPCC] + [f for f in COMMON if f != "-O3"] + SAN_FLAGS + ["-c", src, "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("compile failed: %s\n%s" % (" ".join(cmd), r.stderr))
+        return obj
+
+    def compile_dev(src):
+        obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+        return obj if reuse_device_objects and _fresh(obj, src) else _compile(src)
+
+    with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+        dev_objs = list(ex.map(compile_dev, dev))
+        host_objs = list(ex.map(compile_host, host))
+    tmp = SAN_LIB + ".tmp"
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH] + SAN_LINK + ["-o", tmp] + dev_objs + host_objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed: %s\n%s" % (" ".join(cmd), r.stderr))
+    os.replace(tmp, SAN_LIB)
+    if verbose:
+        print("built", SAN_LIB)
+    return SAN_LIB
+
+
 if __name__ == "__main__":
-    build(verbose=True)
+    if len(sys.argv) > 1 and sys.argv[1] == "sanitized":
+        build_sanitized(verbose=True)
+    else:
+        build(verbose=True)
     sys.exit(0)
