@@ -577,6 +577,12 @@ fr_sg_status frsg::init_with_workspace(const fr_sg_problem* problem, void* hip_s
   K.dt = W.scal;
   K.lam_bits = (unsigned long long*)(W.scal + 1);
   K.status = (unsigned*)(W.scal + 2);  // scal[3] is the second CFL accumulator
+  // small 1D problems run the steps of an fr_sg_steps call in one launch of one
+  // workgroup, where the kernel instance needs no register spills
+  c->resident1d = c->fused1d && c->prob.integrator == FRSG_SSPRK3 &&
+                  launch_steps1d_resident(K, nullptr, nullptr, nullptr, 0, 0, nullptr, nullptr, nullptr, nullptr,
+                                          c->stream) == hipSuccess;
+  (void)hipGetLastError();  // a failed attribute query leaves nothing for a later launch check
   *out = c;
   return FRSG_OK;
 }
@@ -863,6 +869,29 @@ static fr_sg_status step_fused1d(fr_sg_ctx* ctx, double* u, double dt, double* d
   return FRSG_OK;
 }
 
+// the steps of an fr_sg_steps call on a small 1D problem: the CFL pass of u, then
+// every step in one launch of one workgroup (the fused 1D stage code, three
+// stages per step separated by workgroup barriers); the CFL maximum of the result
+// is left where the next call's first step finds it
+static fr_sg_status steps_resident1d(fr_sg_ctx* ctx, double* u, int nsteps, double* dt_used, uint8_t* flags) {
+  const KParams& K = ctx->kp;
+  Workspace& W = ctx->ws;
+  hipStream_t s = ctx->stream;
+  unsigned long long* lam[2] = {(unsigned long long*)(W.scal + 1), (unsigned long long*)(W.scal + 3)};
+  const int cur = ctx->lam_cur;
+  const double sb = state_bytes(ctx);
+  fr_sg_status st;
+  if ((st = timed(ctx, "cfl", sb, [&] { return launch_cfl1d(K, u, lam[cur], s); }))) return st;
+  const char* name = fr1d_resident_lds_state(K) ? "steps_resident_lds" : "steps_resident";
+  if ((st = timed(ctx, name, 8 * sb * nsteps, [&] {
+         return launch_steps1d_resident(K, u, W.w1, W.w2, nsteps, ctx->prob.limiter ? 1 : 0, flags, dt_used,
+                                        lam[cur], lam[cur ^ 1], s);
+       })))
+    return st;
+  ctx->lam_cur = cur ^ 1;
+  return FRSG_OK;
+}
+
 // fused 2D Euler step: one kernel per stage.  chained: u is the state the
 // previous step of the same call produced, so the CFL maximum of u comes from
 // the accumulator its end-of-step pass filled and the face traces of u from the
@@ -1096,6 +1125,7 @@ fr_sg_status fr_sg_steps(fr_sg_ctx* ctx, double* u, int32_t nsteps, double* dt_u
     ctx->err = "nsteps must be >= 0";
     return FRSG_EINVAL;
   }
+  if (ctx->resident1d && nsteps > 0) return steps_resident1d(ctx, u, nsteps, dt_used, flags);
   const long fl = 4l * ctx->E;
   for (int i = 0; i < nsteps; ++i) {
     double* dtu = dt_used ? dt_used + i : nullptr;

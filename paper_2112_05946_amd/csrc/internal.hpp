@@ -237,6 +237,7 @@ struct fr_sg_ctx {
   bool quad = false;             // matrix-core 2D Euler stage kernel (FP64, BF16-split)
   const double* dfrag = nullptr; // its operand tables
   bool fused1d = false;          // fused 1D stage kernel
+  bool resident1d = false;       // SSP-RK3 steps of a small 1D problem in one one-workgroup launch
   int lam_cur = 0;              // which CFL accumulator holds the maximum of the current state
   const double* lam_for = nullptr;  // state whose maximum the previous step recorded (fr_sg_steps)
   int tr_cur = 0;               // fused 2D: which face-trace buffer holds the traces of the current state
@@ -383,6 +384,17 @@ hipError_t launch_stage1d(const KParams& P, const double* in, const double* u, c
                           const unsigned long long* lam_in = nullptr, unsigned long long* lam_reset = nullptr,
                           double* dt_used = nullptr);
 hipError_t launch_cfl1d(const KParams& P, const double* u, unsigned long long* lam, hipStream_t s);
+// nsteps SSP-RK3 steps (CFL time steps, limiter on every stage output when limit,
+// end-of-step filter and CFL maximum) of an FP64 1D problem whose elements fit one
+// workgroup, in one launch; lam_in holds the CFL maximum of u, lam_out receives
+// that of the result.  flags [nsteps][4][E] and dt_used [nsteps] may be null.
+// With u == nullptr: hipSuccess when the problem fits and the instance runs
+// without register spills, launching nothing.
+bool fr1d_resident_fits(const KParams& P);
+bool fr1d_resident_lds_state(const KParams& P);  // the three states stay in LDS for the whole call
+hipError_t launch_steps1d_resident(const KParams& P, double* u, double* w1, double* w2, int nsteps, int limit,
+                                   unsigned char* flags, double* dt_used, const unsigned long long* lam_in,
+                                   unsigned long long* lam_out, hipStream_t s);
 
 // adjoint launchers (kernels_adjoint.hip)
 long adjoint_partials(const KParams& P);

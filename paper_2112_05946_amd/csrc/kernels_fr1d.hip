@@ -61,10 +61,12 @@ struct Stage1DArgs {
   int end_of_step;             // detector-switched filter before the limiter, CFL maximum after
   unsigned char* flag_lim;     // per element: limiter acted (may be null)
   unsigned char* flag_filt;    // per element: filter acted (may be null)
-  unsigned long long* lam_next;  // CFL accumulator of the output (end of step; may be null)
+  int cfl_out;                   // end of step: take the CFL maximum of the output
+  unsigned long long* lam_next;  // accumulator the maximum is merged into (may be null)
   // time step: dt_source 0 reads *P.dt; 1 takes dt_fixed; 2 computes it from the
   // CFL accumulator lam_in.  With 1 or 2, workgroup 0 also stores it in *P.dt and
-  // dt_used, zeroes lam_reset and latches a non-finite or non-positive dt.
+  // dt_used, zeroes lam_reset and latches a non-finite or non-positive dt.  3 takes
+  // dt_fixed and leaves all of that to the caller.
   int dt_source;
   double dt_fixed;
   const unsigned long long* lam_in;
@@ -75,13 +77,20 @@ struct Stage1DArgs {
 // padded sizes of the matrix-core operands: rows of 16, nodes in blocks of 16
 __host__ __device__ inline int pad16(int x) { return (x + 15) & ~15; }
 
-template <int EQ, int N, typename R, int XF>
-__global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
+// One stage over the elements of workgroup blk, run by BS threads.  Returns the
+// CFL maximum of the workgroup's output (every thread) when it is asked for
+// (end of step and cfl_out), else 0.
+template <int EQ, int N, typename R, int XF, int BS>
+__device__ __forceinline__ double stage1d_block(const KParams& P, const Stage1DArgs& A, int blk) {
+  // products fuse with the sum of the same expression only, so every kernel that
+  // runs this code (one launch per stage, or several steps in one launch) rounds
+  // alike whatever it knows of the arguments at compile time
+#pragma clang fp contract(on)
   constexpr int S = nstate<EQ>();
   constexpr int n = N;
   extern __shared__ double smem[];
   const int E = P.E, M = P.M, Nq = P.Nq, EB = A.EB;
-  const int e0 = blockIdx.x * EB;
+  const int e0 = blk * EB;
   const int nloc = min(EB, E - e0);           // elements owned by this workgroup
   const int ncoef = S * M * n;                 // coefficients per element
   const long EN = (long)E * n;
@@ -100,7 +109,7 @@ __global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
   // 1. stage coefficients: local slot ls = 0 .. nloc + 1 holds element e0 - 1 + ls
   // (variable, mode) outer, so consecutive threads read consecutive addresses
   const int span = (nloc + 2) * n;
-  for (int it = tid; it < S * M * span; it += kBlock1) {
+  for (int it = tid; it < S * M * span; it += BS) {
     const int sk = it / span, rem = it - sk * span;  // sk = s * M + k
     const int ls = rem / n, j = rem - ls * n;
     int e = e0 - 1 + ls;
@@ -116,7 +125,7 @@ __global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
   if constexpr (XF) {
     const int xrows = (nloc + 2) * S * n;
     const int RT = (xrows + 15) >> 4, NT = NQP >> 4;
-    for (int t = wave; t < RT * NT; t += kBlock1 / 64) {
+    for (int t = wave; t < RT * NT; t += BS / 64) {
       const int rt = t / NT, nt = t - rt * NT;
       const int r = 16 * rt + li, qq = 16 * nt + li;
       const int lsr = r / (S * n), rr = r - lsr * S * n, sr = rr / n, jr = rr - sr * n;
@@ -146,17 +155,24 @@ __global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
   if (active) {
     R U[S][N];
     const double* C = sC + ls * ncoef;
+    if constexpr (XF) {
 #pragma unroll
-    for (int j = 0; j < n; ++j) {
+      for (int j = 0; j < n; ++j)
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        if constexpr (XF) {
-          U[s][j] = (R)sU[(long)((ls * S + s) * n + j) * NQP + q];
-        } else {
-          R acc = R(0);
-          for (int k = 0; k < M; ++k) acc += (R)C[(s * M + k) * n + j] * (R)P.tab.Phi[k * Nq + q];
-          U[s][j] = acc;
-        }
+        for (int s = 0; s < S; ++s) U[s][j] = (R)sU[(long)((ls * S + s) * n + j) * NQP + q];
+    } else {
+      // mode by mode into every (variable, point) sum: each sum takes its terms in
+      // mode order, and the S n chains are independent
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int j = 0; j < n; ++j) U[s][j] = R(0);
+      for (int k = 0; k < M; ++k) {
+        const R phi = (R)P.tab.Phi[k * Nq + q];
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+          for (int j = 0; j < n; ++j) U[s][j] += (R)C[(s * M + k) * n + j] * phi;
       }
     }
     R tm[S], tp[S];
@@ -249,11 +265,13 @@ __global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
     dt = 0.0;
   } else if (A.dt_source == 0) {
     dt = *P.dt;
+  } else if (A.dt_source == 3) {
+    dt = A.dt_fixed;  // checked and published by the caller
   } else {
     // dt = CFL dx / ((p+1) lambda_max) from the accumulated wave-speed maximum
     dt = A.dt_source == 1 ? A.dt_fixed
                           : P.cfl * P.dx / (P.np1 * __longlong_as_double((long long)*A.lam_in));
-    if (blockIdx.x == 0 && tid == 0) {
+    if (blk == 0 && tid == 0) {
       if (!(dt > 0.0) || !isfinite(dt)) atomicOr(P.status, kStatusNonFinite);
       *P.dt = dt;
       if (A.dt_used) *A.dt_used = dt;
@@ -266,7 +284,7 @@ __global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
   if constexpr (XF) {
     const int prows = nloc * S * n;
     const int RT = (prows + 15) >> 4, KS = NQP >> 4;
-    for (int rt = wave; rt < RT; rt += kBlock1 / 64) {
+    for (int rt = wave; rt < RT; rt += BS / 64) {
       const int r = 16 * rt + li;
       v4f d = {0.0f, 0.0f, 0.0f, 0.0f};
       for (int ks = 0; ks < KS; ++ks) {
@@ -285,7 +303,7 @@ __global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
 #pragma unroll
       for (int reg = 0; reg < 4; ++reg) sPk[(long)(16 * rt + 4 * lc + reg) * 16 + li] = d[reg];
     }
-    for (int r = tid; r < prows; r += kBlock1) {
+    for (int r = tid; r < prows; r += BS) {
       double a0 = 0.0;
       for (int qq = 0; qq < Nq; ++qq) a0 += P.tab.PW[qq] * sR[(long)r * Nq + qq];
       sP0[r] = a0;
@@ -295,7 +313,7 @@ __global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
   const bool epi = A.limit || A.end_of_step;
   double* sO = sC;  // [EB][S][M][n] output coefficients
   const int ospan = nloc * n;
-  for (int it = tid; it < S * M * ospan; it += kBlock1) {
+  for (int it = tid; it < S * M * ospan; it += BS) {
     const int sk = it / ospan, rem = it - sk * ospan;
     const int le = rem / n, j = rem - le * n;
     const int s = sk / M, k = sk - s * M;
@@ -319,8 +337,8 @@ __global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
       A.out[idx] = v;
   }
   if (A.clear_flags)
-    for (int it = tid; it < nloc; it += kBlock1) A.clear_flags[e0 + it] = 0;
-  if (!epi) return;
+    for (int it = tid; it < nloc; it += BS) A.clear_flags[e0 + it] = 0;
+  if (!epi) return 0.0;
   __syncthreads();
 
   // 5. element epilogue: thread (owned element le, node q); per-(element, node)
@@ -443,13 +461,18 @@ __global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
       };
       if (own) {
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
+        for (int s = 0; s < S; ++s)
 #pragma unroll
-          for (int j = 0; j < n; ++j) {
-            double acc = 0.0;
-            for (int k = 0; k < M; ++k) acc += O[(s * M + k) * n + j] * P.tab.Phi[k * Nq + q];
-            Usp[s][j] = acc;
-          }
+          for (int j = 0; j < n; ++j) Usp[s][j] = 0.0;
+        for (int k = 0; k < M; ++k) {
+          const double phi = P.tab.Phi[k * Nq + q];
+#pragma unroll
+          for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int j = 0; j < n; ++j) Usp[s][j] += O[(s * M + k) * n + j] * phi;
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
           double a = 0.0, b = 0.0;
 #pragma unroll
           for (int j = 0; j < n; ++j) {
@@ -528,39 +551,56 @@ __global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
   }
 
   // 5c. CFL maximum of the output for the next step
-  if (A.end_of_step && A.lam_next) {
-    __shared__ double sm[kBlock1];
+  double lam_out = 0.0;
+  if (A.end_of_step && A.cfl_out) {
+    __shared__ double sm[BS / 64];
     double rate = 0.0;
     if (own) {
+      double Uq[S][N];
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int j = 0; j < n; ++j) Uq[s][j] = 0.0;
+      for (int k = 0; k < M; ++k) {
+        const double phi = P.tab.Phi[k * Nq + q];
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+          for (int j = 0; j < n; ++j) Uq[s][j] += O[(s * M + k) * n + j] * phi;
+      }
+#pragma unroll
       for (int j = 0; j < n; ++j) {
         double U[S];
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-          double acc = 0.0;
-          for (int k = 0; k < M; ++k) acc += O[(s * M + k) * n + j] * P.tab.Phi[k * Nq + q];
-          U[s] = acc;
-        }
+        for (int s = 0; s < S; ++s) U[s] = Uq[s][j];
         double r = speed<EQ, 0>(U, P.adv, P.gamma);
         if (!(r == r)) r = __longlong_as_double(0x7ff0000000000000ll);  // NaN -> +inf, dt -> 0
         rate = fmax(rate, r);
       }
     }
-    sm[tid] = rate;
+    // the maximum over the wave, then over the waves (exact in any order: no NaN)
+    for (int o = 32; o > 0; o >>= 1) rate = fmax(rate, __shfl_xor(rate, o));
+    if ((tid & 63) == 0) sm[tid >> 6] = rate;
     __syncthreads();
-    for (int o = kBlock1 / 2; o > 0; o >>= 1) {
-      if (tid < o) sm[tid] = fmax(sm[tid], sm[tid + o]);
-      __syncthreads();
-    }
-    if (tid == 0) atomicMax(A.lam_next, (unsigned long long)__double_as_longlong(sm[0]));
+    lam_out = sm[0];
+    for (int w = 1; w < BS / 64; ++w) lam_out = fmax(lam_out, sm[w]);
+    if (tid == 0 && A.lam_next) atomicMax(A.lam_next, (unsigned long long)__double_as_longlong(lam_out));
   }
 
   // 6. output
-  for (int it = tid; it < S * M * ospan; it += kBlock1) {
+  for (int it = tid; it < S * M * ospan; it += BS) {
     const int sk = it / ospan, rem = it - sk * ospan;
     const int le2 = rem / n, j = rem - le2 * n;
     A.out[(long)sk * EN + (long)(e0 + le2) * n + j] = sO[le2 * ncoef + sk * n + j];
   }
+  return lam_out;
 }
+
+template <int EQ, int N, typename R, int XF>
+__global__ void __launch_bounds__(kBlock1) k_stage1d(KParams P, Stage1DArgs A) {
+  stage1d_block<EQ, N, R, XF, kBlock1>(P, A, blockIdx.x);
+}
+
 
 // CFL maximum of a 1D state: a workgroup stages the coefficients of 256 / Nq
 // elements in LDS; thread (element, node q) takes the maximum over the points
@@ -608,9 +648,130 @@ __global__ void __launch_bounds__(kBlock1) k_cfl1d(KParams P, const double* __re
 
 __global__ void k_zero_lam(unsigned long long* lam) { *lam = 0ull; }
 
+// Several SSP-RK3 steps of a small 1D problem in one launch.  One workgroup of
+// kBlockRes threads covers every element ((E + 2) element slots x N_q nodes <=
+// kBlockRes) and runs the three stages of each step back to back with the
+// stage code of k_stage1d, the stages separated by workgroup barriers.  Where
+// they fit, the state and the two stage states live in LDS for the whole call
+// (u is read once at the start and written once at the end); otherwise a stage
+// writes its output to global memory and the next stage, on the same compute
+// unit, reads it after the barrier.  The CFL maximum of each step's output stays
+// in the workgroup and sets the next step's dt.  Per element the arithmetic, and
+// so the result, is that of the three launches per step.
+constexpr int kBlockRes = 1024;
+
+struct Resident1DArgs {
+  double* u;                         // state, advanced in place
+  double* w1;                        // first and second stage states (global variant)
+  double* w2;
+  int nsteps;
+  int limit;                         // positivity limiter on every stage output
+  unsigned char* flags;              // [nsteps][4][E] or null
+  double* dt_used;                   // [nsteps] or null
+  const unsigned long long* lam_in;  // CFL maximum of u on entry
+  unsigned long long* lam_out;       // CFL maximum of the final state
+  long lds_tab;                      // offset in doubles of the LDS copies of Phi and PW
+  long lds_state;                    // > 0: offset in doubles of the three states in LDS
+  long nstate;                       // doubles per state
+};
+
+template <int EQ, int N>
+__global__ void __launch_bounds__(kBlockRes) k_steps1d_resident(KParams P0, Resident1DArgs RA) {
+  extern __shared__ double smem_res[];
+  // the chaos tables are read with per-thread indices inside loops over the
+  // modes and nodes: one workgroup cannot hide their cache latency, so they are
+  // read from LDS copies
+  KParams P = P0;
+  {
+    double* sPhi = smem_res + RA.lds_tab;
+    double* sPW = sPhi + P.M * P.Nq;
+    for (int i = threadIdx.x; i < P.M * P.Nq; i += kBlockRes) {
+      sPhi[i] = P0.tab.Phi[i];
+      sPW[i] = P0.tab.PW[i];
+    }
+    P.tab.Phi = sPhi;
+    P.tab.PW = sPW;
+  }
+  double *u = RA.u, *w1 = RA.w1, *w2 = RA.w2;
+  if (RA.lds_state > 0) {
+    double* base = smem_res + RA.lds_state;
+    for (long i = threadIdx.x; i < RA.nstate; i += kBlockRes) base[i] = RA.u[i];
+    u = base;
+    w1 = base + RA.nstate;
+    w2 = base + 2 * RA.nstate;
+  }
+  __syncthreads();
+  // the steps' dt collect in LDS and go out kRing at a time: a global store from
+  // inside a stage would hold the next workgroup barrier until it completes
+  constexpr int kRing = 256;
+  __shared__ double sdt[kRing];
+  double lam = __longlong_as_double((long long)*RA.lam_in);
+  double dt = 0.0;
+  const long fl = 4l * P.E;
+  const bool clear = !RA.limit;
+  for (int step = 0; step < RA.nsteps; ++step) {
+    // the expression of the stage kernel's CFL time step
+    dt = P.cfl * P.dx / (P.np1 * lam);
+    if (threadIdx.x == 0) {
+      if (!(dt > 0.0) || !isfinite(dt)) atomicOr(P.status, kStatusNonFinite);
+      sdt[step % kRing] = dt;
+    }
+    unsigned char* f = RA.flags ? RA.flags + step * fl : nullptr;
+    for (int st = 0; st < 3; ++st) {
+      Stage1DArgs A{};
+      A.u = u;
+      A.EB = P.E;
+      A.limit = RA.limit;
+      A.dt_source = 3;
+      A.dt_fixed = dt;
+      unsigned char* fs = f ? f + (st == 2 ? 3 : st) * (long)P.E : nullptr;
+      A.clear_flags = clear ? fs : nullptr;
+      A.flag_lim = fs;
+      if (st == 0) {
+        A.in = u, A.w = u, A.out = w1, A.cu = 0.0, A.cw = 1.0;
+      } else if (st == 1) {
+        A.in = w1, A.w = w1, A.out = w2, A.cu = 0.75, A.cw = 0.25;
+      } else {
+        A.in = w2, A.w = w2, A.out = u, A.cu = 1.0 / 3.0, A.cw = 2.0 / 3.0;
+        A.end_of_step = 1;
+        A.cfl_out = 1;
+        A.flag_filt = f ? f + 2 * (long)P.E : nullptr;
+      }
+      const double r = stage1d_block<EQ, N, double, 0, kBlockRes>(P, A, 0);
+      if (st == 2) lam = r;
+      __syncthreads();
+    }
+    if (step % kRing == kRing - 1 || step == RA.nsteps - 1) {
+      const int first = step - step % kRing;
+      if (RA.dt_used && (int)threadIdx.x <= step - first) RA.dt_used[first + threadIdx.x] = sdt[threadIdx.x];
+      __syncthreads();
+    }
+  }
+  if (RA.lds_state > 0)
+    for (long i = threadIdx.x; i < RA.nstate; i += kBlockRes) RA.u[i] = u[i];
+  if (threadIdx.x == 0) {
+    if (RA.nsteps > 0) *P.dt = dt;
+    *RA.lam_out = (unsigned long long)__double_as_longlong(lam);
+  }
+}
+
 }  // namespace
 
 // elements per workgroup and LDS bytes; EB = 0 when the node count does not fit
+// LDS of a stage over EB elements (plus one neighbour on each side)
+static size_t fr1d_lds(const KParams& P, int EB) {
+  const size_t ncoef = (size_t)P.S * P.M * P.np1;
+  size_t shmem =
+      sizeof(double) * ((EB + 2) * ncoef + (size_t)(EB + 2) * P.Nq * 2 * P.S + (size_t)EB * P.S * P.np1 * P.Nq);
+  if (P.bf16) {  // matrix-core operands: one block of 16 modes
+    const int rows = P.S * P.np1;
+    shmem += sizeof(double) * (size_t)EB * rows +
+             sizeof(float) * ((size_t)pad16((EB + 2) * rows) * pad16(P.Nq) + (size_t)pad16(EB * rows) * 16);
+    if (P.M > 16) shmem = ~(size_t)0;
+  }
+  return shmem;
+}
+
 static void fr1d_shape(const KParams& P, int& EB, size_t& shmem) {
   EB = kBlock1 / P.Nq - 2;
   if (EB < 1 || P.np1 > kMaxN) {
@@ -618,14 +779,7 @@ static void fr1d_shape(const KParams& P, int& EB, size_t& shmem) {
     shmem = 0;
     return;
   }
-  const size_t ncoef = (size_t)P.S * P.M * P.np1;
-  shmem = sizeof(double) * ((EB + 2) * ncoef + (size_t)(EB + 2) * P.Nq * 2 * P.S + (size_t)EB * P.S * P.np1 * P.Nq);
-  if (P.bf16) {  // matrix-core operands: one block of 16 modes
-    const int rows = P.S * P.np1;
-    shmem += sizeof(double) * (size_t)EB * rows +
-             sizeof(float) * ((size_t)pad16((EB + 2) * rows) * pad16(P.Nq) + (size_t)pad16(EB * rows) * 16);
-    if (P.M > 16) shmem = ~(size_t)0;
-  }
+  shmem = fr1d_lds(P, EB);
   if (shmem > 64 * 1024) {
     EB = 0;
     shmem = 0;
@@ -649,9 +803,9 @@ hipError_t launch_stage1d(const KParams& P, const double* in, const double* u, c
   size_t shmem;
   fr1d_shape(P, EB, shmem);
   if (EB == 0) return hipErrorInvalidValue;
-  Stage1DArgs A{in,          u,       w,         out,         cu,         cw,        rhs_only,
-                clear_flags, EB,      limit,     end_of_step, flag_lim,   flag_filt, lam_next,
-                dt_source,   dt_fixed, lam_in,   lam_reset,   dt_used};
+  Stage1DArgs A{in,          u,           w,       out,         cu,          cw,       rhs_only,
+                clear_flags, EB,          limit,   end_of_step, flag_lim,    flag_filt,
+                lam_next != nullptr,      lam_next, dt_source,  dt_fixed,    lam_in,   lam_reset, dt_used};
   const unsigned grid = (unsigned)((P.E + EB - 1) / EB);
   auto go = [&](auto eq_tag) -> hipError_t {
     constexpr int EQ = decltype(eq_tag)::value;
@@ -686,6 +840,68 @@ hipError_t launch_stage1d(const KParams& P, const double* in, const double* u, c
     case kAdvection: return go(std::integral_constant<int, kAdvection>{});
     case kBurgers: return go(std::integral_constant<int, kBurgers>{});
     case kEuler1: return go(std::integral_constant<int, kEuler1>{});
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// the one-workgroup multi-step kernel: FP64 scalar equations of FR degree <= 3
+// (at 1024 threads a lane has 128 registers; the Euler and higher-degree
+// instances would spill), every element and its neighbours in one workgroup, the
+// stage LDS plus the CFL reduction's within 64 KB; the three states join them in
+// LDS where that stays within 64 KB
+constexpr int kMaxNRes = 4;
+constexpr size_t kLdsRes = 64 * 1024;
+static size_t fr1d_state_bytes(const KParams& P) { return sizeof(double) * (size_t)P.S * P.M * P.np1 * P.E; }
+// stage LDS, the chaos tables' copies, the CFL reduction and the ring of time steps
+static size_t fr1d_resident_lds(const KParams& P) {
+  return fr1d_lds(P, P.E) + sizeof(double) * (2 * (size_t)P.M * P.Nq + kBlockRes / 64 + 256);
+}
+bool fr1d_resident_fits(const KParams& P) {
+  if (P.dim != 1 || P.fp32 || P.bf16 || P.eq == kEuler1 || P.np1 < 2 || P.np1 > kMaxNRes) return false;
+  if ((long)(P.E + 2) * P.Nq > kBlockRes) return false;
+  return fr1d_resident_lds(P) <= kLdsRes;
+}
+bool fr1d_resident_lds_state(const KParams& P) {
+  return fr1d_resident_fits(P) && fr1d_resident_lds(P) + 3 * fr1d_state_bytes(P) <= kLdsRes;
+}
+
+template <int EQ, int N>
+static hipError_t go_resident(const KParams& P, const Resident1DArgs& RA, size_t shmem, hipStream_t s,
+                              bool check_only) {
+  if (check_only) {
+    hipFuncAttributes fa;
+    const hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_steps1d_resident<EQ, N>));
+    if (e != hipSuccess) return e;
+    return fa.localSizeBytes == 0 ? hipSuccess : hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL((k_steps1d_resident<EQ, N>), dim3(1), dim3(kBlockRes), shmem, s, P, RA);
+  return hipGetLastError();
+}
+
+// with u == nullptr only checks that the instance for P runs without register
+// spills (hipErrorInvalidValue otherwise)
+hipError_t launch_steps1d_resident(const KParams& P, double* u, double* w1, double* w2, int nsteps, int limit,
+                                   unsigned char* flags, double* dt_used, const unsigned long long* lam_in,
+                                   unsigned long long* lam_out, hipStream_t s) {
+  if (!fr1d_resident_fits(P)) return hipErrorInvalidValue;
+  const bool check_only = u == nullptr;
+  const bool in_lds = fr1d_resident_lds_state(P);
+  const long stage = (long)(fr1d_lds(P, P.E) / sizeof(double)), tab = 2l * P.M * P.Nq;
+  const Resident1DArgs RA{u,      w1,     w2,      nsteps, limit, flags, dt_used, lam_in, lam_out, stage,
+                          in_lds ? stage + tab : 0l, (long)(fr1d_state_bytes(P) / sizeof(double))};
+  const size_t shmem = sizeof(double) * (stage + tab) + (in_lds ? 3 * fr1d_state_bytes(P) : 0);
+  auto go = [&](auto eq_tag) -> hipError_t {
+    constexpr int EQ = decltype(eq_tag)::value;
+    switch (P.np1) {
+      case 2: return go_resident<EQ, 2>(P, RA, shmem, s, check_only);
+      case 3: return go_resident<EQ, 3>(P, RA, shmem, s, check_only);
+      case 4: return go_resident<EQ, 4>(P, RA, shmem, s, check_only);
+      default: return hipErrorInvalidValue;
+    }
+  };
+  switch (P.eq) {
+    case kAdvection: return go(std::integral_constant<int, kAdvection>{});
+    case kBurgers: return go(std::integral_constant<int, kBurgers>{});
     default: return hipErrorInvalidValue;
   }
 }
