@@ -314,17 +314,21 @@ __global__ void __launch_bounds__(kBlockA) k_adj_stage1d(KParams P, AdjStageArgs
     const double* W = sW + ls * nc;
     const double* Gc = sGc + ls * nc;
     const R Jx = (R)P.Jx;
-    R d[n];
+    R d[n], gr[n];
 #pragma unroll
-    for (int j = 0; j < n; ++j) {
-      R u = R(0), gr = R(0);
-      for (int k = 0; k < M; ++k) {
-        u += (R)W[k * n + j] * (R)P.tab.Phi[k * Nq + q];
-        gr += (R)P.tab.PW[k * Nq + q] * (R)Gc[k * n + j];
+    for (int j = 0; j < n; ++j) U[j] = gr[j] = R(0);
+    // mode by mode into every point's sums: each sum takes the modes in order,
+    // and the 2 n chains are independent
+    for (int k = 0; k < M; ++k) {
+      const R phi = (R)P.tab.Phi[k * Nq + q], pw = (R)P.tab.PW[k * Nq + q];
+#pragma unroll
+      for (int j = 0; j < n; ++j) {
+        U[j] += (R)W[k * n + j] * phi;
+        gr[j] += pw * (R)Gc[k * n + j];
       }
-      U[j] = u;
-      d[j] = -gr / Jx;
     }
+#pragma unroll
+    for (int j = 0; j < n; ++j) d[j] = -gr[j] / Jx;
     R GL = R(0), GR = R(0);
 #pragma unroll
     for (int j = 0; j < n; ++j) {
@@ -389,25 +393,48 @@ __global__ void __launch_bounds__(kBlockA) k_adj_stage1d(KParams P, AdjStageArgs
     __syncthreads();
   }
 
+  // thread (block of KB modes, element, point): one pass over the nodal adjoint
+  // feeds KB independent sums, each taking the nodes in order
+  constexpr int KB = 4;
+  const int nkb = (M + KB - 1) / KB;
   const int ospan = nloc * n;
-  for (int it = tid; it < M * ospan; it += kBlockA) {
-    const int k = it / ospan, rem = it - k * ospan;
+  for (int it = tid; it < nkb * ospan; it += kBlockA) {
+    const int kb = it / ospan, rem = it - kb * ospan;
     const int le = rem / n, j = rem - le * n;
+    const int k0 = kb * KB;
     const double* Gq = sU + ((long)le * n + j) * Nq;
-    double acc = 0.0;
-    if (std::is_same<R, double>::value || k == 0) {
-      for (int qq = 0; qq < Nq; ++qq) acc += P.tab.Phi[k * Nq + qq] * Gq[qq];
-    } else {
-      R a = R(0);
-      for (int qq = 0; qq < Nq; ++qq) a += (R)P.tab.Phi[k * Nq + qq] * (R)Gq[qq];
-      acc = (double)a;
+    const double* Phk[KB];
+#pragma unroll
+    for (int i = 0; i < KB; ++i) Phk[i] = P.tab.Phi + min(k0 + i, M - 1) * Nq;  // clamped: past M unused
+    double ad[KB];
+    R ar[KB];
+#pragma unroll
+    for (int i = 0; i < KB; ++i) {
+      ad[i] = 0.0;
+      ar[i] = R(0);
     }
-    const long idx = (long)k * EN + (long)(e0 + le) * n + j;
-    double v = A.cg * acc;
-    if (A.x0) v += A.c0 * A.x0[idx];
-    if (A.x1) v += A.c1 * A.x1[idx];
-    if (A.x2) v += A.c2 * A.x2[idx];
-    A.out[idx] = v;
+    for (int qq = 0; qq < Nq; ++qq) {
+      const double gq = Gq[qq];
+#pragma unroll
+      for (int i = 0; i < KB; ++i) {
+        if (std::is_same<R, double>::value || k0 + i == 0)
+          ad[i] += Phk[i][qq] * gq;  // FP64 (the mean mode in every precision)
+        else
+          ar[i] += (R)Phk[i][qq] * (R)gq;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < KB; ++i) {
+      const int k = k0 + i;
+      if (k >= M) continue;
+      const double acc = (std::is_same<R, double>::value || k == 0) ? ad[i] : (double)ar[i];
+      const long idx = (long)k * EN + (long)(e0 + le) * n + j;
+      double v = A.cg * acc;
+      if (A.x0) v += A.c0 * A.x0[idx];
+      if (A.x1) v += A.c1 * A.x1[idx];
+      if (A.x2) v += A.c2 * A.x2[idx];
+      A.out[idx] = v;
+    }
   }
 }
 

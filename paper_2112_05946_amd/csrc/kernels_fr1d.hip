@@ -313,28 +313,61 @@ __device__ __forceinline__ double stage1d_block(const KParams& P, const Stage1DA
   const bool epi = A.limit || A.end_of_step;
   double* sO = sC;  // [EB][S][M][n] output coefficients
   const int ospan = nloc * n;
-  for (int it = tid; it < S * M * ospan; it += BS) {
-    const int sk = it / ospan, rem = it - sk * ospan;
-    const int le = rem / n, j = rem - le * n;
-    const int s = sk / M, k = sk - s * M;
-    const double* Rq = sR + (((long)le * S + s) * n + j) * Nq;
-    double acc = 0.0;
-    if constexpr (XF) {
-      const int r = (le * S + s) * n + j;
-      acc = (k == 0) ? sP0[r] : (double)sPk[(long)r * 16 + k];
-    } else if (std::is_same<R, double>::value || k == 0) {
-      for (int qq = 0; qq < Nq; ++qq) acc += P.tab.PW[k * Nq + qq] * Rq[qq];
-    } else {
-      R a = R(0);
-      for (int qq = 0; qq < Nq; ++qq) a += (R)P.tab.PW[k * Nq + qq] * (R)Rq[qq];
-      acc = (double)a;
-    }
+  // the combination of the projected residual into the stage output
+  auto combine = [&](int s, int k, int le, int j, double acc) {
+    const int sk = s * M + k;
     const long idx = (long)sk * EN + (long)(e0 + le) * n + j;
     const double v = A.rhs_only ? acc : A.cu * A.u[idx] + A.cw * (A.w[idx] + dt * acc);
     if (epi)
       sO[le * ncoef + sk * n + j] = v;
     else
       A.out[idx] = v;
+  };
+  if constexpr (XF) {
+    for (int it = tid; it < S * M * ospan; it += BS) {
+      const int sk = it / ospan, rem = it - sk * ospan;
+      const int le = rem / n, j = rem - le * n;
+      const int s = sk / M, k = sk - s * M;
+      const int r = (le * S + s) * n + j;
+      combine(s, k, le, j, (k == 0) ? sP0[r] : (double)sPk[(long)r * 16 + k]);
+    }
+  } else {
+    // thread (variable, block of KB modes, element, point): one pass over the
+    // nodal residual feeds KB independent sums, each taking the nodes in order
+    // (so every KB gives the same sums; the one-workgroup kernel, at 128
+    // registers per lane, keeps one mode per thread)
+    constexpr int KB = BS >= 1024 ? 1 : 4;
+    const int nkb = (M + KB - 1) / KB;
+    for (int it = tid; it < S * nkb * ospan; it += BS) {
+      const int skb = it / ospan, rem = it - skb * ospan;
+      const int le = rem / n, j = rem - le * n;
+      const int s = skb / nkb, k0 = (skb - s * nkb) * KB;
+      const double* Rq = sR + (((long)le * S + s) * n + j) * Nq;
+      const double* PWk[KB];
+#pragma unroll
+      for (int i = 0; i < KB; ++i) PWk[i] = P.tab.PW + min(k0 + i, M - 1) * Nq;  // clamped: past M unused
+      double ad[KB];
+      R ar[KB];
+#pragma unroll
+      for (int i = 0; i < KB; ++i) {
+        ad[i] = 0.0;
+        ar[i] = R(0);
+      }
+      for (int qq = 0; qq < Nq; ++qq) {
+        const double r = Rq[qq];
+#pragma unroll
+        for (int i = 0; i < KB; ++i) {
+          if (std::is_same<R, double>::value || k0 + i == 0)
+            ad[i] += PWk[i][qq] * r;  // FP64 (the mean mode in every precision)
+          else
+            ar[i] += (R)PWk[i][qq] * (R)r;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < KB; ++i)
+        if (k0 + i < M)
+          combine(s, k0 + i, le, j, (std::is_same<R, double>::value || k0 + i == 0) ? ad[i] : (double)ar[i]);
+    }
   }
   if (A.clear_flags)
     for (int it = tid; it < nloc; it += BS) A.clear_flags[e0 + it] = 0;
