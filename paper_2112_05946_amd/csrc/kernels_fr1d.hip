@@ -314,14 +314,13 @@ __device__ __forceinline__ double stage1d_block(const KParams& P, const Stage1DA
   double* sO = sC;  // [EB][S][M][n] output coefficients
   const int ospan = nloc * n;
   // the combination of the projected residual into the stage output
-  auto combine = [&](int s, int k, int le, int j, double acc) {
-    const int sk = s * M + k;
-    const long idx = (long)sk * EN + (long)(e0 + le) * n + j;
-    const double v = A.rhs_only ? acc : A.cu * A.u[idx] + A.cw * (A.w[idx] + dt * acc);
+  auto state_index = [&](int sk, int le, int j) { return (long)sk * EN + (long)(e0 + le) * n + j; };
+  auto combine = [&](int sk, int le, int j, double acc, double uv, double wv) {
+    const double v = A.rhs_only ? acc : A.cu * uv + A.cw * (wv + dt * acc);
     if (epi)
       sO[le * ncoef + sk * n + j] = v;
     else
-      A.out[idx] = v;
+      A.out[state_index(sk, le, j)] = v;
   };
   if constexpr (XF) {
     for (int it = tid; it < S * M * ospan; it += BS) {
@@ -329,7 +328,9 @@ __device__ __forceinline__ double stage1d_block(const KParams& P, const Stage1DA
       const int le = rem / n, j = rem - le * n;
       const int s = sk / M, k = sk - s * M;
       const int r = (le * S + s) * n + j;
-      combine(s, k, le, j, (k == 0) ? sP0[r] : (double)sPk[(long)r * 16 + k]);
+      const long idx = state_index(sk, le, j);
+      combine(sk, le, j, (k == 0) ? sP0[r] : (double)sPk[(long)r * 16 + k], A.rhs_only ? 0.0 : A.u[idx],
+              A.rhs_only ? 0.0 : A.w[idx]);
     }
   } else {
     // thread (variable, block of KB modes, element, point): one pass over the
@@ -348,10 +349,15 @@ __device__ __forceinline__ double stage1d_block(const KParams& P, const Stage1DA
       for (int i = 0; i < KB; ++i) PWk[i] = P.tab.PW + min(k0 + i, M - 1) * Nq;  // clamped: past M unused
       double ad[KB];
       R ar[KB];
+      // the combination's inputs, loaded before the sums so that their latency overlaps them
+      double uv[KB], wv[KB];
 #pragma unroll
       for (int i = 0; i < KB; ++i) {
         ad[i] = 0.0;
         ar[i] = R(0);
+        const long idx = state_index(s * M + min(k0 + i, M - 1), le, j);
+        uv[i] = A.rhs_only ? 0.0 : A.u[idx];
+        wv[i] = A.rhs_only ? 0.0 : A.w[idx];
       }
       for (int qq = 0; qq < Nq; ++qq) {
         const double r = Rq[qq];
@@ -366,7 +372,8 @@ __device__ __forceinline__ double stage1d_block(const KParams& P, const Stage1DA
 #pragma unroll
       for (int i = 0; i < KB; ++i)
         if (k0 + i < M)
-          combine(s, k0 + i, le, j, (std::is_same<R, double>::value || k0 + i == 0) ? ad[i] : (double)ar[i]);
+          combine(s * M + k0 + i, le, j, (std::is_same<R, double>::value || k0 + i == 0) ? ad[i] : (double)ar[i],
+                  uv[i], wv[i]);
     }
   }
   if (A.clear_flags)
