@@ -988,6 +988,58 @@ static fr_sg_status step_quad(fr_sg_ctx* ctx, double* u, double dt, double* dt_u
 // with the path's right-hand-side kernels, the stage combination kernel and the
 // element-wise limiter and sensor/filter passes.  Flags: row 0 = limiter acted
 // on any stage state, row 1 = 0, rows 2 and 3 as for SSP-RK3.
+// Butcher-tableau step on the fused 1D path, one stage kernel per stage: kernel i takes
+// the right-hand side of Y_i (Y_0 = u), keeps it as K_i and forms in its epilogue
+// Y_{i+1} = u + dt sum_{j <= i} a_{i+1,j} K_j, limited (flags OR-ed into row 0); the
+// last kernel forms u + dt sum_j b_j K_j in place and runs the detector-switched filter,
+// the limiter and the CFL maximum of the result.  Kernel 0 derives and publishes dt.
+// The same operations in the same order as the combination, limiter and filter passes.
+static fr_sg_status step_rk_fused1d(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, uint8_t* flags,
+                                    bool reuse_cfl) {
+  const KParams& K = ctx->kp;
+  Workspace& W = ctx->ws;
+  hipStream_t s = ctx->stream;
+  const Tableau& tb = *tableau_of(ctx->prob.integrator);
+  const int E = ctx->E;
+  const double sb = state_bytes(ctx);
+  unsigned long long* lam[2] = {(unsigned long long*)(W.scal + 1), (unsigned long long*)(W.scal + 3)};
+  const int cur = ctx->lam_cur;
+  fr_sg_status st;
+  const bool fixed = dt > 0.0;
+  if (!fixed && !reuse_cfl)
+    if ((st = timed(ctx, "cfl", sb, [&] { return launch_cfl1d(K, u, lam[cur], s); }))) return st;
+  if (flags) FRSG_TRY_HIP(launch_fill_flags(flags, 4l * E, s), ctx);
+  uint8_t* f0 = flags ? flags : nullptr;
+  uint8_t* f2 = flags ? flags + 2 * E : nullptr;
+  uint8_t* f3 = flags ? flags + 3 * E : nullptr;
+  const int limiter = ctx->prob.limiter ? 1 : 0;
+  double* Y[2] = {W.w1, W.w2};
+  const double* in = u;
+  for (int i = 0; i < tb.s; ++i) {
+    const bool last = i == tb.s - 1;
+    const double* row = last ? tb.b : tb.A[i + 1];
+    RkTerms T;
+    T.n = 0;
+    for (int j = 0; j < i; ++j)
+      if (row[j] != 0.0) {
+        T.K[T.n] = W.rk[j];
+        T.a[T.n] = row[j];
+        ++T.n;
+      }
+    double* out = last ? u : Y[i & 1];
+    if ((st = timed(ctx, last ? "rk_stage_last" : "rk_stage", (T.n + 3) * sb, [&] {
+           return launch_stage1d_tab(K, in, u, out, last ? nullptr : W.rk[i], T, row[i], s, limiter, last ? 1 : 0,
+                                     last ? f3 : f0, last ? f2 : nullptr, last ? lam[cur ^ 1] : nullptr,
+                                     i == 0 ? (fixed ? 1 : 2) : 0, fixed ? dt : 0.0, i == 0 ? lam[cur] : nullptr,
+                                     i == 0 ? lam[cur ^ 1] : nullptr, i == 0 ? dt_used : nullptr);
+         })))
+      return st;
+    in = out;
+  }
+  ctx->lam_cur = cur ^ 1;
+  return FRSG_OK;
+}
+
 static fr_sg_status step_rk(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, uint8_t* flags) {
   const KParams& K = ctx->kp;
   Workspace& W = ctx->ws;
@@ -1111,7 +1163,8 @@ static fr_sg_status check_step_args(fr_sg_ctx* ctx, double* u, double dt) {
 fr_sg_status fr_sg_step(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, uint8_t* flags) {
   fr_sg_status st = check_step_args(ctx, u, dt);
   if (st != FRSG_OK) return st;
-  if (ctx->prob.integrator != FRSG_SSPRK3) return step_rk(ctx, u, dt, dt_used, flags);
+  if (ctx->prob.integrator != FRSG_SSPRK3)
+    return ctx->fused1d ? step_rk_fused1d(ctx, u, dt, dt_used, flags, false) : step_rk(ctx, u, dt, dt_used, flags);
   if (ctx->quad) return step_quad(ctx, u, dt, dt_used, flags, false);
   if (ctx->fused) return step_fused(ctx, u, dt, dt_used, flags, false);
   if (ctx->fused1d) return step_fused1d(ctx, u, dt, dt_used, flags, false);
@@ -1131,7 +1184,7 @@ fr_sg_status fr_sg_steps(fr_sg_ctx* ctx, double* u, int32_t nsteps, double* dt_u
     double* dtu = dt_used ? dt_used + i : nullptr;
     uint8_t* f = flags ? flags + i * fl : nullptr;
     if (ctx->prob.integrator != FRSG_SSPRK3)
-      st = step_rk(ctx, u, 0.0, dtu, f);
+      st = ctx->fused1d ? step_rk_fused1d(ctx, u, 0.0, dtu, f, i > 0) : step_rk(ctx, u, 0.0, dtu, f);
     else if (ctx->quad)
       st = step_quad(ctx, u, 0.0, dtu, f, i > 0);
     else if (ctx->fused)

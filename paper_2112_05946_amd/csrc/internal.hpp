@@ -383,6 +383,15 @@ hipError_t launch_stage1d(const KParams& P, const double* in, const double* u, c
                           unsigned long long* lam_next = nullptr, int dt_source = 0, double dt_fixed = 0.0,
                           const unsigned long long* lam_in = nullptr, unsigned long long* lam_reset = nullptr,
                           double* dt_used = nullptr);
+// one stage of a Butcher-tableau step: out = u + dt (sum_j T.a[j] T.K[j] + ka_cur R(in)),
+// R(in) also stored in k_out (may be null); the limiter acts on out (flags OR-ed into
+// flag_lim), and with end_of_step the detector-switched filter, the limiter and the CFL
+// maximum follow as in the SSP-RK3 stage; dt as in launch_stage1d
+hipError_t launch_stage1d_tab(const KParams& P, const double* in, const double* u, double* out, double* k_out,
+                              const RkTerms& T, double ka_cur, hipStream_t s, int limit, int end_of_step,
+                              unsigned char* flag_lim, unsigned char* flag_filt, unsigned long long* lam_next,
+                              int dt_source, double dt_fixed, const unsigned long long* lam_in,
+                              unsigned long long* lam_reset, double* dt_used);
 hipError_t launch_cfl1d(const KParams& P, const double* u, unsigned long long* lam, hipStream_t s);
 // nsteps SSP-RK3 steps (CFL time steps, limiter on every stage output when limit,
 // end-of-step filter and CFL maximum) of an FP64 1D problem whose elements fit one

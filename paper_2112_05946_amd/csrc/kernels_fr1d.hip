@@ -63,6 +63,17 @@ struct Stage1DArgs {
   unsigned char* flag_filt;    // per element: filter acted (may be null)
   int cfl_out;                   // end of step: take the CFL maximum of the output
   unsigned long long* lam_next;  // accumulator the maximum is merged into (may be null)
+  // Butcher-row form (tab > 0) instead of cu u + cw (w + dt R): out = u + dt (sum_j ka[j]
+  // kk[j] + ka_cur R) over the nt earlier stage right-hand sides with nonzero
+  // coefficients, in stage order, R last (skipped when ka_cur is 0); R itself is stored
+  // in k_out when that is not null
+  int tab;
+  int nt;
+  const double* kk[kRkMaxTerms];
+  double ka[kRkMaxTerms];
+  double ka_cur;
+  double* k_out;
+  int flag_or;                   // limiter flags OR-ed into flag_lim (set only where it acts)
   // time step: dt_source 0 reads *P.dt; 1 takes dt_fixed; 2 computes it from the
   // CFL accumulator lam_in.  With 1 or 2, workgroup 0 also stores it in *P.dt and
   // dt_used, zeroes lam_reset and latches a non-finite or non-positive dt.  3 takes
@@ -316,7 +327,17 @@ __device__ __forceinline__ double stage1d_block(const KParams& P, const Stage1DA
   // the combination of the projected residual into the stage output
   auto state_index = [&](int sk, int le, int j) { return (long)sk * EN + (long)(e0 + le) * n + j; };
   auto combine = [&](int sk, int le, int j, double acc, double uv, double wv) {
-    const double v = A.rhs_only ? acc : A.cu * uv + A.cw * (wv + dt * acc);
+    double v;
+    if (BS < 1024 && A.tab) {  // (the one-workgroup kernel runs SSP-RK3 stages only)
+      const long idx = state_index(sk, le, j);
+      if (A.k_out) A.k_out[idx] = acc;
+      double t = 0.0;
+      for (int m = 0; m < A.nt; ++m) t = t + A.ka[m] * A.kk[m][idx];
+      if (A.ka_cur != 0.0) t = t + A.ka_cur * acc;
+      v = uv + dt * t;
+    } else {
+      v = A.rhs_only ? acc : A.cu * uv + A.cw * (wv + dt * acc);
+    }
     if (epi)
       sO[le * ncoef + sk * n + j] = v;
     else
@@ -585,7 +606,7 @@ __device__ __forceinline__ double stage1d_block(const KParams& P, const Stage1DA
           O[it] = beta2 * (v - ub[s] * m0) + ub[s] * m0;
         }
       }
-      if (own && q == 0 && A.flag_lim) A.flag_lim[e0 + le] = on ? 1 : 0;
+      if (own && q == 0 && A.flag_lim && !(A.flag_or && !on)) A.flag_lim[e0 + le] = on ? 1 : 0;
       __syncthreads();
     }
   }
@@ -834,18 +855,43 @@ bool fr1d_supported(const KParams& P) {
   return EB > 0;
 }
 
+static hipError_t go_stage1d(const KParams& P, Stage1DArgs A, hipStream_t s);
+
 hipError_t launch_stage1d(const KParams& P, const double* in, const double* u, const double* w, double* out, double cu,
                           double cw, int rhs_only, unsigned char* clear_flags, hipStream_t s, int limit,
                           int end_of_step, unsigned char* flag_lim, unsigned char* flag_filt,
                           unsigned long long* lam_next, int dt_source, double dt_fixed,
                           const unsigned long long* lam_in, unsigned long long* lam_reset, double* dt_used) {
+  Stage1DArgs A{};
+  A.in = in, A.u = u, A.w = w, A.out = out, A.cu = cu, A.cw = cw, A.rhs_only = rhs_only;
+  A.clear_flags = clear_flags, A.limit = limit, A.end_of_step = end_of_step;
+  A.flag_lim = flag_lim, A.flag_filt = flag_filt, A.cfl_out = lam_next != nullptr, A.lam_next = lam_next;
+  A.dt_source = dt_source, A.dt_fixed = dt_fixed, A.lam_in = lam_in, A.lam_reset = lam_reset, A.dt_used = dt_used;
+  return go_stage1d(P, A, s);
+}
+
+hipError_t launch_stage1d_tab(const KParams& P, const double* in, const double* u, double* out, double* k_out,
+                              const RkTerms& T, double ka_cur, hipStream_t s, int limit, int end_of_step,
+                              unsigned char* flag_lim, unsigned char* flag_filt, unsigned long long* lam_next,
+                              int dt_source, double dt_fixed, const unsigned long long* lam_in,
+                              unsigned long long* lam_reset, double* dt_used) {
+  if (T.n < 0 || T.n > kRkMaxTerms) return hipErrorInvalidValue;
+  Stage1DArgs A{};
+  A.in = in, A.u = u, A.w = u, A.out = out;
+  A.tab = 1, A.nt = T.n, A.ka_cur = ka_cur, A.k_out = k_out;
+  for (int m = 0; m < T.n; ++m) A.kk[m] = T.K[m], A.ka[m] = T.a[m];
+  A.limit = limit, A.end_of_step = end_of_step, A.flag_lim = flag_lim, A.flag_or = 1, A.flag_filt = flag_filt;
+  A.cfl_out = lam_next != nullptr, A.lam_next = lam_next;
+  A.dt_source = dt_source, A.dt_fixed = dt_fixed, A.lam_in = lam_in, A.lam_reset = lam_reset, A.dt_used = dt_used;
+  return go_stage1d(P, A, s);
+}
+
+static hipError_t go_stage1d(const KParams& P, Stage1DArgs A, hipStream_t s) {
   int EB;
   size_t shmem;
   fr1d_shape(P, EB, shmem);
   if (EB == 0) return hipErrorInvalidValue;
-  Stage1DArgs A{in,          u,           w,       out,         cu,          cw,       rhs_only,
-                clear_flags, EB,          limit,   end_of_step, flag_lim,    flag_filt,
-                lam_next != nullptr,      lam_next, dt_source,  dt_fixed,    lam_in,   lam_reset, dt_used};
+  A.EB = EB;
   const unsigned grid = (unsigned)((P.E + EB - 1) / EB);
   auto go = [&](auto eq_tag) -> hipError_t {
     constexpr int EQ = decltype(eq_tag)::value;
