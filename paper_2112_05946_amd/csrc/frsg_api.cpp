@@ -1040,6 +1040,69 @@ static fr_sg_status step_rk_fused1d(fr_sg_ctx* ctx, double* u, double dt, double
   return FRSG_OK;
 }
 
+// Butcher-tableau step on the fused 2D path, one stage kernel per stage, as on the 1D
+// path: kernel i keeps R(Y_i) as K_i and forms Y_{i+1} = u + dt sum_{j <= i} a_{i+1,j} K_j,
+// limited (flags OR-ed into row 0), in its epilogue; the last kernel forms the update in
+// place and runs the filter, the limiter and the CFL maximum.  Each launch writes the
+// face traces of its output for the next; the first reads those of u when the previous
+// step of the same call wrote them (chained).
+static fr_sg_status step_rk_fused2d(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, uint8_t* flags,
+                                    bool chained) {
+  const KParams& K = ctx->kp;
+  Workspace& W = ctx->ws;
+  hipStream_t s = ctx->stream;
+  const Tableau& tb = *tableau_of(ctx->prob.integrator);
+  const int E = ctx->E;
+  const double sb = state_bytes(ctx);
+  unsigned long long* lam[2] = {(unsigned long long*)(W.scal + 1), (unsigned long long*)(W.scal + 3)};
+  const int cur = ctx->lam_cur;
+  fr_sg_status st;
+  if (dt > 0.0) {
+    FRSG_TRY_HIP(launch_set_dt(K, dt, nullptr, lam[cur ^ 1], s), ctx);
+  } else {
+    if (!chained)
+      if ((st = timed(ctx, "cfl", sb, [&] { return launch_fused_cfl(K, u, lam[cur], s); }))) return st;
+    FRSG_TRY_HIP(launch_dt_from(K, lam[cur], lam[cur ^ 1], nullptr, s), ctx);
+  }
+  if (flags) FRSG_TRY_HIP(launch_fill_flags(flags, 4l * E, s), ctx);
+  uint8_t* f0 = flags ? flags : nullptr;
+  uint8_t* f2 = flags ? flags + 2 * E : nullptr;
+  uint8_t* f3 = flags ? flags + 3 * E : nullptr;
+  const int f32 = fp32(ctx);
+  double* Y[2] = {W.w1, W.w2};
+  const double* in = u;
+  int tc = ctx->tr_cur;
+  const double* tr_in = chained ? W.tr[tc] : nullptr;
+  for (int i = 0; i < tb.s; ++i) {
+    const bool last = i == tb.s - 1;
+    const double* row = last ? tb.b : tb.A[i + 1];
+    FusedStage S{in,        u,         last ? u : Y[i & 1], 0.0, 1.0, last ? 3 : 1, last ? f3 : f0, last ? f2 : nullptr,
+                 last ? lam[cur ^ 1] : nullptr, ctx->dDt, ctx->dcmax, ctx->dPhiT, ctx->dPWT, f32, ctx->dPhiT32,
+                 ctx->dPWT32, tr_in, W.tr[tc ^ 1]};
+    S.tab = 1;
+    S.terms.n = 0;
+    for (int j = 0; j < i; ++j)
+      if (row[j] != 0.0) {
+        S.terms.K[S.terms.n] = W.rk[j];
+        S.terms.a[S.terms.n] = row[j];
+        ++S.terms.n;
+      }
+    S.ka_cur = row[i];
+    S.k_out = last ? nullptr : W.rk[i];
+    if ((st = timed(ctx, last ? "rk_stage_last" : "rk_stage", (S.terms.n + 3) * sb,
+                    [&] { return launch_fused_stage(K, S, s); })))
+      return st;
+    in = S.out;
+    tr_in = W.tr[tc ^ 1];
+    tc ^= 1;
+  }
+  ctx->tr_cur = tc;
+  ctx->lam_cur = cur ^ 1;
+  ctx->lam_for = u;
+  if (dt_used) FRSG_TRY_HIP(launch_copy_dt(K, dt_used, s), ctx);
+  return FRSG_OK;
+}
+
 static fr_sg_status step_rk(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, uint8_t* flags) {
   const KParams& K = ctx->kp;
   Workspace& W = ctx->ws;
@@ -1164,7 +1227,9 @@ fr_sg_status fr_sg_step(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, u
   fr_sg_status st = check_step_args(ctx, u, dt);
   if (st != FRSG_OK) return st;
   if (ctx->prob.integrator != FRSG_SSPRK3)
-    return ctx->fused1d ? step_rk_fused1d(ctx, u, dt, dt_used, flags, false) : step_rk(ctx, u, dt, dt_used, flags);
+    return ctx->fused1d ? step_rk_fused1d(ctx, u, dt, dt_used, flags, false)
+           : ctx->fused ? step_rk_fused2d(ctx, u, dt, dt_used, flags, false)
+                        : step_rk(ctx, u, dt, dt_used, flags);
   if (ctx->quad) return step_quad(ctx, u, dt, dt_used, flags, false);
   if (ctx->fused) return step_fused(ctx, u, dt, dt_used, flags, false);
   if (ctx->fused1d) return step_fused1d(ctx, u, dt, dt_used, flags, false);
@@ -1184,7 +1249,9 @@ fr_sg_status fr_sg_steps(fr_sg_ctx* ctx, double* u, int32_t nsteps, double* dt_u
     double* dtu = dt_used ? dt_used + i : nullptr;
     uint8_t* f = flags ? flags + i * fl : nullptr;
     if (ctx->prob.integrator != FRSG_SSPRK3)
-      st = ctx->fused1d ? step_rk_fused1d(ctx, u, 0.0, dtu, f, i > 0) : step_rk(ctx, u, 0.0, dtu, f);
+      st = ctx->fused1d ? step_rk_fused1d(ctx, u, 0.0, dtu, f, i > 0)
+           : ctx->fused ? step_rk_fused2d(ctx, u, 0.0, dtu, f, i > 0)
+                        : step_rk(ctx, u, 0.0, dtu, f);
     else if (ctx->quad)
       st = step_quad(ctx, u, 0.0, dtu, f, i > 0);
     else if (ctx->fused)

@@ -261,6 +261,11 @@ fr_sg_status init_with_workspace(const fr_sg_problem* problem, void* hip_stream,
 void set_init_error(const std::string& msg);
 
 // one fused stage of the 2D Euler path (kernels_euler2d.hip)
+struct RkTerms {
+  const double* K[kRkMaxTerms];
+  double a[kRkMaxTerms];
+  int n;
+};
 struct FusedStage {
   const double* in;
   const double* u;
@@ -279,6 +284,12 @@ struct FusedStage {
   const float* PWT32;
   const double* tr_in = nullptr;  // modal face traces of `in` on tile boundaries (null: from the state)
   double* tr_out = nullptr;       // where to write those of `out` (may be null)
+  // tab: out = u + dt (sum_j terms.a[j] terms.K[j] + ka_cur R(in)) instead of cu u + cw (in + dt R),
+  // R(in) stored in k_out (may be null), limiter flags OR-ed into flag_lim
+  int tab = 0;
+  RkTerms terms{};
+  double ka_cur = 0.0;
+  double* k_out = nullptr;
 };
 bool fused2d_supported(const KParams& P);
 
@@ -360,11 +371,6 @@ hipError_t launch_post_tri(const KParams& P, double* u, const TriPost& post, hip
 // CFL maximum of a modal state on triangles into P.lam_bits
 hipError_t launch_cfl_tri_modal(const KParams& P, const double* u, hipStream_t s);
 // explicit Runge-Kutta stage combination: out = u + dt sum_j a[j] K[j] (flat state of n doubles)
-struct RkTerms {
-  const double* K[kRkMaxTerms];
-  double a[kRkMaxTerms];
-  int n;
-};
 hipError_t launch_rk_combine(const double* u, const RkTerms& T, const double* dt, double* out, long n,
                              hipStream_t s);
 hipError_t launch_or_flags(unsigned char* dst, const unsigned char* src, long n, hipStream_t s);

@@ -76,6 +76,15 @@ struct StageArgs {
   const double* cmax;        // [M] max_q |Phi_k(z_q)|
   const double* tr_in;       // modal face traces of the input, or null: interpolate from the neighbours
   double* tr_out;            // modal face traces of the output (may be null)
+  // Butcher-row form (tab) instead of cu u + cw (in + dt R): out = u + dt (sum_m ka[m] kk[m]
+  // + ka_cur R) over the earlier stage right-hand sides with nonzero coefficients, in stage
+  // order, R last (skipped when ka_cur is 0); R is also stored in k_out (may be null)
+  int tab, nt;
+  const double* kk[kRkMaxTerms];
+  double ka[kRkMaxTerms];
+  double ka_cur;
+  double* k_out;
+  int flag_or;               // limiter flags OR-ed into flag_lim (set only where it acts)
 };
 
 // Lane layout of a workgroup (one TX x TY tile of elements, 32 threads per element):
@@ -756,7 +765,32 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ PhiTd,
     return;
   }
   double o[2][M];
-  {
+  if (A.tab) {
+    // the earlier stages' terms first, in stage order, then this stage's
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int k = 0; k < M; ++k) o[i][k] = 0.0;
+    for (int t = 0; t < A.nt; ++t) {
+      const auto rk = state_rsrc(A.kk[t], sbytes);
+      const double at = A.ka[t];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int k = 0; k < M; ++k) o[i][k] = o[i][k] + at * bload_stream(rk, voff, soff(i, k));
+    }
+    const auto ru = state_rsrc(uin, sbytes);
+    const auto rko = state_rsrc(A.k_out, A.k_out ? sbytes : 0u);  // no k_out: an empty range drops the stores
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        const double r = res(i, k);
+        bstore(r, rko, voff, soff(i, k));
+        const double t = (A.ka_cur != 0.0) ? o[i][k] + A.ka_cur * r : o[i][k];
+        o[i][k] = bload_stream(ru, voff, soff(i, k)) + dt * t;
+      }
+  } else {
     const auto ru = state_rsrc(uin, A.cu != 0.0 ? sbytes : 0u);
     const auto rin2 = state_rsrc(in_again, sbytes);
 #pragma unroll
@@ -785,8 +819,8 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ PhiTd,
       L.rry[k] = P.tab.lR[(b - k) & 3];
     }
     const int lf = limit_pair<M, NQ>(P, PhiTd, o, h, a, b, L, A.cmax);
-    if (tid % 32 == 0 && A.flag_lim) A.flag_lim[e] = (unsigned char)lf;
-  } else if (tid % 32 == 0 && A.flag_lim) {
+    if (tid % 32 == 0 && A.flag_lim && (lf || !A.flag_or)) A.flag_lim[e] = (unsigned char)lf;
+  } else if (tid % 32 == 0 && A.flag_lim && !A.flag_or) {
     A.flag_lim[e] = 0;
   }
 
@@ -1016,6 +1050,15 @@ static hipError_t launch_stage_t(const KParams& P, const FusedStage& S, hipStrea
   A.cmax = S.cmax;
   A.tr_in = S.tr_in;
   A.tr_out = S.tr_out;
+  A.tab = S.tab;
+  A.nt = S.tab ? S.terms.n : 0;
+  for (int t = 0; t < kRkMaxTerms; ++t) {
+    A.kk[t] = t < A.nt ? S.terms.K[t] : nullptr;
+    A.ka[t] = t < A.nt ? S.terms.a[t] : 0.0;
+  }
+  A.ka_cur = S.ka_cur;
+  A.k_out = S.k_out;
+  A.flag_or = S.tab;
   const int ntiles = (P.nx / TX) * (P.ny / TY);
   if (S.fp32) {
     if (P.flux == FRSG_FLUX_HLL)
