@@ -19,6 +19,7 @@ CASES = [
     ("sod_bs3_hll_fused", dict(inputs.small(inputs.SOD, 40), integrator="bs3", flux="hll")),
     ("sod_tsit5_lasso", dict(inputs.small(inputs.SOD, 30), integrator="tsit5", filter="lasso", sensor="always")),
     ("sv_bs3_hll_fused", dict(inputs.small(inputs.SHOCK_VORTEX, 12, 8), integrator="bs3", flux="hll")),
+    ("sv_tsit5_fused", dict(inputs.small(inputs.SHOCK_VORTEX, 8, 6), integrator="tsit5")),
     ("sv_rk4_generic", dict(inputs.small(inputs.SHOCK_VORTEX, 7, 5), integrator="rk4")),
     ("advection_tsit5", dict(inputs.small(inputs.ADVECTION, 16), integrator="tsit5")),
 ]
@@ -60,6 +61,29 @@ def test_integrator_chained_steps():
     ud = to_dev(u0)
     dts = torch.empty(6, dtype=torch.float64, device=ud.device)
     sol.steps(ud, 6, dts)
+    sol.sync()
+    assert np.allclose(to_np(dts), rdts, rtol=1e-13, atol=0)
+    assert rel_l2(to_np(ud), ref) < RTOL_FP64
+
+
+def test_integrator_chained_steps_2d():
+    """fr_sg_steps on the fused 2D path: each stage kernel forms the next stage state in its
+    epilogue and writes its face traces for the next launch; later steps take the first
+    stage's traces and CFL maximum from the previous step's last launch."""
+    import torch
+    cfg = dict(inputs.small(inputs.SHOCK_VORTEX, 12, 8), integrator="rk4", flux="hll")
+    announce("integrator_chained_2d")
+    prob, (T, R) = oracle_for(cfg)
+    u0 = project_initial(prob, cfg["ic"], (T, R))
+    ref = u0.copy()
+    rdts = []
+    for _ in range(4):
+        ref, rdt, _ = ostep.step(prob, ref, None, (T, R))
+        rdts.append(rdt)
+    sol = solver_for(cfg)
+    ud = to_dev(u0)
+    dts = torch.empty(4, dtype=torch.float64, device=ud.device)
+    sol.steps(ud, 4, dts)
     sol.sync()
     assert np.allclose(to_np(dts), rdts, rtol=1e-13, atol=0)
     assert rel_l2(to_np(ud), ref) < RTOL_FP64
