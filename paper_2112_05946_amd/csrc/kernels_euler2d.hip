@@ -378,10 +378,7 @@ __global__ void __launch_bounds__(BLKS) __attribute__((amdgpu_waves_per_eu(sizeo
 k_stage2d(KParams P, StageArgs A, const double* __restrict__ PhiTd,
                                                   const R* __restrict__ PhiT, const R* __restrict__ PWT,
                                                   const double* __restrict__ in, const double* __restrict__ uin,
-                                                  const double* in_again, double* out) {
-  // in_again == in: the epilogue of the FP32 loop reads the FP64 input through
-  // it, so that the compiler cannot merge those loads with the ones at the top
-  // and keep the FP64 values live across the node loop
+                                                  double* out) {
   constexpr bool kFP64 = sizeof(R) == sizeof(double);
   // per element and row h (node q0 or q1 of the pair in hand): nodal values at
   // the solution points, traces at the flux points (x-lo row i, x-hi row i,
@@ -456,15 +453,19 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ PhiTd,
   const unsigned sbytes = (unsigned)(4 * M * EN * (long)sizeof(double));
   const unsigned voff = (unsigned)(((long)(2 * h) * M * EN + (long)e * NSP + j) * (long)sizeof(double));
   auto soff = [&](int i, int k) { return (unsigned)(((long)i * M + k) * EN * (long)sizeof(double)); };
+  // the input in FP64 for the epilogue's combination, and in the loop's type (the same
+  // registers in FP64; the FP32 loop keeps both, 255 registers without spills)
   R m[2][M];
+  double md[2][M];
   {
     const auto rin = state_rsrc(in, sbytes);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int k = 0; k < M; ++k)
-        // the FP32 loop reads its input again in the epilogue: keep it cacheable there
-        m[i][k] = (R)(kFP64 ? bload_stream(rin, voff, soff(i, k)) : bload(rin, voff, soff(i, k)));
+      for (int k = 0; k < M; ++k) {
+        md[i][k] = bload_stream(rin, voff, soff(i, k));
+        m[i][k] = (R)md[i][k];
+      }
   }
 
   // traces of the elements around the tile at every node: one thread per
@@ -792,15 +793,12 @@ k_stage2d(KParams P, StageArgs A, const double* __restrict__ PhiTd,
       }
   } else {
     const auto ru = state_rsrc(uin, A.cu != 0.0 ? sbytes : 0u);
-    const auto rin2 = state_rsrc(in_again, sbytes);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int k = 0; k < M; ++k) {
         const double uu = bload_stream(ru, voff, soff(i, k));  // 0 from an empty range when cu = 0
-        // the FP64 input: kept in registers by the FP64 loop, re-read otherwise
-        const double mi = kFP64 ? (double)m[i][k] : bload_stream(rin2, voff, soff(i, k));
-        o[i][k] = A.cu * uu + A.cw * (mi + dt * res(i, k));
+        o[i][k] = A.cu * uu + A.cw * (md[i][k] + dt * res(i, k));
       }
   }
 
@@ -1063,17 +1061,17 @@ static hipError_t launch_stage_t(const KParams& P, const FusedStage& S, hipStrea
   if (S.fp32) {
     if (P.flux == FRSG_FLUX_HLL)
       hipLaunchKernelGGL((k_stage2d<M, NQ, float, FRSG_FLUX_HLL>), dim3(ntiles), dim3(BLKS), 0, s, P, A, S.PhiT,
-                         S.PhiT32, S.PWT32, S.in, S.u, S.in, S.out);
+                         S.PhiT32, S.PWT32, S.in, S.u, S.out);
     else
       hipLaunchKernelGGL((k_stage2d<M, NQ, float, FRSG_FLUX_RUSANOV>), dim3(ntiles), dim3(BLKS), 0, s, P, A, S.PhiT,
-                         S.PhiT32, S.PWT32, S.in, S.u, S.in, S.out);
+                         S.PhiT32, S.PWT32, S.in, S.u, S.out);
   } else {
     if (P.flux == FRSG_FLUX_HLL)
       hipLaunchKernelGGL((k_stage2d<M, NQ, double, FRSG_FLUX_HLL>), dim3(ntiles), dim3(BLKS), 0, s, P, A, S.PhiT,
-                         S.PhiT, S.PWT, S.in, S.u, S.in, S.out);
+                         S.PhiT, S.PWT, S.in, S.u, S.out);
     else
       hipLaunchKernelGGL((k_stage2d<M, NQ, double, FRSG_FLUX_RUSANOV>), dim3(ntiles), dim3(BLKS), 0, s, P, A,
-                         S.PhiT, S.PhiT, S.PWT, S.in, S.u, S.in, S.out);
+                         S.PhiT, S.PhiT, S.PWT, S.in, S.u, S.out);
   }
   return hipGetLastError();
 }
