@@ -291,7 +291,11 @@ fr_sg_status fr_sg_rhs(fr_sg_ctx* ctx, const double* u, double* dudt);
  * dt_used: device double[1] or NULL, receives the step used.
  * flags: device uint8[4*E] or NULL: [0*E+e] limiter after stage 1,
  * [1*E+e] limiter after stage 2, [2*E+e] sensor/filter at the end of the
- * step, [3*E+e] limiter at the end of the step (1 = acted). */
+ * step, [3*E+e] limiter at the end of the step (1 = acted).  With a tableau
+ * integrator (RK4, Bogacki-Shampine, Tsitouras) the step is
+ * Y_i = Lim(u + dt sum_{j<i} a_ij K_j), K_i = R(Y_i), u <- Lim(Filter(u + dt
+ * sum_i b_i K_i)); row 0 then flags the limiter acting on any stage state and
+ * row 1 is 0. */
 fr_sg_status fr_sg_step(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, uint8_t* flags);
 
 /* nsteps CFL steps in a row (dt from the CFL condition at the start of each
@@ -303,7 +307,10 @@ fr_sg_status fr_sg_step(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, u
  * interpolates them from u).  The end-of-step pass evaluates the wave speeds
  * in another order than the separate CFL pass of fr_sg_step, so a time step
  * can differ from that of a separate fr_sg_step call in the last bits; given
- * equal time steps the states are equal bit for bit.
+ * equal time steps the states are equal bit for bit.  A scalar 1D problem in
+ * FP64 of FR degree <= 3 whose elements fit one workgroup ((E + 2) N_q <=
+ * 1024, its stage data within 64 KB of LDS) runs the SSP-RK3 steps of the
+ * call in one launch of one workgroup, with the same per-element arithmetic.
  * dt_used: device double[nsteps] or NULL; flags: device uint8[nsteps * 4 * E]
  * or NULL, laid out per step as in fr_sg_step. */
 fr_sg_status fr_sg_steps(fr_sg_ctx* ctx, double* u, int32_t nsteps, double* dt_used, uint8_t* flags);
