@@ -883,12 +883,21 @@ static fr_sg_status steps_resident1d(fr_sg_ctx* ctx, double* u, int nsteps, doub
   fr_sg_status st;
   if ((st = timed(ctx, "cfl", sb, [&] { return launch_cfl1d(K, u, lam[cur], s); }))) return st;
   const char* name = fr1d_resident_lds_state(K) ? "steps_resident_lds" : "steps_resident";
-  if ((st = timed(ctx, name, 8 * sb * nsteps, [&] {
-         return launch_steps1d_resident(K, u, W.w1, W.w2, nsteps, ctx->prob.limiter ? 1 : 0, flags, dt_used,
-                                        lam[cur], lam[cur ^ 1], s);
-       })))
-    return st;
-  ctx->lam_cur = cur ^ 1;
+  // at most kChunk steps per launch (a few tens of milliseconds), the CFL maximum
+  // handed from launch to launch through the two accumulators
+  constexpr int kChunk = 4096;
+  int c = cur;
+  for (int done = 0; done < nsteps; done += kChunk) {
+    const int n = std::min(kChunk, nsteps - done);
+    if ((st = timed(ctx, name, 8 * sb * n, [&] {
+           return launch_steps1d_resident(K, u, W.w1, W.w2, n, ctx->prob.limiter ? 1 : 0,
+                                          flags ? flags + 4l * ctx->E * done : nullptr,
+                                          dt_used ? dt_used + done : nullptr, lam[c], lam[c ^ 1], s);
+         })))
+      return st;
+    c ^= 1;
+  }
+  ctx->lam_cur = c;
   return FRSG_OK;
 }
 

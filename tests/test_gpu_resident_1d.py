@@ -152,6 +152,34 @@ def test_advection_full_horizon_one_call():
     assert rel_l2(to_np(ud), ref) < RTOL_FP64
 
 
+def test_long_call_is_split_into_launches():
+    """5000 steps: two launches (4096 + 904 steps) hand the CFL maximum on; the result equals
+    5000 steps taken as 2500 + 2500 in two calls, and the time steps sum to the elapsed time."""
+    import torch
+    announce("resident_1d", "long_call")
+    cfg = ADV
+    prob, (T, R) = oracle_for(cfg)
+    u0 = project_initial(prob, cfg["ic"], (T, R))
+    n = 5000
+    a = solver_for(cfg)
+    a.timing(True)
+    ua = to_dev(u0)
+    da = torch.empty(n, dtype=torch.float64, device=ua.device)
+    a.steps(ua, n, da)
+    a.sync()
+    passes = a.timing_read()
+    assert passes["steps_resident_lds"][0] == 2, passes
+    b = solver_for(cfg)
+    ub = to_dev(u0)
+    db = torch.empty(n, dtype=torch.float64, device=ub.device)
+    b.steps(ub, n // 2, db[: n // 2])
+    b.steps(ub, n // 2, db[n // 2:])
+    b.sync()
+    assert np.array_equal(to_np(da), to_np(db))
+    assert np.array_equal(to_np(ua), to_np(ub))
+    assert np.all(to_np(da) > 0)
+
+
 @pytest.mark.parametrize("label,cfg", [("threads", ADV_OVER), ("lds", BURG_OVER)])
 def test_over_the_size_limit_runs_launched_stages(label, cfg):
     """One element past either limit: the steps take the three-launch path, with the oracle's results."""
