@@ -779,13 +779,17 @@ k_quad_stage(KParams P, QArgs A) {
     const int kl = (MODE == kQF64) ? g : 4 * g;
     const unsigned ob = (unsigned)((((long)tile_id * QNHF + myslot) * 4 * M * NP + kl * NP + Q.fi) *
                                    (long)sizeof(double));
+    // one store instruction writes 32-byte pieces of four lines, the other three fill
+    // the rest: cached stores, so that the L2 merges the pieces before they go out
+    // (streaming stores here measured 2 % slower)
     if (tb) {
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
         for (int t = 0; t < 4; ++t)
           if (qmode<MODE>(t, g) < M)
-            bstore(tr[s][t], rtr, ob, (unsigned)((s * M * NP + (MODE == kQF64 ? 4 * t : t) * NP) * sizeof(double)));
+            bstore_cached(tr[s][t], rtr, ob,
+                          (unsigned)((s * M * NP + (MODE == kQF64 ? 4 * t : t) * NP) * sizeof(double)));
     }
   }
 

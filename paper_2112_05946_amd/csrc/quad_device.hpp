@@ -218,6 +218,11 @@ __device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, unsigned voff,
 __device__ __forceinline__ double bload_stream(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, kNonTemporal));
 }
+// stores that the L2 should combine: pieces of a line written by several instructions
+__device__ __forceinline__ void bstore_cached(double v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0u, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, voff, soff, 0);
+}
 __device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
   using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0u, 0));
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, voff, soff, kNonTemporal);
