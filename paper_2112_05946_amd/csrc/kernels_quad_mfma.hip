@@ -553,28 +553,27 @@ k_quad_stage(KParams P, QArgs A) {
     accbf[s] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
     acc0[s] = 0.0;
   }
-  // bfloat16 operands of the coefficients and both traces (formed once)
-  v4s ch[4], cl[4], oh[4], ol[4], nh[4], nl[4];
-  if constexpr (MODE == kQBF16) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      float x[4], y[4], z[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        x[t] = (float)cf[s][t];
-        y[t] = (float)L.tm[w][s * 4 + t][l];
-        z[t] = (float)nsrc[(s * 4 + t) * nstride];
-      }
-      split4(x, ch[s], cl[s]);
-      split4(y, oh[s], ol[s]);
-      split4(z, nh[s], nl[s]);
-    }
-  }
-
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
-    constexpr int dummy = 0;
-    (void)dummy;
+    // bfloat16 operands of the coefficients and both traces, formed again for every
+    // node block: kept across the blocks they held 48 registers through the flux and
+    // residual work, where the kernel spills
+    v4s ch[4], cl[4], oh[4], ol[4], nh[4], nl[4];
+    if constexpr (MODE == kQBF16) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        float x[4], y[4], z[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          x[t] = (float)cf[s][t];
+          y[t] = (float)L.tm[w][s * 4 + t][l];
+          z[t] = (float)nsrc[(s * 4 + t) * nstride];
+        }
+        split4(x, ch[s], cl[s]);
+        split4(y, oh[s], ol[s]);
+        split4(z, nh[s], nl[s]);
+      }
+    }
     // nodal values at the solution point, own trace and neighbour trace at the flux point
     T U[4][4], To[4][4], Tn[4][4];
     if constexpr (MODE == kQF64) {
