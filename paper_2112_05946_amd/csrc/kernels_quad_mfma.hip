@@ -104,7 +104,9 @@ template <typename T, int NB>
 struct QLds {
   double tm[QTE][16][64];            // per wave: staging of 16 doubles per lane; own modal traces
   double th[QTE][2][16][16];         // per wave: modal traces across the tile-boundary x / y face
-  Half2<T> fs[QTE][2][4][2][16];     // per wave: interactive fluxes of two node slots
+  // per wave: interactive fluxes of two node slots (FP64), or of the four of a node
+  // block (bfloat16-split, T = float, whose node loop forms all of them before the residuals)
+  Half2<T> fs[QTE][sizeof(T) == 8 ? 2 : 4][4][2][16];
   double fA[NB * 4 * 64];            // FP64 expansion operands (this kernel's mode mapping)
   double fP[NB * 4 * 64];            // FP64 projection operands, or the bfloat16 pairs
   double fW[NB * 16];                // quadrature weight per (register, lane group)
@@ -555,28 +557,64 @@ k_quad_stage(KParams P, QArgs A) {
   }
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
-    // bfloat16 operands of the coefficients and both traces, formed again for every
-    // node block: kept across the blocks they held 48 registers through the flux and
-    // residual work, where the kernel spills
-    v4s ch[4], cl[4], oh[4], ol[4], nh[4], nl[4];
-    if constexpr (MODE == kQBF16) {
+    // interactive flux at the flux point of node slot r (own and neighbour traces
+    // there), into flux buffer slot `slot`
+    auto face_flux = [&](const T (&To)[4][4], const T (&Tn)[4][4], int r, int slot) {
+      T own[4] = {To[0][r], To[1][r], To[2][r], To[3][r]};
+      T nbv[4] = {Tn[0][r], Tn[1][r], Tn[2][r], Tn[3][r]};
+      if (wave_at_boundary) {  // uniform: only waves with a domain-boundary face pay for the ghosts
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          T gh = (gkind == FRSG_BC_DIRICHLET) ? gstate[s] : own[s];
+          if (gkind == FRSG_BC_REFLECT && s == gnormal) gh = -gh;
+          nbv[s] = Q.boundary ? gh : nbv[s];
+        }
+      }
+      T Fs[4];
+      if constexpr (FLUX == FRSG_FLUX_HLL)
+        hll_e2(own, nbv, Q.lo_side, Fs, gm, Q.side >> 1);
+      else
+        rusanov_e2(own, nbv, Q.lo_side, Fs, gm, Q.side >> 1);
+      L.fs[w][slot][g][0][j] = Half2<T>{Fs[0], Fs[1]};
+      L.fs[w][slot][g][1][j] = Half2<T>{Fs[2], Fs[3]};
+    };
+    // nodal residual of node slot r from its nodal values U[.][r] and the interactive
+    // fluxes of the element's faces in flux buffer slot `slot`; it takes U's place
+    auto residual = [&](T (&U)[4][4], int r, int slot) {
+      T F[4], G[4];
+      {
+        const T U0 = U[0][r], U1 = U[1][r], U2 = U[2][r], U3 = U[3][r];
+        const T ir = recip(U0);
+        const T p = (gm - T(1)) * (U3 - T(0.5) * (U1 * U1 + U2 * U2) * ir);
+        const T vx = U1 * ir, vy = U2 * ir;
+        F[0] = U1;
+        F[1] = U1 * vx + p;
+        F[2] = U2 * vx;
+        F[3] = (U3 + p) * vx;
+        G[0] = U2;
+        G[1] = U1 * vy;
+        G[2] = U2 * vy + p;
+        G[3] = (U3 + p) * vy;
+      }
+      const Half2<T> fxl0 = L.fs[w][slot][g][0][0 + b], fxr0 = L.fs[w][slot][g][0][4 + b];
+      const Half2<T> fyl0 = L.fs[w][slot][g][0][8 + a], fyr0 = L.fs[w][slot][g][0][12 + a];
+      const Half2<T> fxl1 = L.fs[w][slot][g][1][0 + b], fxr1 = L.fs[w][slot][g][1][4 + b];
+      const Half2<T> fyl1 = L.fs[w][slot][g][1][8 + a], fyr1 = L.fs[w][slot][g][1][12 + a];
+      const T fxl[4] = {fxl0.x, fxl0.y, fxl1.x, fxl1.y}, fxr[4] = {fxr0.x, fxr0.y, fxr1.x, fxr1.y};
+      const T fyl[4] = {fyl0.x, fyl0.y, fyl1.x, fyl1.y}, fyr[4] = {fyr0.x, fyr0.y, fyr1.x, fyr1.y};
+      const bool valid = 16 * nb + g + 4 * r < NQ;
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        float x[4], y[4], z[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          x[t] = (float)cf[s][t];
-          y[t] = (float)L.tm[w][s * 4 + t][l];
-          z[t] = (float)nsrc[(s * 4 + t) * nstride];
-        }
-        split4(x, ch[s], cl[s]);
-        split4(y, oh[s], ol[s]);
-        split4(z, nh[s], nl[s]);
+        const T res = -(xdot(dx, F[s]) + fxl[s] * dhLa + fxr[s] * dhRa) * iJx -
+                      (ydot(dy, G[s]) + fyl[s] * dhLb + fyr[s] * dhRb) * iJy;
+        U[s][r] = valid ? res : T(0);
       }
-    }
-    // nodal values at the solution point, own trace and neighbour trace at the flux point
-    T U[4][4], To[4][4], Tn[4][4];
+    };
+
+    T U[4][4];
     if constexpr (MODE == kQF64) {
+      // nodal values at the solution point, own trace and neighbour trace at the flux point
+      T To[4][4], Tn[4][4];
       const double* fA = L.fA + nb * 256;
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
@@ -596,85 +634,77 @@ k_quad_stage(KParams P, QArgs A) {
           Tn[s][r] = dN[r];
         }
       }
-    } else {
-      const v4s ah = as_v4s(L.fP[(nb * 2 + 0) * 64 + l]), al = as_v4s(L.fP[(nb * 2 + 1) * 64 + l]);
+      // node slots in pairs: interactive fluxes at the flux points, then residuals
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const v4f du = expand_bf(ah, al, ch[s], cl[s]);
-        const v4f dO = expand_bf(ah, al, oh[s], ol[s]);
-        const v4f dN = expand_bf(ah, al, nh[s], nl[s]);
+      for (int rp = 0; rp < 2; ++rp) {
+        if (2 * rp >= qslots(NQ, nb)) break;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          U[s][r] = du[r];
-          To[s][r] = dO[r];
-          Tn[s][r] = dN[r];
+        for (int rr = 0; rr < 2; ++rr) {
+          const int r = 2 * rp + rr;
+          if (r >= qslots(NQ, nb)) break;
+          face_flux(To, Tn, r, rr);
         }
+        wave_sync();
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr) {
+          const int r = 2 * rp + rr;
+          if (r >= qslots(NQ, nb)) break;
+          residual(U, r, rr);
+        }
+        wave_sync();  // the interactive fluxes of this pair are consumed
       }
-    }
-
-    // node slots in pairs: interactive fluxes at the flux points, then residuals
+    } else {
+      // traces first: their bfloat16 operands and expansions, the interactive fluxes of
+      // all four node slots; then the solution points' operands, expansion and
+      // residuals.  The operands are formed again for every node block (held across
+      // the blocks they took 48 registers), and the traces' values die before the
+      // nodal values are formed.
+      const v4s ah = as_v4s(L.fP[(nb * 2 + 0) * 64 + l]), al = as_v4s(L.fP[(nb * 2 + 1) * 64 + l]);
+      {
+        T To[4][4], Tn[4][4];
 #pragma unroll
-    for (int rp = 0; rp < 2; ++rp) {
-      if (2 * rp >= qslots(NQ, nb)) break;
+        for (int s = 0; s < 4; ++s) {
+          float y[4], z[4];
 #pragma unroll
-      for (int rr = 0; rr < 2; ++rr) {
-        const int r = 2 * rp + rr;
-        if (r >= qslots(NQ, nb)) break;
-        T own[4] = {To[0][r], To[1][r], To[2][r], To[3][r]};
-        T nbv[4] = {Tn[0][r], Tn[1][r], Tn[2][r], Tn[3][r]};
-        if (wave_at_boundary) {  // uniform: only waves with a domain-boundary face pay for the ghosts
+          for (int t = 0; t < 4; ++t) {
+            y[t] = (float)L.tm[w][s * 4 + t][l];
+            z[t] = (float)nsrc[(s * 4 + t) * nstride];
+          }
+          v4s oh, ol, nh, nl;
+          split4(y, oh, ol);
+          split4(z, nh, nl);
+          const v4f dO = expand_bf(ah, al, oh, ol);
+          const v4f dN = expand_bf(ah, al, nh, nl);
 #pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            T gh = (gkind == FRSG_BC_DIRICHLET) ? gstate[s] : own[s];
-            if (gkind == FRSG_BC_REFLECT && s == gnormal) gh = -gh;
-            nbv[s] = Q.boundary ? gh : nbv[s];
+          for (int r = 0; r < 4; ++r) {
+            To[s][r] = dO[r];
+            Tn[s][r] = dN[r];
           }
         }
-        T Fs[4];
-        if constexpr (FLUX == FRSG_FLUX_HLL)
-          hll_e2(own, nbv, Q.lo_side, Fs, gm, Q.side >> 1);
-        else
-          rusanov_e2(own, nbv, Q.lo_side, Fs, gm, Q.side >> 1);
-        L.fs[w][rr][g][0][j] = Half2<T>{Fs[0], Fs[1]};
-        L.fs[w][rr][g][1][j] = Half2<T>{Fs[2], Fs[3]};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (r >= qslots(NQ, nb)) break;
+          face_flux(To, Tn, r, r);
+        }
       }
       wave_sync();
 #pragma unroll
-      for (int rr = 0; rr < 2; ++rr) {
-        const int r = 2 * rp + rr;
-        if (r >= qslots(NQ, nb)) break;
-        const T* Us = nullptr;
-        (void)Us;
-        T F[4], G[4];
-        {
-          const T U0 = U[0][r], U1 = U[1][r], U2 = U[2][r], U3 = U[3][r];
-          const T ir = recip(U0);
-          const T p = (gm - T(1)) * (U3 - T(0.5) * (U1 * U1 + U2 * U2) * ir);
-          const T vx = U1 * ir, vy = U2 * ir;
-          F[0] = U1;
-          F[1] = U1 * vx + p;
-          F[2] = U2 * vx;
-          F[3] = (U3 + p) * vx;
-          G[0] = U2;
-          G[1] = U1 * vy;
-          G[2] = U2 * vy + p;
-          G[3] = (U3 + p) * vy;
-        }
-        const Half2<T> fxl0 = L.fs[w][rr][g][0][0 + b], fxr0 = L.fs[w][rr][g][0][4 + b];
-        const Half2<T> fyl0 = L.fs[w][rr][g][0][8 + a], fyr0 = L.fs[w][rr][g][0][12 + a];
-        const Half2<T> fxl1 = L.fs[w][rr][g][1][0 + b], fxr1 = L.fs[w][rr][g][1][4 + b];
-        const Half2<T> fyl1 = L.fs[w][rr][g][1][8 + a], fyr1 = L.fs[w][rr][g][1][12 + a];
-        const T fxl[4] = {fxl0.x, fxl0.y, fxl1.x, fxl1.y}, fxr[4] = {fxr0.x, fxr0.y, fxr1.x, fxr1.y};
-        const T fyl[4] = {fyl0.x, fyl0.y, fyl1.x, fyl1.y}, fyr[4] = {fyr0.x, fyr0.y, fyr1.x, fyr1.y};
-        const bool valid = 16 * nb + g + 4 * r < NQ;
+      for (int s = 0; s < 4; ++s) {
+        float x[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const T res = -(xdot(dx, F[s]) + fxl[s] * dhLa + fxr[s] * dhRa) * iJx -
-                        (ydot(dy, G[s]) + fyl[s] * dhLb + fyr[s] * dhRb) * iJy;
-          U[s][r] = valid ? res : T(0);  // the residual takes the place of the nodal value
-        }
+        for (int t = 0; t < 4; ++t) x[t] = (float)cf[s][t];
+        v4s ch, cl;
+        split4(x, ch, cl);
+        const v4f du = expand_bf(ah, al, ch, cl);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) U[s][r] = du[r];
       }
-      wave_sync();  // the interactive fluxes of this pair are consumed
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (r >= qslots(NQ, nb)) break;
+        residual(U, r, r);
+      }
+      wave_sync();  // the interactive fluxes of this block are consumed
     }
 
     // Galerkin projection of the residuals of this node block
