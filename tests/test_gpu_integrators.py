@@ -46,6 +46,29 @@ def test_integrator_steps_match_oracle(label, cfg):
         assert err < RTOL_FP64
 
 
+@pytest.mark.parametrize("label,cfg,dt", [
+    ("sod_rk4_fixed", dict(inputs.small(inputs.SOD, 24), integrator="rk4"), 2e-4),
+    ("sv_bs3_fixed", dict(inputs.small(inputs.SHOCK_VORTEX, 12, 8), integrator="bs3"), 1e-3),
+])
+def test_integrator_fixed_dt(label, cfg, dt):
+    """A tableau step at a given dt (the first stage kernel publishes it instead of
+    deriving it from the CFL maximum) on the fused 1D and 2D paths."""
+    announce("integrator_fixed_dt", label)
+    prob, (T, R) = oracle_for(cfg)
+    u0 = project_initial(prob, cfg["ic"], (T, R))
+    sol = solver_for(cfg)
+    ud = to_dev(u0)
+    ref = u0.copy()
+    for _ in range(2):
+        ref, rdt, rflags = ostep.step(prob, ref, dt, (T, R))
+        dtd, flags = sol.step(ud, dt)
+        sol.sync()
+        assert to_np(dtd)[0] == dt and rdt == dt
+        g = to_np(flags).reshape(4, prob.E)
+        assert np.array_equal(g[0], rflags[0]) and np.array_equal(g[3], rflags[3]) and not g[1].any()
+    assert rel_l2(to_np(ud), ref) < RTOL_FP64
+
+
 def test_integrator_chained_steps():
     import torch
     cfg = dict(inputs.small(inputs.SOD, 24), integrator="bs3", flux="hll")
