@@ -341,6 +341,25 @@ fr_sg_status fr_sg_steps(fr_sg_ctx* ctx, double* u, int32_t nsteps, double* dt_u
 fr_sg_status fr_sg_adjoint_step(fr_sg_ctx* ctx, const double* u_n, const uint8_t* flags_n, double dt, double* lam,
                                 double* dparams);
 
+/* fr_sg_step that also leaves its first and second SSP-RK3 stage states
+ * (w1 = u + dt R(u), w2 = 3/4 u + 1/4 (w1 + dt R(w1))) in the caller's w1 and
+ * w2, for fr_sg_adjoint_step_stages (a checkpointed gradient's recomputation
+ * keeps them instead of having every adjoint step recompute them).  Same
+ * arguments and results as fr_sg_step otherwise.  Covered where the adjoint
+ * runs on the fused 1D stage kernel (scalar 1D equations, SSP-RK3; else
+ * FRSG_EUNSUPPORTED).  w1, w2: device state-shaped arrays, distinct from each
+ * other and from u (else FRSG_EINVAL), written in full. */
+fr_sg_status fr_sg_step_stages(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, uint8_t* flags, double* w1,
+                               double* w2);
+
+/* fr_sg_adjoint_step given the step's stage states from fr_sg_step_stages
+ * instead of recomputing them: the same transposed passes in the same order, so
+ * the same result bit for bit, two launches fewer.  w1, w2: device state-shaped
+ * arrays (read only), distinct from each other and from lam (else FRSG_EINVAL);
+ * the other arguments, conditions and errors as for fr_sg_adjoint_step. */
+fr_sg_status fr_sg_adjoint_step_stages(fr_sg_ctx* ctx, const double* u_n, const double* w1, const double* w2,
+                                       const uint8_t* flags_n, double dt, double* lam, double* dparams);
+
 /* Synchronise the stream and return (then clear) the latched device status:
  * FRSG_OK, FRSG_ENONFINITE or FRSG_ENOTREALIZABLE. */
 fr_sg_status fr_sg_sync(fr_sg_ctx* ctx);

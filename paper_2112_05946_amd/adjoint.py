@@ -10,7 +10,10 @@ of each forward step, then held frozen in the backward pass).
 Checkpointing: the state is kept every k steps; the backward pass walks the
 segments in reverse, recomputes each segment's step-start states from its
 checkpoint with the same forward steps (bitwise the same arithmetic), then
-applies the adjoint steps in reverse.  Memory: n_steps/k + k states.
+applies the adjoint steps in reverse.  Where the library hands out a step's
+stage states (fr_sg_step_stages: the fused 1D path), the recomputation keeps
+them too and the adjoint steps take them (fr_sg_adjoint_step_stages) instead of
+recomputing them.  Memory: n_steps/k checkpoints plus k (or 3 k) states.
 
 Switch decisions (the detector's filter flags) and dt are those of the forward
 run; the derivative is that of the discrete map at those decisions.
@@ -56,8 +59,14 @@ class AdjointSolve(torch.autograd.Function):
         scratch_dt = torch.empty(1, dtype=torch.float64, device=lam.device)
         scratch_fl = torch.empty(4 * solver.E, dtype=torch.uint8, device=lam.device)
         nseg = math.ceil(n / k)
+        kept = None  # the segment's step-start states and stage states, where the path hands them out
         for seg in reversed(range(nseg)):
             start, end = seg * k, min(seg * k + k, n)
+            if kept is not False:
+                kept = _segment_from_kept_stages(solver, ctx.ckpts[seg], start, end, dt_host, flags, lam, dparams,
+                                                 scratch_dt, scratch_fl, kept)
+                if kept is not False:
+                    continue
             states = [ctx.ckpts[seg]]
             u = ctx.ckpts[seg].clone()
             for i in range(start, end - 1):
@@ -67,6 +76,31 @@ class AdjointSolve(torch.autograd.Function):
                 solver.adjoint_step(states[i - start], flags[i], float(dt_host[i]), lam, dparams)
         ctx.ckpts = None
         return lam, dparams.to(ctx.params_device), None, None, None, None
+
+
+def _segment_from_kept_stages(solver, ckpt, start, end, dt_host, flags, lam, dparams, scratch_dt, scratch_fl, bufs):
+    """One segment of the backward pass with the library's stage-keeping step: the
+    recomputation keeps every step's start state and its two stage states, and the
+    adjoint steps take them instead of recomputing the stages (the same values, so
+    the same gradient).  Returns the buffers for the next segment, or False, having
+    done nothing, where the path does not hand stage states out."""
+    from .binding import FrsgError
+    k = end - start
+    if bufs is None or bufs.shape[1] < k:
+        bufs = torch.empty((3, k) + tuple(ckpt.shape), dtype=torch.float64, device=ckpt.device)
+    u = ckpt.clone()
+    for j in range(k):
+        bufs[0, j].copy_(u)
+        try:
+            solver.step_stages(u, bufs[1, j], bufs[2, j], float(dt_host[start + j]), scratch_dt, scratch_fl)
+        except FrsgError as err:
+            if j == 0 and err.status == -2:
+                return False
+            raise
+    for j in reversed(range(k)):
+        solver.adjoint_step_stages(bufs[0, j], bufs[1, j], bufs[2, j], flags[start + j], float(dt_host[start + j]),
+                                   lam, dparams)
+    return bufs
 
 
 def quadrature_weights(solver):

@@ -82,6 +82,8 @@ SYMBOLS = [
     ("fr_sg_step", ctypes.c_int32, [_VP, _VP, ctypes.c_double, _VP, _VP]),
     ("fr_sg_steps", ctypes.c_int32, [_VP, _VP, ctypes.c_int32, _VP, _VP]),
     ("fr_sg_adjoint_step", ctypes.c_int32, [_VP, _VP, _VP, ctypes.c_double, _VP, _VP]),
+    ("fr_sg_step_stages", ctypes.c_int32, [_VP, _VP, ctypes.c_double, _VP, _VP, _VP, _VP]),
+    ("fr_sg_adjoint_step_stages", ctypes.c_int32, [_VP, _VP, _VP, _VP, _VP, ctypes.c_double, _VP, _VP]),
     ("fr_sg_sync", ctypes.c_int32, [_VP]),
     ("fr_sg_timing_enable", ctypes.c_int32, [_VP, ctypes.c_int32]),
     ("fr_sg_timing_read", ctypes.c_int32, [_VP, ctypes.POINTER(PassTime), ctypes.c_int32,
@@ -337,6 +339,39 @@ class Solver:
             raise ValueError("dparams must be a float64 device tensor of 2 entries")
         self._check(self.lib.fr_sg_adjoint_step(self._ctx, _ptr(u_n), _ptr(flags_n), float(dt), _ptr(lam),
                                                 _ptr(dparams)))
+        return lam
+
+    def step_stages(self, u, w1, w2, dt=None, dt_used=None, flags=None):
+        """step() that also leaves the first and second stage states in w1 and w2."""
+        torch = self._torch
+        self._state(u, "u")
+        self._state(w1, "w1")
+        self._state(w2, "w2")
+        if dt_used is None:
+            dt_used = torch.empty(1, dtype=torch.float64, device=self.device)
+        if flags is None:
+            flags = torch.empty(4 * self.E, dtype=torch.uint8, device=self.device)
+        self._aux(dt_used, torch.float64, 1, "dt_used")
+        self._aux(flags, torch.uint8, 4 * self.E, "flags")
+        self._check(self.lib.fr_sg_step_stages(self._ctx, _ptr(u), float(dt) if dt else 0.0, _ptr(dt_used),
+                                               _ptr(flags), _ptr(w1), _ptr(w2)))
+        return dt_used, flags
+
+    def adjoint_step_stages(self, u_n, w1, w2, flags_n, dt, lam, dparams=None):
+        """adjoint_step() from the stage states step_stages() left (no recomputation)."""
+        self._state(u_n, "u_n")
+        self._state(w1, "w1")
+        self._state(w2, "w2")
+        self._state(lam, "lam")
+        torch = self._torch
+        if flags_n is not None and (flags_n.dtype != torch.uint8 or flags_n.numel() != 4 * self.E
+                                    or flags_n.device != self.device or not flags_n.is_contiguous()):
+            raise ValueError("flags_n must be a contiguous uint8 device tensor of 4*E entries")
+        if dparams is not None and (dparams.dtype != torch.float64 or dparams.numel() != 2
+                                    or dparams.device != self.device):
+            raise ValueError("dparams must be a float64 device tensor of 2 entries")
+        self._check(self.lib.fr_sg_adjoint_step_stages(self._ctx, _ptr(u_n), _ptr(w1), _ptr(w2), _ptr(flags_n),
+                                                       float(dt), _ptr(lam), _ptr(dparams)))
         return lam
 
     def timing(self, enable=True):

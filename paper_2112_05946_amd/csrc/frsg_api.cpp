@@ -819,9 +819,12 @@ static fr_sg_status step_generic(fr_sg_ctx* ctx, double* u, double dt, double* d
 static fr_sg_status stages_fused1d(fr_sg_ctx* ctx, const double* u, double* out, uint8_t* f0, uint8_t* f1,
                                    uint8_t* f2, uint8_t* f3, bool lim, unsigned long long* lam_next,
                                    int dt_source = 0, double dt_fixed = 0.0,
-                                   const unsigned long long* lam_in = nullptr, double* dt_used = nullptr) {
+                                   const unsigned long long* lam_in = nullptr, double* dt_used = nullptr,
+                                   double* w1 = nullptr, double* w2 = nullptr) {
   const KParams& K = ctx->kp;
-  Workspace& W = ctx->ws;
+  Workspace W = ctx->ws;  // the stage states go to the workspace, or to the caller's w1, w2
+  if (w1) W.w1 = w1;
+  if (w2) W.w2 = w2;
   hipStream_t s = ctx->stream;
   const double sb = state_bytes(ctx);
   const int limiter = (lim && ctx->prob.limiter) ? 1 : 0;
@@ -847,7 +850,7 @@ static fr_sg_status stages_fused1d(fr_sg_ctx* ctx, const double* u, double* out,
 // stage kernels with the limiter, filter and next CFL maximum in their epilogues;
 // the first stage derives and publishes dt
 static fr_sg_status step_fused1d(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, uint8_t* flags,
-                                 bool reuse_cfl) {
+                                 bool reuse_cfl, double* w1 = nullptr, double* w2 = nullptr) {
   const KParams& K = ctx->kp;
   Workspace& W = ctx->ws;
   hipStream_t s = ctx->stream;
@@ -863,7 +866,7 @@ static fr_sg_status step_fused1d(fr_sg_ctx* ctx, double* u, double dt, double* d
   uint8_t* f2 = flags ? flags + 2 * E : nullptr;
   uint8_t* f3 = flags ? flags + 3 * E : nullptr;
   if ((st = stages_fused1d(ctx, u, u, f0, f1, f2, f3, true, lam[cur ^ 1], fixed ? 1 : 2, fixed ? dt : 0.0,
-                           lam[cur], dt_used)) != FRSG_OK)
+                           lam[cur], dt_used, w1, w2)) != FRSG_OK)
     return st;
   ctx->lam_cur = cur ^ 1;
   return FRSG_OK;
@@ -1274,9 +1277,9 @@ fr_sg_status fr_sg_steps(fr_sg_ctx* ctx, double* u, int32_t nsteps, double* dt_u
   return FRSG_OK;
 }
 
-fr_sg_status fr_sg_adjoint_step(fr_sg_ctx* ctx, const double* u_n, const uint8_t* flags_n, double dt, double* lam,
-                                double* dparams) {
-  if (!ctx) return FRSG_EINVAL;
+// the conditions both adjoint entry points share
+static fr_sg_status check_adjoint_args(fr_sg_ctx* ctx, const double* u_n, const uint8_t* flags_n, double dt,
+                                       double* lam) {
   if (!ctx->ws.avb) {
     ctx->err = "the adjoint covers the scalar 1D equations (advection, Burgers) only";
     return FRSG_EUNSUPPORTED;
@@ -1310,11 +1313,21 @@ fr_sg_status fr_sg_adjoint_step(fr_sg_ctx* ctx, const double* u_n, const uint8_t
                "LDS within 48 KiB)";
     return FRSG_EUNSUPPORTED;
   }
+  return FRSG_OK;
+}
+
+static fr_sg_status adjoint_from_stages(fr_sg_ctx* ctx, const double* u_n, const double* w1, const double* w2,
+                                        const uint8_t* flags_n, double dt, double* lam, double* dparams);
+
+fr_sg_status fr_sg_adjoint_step(fr_sg_ctx* ctx, const double* u_n, const uint8_t* flags_n, double dt, double* lam,
+                                double* dparams) {
+  if (!ctx) return FRSG_EINVAL;
+  fr_sg_status st = check_adjoint_args(ctx, u_n, flags_n, dt, lam);
+  if (st != FRSG_OK) return st;
   const KParams& K = ctx->kp;
   Workspace& W = ctx->ws;
   hipStream_t s = ctx->stream;
   const double sb = state_bytes(ctx);
-  fr_sg_status st;
   // stage states of the forward step, recomputed with the same kernels as the
   // forward step (no limiter: the scalar equations do not use it); the first
   // stage kernel publishes dt for the passes after it
@@ -1333,6 +1346,17 @@ fr_sg_status fr_sg_adjoint_step(fr_sg_ctx* ctx, const double* u_n, const uint8_t
                     [&] { return launch_project_stage(K, W.Un, u_n, W.w1, W.w2, 0.75, 0.25, 0, s); })))
       return st;
   }
+  return adjoint_from_stages(ctx, u_n, W.w1, W.w2, flags_n, dt, lam, dparams);
+}
+
+// the transposed step given the forward step's stage states w1, w2 (dt on the device)
+static fr_sg_status adjoint_from_stages(fr_sg_ctx* ctx, const double* u_n, const double* w1, const double* w2,
+                                        const uint8_t* flags_n, double dt, double* lam, double* dparams) {
+  const KParams& K = ctx->kp;
+  Workspace& W = ctx->ws;
+  hipStream_t s = ctx->stream;
+  const double sb = state_bytes(ctx);
+  fr_sg_status st;
   // u+ = Filter(v): vb = Filter^T lam
   if (ctx->prob.filter != FRSG_FILTER_NONE) {
     if ((st = timed(ctx, "adj_filter", 2 * sb,
@@ -1357,14 +1381,43 @@ fr_sg_status fr_sg_adjoint_step(fr_sg_ctx* ctx, const double* u_n, const uint8_t
     });
   };
   // v = u/3 + 2/3 (w2 + dt R(w2)):   b2 = 2/3 vb + 2/3 dt R'(w2)^T vb
-  if ((st = vjp("adj_stage3", W.w2, W.avb, W.avb, nullptr, nullptr, W.ab2, 2.0 / 3.0, 0.0, 0.0, 2.0 / 3.0 * dt,
+  if ((st = vjp("adj_stage3", w2, W.avb, W.avb, nullptr, nullptr, W.ab2, 2.0 / 3.0, 0.0, 0.0, 2.0 / 3.0 * dt,
                 2.0 / 3.0 * dt)))
     return st;
   // w2 = 3/4 u + 1/4 (w1 + dt R(w1)):  b1 = 1/4 b2 + 1/4 dt R'(w1)^T b2
-  if ((st = vjp("adj_stage2", W.w1, W.ab2, W.ab2, nullptr, nullptr, W.ab1, 0.25, 0.0, 0.0, 0.25 * dt, 0.25 * dt)))
+  if ((st = vjp("adj_stage2", w1, W.ab2, W.ab2, nullptr, nullptr, W.ab1, 0.25, 0.0, 0.0, 0.25 * dt, 0.25 * dt)))
     return st;
   // w1 = u + dt R(u):  lam_n = vb/3 + 3/4 b2 + b1 + dt R'(u)^T b1
   return vjp("adj_stage1", u_n, W.ab1, W.avb, W.ab2, W.ab1, lam, 1.0 / 3.0, 0.75, 1.0, dt, dt);
+}
+
+fr_sg_status fr_sg_step_stages(fr_sg_ctx* ctx, double* u, double dt, double* dt_used, uint8_t* flags, double* w1,
+                               double* w2) {
+  fr_sg_status st = check_step_args(ctx, u, dt);
+  if (st != FRSG_OK) return st;
+  if (!ctx->fused1d || !ctx->ws.avb || ctx->prob.integrator != FRSG_SSPRK3) {
+    ctx->err = "stage states are handed out by the fused 1D SSP-RK3 step of the scalar equations";
+    return FRSG_EUNSUPPORTED;
+  }
+  if (!w1 || !w2 || w1 == w2 || w1 == u || w2 == u) {
+    ctx->err = "w1 and w2 must be distinct device state buffers, distinct from u";
+    return FRSG_EINVAL;
+  }
+  return step_fused1d(ctx, u, dt, dt_used, flags, false, w1, w2);
+}
+
+fr_sg_status fr_sg_adjoint_step_stages(fr_sg_ctx* ctx, const double* u_n, const double* w1, const double* w2,
+                                       const uint8_t* flags_n, double dt, double* lam, double* dparams) {
+  if (!ctx) return FRSG_EINVAL;
+  fr_sg_status st = check_adjoint_args(ctx, u_n, flags_n, dt, lam);
+  if (st != FRSG_OK) return st;
+  if (!w1 || !w2 || w1 == w2 || w1 == lam || w2 == lam) {
+    ctx->err = "w1 and w2 must be distinct device state buffers, distinct from lam";
+    return FRSG_EINVAL;
+  }
+  // the transposed passes read dt from the device, as after a recomputation
+  FRSG_TRY_HIP(launch_set_dt(ctx->kp, dt, nullptr, nullptr, ctx->stream), ctx);
+  return adjoint_from_stages(ctx, u_n, w1, w2, flags_n, dt, lam, dparams);
 }
 
 fr_sg_status fr_sg_sync(fr_sg_ctx* ctx) {

@@ -222,3 +222,86 @@ def test_adjoint_rejected_for_euler():
     with pytest.raises(FrsgError) as ei:
         sol.adjoint_step(u, fl, 1e-3, lam)
     assert ei.value.status == -2
+
+
+@pytest.mark.parametrize("label,cfg,dt", [c for c in CASES if c[0] != "burgers_multipass"])
+def test_adjoint_from_kept_stages_equals_recomputed(label, cfg, dt):
+    """fr_sg_step_stages leaves w1, w2; fr_sg_adjoint_step_stages from them gives the
+    adjoint step of fr_sg_adjoint_step bit for bit, and the step itself equals fr_sg_step."""
+    import torch
+    announce("adjoint_kept_stages", label)
+    prob, (T, R) = oracle_for(cfg)
+    u = _state(cfg, prob, T, R, 21)
+    lam = np.random.default_rng(22).standard_normal(u.shape)
+    sol = solver_for(cfg)
+    ud = to_dev(u)
+    a, b = ud.clone(), ud.clone()
+    w1, w2 = torch.empty_like(ud), torch.empty_like(ud)
+    _, fa = sol.step(a, dt)
+    _, fb = sol.step_stages(b, w1, w2, dt)
+    sol.sync()
+    assert torch.equal(a, b) and torch.equal(fa, fb)
+    l1, l2 = to_dev(lam), to_dev(lam)
+    d1 = torch.zeros(2, dtype=torch.float64, device=ud.device)
+    d2 = torch.zeros(2, dtype=torch.float64, device=ud.device)
+    sol.adjoint_step(ud, fa, dt, l1, d1)
+    sol.adjoint_step_stages(ud, w1, w2, fa, dt, l2, d2)
+    sol.sync()
+    assert torch.equal(l1, l2) and torch.equal(d1, d2)
+
+
+def test_checkpointed_gradient_with_kept_stages_equals_recomputed():
+    """AdjointSolve keeps the stage states on the fused 1D path; the gradient equals that
+    of the loop over fr_sg_step and fr_sg_adjoint_step (recomputed stages) bit for bit."""
+    import torch
+    from paper_2112_05946_amd.adjoint import AdjointSolve, mean_square
+    cfg = inputs.small(inputs.BURGERS_ADJOINT, 40)
+    announce("adjoint_kept_stages_gradient")
+    sol = solver_for(cfg)
+    sol.timing(True)
+    u0 = sol.initial_state()
+    params = torch.tensor([0.0, 1.4], dtype=torch.float64)
+    n, k, dt = 23, 5, 3e-4
+    x = u0.clone().requires_grad_(True)
+    J = mean_square(AdjointSolve.apply(x, params, sol, n, dt, k), sol)
+    J.backward()
+    passes = sol.timing_read()
+    # first stages: n forward steps and n kept-stage recomputations (recomputing inside
+    # the adjoint steps would add n more, less one per segment)
+    assert passes["stage1"][0] == 2 * n, passes
+    # the same gradient by recomputing every stage inside the adjoint steps
+    u = u0.detach().clone()
+    flags = []
+    for _ in range(n):
+        flags.append(sol.step(u, dt)[1].clone())
+    uT = u.clone().requires_grad_(True)
+    (g,) = torch.autograd.grad(mean_square(uT, sol), [uT])
+    lam = g.detach().clone()
+    states = [u0.detach().clone()]
+    for i in range(n - 1):
+        s = states[-1].clone()
+        sol.step(s, dt)
+        states.append(s)
+    for i in reversed(range(n)):
+        sol.adjoint_step(states[i], flags[i], dt, lam)
+    sol.sync()
+    assert torch.equal(x.grad, lam)
+
+
+def test_kept_stage_entry_points_checked():
+    import torch
+    from paper_2112_05946_amd.binding import FrsgError
+    sol = solver_for(inputs.small(inputs.BURGERS, 8))
+    u = sol.initial_state()
+    w = torch.empty_like(u)
+    with pytest.raises(FrsgError) as ei:
+        sol.step_stages(u, w, w, 1e-4)
+    assert ei.value.status == -1
+    with pytest.raises(FrsgError) as ei:
+        sol.adjoint_step_stages(u, w, w.clone(), None, 1e-4, w)       # w1 aliases lam
+    assert ei.value.status == -1
+    sod = solver_for(inputs.small(inputs.SOD, 8))
+    us = sod.initial_state()
+    with pytest.raises(FrsgError) as ei:
+        sod.step_stages(us, torch.empty_like(us), torch.empty_like(us), 1e-4)
+    assert ei.value.status == -2
