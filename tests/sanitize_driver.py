@@ -110,6 +110,8 @@ def main(path):
         lib.fr_sg_step(None, None, 0.0, None, None) == -1,
         lib.fr_sg_steps(None, None, 1, None, None) == -1,
         lib.fr_sg_adjoint_step(None, None, None, 1e-3, None, None) == -1,
+        lib.fr_sg_step_stages(None, None, 0.0, None, None, None, None) == -1,
+        lib.fr_sg_adjoint_step_stages(None, None, None, None, None, 1e-3, None, None) == -1,
         lib.fr_sg_destroy(None) == 0,
         lib.fr_sg_copy(None, None, 0, None) == 0,
         lib.fr_sg_copy(None, None, -1, None) == -1,

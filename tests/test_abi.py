@@ -115,6 +115,8 @@ def test_null_arguments(lib):
     assert lib.fr_sg_rhs(None, None, None) == -1
     assert lib.fr_sg_step(None, None, 0.0, None, None) == -1
     assert lib.fr_sg_adjoint_step(None, None, None, 1e-3, None, None) == -1
+    assert lib.fr_sg_step_stages(None, None, 0.0, None, None, None, None) == -1
+    assert lib.fr_sg_adjoint_step_stages(None, None, None, None, None, 1e-3, None, None) == -1
     assert lib.fr_sg_destroy(None) == 0
 
 
