@@ -120,13 +120,22 @@ __device__ __forceinline__ double stage1d_block(const KParams& P, const Stage1DA
   // 1. stage coefficients: local slot ls = 0 .. nloc + 1 holds element e0 - 1 + ls
   // (variable, mode) outer, so consecutive threads read consecutive addresses
   const int span = (nloc + 2) * n;
-  for (int it = tid; it < S * M * span; it += BS) {
+  auto stage_in = [&](int it) {
     const int sk = it / span, rem = it - sk * span;  // sk = s * M + k
     const int ls = rem / n, j = rem - ls * n;
     int e = e0 - 1 + ls;
     if (e < 0) e = periodic ? E - 1 : 0;         // non-periodic: replaced by ghosts below
     if (e >= E) e = periodic ? 0 : E - 1;
     sC[ls * ncoef + sk * n + j] = A.in[(long)sk * EN + (long)e * n + j];
+  };
+  if constexpr (S > 1) {
+    // several loads in flight per thread: a system's workgroup stages several
+    // values per thread (the Euler problem with 11 modes: 5-6); the scalar
+    // equations' 1-3 per thread gain nothing from it
+#pragma unroll 4
+    for (int it = tid; it < S * M * span; it += BS) stage_in(it);
+  } else {
+    for (int it = tid; it < S * M * span; it += BS) stage_in(it);
   }
   __syncthreads();
 
@@ -358,44 +367,58 @@ __device__ __forceinline__ double stage1d_block(const KParams& P, const Stage1DA
     // nodal residual feeds KB independent sums, each taking the nodes in order
     // (so every KB gives the same sums; the one-workgroup kernel, at 128
     // registers per lane, keeps one mode per thread)
-    constexpr int KB = BS >= 1024 ? 1 : 4;
-    const int nkb = (M + KB - 1) / KB;
-    for (int it = tid; it < S * nkb * ospan; it += BS) {
-      const int skb = it / ospan, rem = it - skb * ospan;
-      const int le = rem / n, j = rem - le * n;
-      const int s = skb / nkb, k0 = (skb - s * nkb) * KB;
-      const double* Rq = sR + (((long)le * S + s) * n + j) * Nq;
-      const double* PWk[KB];
+    auto project = [&](auto kb_tag) {
+      constexpr int KB = decltype(kb_tag)::value;
+      const int nkb = (M + KB - 1) / KB;
+      for (int it = tid; it < S * nkb * ospan; it += BS) {
+        const int skb = it / ospan, rem = it - skb * ospan;
+        const int le = rem / n, j = rem - le * n;
+        const int s = skb / nkb, k0 = (skb - s * nkb) * KB;
+        const double* Rq = sR + (((long)le * S + s) * n + j) * Nq;
+        const double* PWk[KB];
 #pragma unroll
-      for (int i = 0; i < KB; ++i) PWk[i] = P.tab.PW + min(k0 + i, M - 1) * Nq;  // clamped: past M unused
-      double ad[KB];
-      R ar[KB];
-      // the combination's inputs, loaded before the sums so that their latency overlaps them
-      double uv[KB], wv[KB];
-#pragma unroll
-      for (int i = 0; i < KB; ++i) {
-        ad[i] = 0.0;
-        ar[i] = R(0);
-        const long idx = state_index(s * M + min(k0 + i, M - 1), le, j);
-        uv[i] = A.rhs_only ? 0.0 : A.u[idx];
-        wv[i] = A.rhs_only ? 0.0 : A.w[idx];
-      }
-      for (int qq = 0; qq < Nq; ++qq) {
-        const double r = Rq[qq];
+        for (int i = 0; i < KB; ++i) PWk[i] = P.tab.PW + min(k0 + i, M - 1) * Nq;  // clamped: past M unused
+        double ad[KB];
+        R ar[KB];
+        // the combination's inputs, loaded before the sums so that their latency overlaps them
+        double uv[KB], wv[KB];
 #pragma unroll
         for (int i = 0; i < KB; ++i) {
-          if (std::is_same<R, double>::value || k0 + i == 0)
-            ad[i] += PWk[i][qq] * r;  // FP64 (the mean mode in every precision)
-          else
-            ar[i] += (R)PWk[i][qq] * (R)r;
+          ad[i] = 0.0;
+          ar[i] = R(0);
+          const long idx = state_index(s * M + min(k0 + i, M - 1), le, j);
+          uv[i] = A.rhs_only ? 0.0 : A.u[idx];
+          wv[i] = A.rhs_only ? 0.0 : A.w[idx];
         }
-      }
+        for (int qq = 0; qq < Nq; ++qq) {
+          const double r = Rq[qq];
 #pragma unroll
-      for (int i = 0; i < KB; ++i)
-        if (k0 + i < M)
-          combine(s * M + k0 + i, le, j, (std::is_same<R, double>::value || k0 + i == 0) ? ad[i] : (double)ar[i],
-                  uv[i], wv[i]);
-    }
+          for (int i = 0; i < KB; ++i) {
+            if (std::is_same<R, double>::value || k0 + i == 0)
+              ad[i] += PWk[i][qq] * r;  // FP64 (the mean mode in every precision)
+            else
+              ar[i] += (R)PWk[i][qq] * (R)r;
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < KB; ++i)
+          if (k0 + i < M)
+            combine(s * M + k0 + i, le, j, (std::is_same<R, double>::value || k0 + i == 0) ? ad[i] : (double)ar[i],
+                    uv[i], wv[i]);
+      }
+    };
+    // systems take blocks of six modes where blocks of four would leave part of
+    // the tasks to a second round of the workgroup's threads (the Euler problem
+    // with 11 modes and 8 elements per workgroup: 288 tasks of four modes, 192 of
+    // six, for 256 threads)
+    if constexpr (BS >= 1024)
+      project(std::integral_constant<int, 1>{});
+    else if constexpr (S == 1)
+      project(std::integral_constant<int, 4>{});
+    else if (S * ((M + 3) / 4) * ospan > BS && S * ((M + 5) / 6) * ospan <= BS)
+      project(std::integral_constant<int, 6>{});
+    else
+      project(std::integral_constant<int, 4>{});
   }
   if (A.clear_flags)
     for (int it = tid; it < nloc; it += BS) A.clear_flags[e0 + it] = 0;
@@ -506,6 +529,12 @@ __device__ __forceinline__ double stage1d_block(const KParams& P, const Stage1DA
     if (own && q == 0) A.flag_filt[e0 + le] = 0;
   }
 
+  // nodal values of the output at node q: the limiter forms them, and the CFL
+  // maximum takes them where the limiter left the element as it was (the same
+  // sums in the same order as its own expansion)
+  double Usp[S][N];
+  bool usp_ok = false;
+
   // 5b. positivity limiter (Sec. 4.3): minimum of density and pressure over the
   // solution and face points at node q, then over the element's nodes
   if constexpr (S > 1) {
@@ -515,7 +544,7 @@ __device__ __forceinline__ double stage1d_block(const KParams& P, const Stage1DA
       bool realizable = false;
       double eps = 0.0;
       // values at node q: the n solution points, then the two faces by interpolation
-      double Usp[S][N], Ufc[S][2];
+      double Ufc[S][2];
       auto point = [&](int pt, double* U) {  // pt < n: solution point; n, n+1: faces
 #pragma unroll
         for (int s = 0; s < S; ++s) U[s] = pt < n ? Usp[s][pt] : Ufc[s][pt - n];
@@ -607,6 +636,7 @@ __device__ __forceinline__ double stage1d_block(const KParams& P, const Stage1DA
         }
       }
       if (own && q == 0 && A.flag_lim && !(A.flag_or && !on)) A.flag_lim[e0 + le] = on ? 1 : 0;
+      usp_ok = own && !on;
       __syncthreads();
     }
   }
@@ -617,23 +647,24 @@ __device__ __forceinline__ double stage1d_block(const KParams& P, const Stage1DA
     __shared__ double sm[BS / 64];
     double rate = 0.0;
     if (own) {
-      double Uq[S][N];
-#pragma unroll
-      for (int s = 0; s < S; ++s)
-#pragma unroll
-        for (int j = 0; j < n; ++j) Uq[s][j] = 0.0;
-      for (int k = 0; k < M; ++k) {
-        const double phi = P.tab.Phi[k * Nq + q];
+      if (!usp_ok) {
 #pragma unroll
         for (int s = 0; s < S; ++s)
 #pragma unroll
-          for (int j = 0; j < n; ++j) Uq[s][j] += O[(s * M + k) * n + j] * phi;
+          for (int j = 0; j < n; ++j) Usp[s][j] = 0.0;
+        for (int k = 0; k < M; ++k) {
+          const double phi = P.tab.Phi[k * Nq + q];
+#pragma unroll
+          for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int j = 0; j < n; ++j) Usp[s][j] += O[(s * M + k) * n + j] * phi;
+        }
       }
 #pragma unroll
       for (int j = 0; j < n; ++j) {
         double U[S];
 #pragma unroll
-        for (int s = 0; s < S; ++s) U[s] = Uq[s][j];
+        for (int s = 0; s < S; ++s) U[s] = Usp[s][j];
         double r = speed<EQ, 0>(U, P.adv, P.gamma);
         if (!(r == r)) r = __longlong_as_double(0x7ff0000000000000ll);  // NaN -> +inf, dt -> 0
         rate = fmax(rate, r);
