@@ -454,17 +454,30 @@ def adjoint_cost(torch, Solver, inputs):
         grad()
         t_grad = timed(grad) / n
         grads[prec] = box["g"]
+
+        # every step's states kept from the forward run (k = 0): nothing recomputed
+        def grad_all():
+            x = u0.clone().requires_grad_(True)
+            J = mean_square(AdjointSolve.apply(x, params, sol, n, dt, 0), sol)
+            J.backward()
+            box["g0"] = x.grad
+        grad_all()
+        t_grad_all = timed(grad_all) / n
         dof = int(sol.info["n_dof"])
         res[prec] = {"forward_ms_per_step": t_fwd, "adjoint_step_ms": t_adj, "adjoint_over_forward": t_adj / t_fwd,
                      "adjoint_step_from_kept_stages_ms": t_adj_kept,
-                     "gradient_ms_per_step": t_grad, "gradient_over_forward": t_grad / t_fwd}
+                     "gradient_ms_per_step": t_grad, "gradient_over_forward": t_grad / t_fwd,
+                     "gradient_keep_all_ms_per_step": t_grad_all, "gradient_keep_all_over_forward": t_grad_all / t_fwd,
+                     "gradient_keep_all_equal": bool(torch.equal(box["g0"], box["g"])),
+                     "gradient_keep_all_state_bytes": 3 * n * int(u0.numel()) * 8}
         shape = (sol.shape[1], sol.info["n_nodes"])
         sol.close()
     res["fp32"]["gradient_rel_l2_vs_fp64"] = _rel(torch)(grads["fp32"], grads["fp64"])
     res["fp32"]["speedup_vs_fp64_gradient"] = res["fp64"]["gradient_ms_per_step"] / res["fp32"]["gradient_ms_per_step"]
     out = {"workload": "burgers_adjoint %d elements, p=%d, %d modes, %d nodes, %d DOF, %d steps, checkpoint every %d"
                        % (cfg["nx"], cfg["p"], shape[0], shape[1], dof, n, k),
-           "note": "gradient = forward with checkpoints + backward (segment recompute keeping the stage states + adjoint steps from them), per step"}
+           "note": "gradient = forward with checkpoints + backward (segment recompute keeping the stage states + adjoint steps from them), per step; "
+                   "gradient_keep_all: every step's start and stage states kept from the forward run (3 states per step), adjoint steps only"}
     out.update(res["fp64"])
     out["fp32_mixed"] = res["fp32"]
     return out

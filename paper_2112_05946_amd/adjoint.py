@@ -15,6 +15,12 @@ stage states (fr_sg_step_stages: the fused 1D path), the recomputation keeps
 them too and the adjoint steps take them (fr_sg_adjoint_step_stages) instead of
 recomputing them.  Memory: n_steps/k checkpoints plus k (or 3 k) states.
 
+k = 0 keeps every step's start state (and, where the path hands them out, its
+two stage states) from the forward run itself: 3 n_steps states (the Burgers
+workload of 4096 elements and 500 steps: 1.8 GB), and the backward pass runs the
+adjoint steps alone, with nothing recomputed.  The gradient is the same bit for
+bit: the kept values are those the recomputation would produce.
+
 Switch decisions (the detector's filter flags) and dt are those of the forward
 run; the derivative is that of the discrete map at those decisions.
 """
@@ -32,17 +38,23 @@ class AdjointSolve(torch.autograd.Function):
         want = np.array([float(solver.cfg.get("adv_speed", 0.0)), float(solver.cfg.get("gamma", 1.4))])
         if solver.cfg.get("equation") == "advection" and pv[0] != want[0]:
             raise ValueError("params[0] must equal the solver's advection speed %r" % want[0])
-        k = max(1, int(k))
+        k = int(k)
+        if k < 0:
+            raise ValueError("k must be >= 0 (0: keep every step's states)")
         n = int(n_steps)
         dev = u0.device
         u = u0.detach().contiguous().clone()
         flags = torch.empty((max(n, 1), 4 * solver.E), dtype=torch.uint8, device=dev)
         dts = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
         ckpts = []
-        for i in range(n):
-            if i % k == 0:
-                ckpts.append(u.clone())
-            solver.step(u, dt, dts[i:i + 1], flags[i])
+        ctx.kept, ctx.kept_stages = None, False
+        if k == 0:
+            ctx.kept, ctx.kept_stages = _forward_keeping_all(solver, u, n, dt, dts, flags)
+        else:
+            for i in range(n):
+                if i % k == 0:
+                    ckpts.append(u.clone())
+                solver.step(u, dt, dts[i:i + 1], flags[i])
         ctx.solver, ctx.n, ctx.k = solver, n, k
         ctx.params_device = params.device
         ctx.ckpts = ckpts
@@ -58,6 +70,16 @@ class AdjointSolve(torch.autograd.Function):
         dt_host = dts.cpu().numpy()
         scratch_dt = torch.empty(1, dtype=torch.float64, device=lam.device)
         scratch_fl = torch.empty(4 * solver.E, dtype=torch.uint8, device=lam.device)
+        if ctx.kept is not None:
+            bufs = ctx.kept
+            for i in reversed(range(n)):
+                if ctx.kept_stages:
+                    solver.adjoint_step_stages(bufs[0, i], bufs[1, i], bufs[2, i], flags[i], float(dt_host[i]), lam,
+                                               dparams)
+                else:
+                    solver.adjoint_step(bufs[0, i], flags[i], float(dt_host[i]), lam, dparams)
+            ctx.kept = None
+            return lam, dparams.to(ctx.params_device), None, None, None, None
         nseg = math.ceil(n / k)
         kept = None  # the segment's step-start states and stage states, where the path hands them out
         for seg in reversed(range(nseg)):
@@ -76,6 +98,28 @@ class AdjointSolve(torch.autograd.Function):
                 solver.adjoint_step(states[i - start], flags[i], float(dt_host[i]), lam, dparams)
         ctx.ckpts = None
         return lam, dparams.to(ctx.params_device), None, None, None, None
+
+
+def _forward_keeping_all(solver, u, n, dt, dts, flags):
+    """The forward steps of k = 0: every step's start state and, where the path hands
+    them out (fr_sg_step_stages), its two stage states into one [3, n] buffer of
+    states; returns the buffer and whether it holds the stage states."""
+    from .binding import FrsgError
+    bufs = torch.empty((3, max(n, 1)) + tuple(u.shape), dtype=torch.float64, device=u.device)
+    stages = True
+    for i in range(n):
+        bufs[0, i].copy_(u)
+        if stages:
+            try:
+                solver.step_stages(u, bufs[1, i], bufs[2, i], dt, dts[i:i + 1], flags[i])
+                continue
+            except FrsgError as err:
+                if i > 0 or err.status != -2:
+                    raise
+                stages = False
+                bufs = bufs[:1].clone()  # start states only
+        solver.step(u, dt, dts[i:i + 1], flags[i])
+    return bufs, stages
 
 
 def _segment_from_kept_stages(solver, ckpt, start, end, dt_host, flags, lam, dparams, scratch_dt, scratch_fl, bufs):

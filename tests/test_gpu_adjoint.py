@@ -178,13 +178,44 @@ def test_checkpoint_interval_invariance():
     u0 = sol.initial_state()
     params = torch.tensor([0.0, 1.4], dtype=torch.float64)
     grads = []
-    for k in (1, 7, 25, 100):
+    for k in (1, 7, 25, 100, 0):  # 0: every step's states kept from the forward run
         x = u0.clone().requires_grad_(True)
         J = mean_square(AdjointSolve.apply(x, params, sol, 30, 3e-4, k), sol)
         J.backward()
         grads.append(x.grad.clone())
     for gk in grads[1:]:
         assert torch.equal(gk, grads[0])
+
+
+@pytest.mark.parametrize("label,cfg", [("fused_cfl_dt", inputs.small(inputs.BURGERS_ADJOINT, 40)),
+                                       ("multipass", CASES[2][1])])
+def test_gradient_keeping_every_state_equals_checkpointed(label, cfg):
+    """k = 0 keeps every step's start state and stage states (on the fused path; the start
+    states alone on the multi-pass path, which hands no stage states out) and recomputes
+    nothing: the gradient equals the checkpointed one bit for bit, here with the CFL dt of
+    every forward step, and the backward pass launches no forward stage."""
+    import torch
+    from paper_2112_05946_amd.adjoint import AdjointSolve, mean_square
+    announce("adjoint_keep_all", label)
+    sol = solver_for(cfg)
+    u0 = sol.initial_state()
+    params = torch.tensor([0.0, 1.4], dtype=torch.float64)
+    n = 17
+    grads, uTs = [], []
+    for k in (6, 0):
+        x = u0.clone().requires_grad_(True)
+        uT = AdjointSolve.apply(x, params, sol, n, None, k)
+        sol.timing(True)
+        mean_square(uT, sol).backward()
+        passes = sol.timing_read()
+        sol.timing(False)
+        grads.append(x.grad.clone())
+        uTs.append(uT.detach().clone())
+    assert torch.equal(uTs[0], uTs[1])
+    assert torch.equal(grads[0], grads[1])
+    assert torch.isfinite(grads[1]).all() and grads[1].abs().max() > 0
+    if label == "fused_cfl_dt":
+        assert "stage1" not in passes, passes  # the last backward pass (k = 0) took no forward stage
 
 
 def test_adjoint_full_size_burgers_500_steps():
