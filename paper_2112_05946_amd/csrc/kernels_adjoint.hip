@@ -291,6 +291,8 @@ __global__ void __launch_bounds__(kBlockA) k_adj_stage1d(KParams P, AdjStageArgs
   const int tid = threadIdx.x;
 
   const int span = (nloc + 2) * n;
+  // unrolled so that a thread's loads of both arrays are in flight together
+#pragma unroll 3
   for (int it = tid; it < M * span; it += kBlockA) {
     const int k = it / span, rem = it - k * span;
     const int ls = rem / n, j = rem - ls * n;
