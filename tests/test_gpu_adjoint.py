@@ -187,9 +187,10 @@ def test_checkpoint_interval_invariance():
         assert torch.equal(gk, grads[0])
 
 
-@pytest.mark.parametrize("label,cfg", [("fused_cfl_dt", inputs.small(inputs.BURGERS_ADJOINT, 40)),
-                                       ("multipass", CASES[2][1])])
-def test_gradient_keeping_every_state_equals_checkpointed(label, cfg):
+@pytest.mark.parametrize("label,cfg,precision", [("fused_cfl_dt", inputs.small(inputs.BURGERS_ADJOINT, 40), "fp64"),
+                                                 ("fused_cfl_dt_fp32", inputs.small(inputs.BURGERS_ADJOINT, 40), "fp32"),
+                                                 ("multipass", CASES[2][1], "fp64")])
+def test_gradient_keeping_every_state_equals_checkpointed(label, cfg, precision):
     """k = 0 keeps every step's start state and stage states (on the fused path; the start
     states alone on the multi-pass path, which hands no stage states out) and recomputes
     nothing: the gradient equals the checkpointed one bit for bit, here with the CFL dt of
@@ -197,7 +198,7 @@ def test_gradient_keeping_every_state_equals_checkpointed(label, cfg):
     import torch
     from paper_2112_05946_amd.adjoint import AdjointSolve, mean_square
     announce("adjoint_keep_all", label)
-    sol = solver_for(cfg)
+    sol = solver_for(cfg, precision)
     u0 = sol.initial_state()
     params = torch.tensor([0.0, 1.4], dtype=torch.float64)
     n = 17
@@ -214,7 +215,7 @@ def test_gradient_keeping_every_state_equals_checkpointed(label, cfg):
     assert torch.equal(uTs[0], uTs[1])
     assert torch.equal(grads[0], grads[1])
     assert torch.isfinite(grads[1]).all() and grads[1].abs().max() > 0
-    if label == "fused_cfl_dt":
+    if label.startswith("fused"):
         assert "stage1" not in passes, passes  # the last backward pass (k = 0) took no forward stage
 
 
