@@ -533,6 +533,8 @@ def main():
     snapshot = u.clone()
     n_dof = int(sol.info["n_dof"])
     value = n_dof / (ms / 1e3)
+    # the same K-step call five more times, the state marching on: the spread of the timing
+    repeats = [timed_steps(torch, sol, u, args.steps, 0)[0] for _ in range(5)]
 
     # per-pass device times over a second run of K steps (events around each launch)
     passes = pass_times(sol, u, args.steps)
@@ -564,6 +566,8 @@ def main():
                    "precision": args.precision, "wall_s_timed": wall},
         "roofline": roofline,
         "roofline_alu": roof_alu,
+        "ms_per_step_repeats": {"runs": repeats, "median": sorted(repeats)[len(repeats) // 2],
+                                "min": min(repeats), "max": max(repeats)},
         "passes_ms_per_step": {k: v[1] / args.steps for k, v in passes.items()},
         "copy_bandwidth": copy,
         "reduced_precision": reduced,
