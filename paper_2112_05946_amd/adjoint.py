@@ -117,7 +117,11 @@ def _forward_keeping_all(solver, u, n, dt, dts, flags):
                 if i > 0 or err.status != -2:
                     raise
                 stages = False
-                bufs = bufs[:1].clone()  # start states only
+                # start states only: the n-state buffer replaces the 3 n-state one
+                first = bufs[0, 0].clone()
+                del bufs
+                bufs = torch.empty((1, max(n, 1)) + tuple(u.shape), dtype=torch.float64, device=u.device)
+                bufs[0, 0].copy_(first)
         solver.step(u, dt, dts[i:i + 1], flags[i])
     return bufs, stages
 
