@@ -408,7 +408,7 @@ __device__ __forceinline__ double stage1d_block(const KParams& P, const Stage1DA
       }
     };
     // systems take blocks of six modes where blocks of four would leave part of
-    // the tasks to a second round of the workgroup's threads (the Euler problem
+    // the tasks to a second pass of the workgroup's threads (the Euler problem
     // with 11 modes and 8 elements per workgroup: 288 tasks of four modes, 192 of
     // six, for 256 threads)
     if constexpr (BS >= 1024)
